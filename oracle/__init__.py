@@ -1,0 +1,353 @@
+"""CPU oracle for the mixed-precision matrix square root.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the library itself.  It shares no code
+with the HIP path.
+
+What it computes (each function cites the passage of the paper it follows):
+
+* ``sqrtm``: the principal square root (Sec. 1 definition) by the Schur method
+  in float64/complex128: complex Schur form, column recurrence Eq. (subst),
+  X = Q S Q^H (Sec. 2.1).  Real input returns the real part after asserting
+  that the imaginary part is at rounding level.
+* ``sqrtm_spd``: the SPD route of Alg. 3 in float64: spectral decomposition,
+  s_i = lam_i^{1/2}, X = Q S Q^T.
+* ``trsyl`` / ``rtrsyl``: the triangular Sylvester equation S Y + Y St = C
+  (Eq. (triangsylv)) by back-substitution, and Alg. 1's block recursion.
+* ``adjoint``: G with X^H G + G X^H = Gbar, the adjoint of the Frechet
+  derivative of the square root (the correction operator B_X of Sec. 3.1).
+* ``kron_sylvester``: brute-force Kronecker solve of S Y + Y St = C
+  (vec form of Sec. 3.1) for tiny sizes.
+* ``emulate_mixed``: Alg. 2 / Alg. 3 with the factorisation run by this
+  module's own textbook routines in single precision and the residual and
+  update in double precision, with the stopping rule of Alg. 2 and the
+  divergence / stagnation rules stated below.  Used for step counts and the
+  failure paths without a GPU.
+* ``mlp_*``: float64 forward/backward of the small precision-selector network.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+OK, NOCONV, NO_PRINCIPAL = 0, 1, 2
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        _lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        i = ctypes.c_int
+        _lib.orc_schur_z.argtypes = [i, dp, dp]
+        _lib.orc_schur_c.argtypes = [i, fp, fp]
+        _lib.orc_trsqrt_z.argtypes = [i, dp, dp]
+        _lib.orc_trsqrt_c.argtypes = [i, fp, fp]
+        _lib.orc_sqrtm_z.argtypes = [i, dp, dp, dp, dp, dp]
+        _lib.orc_syev_d.argtypes = [i, dp, dp, dp]
+        _lib.orc_syev_s.argtypes = [i, fp, fp, fp]
+        _lib.orc_trsyl_z.argtypes = [i, i, dp, dp, dp, dp]
+        _lib.orc_trsyl_c.argtypes = [i, i, fp, fp, fp, fp]
+        _lib.orc_rtrsyl_z.argtypes = [i, i, dp, dp, dp, i]
+        _lib.orc_rtrsyl_c.argtypes = [i, i, fp, fp, fp, i]
+        _lib.orc_adjoint_z.argtypes = [i, dp, dp, dp]
+        for f in ("orc_schur_z", "orc_schur_c", "orc_trsqrt_z", "orc_trsqrt_c", "orc_sqrtm_z",
+                  "orc_syev_d", "orc_syev_s", "orc_adjoint_z"):
+            getattr(_lib, f).restype = ctypes.c_int
+        for f in ("orc_trsyl_z", "orc_trsyl_c", "orc_rtrsyl_z", "orc_rtrsyl_c"):
+            getattr(_lib, f).restype = None
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _f(a, dtype):
+    return np.asfortranarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _check(st, what):
+    if st == NOCONV:
+        raise OracleError(f"{what}: QR iteration did not converge")
+    if st == NO_PRINCIPAL:
+        raise OracleError(f"{what}: eigenvalue on the closed negative real axis; no principal root")
+
+
+# ---------------------------------------------------------------------------
+# Factorisations and the triangular square root
+
+
+def schur(a, single=False):
+    """Complex Schur form A = Q T Q^H.  Returns (T, Q)."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    t = _f(a, dt).copy(order="F")
+    n = t.shape[0]
+    q = np.zeros((n, n), dtype=dt, order="F")
+    fn = lib().orc_schur_c if single else lib().orc_schur_z
+    _check(fn(n, _ptr(t, ct), _ptr(q, ct)), "schur")
+    return t, q
+
+
+def trsqrt(t, single=False):
+    """Square root of an upper triangular matrix by Eq. (subst)."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    t = _f(t, dt)
+    n = t.shape[0]
+    s = np.zeros((n, n), dtype=dt, order="F")
+    fn = lib().orc_trsqrt_c if single else lib().orc_trsqrt_z
+    _check(fn(n, _ptr(t, ct), _ptr(s, ct)), "trsqrt")
+    return s
+
+
+def syev(a, single=False):
+    """Symmetric eigendecomposition A = Q diag(lam) Q^T, lam ascending."""
+    dt = np.float32 if single else np.float64
+    ct = ctypes.c_float if single else ctypes.c_double
+    a = _f(a, dt)
+    n = a.shape[0]
+    lam = np.zeros(n, dtype=dt)
+    q = np.zeros((n, n), dtype=dt, order="F")
+    fn = lib().orc_syev_s if single else lib().orc_syev_d
+    _check(fn(n, _ptr(a, ct), _ptr(lam, ct), _ptr(q, ct)), "syev")
+    return lam, q
+
+
+def sqrtm(a, return_factors=False, imag_tol=1e-12):
+    """Principal square root by the float64 Schur method (Sec. 1, Sec. 2.1)."""
+    a = np.asarray(a)
+    is_real = not np.iscomplexobj(a)
+    az = _f(a, np.complex128)
+    n = az.shape[0]
+    if n == 0:
+        x = np.zeros((0, 0), dtype=a.dtype)
+        return (x, None) if return_factors else x
+    if not np.all(np.isfinite(az)):
+        raise OracleError("sqrtm: non-finite input")
+    x = np.zeros((n, n), dtype=np.complex128, order="F")
+    q = np.zeros_like(x)
+    t = np.zeros_like(x)
+    s = np.zeros_like(x)
+    dp = ctypes.c_double
+    st = lib().orc_sqrtm_z(n, _ptr(az, dp), _ptr(x, dp), _ptr(q, dp), _ptr(t, dp), _ptr(s, dp))
+    _check(st, "sqrtm")
+    if is_real:
+        nx = np.linalg.norm(x)
+        ni = np.linalg.norm(x.imag)
+        if nx > 0 and ni > imag_tol * nx:
+            raise OracleError(f"sqrtm: real input gave imaginary part {ni / nx:.2e}")
+        x = np.asfortranarray(x.real)
+    if return_factors:
+        return x, {"Q": q, "T": t, "S": s}
+    return x
+
+
+def sqrtm_spd(a):
+    """SPD route of Alg. 3 in float64: A = Q diag(lam) Q^T, X = Q diag(lam^1/2) Q^T."""
+    lam, q = syev(a)
+    if np.any(lam <= 0):
+        raise OracleError("sqrtm_spd: matrix is not positive definite")
+    x = (q * np.sqrt(lam)[None, :]) @ q.T
+    return np.asfortranarray(0.5 * (x + x.T))
+
+
+# ---------------------------------------------------------------------------
+# Sylvester and adjoint solves
+
+
+def trsyl(s, st, c, single=False):
+    """S Y + Y St = C, S and St upper triangular (complex), back-substitution."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    s, st, c = _f(s, dt), _f(st, dt), _f(c, dt)
+    m, n = c.shape
+    y = np.zeros((m, n), dtype=dt, order="F")
+    fn = lib().orc_trsyl_c if single else lib().orc_trsyl_z
+    fn(m, n, _ptr(s, ct), _ptr(st, ct), _ptr(c, ct), _ptr(y, ct))
+    return y
+
+
+def rtrsyl(s, st, c, blks=32, single=False):
+    """Alg. 1 block recursion for S Y + Y St = C."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    s, st = _f(s, dt), _f(st, dt)
+    y = _f(c, dt).copy(order="F")
+    m, n = y.shape
+    fn = lib().orc_rtrsyl_c if single else lib().orc_rtrsyl_z
+    fn(m, n, _ptr(s, ct), _ptr(st, ct), _ptr(y, ct), int(blks))
+    return y
+
+
+def kron_sylvester(s, st, c):
+    """Brute force: (I kron S + St^T kron I) vec(Y) = vec(C) (Sec. 3.1 vec form)."""
+    s = np.asarray(s, dtype=np.complex128)
+    st = np.asarray(st, dtype=np.complex128)
+    c = np.asarray(c, dtype=np.complex128)
+    m, n = c.shape
+    big = np.kron(np.eye(n), s) + np.kron(st.T, np.eye(m))
+    y = np.linalg.solve(big, c.reshape(-1, order="F"))
+    return y.reshape((m, n), order="F")
+
+
+def adjoint(x, gbar):
+    """G with X^H G + G X^H = Gbar (complex128), through the Schur form of X.
+    Real inputs give a real G."""
+    is_real = not (np.iscomplexobj(x) or np.iscomplexobj(gbar))
+    xz = _f(x, np.complex128)
+    gz = _f(gbar, np.complex128)
+    n = xz.shape[0]
+    g = np.zeros((n, n), dtype=np.complex128, order="F")
+    dp = ctypes.c_double
+    _check(lib().orc_adjoint_z(n, _ptr(xz, dp), _ptr(gz, dp), _ptr(g, dp)), "adjoint")
+    return np.asfortranarray(g.real) if is_real else g
+
+
+def kron_adjoint(x, gbar):
+    """Brute force for X^H G + G X^H = Gbar: (I kron X^H + conj(X) kron I) vec G."""
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[0]
+    xh = x.conj().T
+    big = np.kron(np.eye(n), xh) + np.kron(xh.T, np.eye(n))
+    g = np.linalg.solve(big, np.asarray(gbar, dtype=np.complex128).reshape(-1, order="F"))
+    return g.reshape((n, n), order="F")
+
+
+# ---------------------------------------------------------------------------
+# Accuracy measures (Sec. 5.1)
+
+
+def relres(x, a):
+    """||X^2 - A||_F / ||A||_F."""
+    return float(np.linalg.norm(x @ x - a) / np.linalg.norm(a))
+
+
+def relerr(x, xref):
+    """||X - Xref||_F / ||Xref||_F."""
+    return float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision emulator (Alg. 2 / Alg. 3)
+
+ST_OK, ST_NOT_CONVERGED, ST_DIVERGED, ST_NO_PRINCIPAL, ST_NONFINITE = (
+    "ok", "not_converged", "diverged", "no_principal", "nonfinite")
+
+
+def scale_exponent(a):
+    """k with A/4^k of Frobenius norm near sqrt(n) (exact power-of-4 scaling
+    before the down-conversion, Sec. 5)."""
+    n = a.shape[0]
+    nrm = np.linalg.norm(a)
+    if nrm == 0 or n == 0:
+        return 0
+    return int(np.round(np.log(nrm / np.sqrt(n)) / np.log(4.0)))
+
+
+def _stop_rule(hist):
+    """Divergence and stagnation reading of the paper's 'diverges in our
+    tests' (Sec. 5.1), applied after each new residual:
+      diverged   if the residual is non-finite, grew on two consecutive
+                 sweeps, or exceeds 10x the first residual;
+      stagnated  if it failed to drop below 0.9x the previous residual on two
+                 consecutive sweeps."""
+    r = hist[-1]
+    if not np.isfinite(r):
+        return ST_DIVERGED
+    if r > 10.0 * hist[0]:
+        return ST_DIVERGED
+    if len(hist) >= 3 and hist[-1] > hist[-2] and hist[-2] > hist[-3]:
+        return ST_DIVERGED
+    if len(hist) >= 3 and hist[-1] > 0.9 * hist[-2] and hist[-2] > 0.9 * hist[-3]:
+        return ST_NOT_CONVERGED
+    return None
+
+
+def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32):
+    """Alg. 3 (SPD, structure='spd') or Alg. 2 (structure='general') with the
+    low precision emulated by this module's single-precision factorisation and
+    float32 arithmetic for the transforms, float64 for residual and update.
+
+    Returns dict(X, steps, hist, status).  steps counts applied corrections;
+    hist holds ||R_k||_F / ||A||_F for every residual evaluated.
+    """
+    a = np.asarray(a)
+    n = a.shape[0]
+    is_real = not np.iscomplexobj(a)
+    if structure == "auto":
+        structure = "spd" if (is_real and np.array_equal(a, a.T)) else "general"
+    if not np.all(np.isfinite(a)):
+        return {"X": None, "steps": 0, "hist": [], "status": ST_NONFINITE}
+    k = scale_exponent(a)
+    asc = a / (4.0 ** k)
+    na = np.linalg.norm(asc)
+    if structure == "spd":
+        lam, q = syev(asc.astype(np.float32), single=True)
+        if np.any(lam <= 0):
+            return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
+        s = np.sqrt(lam).astype(np.float32)
+        x = ((q * s[None, :]) @ q.T).astype(np.float64)
+        denom = (s[:, None] + s[None, :]).astype(np.float32)
+
+        def correction(r):
+            rl = r.astype(np.float32)
+            rt = q.T @ rl @ q
+            y = rt / denom
+            return (q @ y @ q.T).astype(np.float64)
+    else:
+        t, q = schur(asc.astype(np.complex64), single=True)
+        d = np.diag(t)
+        if np.any((d.imag == 0) & (d.real <= 0)):
+            return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
+        s = trsqrt(t, single=True)
+        qh = q.conj().T
+        x0 = (q @ s @ qh).astype(np.complex128)
+        x = x0.real.copy() if is_real else x0
+
+        def correction(r):
+            rl = r.astype(np.complex64)
+            rt = qh @ rl @ q
+            y = rtrsyl(s, s, rt, blks=blks, single=True)
+            dx = (q @ y @ qh).astype(np.complex128)
+            return dx.real if is_real else dx
+
+    hist = []
+    best = (np.inf, x)
+    status = ST_NOT_CONVERGED
+    steps = 0
+    for it in range(maxit + 1):
+        r = asc - x @ x
+        rr = float(np.linalg.norm(r) / na)
+        hist.append(rr)
+        if rr < best[0]:
+            best = (rr, x)
+        if rr <= tol:
+            status = ST_OK
+            break
+        verdict = _stop_rule(hist)
+        if verdict is not None:
+            status = verdict
+            break
+        if it == maxit:
+            break
+        x = x + correction(r)
+        steps += 1
+    xout = (x if status == ST_OK else best[1]) * (2.0 ** k)
+    return {"X": xout, "steps": steps if status == ST_OK else steps, "hist": hist,
+            "status": status}

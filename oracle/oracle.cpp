@@ -1,0 +1,525 @@
+// Plain CPU oracle for the principal matrix square root and the linear solves
+// that the mixed-precision method (Gao, Kressner, Shao) is built from.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code with
+// the HIP path: no headers, kernels, tables or helpers.
+//
+// Everything here is unblocked, textbook and slow on purpose, so that a reader
+// can check it against the paper by eye:
+//   * complex Schur form by Householder Hessenberg reduction followed by the
+//     implicit single-shift complex QR iteration (Wilkinson shift, Givens
+//     rotations, accumulated unitary factor) -- the decomposition A = Q T Q^H
+//     that the paper's Schur algorithm starts from (Sec. 1, Sec. 2.1);
+//   * the column recurrence for the square root of an upper triangular matrix
+//     (Eq. (subst), Sec. 2.2.1);
+//   * the symmetric spectral decomposition by Householder tridiagonalisation
+//     and implicit symmetric QR with Wilkinson shifts, the factorisation that
+//     the SPD algorithm (Alg. 3) starts from;
+//   * the triangular Sylvester equation S Y + Y St = C by plain
+//     back-substitution (Bartels-Stewart on triangular factors, Sec. 2.2.2) and
+//     the block recursion of Alg. 1 on top of it;
+//   * the adjoint solve X^H G + G X^H = Gbar used for differentiation.
+//
+// All routines are templated on the real type so that the mixed-precision
+// emulator can run the *same* textbook factorisation in single precision.
+// Matrices are column-major: element (i,j) of an n-by-n matrix is a[i + j*n].
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace orc {
+
+template <class R> using C = std::complex<R>;
+
+// ---------------------------------------------------------------------------
+// Principal complex square root by the half-angle formula.  For z = x + i y
+// with |z| = r:  t = sqrt((|x| + r)/2);  x >= 0 -> (t, y/(2t)),
+// x < 0 -> (|y|/(2t), sign(y) t).  The result has non-negative real part; the
+// branch cut is the non-positive real axis, matching the definition of the
+// principal root in Sec. 1.
+template <class R> C<R> csqrt_principal(C<R> z) {
+  R x = z.real(), y = z.imag();
+  if (x == R(0) && y == R(0)) return C<R>(0, 0);
+  R r = std::hypot(x, y);
+  R t = std::sqrt((std::fabs(x) + r) / R(2));
+  if (x >= R(0)) return C<R>(t, y / (R(2) * t));
+  return C<R>(std::fabs(y) / (R(2) * t), (y >= R(0) ? t : -t));
+}
+
+// ---------------------------------------------------------------------------
+// Complex Householder reflector P = I - 2 u u^H / (u^H u) that maps x (length
+// len) onto a multiple of e_1.  u = x + e^{i arg x_0} ||x|| e_1.  Returns false
+// when x is already zero below its first entry (no reflection needed).
+template <class R>
+bool householder(int len, const C<R>* x, C<R>* u, R* unorm2) {
+  R nx2 = 0;
+  for (int i = 0; i < len; ++i) nx2 += std::norm(x[i]);
+  R tail = nx2 - std::norm(x[0]);
+  if (tail <= R(0)) return false;
+  R nx = std::sqrt(nx2);
+  R a0 = std::abs(x[0]);
+  C<R> phase = a0 > R(0) ? x[0] / a0 : C<R>(1, 0);
+  for (int i = 0; i < len; ++i) u[i] = x[i];
+  u[0] += phase * nx;
+  R s = 0;
+  for (int i = 0; i < len; ++i) s += std::norm(u[i]);
+  *unorm2 = s;
+  return true;
+}
+
+// Hessenberg reduction A <- P^H A P with Q accumulating the reflectors, so
+// that on exit A_in = Q H Q^H.
+template <class R> void hessenberg(int n, C<R>* a, C<R>* q) {
+  std::vector<C<R>> u(n), x(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    int len = n - k - 1;
+    for (int i = 0; i < len; ++i) x[i] = a[(k + 1 + i) + (size_t)k * n];
+    R un2;
+    if (!householder<R>(len, x.data(), u.data(), &un2)) continue;
+    R f = R(2) / un2;
+    // Left: rows k+1..n-1, all columns.  A <- (I - f u u^H) A
+    for (int j = 0; j < n; ++j) {
+      C<R> s = 0;
+      for (int i = 0; i < len; ++i) s += std::conj(u[i]) * a[(k + 1 + i) + (size_t)j * n];
+      s *= f;
+      for (int i = 0; i < len; ++i) a[(k + 1 + i) + (size_t)j * n] -= u[i] * s;
+    }
+    // Right: columns k+1..n-1, all rows.  A <- A (I - f u u^H), and the
+    // same for Q.  r = M u is formed column by column, then M -= f r u^H.
+    for (C<R>* m : {a, q}) {
+      std::vector<C<R>> r(n, C<R>(0, 0));
+      for (int jj = 0; jj < len; ++jj)
+        for (int i = 0; i < n; ++i) r[i] += m[i + (size_t)(k + 1 + jj) * n] * u[jj];
+      for (int jj = 0; jj < len; ++jj) {
+        C<R> cu = f * std::conj(u[jj]);
+        for (int i = 0; i < n; ++i) m[i + (size_t)(k + 1 + jj) * n] -= r[i] * cu;
+      }
+    }
+    for (int i = k + 2; i < n; ++i) a[i + (size_t)k * n] = 0;
+  }
+}
+
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [a; b] = [r; 0].
+template <class R> void givens(C<R> a, C<R> b, R* c, C<R>* s) {
+  R aa = std::abs(a), bb = std::abs(b);
+  if (bb == R(0)) { *c = 1; *s = 0; return; }
+  if (aa == R(0)) { *c = 0; *s = 1; return; }
+  R rho = std::hypot(aa, bb);
+  *c = aa / rho;
+  *s = (a / aa) * std::conj(b) / rho;
+}
+
+// Similarity with G acting on indices (p, p+1): H <- G H G^H restricted to the
+// columns/rows that can be non-zero, Q <- Q G^H.
+template <class R>
+void apply_rot(int n, C<R>* h, C<R>* q, int p, R c, C<R> s, int col_lo, int row_hi) {
+  for (int j = col_lo; j < n; ++j) {
+    C<R> x = h[p + (size_t)j * n], y = h[p + 1 + (size_t)j * n];
+    h[p + (size_t)j * n] = c * x + s * y;
+    h[p + 1 + (size_t)j * n] = -std::conj(s) * x + c * y;
+  }
+  for (int i = 0; i <= row_hi; ++i) {
+    C<R> x = h[i + (size_t)p * n], y = h[i + (size_t)(p + 1) * n];
+    h[i + (size_t)p * n] = x * c + y * std::conj(s);
+    h[i + (size_t)(p + 1) * n] = -x * s + y * c;
+  }
+  for (int i = 0; i < n; ++i) {
+    C<R> x = q[i + (size_t)p * n], y = q[i + (size_t)(p + 1) * n];
+    q[i + (size_t)p * n] = x * c + y * std::conj(s);
+    q[i + (size_t)(p + 1) * n] = -x * s + y * c;
+  }
+}
+
+// Complex Schur decomposition.  On entry a holds A; on exit a holds the upper
+// triangular T and q the unitary Q with A = Q T Q^H.  Returns 0 on success,
+// 1 if the QR iteration failed to converge within 30 n iterations.
+template <class R> int schur(int n, C<R>* a, C<R>* q) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) q[i + (size_t)j * n] = (i == j) ? C<R>(1, 0) : C<R>(0, 0);
+  if (n <= 1) return 0;
+  hessenberg<R>(n, a, q);
+  const R eps = std::numeric_limits<R>::epsilon() / 2;
+  auto H = [&](int i, int j) -> C<R>& { return a[i + (size_t)j * n]; };
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    // Find the start of the active unreduced block by scanning for negligible
+    // subdiagonal entries.
+    int lo = hi;
+    while (lo > 0) {
+      R scale = std::abs(H(lo, lo)) + std::abs(H(lo - 1, lo - 1));
+      if (scale == R(0)) scale = 1;
+      if (std::abs(H(lo, lo - 1)) <= eps * scale) { H(lo, lo - 1) = 0; break; }
+      --lo;
+    }
+    if (lo == hi) { --hi; iter = 0; continue; }
+    if (++total > 30 * n) return 1;
+    ++iter;
+    // Wilkinson shift: eigenvalue of the trailing 2x2 block closest to H(hi,hi).
+    C<R> mu;
+    if (iter % 10 == 0) {
+      // Exceptional shift after 10 iterations without deflation.
+      mu = H(hi, hi) + C<R>(R(0.75) * std::abs(H(hi, hi - 1)), 0);
+    } else {
+      C<R> a11 = H(hi - 1, hi - 1), a12 = H(hi - 1, hi), a21 = H(hi, hi - 1), a22 = H(hi, hi);
+      C<R> tr = a11 + a22, det = a11 * a22 - a12 * a21;
+      C<R> disc = std::sqrt(tr * tr / R(4) - det);
+      C<R> l1 = tr / R(2) + disc, l2 = tr / R(2) - disc;
+      mu = (std::abs(l1 - a22) < std::abs(l2 - a22)) ? l1 : l2;
+    }
+    // Implicit single-shift sweep over the active block [lo, hi].
+    C<R> x = H(lo, lo) - mu, y = H(lo + 1, lo);
+    for (int k = lo; k < hi; ++k) {
+      R c; C<R> s;
+      givens<R>(x, y, &c, &s);
+      int col_lo = (k > lo) ? k - 1 : lo;
+      int row_hi = std::min(k + 2, hi);
+      apply_rot<R>(n, a, q, k, c, s, col_lo, row_hi);
+      if (k > lo) H(k + 1, k - 1) = 0;
+      if (k + 1 < hi) { x = H(k + 1, k); y = H(k + 2, k); }
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i) a[i + (size_t)j * n] = 0;
+  return 0;
+}
+
+// Square root of an upper triangular matrix by the column recurrence
+// (Eq. (subst)): s_ii = t_ii^{1/2}; for j = 2..n and i = j-1 down to 1,
+// s_ij = (t_ij - sum_{k=i+1}^{j-1} s_ik s_kj) / (s_ii + s_jj).
+// Returns 2 if a diagonal entry lies on the closed negative real axis.
+template <class R> int trsqrt(int n, const C<R>* t, C<R>* s) {
+  for (size_t k = 0; k < (size_t)n * n; ++k) s[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    C<R> d = t[i + (size_t)i * n];
+    if (d.imag() == R(0) && d.real() <= R(0)) return 2;
+    s[i + (size_t)i * n] = csqrt_principal<R>(d);
+  }
+  for (int j = 1; j < n; ++j) {
+    for (int i = j - 1; i >= 0; --i) {
+      C<R> acc = t[i + (size_t)j * n];
+      for (int k = i + 1; k <= j - 1; ++k) acc -= s[i + (size_t)k * n] * s[k + (size_t)j * n];
+      s[i + (size_t)j * n] = acc / (s[i + (size_t)i * n] + s[j + (size_t)j * n]);
+    }
+  }
+  return 0;
+}
+
+// C = A * B (n x n, complex), plain triple loop.
+template <class R> void cgemm(int n, const C<R>* a, const C<R>* b, C<R>* c) {
+  for (size_t k = 0; k < (size_t)n * n; ++k) c[k] = 0;
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k) {
+      C<R> bkj = b[k + (size_t)j * n];
+      for (int i = 0; i < n; ++i) c[i + (size_t)j * n] += a[i + (size_t)k * n] * bkj;
+    }
+}
+
+// Triangular Sylvester equation S Y + Y St = Cm with S (m x m) and St (n x n)
+// upper triangular, solved by back-substitution: columns left to right, rows
+// bottom to top,
+//   y_ij = (c_ij - sum_{k>i} s_ik y_kj - sum_{k<j} y_ik st_kj) / (s_ii + st_jj).
+// Leading dimensions ldS, ldT, ldC, ldY allow operating on sub-blocks.
+template <class R>
+void trsyl(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, const C<R>* Cm,
+           int ldC, C<R>* Y, int ldY) {
+  for (int j = 0; j < n; ++j) {
+    for (int i = m - 1; i >= 0; --i) {
+      C<R> acc = Cm[i + (size_t)j * ldC];
+      for (int k = i + 1; k < m; ++k) acc -= S[i + (size_t)k * ldS] * Y[k + (size_t)j * ldY];
+      for (int k = 0; k < j; ++k) acc -= Y[i + (size_t)k * ldY] * St[k + (size_t)j * ldT];
+      Y[i + (size_t)j * ldY] = acc / (S[i + (size_t)i * ldS] + St[j + (size_t)j * ldT]);
+    }
+  }
+}
+
+// Cm(mxn) -= A(mxk) * B(kxn) for sub-blocks with leading dimensions.
+template <class R>
+void sub_gemm(int m, int n, int k, const C<R>* A, int lda, const C<R>* B, int ldb, C<R>* Cm,
+              int ldc) {
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < k; ++l) {
+      C<R> b = B[l + (size_t)j * ldb];
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldc] -= A[i + (size_t)l * lda] * b;
+    }
+}
+
+// Block recursion of Alg. 1: solves S Y + Y St = Cm, overwriting Cm with Y.
+// The split point of a dimension m is floor(m/2); "n <= m/2" and "m <= n/2"
+// are tested as 2n <= m and 2m <= n.
+template <class R>
+void rtrsyl(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, C<R>* Cm, int ldC,
+            int blks) {
+  if (m <= 0 || n <= 0) return;
+  if (m <= blks && n <= blks) {
+    std::vector<C<R>> y((size_t)m * n);
+    trsyl<R>(m, n, S, ldS, St, ldT, Cm, ldC, y.data(), m);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldC] = y[i + (size_t)j * m];
+    return;
+  }
+  if (2 * n <= m) {
+    // Split rows only: S = [S11 S12; 0 S22], Cm = [C1; C2].
+    int m1 = m / 2, m2 = m - m1;
+    const C<R>* S11 = S;
+    const C<R>* S12 = S + (size_t)m1 * ldS;
+    const C<R>* S22 = S + m1 + (size_t)m1 * ldS;
+    C<R>* C1 = Cm;
+    C<R>* C2 = Cm + m1;
+    rtrsyl<R>(m2, n, S22, ldS, St, ldT, C2, ldC, blks);
+    sub_gemm<R>(m1, n, m2, S12, ldS, C2, ldC, C1, ldC);
+    rtrsyl<R>(m1, n, S11, ldS, St, ldT, C1, ldC, blks);
+    return;
+  }
+  if (2 * m <= n) {
+    // Split columns only: St = [St11 St12; 0 St22], Cm = [C1 C2].
+    int n1 = n / 2, n2 = n - n1;
+    const C<R>* T11 = St;
+    const C<R>* T12 = St + (size_t)n1 * ldT;
+    const C<R>* T22 = St + n1 + (size_t)n1 * ldT;
+    C<R>* C1 = Cm;
+    C<R>* C2 = Cm + (size_t)n1 * ldC;
+    rtrsyl<R>(m, n1, S, ldS, T11, ldT, C1, ldC, blks);
+    // C2 -= Y1 * St12
+    sub_gemm<R>(m, n2, n1, C1, ldC, T12, ldT, C2, ldC);
+    rtrsyl<R>(m, n2, S, ldS, T22, ldT, C2, ldC, blks);
+    return;
+  }
+  int m1 = m / 2, m2 = m - m1, n1 = n / 2, n2 = n - n1;
+  const C<R>* S11 = S;
+  const C<R>* S12 = S + (size_t)m1 * ldS;
+  const C<R>* S22 = S + m1 + (size_t)m1 * ldS;
+  const C<R>* T11 = St;
+  const C<R>* T12 = St + (size_t)n1 * ldT;
+  const C<R>* T22 = St + n1 + (size_t)n1 * ldT;
+  C<R>* C11 = Cm;
+  C<R>* C21 = Cm + m1;
+  C<R>* C12 = Cm + (size_t)n1 * ldC;
+  C<R>* C22 = Cm + m1 + (size_t)n1 * ldC;
+  rtrsyl<R>(m2, n1, S22, ldS, T11, ldT, C21, ldC, blks);             // Y21
+  sub_gemm<R>(m1, n1, m2, S12, ldS, C21, ldC, C11, ldC);              // C11 -= S12 Y21
+  sub_gemm<R>(m2, n2, n1, C21, ldC, T12, ldT, C22, ldC);              // C22 -= Y21 St12
+  rtrsyl<R>(m1, n1, S11, ldS, T11, ldT, C11, ldC, blks);             // Y11
+  rtrsyl<R>(m2, n2, S22, ldS, T22, ldT, C22, ldC, blks);             // Y22
+  sub_gemm<R>(m1, n2, m2, S12, ldS, C22, ldC, C12, ldC);              // C12 -= S12 Y22
+  sub_gemm<R>(m1, n2, n1, C11, ldC, T12, ldT, C12, ldC);              // C12 -= Y11 St12
+  rtrsyl<R>(m1, n2, S11, ldS, T22, ldT, C12, ldC, blks);             // Y12
+}
+
+// ---------------------------------------------------------------------------
+// Real symmetric eigendecomposition A = Q diag(lam) Q^T: Householder
+// tridiagonalisation with explicit accumulation of Q, then the implicit
+// symmetric QR iteration with Wilkinson shifts (Golub & Van Loan, Sec. 8.3),
+// each step a chase of a bulge by Givens rotations that are also applied to Q.
+// Eigenvalues are returned in ascending order with matching columns of Q.
+// Returns 0, or 1 if the iteration did not converge within 30 n sweeps.
+template <class R> int syev(int n, const R* ain, R* lam, R* q) {
+  std::vector<R> a(ain, ain + (size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) q[i + (size_t)j * n] = (i == j) ? R(1) : R(0);
+  auto A = [&](int i, int j) -> R& { return a[i + (size_t)j * n]; };
+  std::vector<R> u(n), p(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    int len = n - k - 1;
+    R nx2 = 0;
+    for (int i = 0; i < len; ++i) nx2 += A(k + 1 + i, k) * A(k + 1 + i, k);
+    R x0 = A(k + 1, k);
+    if (nx2 - x0 * x0 <= R(0)) continue;
+    R nx = std::sqrt(nx2);
+    for (int i = 0; i < len; ++i) u[i] = A(k + 1 + i, k);
+    u[0] += (x0 >= R(0) ? nx : -nx);
+    R un2 = 0;
+    for (int i = 0; i < len; ++i) un2 += u[i] * u[i];
+    R f = R(2) / un2;
+    // Two-sided update of the trailing block B = A(k+1:, k+1:) and of the
+    // column/row k: A <- P A P with P = I - f u u^T.
+    // p = f B u ; K = f/2 u^T p ; w = p - K u ; B <- B - u w^T - w u^T.
+    for (int i = 0; i < len; ++i) p[i] = 0;
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < len; ++i) p[i] += A(k + 1 + i, k + 1 + j) * u[j];
+    for (int i = 0; i < len; ++i) p[i] *= f;
+    R K = 0;
+    for (int i = 0; i < len; ++i) K += u[i] * p[i];
+    K *= f / R(2);
+    for (int i = 0; i < len; ++i) w[i] = p[i] - K * u[i];
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < len; ++i) A(k + 1 + i, k + 1 + j) -= u[i] * w[j] + w[i] * u[j];
+    R newv = (x0 >= R(0) ? -nx : nx);
+    A(k + 1, k) = newv;
+    A(k, k + 1) = newv;
+    for (int i = 1; i < len; ++i) { A(k + 1 + i, k) = 0; A(k, k + 1 + i) = 0; }
+    // Q <- Q P:  r = Q u, then Q -= f r u^T.
+    std::vector<R> r(n, R(0));
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < n; ++i) r[i] += q[i + (size_t)(k + 1 + j) * n] * u[j];
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < n; ++i) q[i + (size_t)(k + 1 + j) * n] -= f * r[i] * u[j];
+  }
+  std::vector<R> d(n), e(n, R(0));
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+  const R eps = std::numeric_limits<R>::epsilon() / 2;
+  int hi = n - 1, total = 0;
+  while (hi > 0) {
+    int lo = hi;
+    while (lo > 0) {
+      if (std::fabs(e[lo - 1]) <= eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) {
+        e[lo - 1] = 0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) { --hi; continue; }
+    if (++total > 30 * n) return 1;
+    // Wilkinson shift from the trailing 2x2 block.
+    R dd = (d[hi - 1] - d[hi]) / R(2);
+    R b2 = e[hi - 1] * e[hi - 1];
+    R den = dd + (dd >= R(0) ? R(1) : R(-1)) * std::sqrt(dd * dd + b2);
+    R mu = (den == R(0)) ? d[hi] : d[hi] - b2 / den;
+    R x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      // Rotation in the (k, k+1) plane that annihilates z against x.
+      R r = std::hypot(x, z);
+      R c = (r == R(0)) ? R(1) : x / r;
+      R s = (r == R(0)) ? R(0) : z / r;
+      if (k > lo) e[k - 1] = r;
+      // Apply G^T T G on the tridiagonal entries touched by the rotation.
+      R dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk + R(2) * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk - R(2) * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk1 - dk) + (c * c - s * s) * ek;
+      if (k + 1 < hi) {
+        x = e[k];
+        z = s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      for (int i = 0; i < n; ++i) {
+        R qa = q[i + (size_t)k * n], qb = q[i + (size_t)(k + 1) * n];
+        q[i + (size_t)k * n] = c * qa + s * qb;
+        q[i + (size_t)(k + 1) * n] = -s * qa + c * qb;
+      }
+    }
+  }
+  // Sort ascending (selection sort keeps it obviously correct).
+  for (int i = 0; i < n; ++i) {
+    int m = i;
+    for (int j = i + 1; j < n; ++j)
+      if (d[j] < d[m]) m = j;
+    if (m != i) {
+      std::swap(d[i], d[m]);
+      for (int r = 0; r < n; ++r) std::swap(q[r + (size_t)i * n], q[r + (size_t)m * n]);
+    }
+  }
+  for (int i = 0; i < n; ++i) lam[i] = d[i];
+  return 0;
+}
+
+}  // namespace orc
+
+using orc::C;
+
+extern "C" {
+
+// Status codes shared by the oracle entry points.
+enum { ORC_OK = 0, ORC_NOCONV = 1, ORC_NO_PRINCIPAL = 2 };
+
+// Complex Schur decomposition A = Q T Q^H (complex128).  a: in A, out T.
+int orc_schur_z(int n, double* a, double* q) {
+  return orc::schur<double>(n, reinterpret_cast<C<double>*>(a), reinterpret_cast<C<double>*>(q));
+}
+int orc_schur_c(int n, float* a, float* q) {
+  return orc::schur<float>(n, reinterpret_cast<C<float>*>(a), reinterpret_cast<C<float>*>(q));
+}
+
+int orc_trsqrt_z(int n, const double* t, double* s) {
+  return orc::trsqrt<double>(n, reinterpret_cast<const C<double>*>(t), reinterpret_cast<C<double>*>(s));
+}
+int orc_trsqrt_c(int n, const float* t, float* s) {
+  return orc::trsqrt<float>(n, reinterpret_cast<const C<float>*>(t), reinterpret_cast<C<float>*>(s));
+}
+
+// Principal square root by the Schur method: A = Q T Q^H, S = T^{1/2},
+// X = Q S Q^H.  complex128 in/out.  Optionally returns Q, T, S.
+int orc_sqrtm_z(int n, const double* a_in, double* x_out, double* q_out, double* t_out,
+                double* s_out) {
+  using Z = C<double>;
+  std::vector<Z> a(reinterpret_cast<const Z*>(a_in), reinterpret_cast<const Z*>(a_in) + (size_t)n * n);
+  std::vector<Z> q((size_t)n * n), s((size_t)n * n), tmp((size_t)n * n), x((size_t)n * n);
+  int st = orc::schur<double>(n, a.data(), q.data());
+  if (st) return st;
+  st = orc::trsqrt<double>(n, a.data(), s.data());
+  if (st) return st;
+  // X = Q S Q^H
+  orc::cgemm<double>(n, q.data(), s.data(), tmp.data());
+  std::vector<Z> qh((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) qh[i + (size_t)j * n] = std::conj(q[j + (size_t)i * n]);
+  orc::cgemm<double>(n, tmp.data(), qh.data(), x.data());
+  std::memcpy(x_out, x.data(), sizeof(Z) * (size_t)n * n);
+  if (q_out) std::memcpy(q_out, q.data(), sizeof(Z) * (size_t)n * n);
+  if (t_out) std::memcpy(t_out, a.data(), sizeof(Z) * (size_t)n * n);
+  if (s_out) std::memcpy(s_out, s.data(), sizeof(Z) * (size_t)n * n);
+  return 0;
+}
+
+// Symmetric eigendecomposition (float64 / float32).
+int orc_syev_d(int n, const double* a, double* lam, double* q) { return orc::syev<double>(n, a, lam, q); }
+int orc_syev_s(int n, const float* a, float* lam, float* q) { return orc::syev<float>(n, a, lam, q); }
+
+// Triangular Sylvester S Y + Y St = Cm (complex128), unblocked.
+void orc_trsyl_z(int m, int n, const double* s, const double* st, const double* cm, double* y) {
+  using Z = C<double>;
+  orc::trsyl<double>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                     reinterpret_cast<const Z*>(cm), m, reinterpret_cast<Z*>(y), m);
+}
+void orc_trsyl_c(int m, int n, const float* s, const float* st, const float* cm, float* y) {
+  using Z = C<float>;
+  orc::trsyl<float>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                    reinterpret_cast<const Z*>(cm), m, reinterpret_cast<Z*>(y), m);
+}
+
+// Alg. 1 block recursion; cm is overwritten by Y.
+void orc_rtrsyl_z(int m, int n, const double* s, const double* st, double* cm, int blks) {
+  using Z = C<double>;
+  orc::rtrsyl<double>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                      reinterpret_cast<Z*>(cm), m, blks);
+}
+void orc_rtrsyl_c(int m, int n, const float* s, const float* st, float* cm, int blks) {
+  using Z = C<float>;
+  orc::rtrsyl<float>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                     reinterpret_cast<Z*>(cm), m, blks);
+}
+
+// Adjoint of the Frechet derivative of the square root: solve
+// X^H G + G X^H = Gbar (complex128) through the Schur form X = U S U^H.
+// With H = U^H G U and K = H^H the equation becomes S K + K S = (U^H Gbar U)^H,
+// an upper triangular Sylvester equation solved by back-substitution.
+int orc_adjoint_z(int n, const double* x_in, const double* gb_in, double* g_out) {
+  using Z = C<double>;
+  std::vector<Z> s(reinterpret_cast<const Z*>(x_in), reinterpret_cast<const Z*>(x_in) + (size_t)n * n);
+  std::vector<Z> u((size_t)n * n), uh((size_t)n * n), t1((size_t)n * n), t2((size_t)n * n),
+      k((size_t)n * n);
+  int st = orc::schur<double>(n, s.data(), u.data());
+  if (st) return st;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) uh[i + (size_t)j * n] = std::conj(u[j + (size_t)i * n]);
+  const Z* gb = reinterpret_cast<const Z*>(gb_in);
+  orc::cgemm<double>(n, uh.data(), gb, t1.data());
+  orc::cgemm<double>(n, t1.data(), u.data(), t2.data());   // U^H Gbar U
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) t1[i + (size_t)j * n] = std::conj(t2[j + (size_t)i * n]);
+  orc::trsyl<double>(n, n, s.data(), n, s.data(), n, t1.data(), n, k.data(), n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) t2[i + (size_t)j * n] = std::conj(k[j + (size_t)i * n]);  // H
+  orc::cgemm<double>(n, u.data(), t2.data(), t1.data());
+  orc::cgemm<double>(n, t1.data(), uh.data(), t2.data());
+  std::memcpy(g_out, t2.data(), sizeof(Z) * (size_t)n * n);
+  return 0;
+}
+
+}  // extern "C"

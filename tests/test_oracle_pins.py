@@ -1,0 +1,349 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other
+than itself -- closed forms, exact constructions, invariants, an independent
+library routine, multiprecision arithmetic or Kronecker brute force."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+
+
+def test_diagonal_principal_branch():
+    # Diagonal A: X = diag(sqrt(a_ii)), principal branch (Sec. 1 definition).
+    d = np.array([4.0, 0.25, 2.0 + 0j, -3.0 + 1e-3j, -3.0 - 1e-3j, 1j, -1j, 1e-8])
+    x = oracle.sqrtm(np.diag(d))
+    expect = np.sqrt(d.astype(np.complex128))  # numpy's principal complex sqrt
+    assert np.allclose(np.diag(x), expect, rtol=1e-14, atol=0)
+    assert np.all(np.diag(x).real > 0)
+    assert np.abs(x - np.diag(np.diag(x))).max() == 0
+
+
+def test_2x2_cayley_hamilton():
+    # For 2x2 A with eigenvalues l1, l2 (no eigenvalue on R<=0):
+    # sqrt(A) = (A + s I) / t with s = sqrt(l1) sqrt(l2), t = sqrt(l1) + sqrt(l2).
+    r = rng(1)
+    for _ in range(20):
+        a = r.standard_normal((2, 2)) + 1j * r.standard_normal((2, 2)) + 3 * np.eye(2)
+        l = np.linalg.eigvals(a)
+        sq = np.sqrt(l)
+        s = sq[0] * sq[1]
+        t = sq[0] + sq[1]
+        expect = (a + s * np.eye(2)) / t
+        x = oracle.sqrtm(a)
+        assert np.abs(x - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+def test_upper_triangular_2x2_recurrence():
+    # [[a, b], [0, c]] -> [[sqrt a, b/(sqrt a + sqrt c)], [0, sqrt c]] (Eq. (subst), n=2).
+    a, b, c = 2.0 + 1j, -0.5 + 3j, 0.3 - 0.1j
+    t = np.array([[a, b], [0, c]])
+    s = oracle.trsqrt(t)
+    sa, sc = np.sqrt(a), np.sqrt(c)
+    expect = np.array([[sa, b / (sa + sc)], [0, sc]])
+    assert np.abs(s - expect).max() <= 1e-15 * 4
+
+
+def test_triangular_3x3_hand_expansion():
+    # n = 3: s_13 = (t_13 - s_12 s_23) / (s_11 + s_33), written out by hand.
+    t = np.array([[4.0, 1.0, 2.0], [0, 9.0, -1.0], [0, 0, 1.0]], dtype=complex)
+    s11, s22, s33 = 2.0, 3.0, 1.0
+    s12 = 1.0 / (s11 + s22)
+    s23 = -1.0 / (s22 + s33)
+    s13 = (2.0 - s12 * s23) / (s11 + s33)
+    expect = np.array([[s11, s12, s13], [0, s22, s23], [0, 0, s33]])
+    s = oracle.trsqrt(t)
+    assert np.abs(s - expect).max() <= 1e-15 * 8
+    assert np.abs(s @ s - t).max() <= 1e-14
+
+
+def test_no_principal_root_rejected():
+    with pytest.raises(oracle.OracleError):
+        oracle.sqrtm(np.diag([1.0, -2.0, 3.0]))
+    with pytest.raises(oracle.OracleError):
+        oracle.sqrtm(np.diag([1.0, 0.0]))
+
+
+# ---------------------------------------------------------------------------
+# Exact constructions A = B^2
+
+
+@pytest.mark.parametrize("n,seed", [(8, 6), (40, 7), (96, 8)])
+def test_complex_square_known_root(n, seed):
+    a, b = W.complex_square(n, seed)
+    x = oracle.sqrtm(a)
+    assert oracle.relerr(x, b) < 1e-12
+    assert oracle.relres(x, a) < 1e-13
+
+
+@pytest.mark.parametrize("n,kappa,seed", [(16, 1e2, 1), (64, 1e4, 2), (128, 1e6, 3)])
+def test_spd_known_root_both_routes(n, kappa, seed):
+    a, q, lam = W.spd(n, kappa, seed)
+    xt = (q * np.sqrt(lam)[None, :]) @ q.T
+    x1 = oracle.sqrtm(a)
+    x2 = oracle.sqrtm_spd(a)
+    bound = 1e-15 * np.sqrt(kappa) * n * 4
+    assert oracle.relerr(x1, xt) < bound
+    assert oracle.relerr(x2, xt) < bound
+    # the two independent routes agree
+    assert oracle.relerr(x1, x2) < bound
+
+
+# ---------------------------------------------------------------------------
+# Factorisations against library routines and invariants
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64])
+def test_schur_invariants(n):
+    r = rng(n)
+    a = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    t, q = oracle.schur(a)
+    assert np.abs(np.tril(t, -1)).max(initial=0) == 0
+    assert np.linalg.norm(q.conj().T @ q - np.eye(n)) < 1e-13 * max(n, 1)
+    assert np.linalg.norm(q @ t @ q.conj().T - a) < 1e-13 * np.linalg.norm(a)
+    ev = np.sort_complex(np.diag(t))
+    ref = np.sort_complex(np.linalg.eigvals(a))
+    assert np.abs(ev - ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 100])
+def test_syev_against_library(n):
+    a, _, _ = W.spd(n, 1e3, 10 + n)
+    lam, q = oracle.syev(a)
+    ref = np.linalg.eigvalsh(a)
+    assert np.abs(lam - ref).max() < 1e-13 * np.abs(ref).max() * n
+    assert np.linalg.norm(q.T @ q - np.eye(n)) < 1e-13 * n
+    assert np.linalg.norm((q * lam) @ q.T - a) < 1e-13 * n * np.linalg.norm(a)
+
+
+def test_syev_single_precision_backward_error():
+    a, _, _ = W.spd(80, 1e2, 5)
+    lam, q = oracle.syev(a.astype(np.float32), single=True)
+    assert lam.dtype == np.float32 and q.dtype == np.float32
+    q64 = q.astype(np.float64)
+    assert np.linalg.norm(q64.T @ q64 - np.eye(80)) < 80 * 6e-8 * 10
+    assert np.linalg.norm((q64 * lam) @ q64.T - a) < 80 * 6e-8 * 10 * np.linalg.norm(a)
+
+
+def test_against_scipy_sqrtm():
+    import scipy.linalg as sl
+    a = W.nonsym_shifted(60, 5)
+    x = oracle.sqrtm(a)
+    assert oracle.relerr(x, np.real(sl.sqrtm(a))) < 1e-12
+
+
+def test_against_mpmath_50_digits():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    r = rng(11)
+    n = 5
+    a = r.standard_normal((n, n)) + 3 * np.eye(n)
+    x = oracle.sqrtm(a)
+    xm = mp.sqrtm(mp.matrix(a.tolist()))
+    ref = np.array([[complex(xm[i, j]) for j in range(n)] for i in range(n)]).real
+    assert oracle.relerr(x, ref) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Invariants of the principal root
+
+
+def test_invariants_real_nonsymmetric():
+    a = W.nonsym_shifted(50, 3)
+    x = oracle.sqrtm(a)
+    assert x.dtype == np.float64  # real A -> real X
+    assert oracle.relres(x, a) < 1e-13
+    comm = np.linalg.norm(x @ a - a @ x) / (np.linalg.norm(x) * np.linalg.norm(a))
+    assert comm < 1e-14
+    assert np.all(np.linalg.eigvals(x).real > 0)
+
+
+def test_equivariance_permutation_transpose_scaling():
+    a = W.nonsym_shifted(30, 4)
+    x = oracle.sqrtm(a)
+    p = rng(2).permutation(30)
+    pm = np.eye(30)[p]
+    assert oracle.relerr(oracle.sqrtm(pm @ a @ pm.T), pm @ x @ pm.T) < 1e-13
+    assert oracle.relerr(oracle.sqrtm(a.T), x.T) < 1e-13
+    assert oracle.relerr(oracle.sqrtm(16.0 * a), 4.0 * x) < 1e-13
+
+
+def test_spd_root_is_spd():
+    a, _, _ = W.spd(40, 1e3, 9)
+    x = oracle.sqrtm_spd(a)
+    assert np.array_equal(x, x.T)
+    assert np.linalg.eigvalsh(x).min() > 0
+
+
+# ---------------------------------------------------------------------------
+# Sylvester, Alg. 1 recursion and the adjoint
+
+
+def _tri(r, m, shift=3.0):
+    return np.triu(r.standard_normal((m, m)) + 1j * r.standard_normal((m, m))) + shift * np.eye(m)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 7), (8, 2), (9, 9), (12, 5)])
+def test_trsyl_against_kronecker(m, n):
+    r = rng(m * 13 + n)
+    s, st = _tri(r, m), _tri(r, n)
+    c = r.standard_normal((m, n)) + 1j * r.standard_normal((m, n))
+    ref = oracle.kron_sylvester(s, st, c)
+    assert np.abs(oracle.trsyl(s, st, c) - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("m,n,blks", [(12, 12, 2), (12, 3, 2), (3, 12, 2), (11, 7, 3), (10, 10, 32)])
+def test_rtrsyl_all_branches_against_kronecker(m, n, blks):
+    # (12,3): row-only split (2n <= m); (3,12): column-only split (2m <= n);
+    # (12,12), (11,7): the 2x2 split; (10,10,32): base case.
+    r = rng(m + 100 * n + blks)
+    s, st = _tri(r, m), _tri(r, n)
+    c = r.standard_normal((m, n)) + 1j * r.standard_normal((m, n))
+    ref = oracle.kron_sylvester(s, st, c)
+    assert np.abs(oracle.rtrsyl(s, st, c, blks=blks) - ref).max() < 1e-13
+
+
+def test_four_block_equations_hold():
+    # One level of the partition in Eq. (partition): the four sub-equations are
+    # satisfied by the blocks of the solution.
+    r = rng(21)
+    m, n = 10, 8
+    s, st = _tri(r, m), _tri(r, n)
+    c = r.standard_normal((m, n)) + 1j * r.standard_normal((m, n))
+    y = oracle.trsyl(s, st, c)
+    m1, n1 = m // 2, n // 2
+    S11, S12, S22 = s[:m1, :m1], s[:m1, m1:], s[m1:, m1:]
+    T11, T12, T22 = st[:n1, :n1], st[:n1, n1:], st[n1:, n1:]
+    Y11, Y12, Y21, Y22 = y[:m1, :n1], y[:m1, n1:], y[m1:, :n1], y[m1:, n1:]
+    C11, C12, C21, C22 = c[:m1, :n1], c[:m1, n1:], c[m1:, :n1], c[m1:, n1:]
+    tol = 1e-12
+    assert np.abs(S11 @ Y11 + Y11 @ T11 - (C11 - S12 @ Y21)).max() < tol
+    assert np.abs(S11 @ Y12 + Y12 @ T22 - (C12 - S12 @ Y22 - Y11 @ T12)).max() < tol
+    assert np.abs(S22 @ Y21 + Y21 @ T11 - C21).max() < tol
+    assert np.abs(S22 @ Y22 + Y22 @ T22 - (C22 - Y21 @ T12)).max() < tol
+
+
+@pytest.mark.parametrize("n,cplx", [(1, False), (6, False), (9, True)])
+def test_adjoint_against_kronecker(n, cplx):
+    r = rng(30 + n)
+    if cplx:
+        a, _ = W.complex_square(n, 40 + n)
+        g = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    else:
+        a = W.nonsym_shifted(n, 50 + n)
+        g = r.standard_normal((n, n))
+    x = oracle.sqrtm(a)
+    ga = oracle.adjoint(x, g)
+    ref = oracle.kron_adjoint(x, g)
+    assert np.abs(ga - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_adjoint_against_central_differences():
+    # <Gbar, d sqrtm(A)[E]> = <G, E> with G = adjoint(X, Gbar).
+    n = 7
+    a = W.nonsym_shifted(n, 60)
+    r = rng(61)
+    gbar = r.standard_normal((n, n))
+    e = r.standard_normal((n, n))
+    e /= np.linalg.norm(e)
+    h = 1e-5
+    fd = np.sum(gbar * (oracle.sqrtm(a + h * e) - oracle.sqrtm(a - h * e))) / (2 * h)
+    g = oracle.adjoint(oracle.sqrtm(a), gbar)
+    assert abs(fd - np.sum(g * e)) < 1e-8 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# Convergence theorem (Sec. 3.1) in exact-ish arithmetic
+
+
+def test_convergence_theorem_inequality():
+    # Iteration vec(X_{k+1}) = vec(X_k) + B_Z^{-1} vec(A - X_k^2) with a frozen,
+    # perturbed Z satisfies ||E_{k+1}|| <= 2||B_Z^-1|| ||E_Z|| ||E_k||
+    #                                      + ||B_Z^-1|| ||E_k||^2.
+    n = 6
+    a = W.nonsym_shifted(n, 70)
+    x = oracle.sqrtm(a)
+    r = rng(71)
+    z = x + 1e-3 * r.standard_normal((n, n))
+    bz = np.kron(np.eye(n), z) + np.kron(z.T, np.eye(n))
+    binv = np.linalg.inv(bz)
+    nb = np.linalg.norm(binv, 2)
+    ez = np.linalg.norm(z - x)
+    xk = x + 1e-2 * r.standard_normal((n, n))
+    for _ in range(6):
+        ek = np.linalg.norm(xk - x)
+        upd = binv @ (a - xk @ xk).reshape(-1, order="F")
+        xk = xk + upd.reshape((n, n), order="F")
+        ek1 = np.linalg.norm(xk - x)
+        assert ek1 <= 2 * nb * ez * ek + nb * ek ** 2 + 1e-14
+    assert np.linalg.norm(xk - x) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision emulator against the paper's observations (Sec. 5.1)
+
+
+def _obs():
+    with open(os.path.join(GOLDEN, "paper_observations.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("kappa,seed", [(1e2, 2), (1e4, 3)])
+def test_emulator_spd_steps(kappa, seed):
+    obs = _obs()["steps_not_ill_conditioned"]
+    a, q, lam = W.spd(256, kappa, seed)
+    res = oracle.emulate_mixed(a, tol=1e-13)
+    assert res["status"] == "ok"
+    assert obs["min"] <= res["steps"] <= obs["max"]
+    xt = (q * np.sqrt(lam)[None, :]) @ q.T
+    assert oracle.relerr(res["X"], xt) < 1e-12
+
+
+def test_emulator_general_steps():
+    obs = _obs()["steps_not_ill_conditioned"]
+    a = W.nonsym_shifted(128, 5)
+    res = oracle.emulate_mixed(a, tol=1e-13)
+    assert res["status"] == "ok"
+    assert obs["min"] <= res["steps"] <= obs["max"]
+    assert oracle.relerr(res["X"], oracle.sqrtm(a)) < 1e-12
+
+
+def test_emulator_complex_steps():
+    a, b = W.complex_square(64, 6)
+    res = oracle.emulate_mixed(a, tol=1e-13)
+    assert res["status"] == "ok" and 1 <= res["steps"] <= 3
+    assert oracle.relerr(res["X"], b) < 1e-12
+
+
+@pytest.mark.slow
+def test_emulator_hilbert_slow_convergence_and_divergence():
+    obs = _obs()
+    h = obs["hilbert"]
+    res = oracle.emulate_mixed(W.hilbert(h["n"], h["tau"]), tol=obs["parameters"]["tol"])
+    assert res["status"] == "ok"
+    # Reading: the paper's eigensolver differs from this one, so the count is
+    # pinned to "clearly more than the 1-3 of well-conditioned inputs and at
+    # most a few more than the paper's 11-12".
+    assert 5 <= res["steps"] <= h["steps_approx"][1] + 2
+    bad = oracle.emulate_mixed(W.hilbert(h["n"], obs["hilbert_divergence"]["tau_below"] / 10),
+                               tol=obs["parameters"]["tol"])
+    assert bad["status"] != "ok"
+
+
+def test_emulator_failure_statuses():
+    assert oracle.emulate_mixed(np.array([[np.nan, 0], [0, 1.0]]))["status"] == "nonfinite"
+    res = oracle.emulate_mixed(W.spd(64, 1e4, 1)[0], maxit=0)
+    assert res["status"] == "not_converged" and res["steps"] == 0
