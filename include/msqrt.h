@@ -1,0 +1,182 @@
+/*
+ * msqrt -- mixed-precision principal matrix square root on AMD MI355X (gfx950).
+ *
+ * Problem (Sec. 1 of Gao, Kressner, Shao): for A in C^{n x n} (or R^{n x n})
+ * with no eigenvalue on the closed negative real axis, compute the principal
+ * square root X = A^{1/2}: the unique X with X^2 = A whose eigenvalues lie in
+ * the open right half-plane.
+ *
+ * Method (Sec. 2, Alg. 2 and Alg. 3): a low-precision Schur factorisation
+ * A ~ Q T Q^*, S = T^{1/2}, X_0 = Q S Q^*, then approximate-Newton refinement:
+ * every sweep forms the working-precision residual R = A - X_k^2, stops when
+ * ||R||_F <= tol ||A||_F, otherwise transforms R to the Schur basis
+ * (Q^* R Q, low precision), solves S Y + Y S = Q^* R Q (Eq. (triangsylv); for
+ * symmetric positive definite A the equation is diagonal,
+ * y_ij = r_ij / (s_i + s_j)), and adds X_{k+1} = X_k + Q Y Q^* in working
+ * precision.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are column-major device buffers; element (i, j) of matrix b of a
+ *    batch is at ptr[b * stride + i + j * ld], ld >= n.  Because the square
+ *    root of A^T is the transpose of the square root of A (and the adjoint
+ *    equation transposes the same way), a row-major buffer may be passed
+ *    unchanged: the result is then row-major too.
+ *  - MSQRT_REAL64 buffers hold double; MSQRT_COMPLEX128 buffers hold
+ *    interleaved (re, im) double pairs.
+ *  - The caller owns every buffer it passes.  Input buffers are never
+ *    modified.  Buffers must stay valid until the call returns.
+ *  - All work is ordered on `stream` (a hipStream_t; NULL = the default
+ *    stream).  Calls are blocking: the convergence test reads back one scalar
+ *    per sweep.  A factor handle must not be used from two threads at once.
+ *  - Every call returns a status and never aborts.  On NOT_CONVERGED or
+ *    DIVERGED the output holds the iterate with the smallest residual seen and
+ *    `info` holds the residual history.
+ */
+#ifndef MSQRT_H
+#define MSQRT_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msqrt_factor_s* msqrt_factor_t; /* opaque, library-owned */
+
+typedef enum {
+  MSQRT_OK = 0,
+  MSQRT_ERR_INVALID_ARG = 1,   /* bad size, pointer, stride or option */
+  MSQRT_ERR_NONFINITE = 2,     /* A (or Gbar) holds Inf or NaN */
+  MSQRT_ERR_NO_PRINCIPAL = 3,  /* an eigenvalue lies on or next to R<=0 even in FP64 */
+  MSQRT_ERR_NOT_CONVERGED = 4, /* maxit reached or the residual stagnated */
+  MSQRT_ERR_DIVERGED = 5,      /* residual grew; output = best iterate */
+  MSQRT_ERR_DEVICE = 6,        /* a HIP runtime call failed */
+  MSQRT_ERR_OUT_OF_MEMORY = 7,
+  MSQRT_ERR_UNSUPPORTED = 8    /* combination not implemented (see message) */
+} msqrt_status;
+
+typedef enum { MSQRT_REAL64 = 0, MSQRT_COMPLEX128 = 1 } msqrt_dtype; /* working precision */
+
+/* Precision of the Schur factorisation and of the Schur-basis transforms.
+ * BF16SPLIT: transforms as two-term bfloat16 splits with float32 accumulation
+ * (factorisation in FP32).  AUTO: the learned selector picks per input. */
+typedef enum {
+  MSQRT_PREC_AUTO = 0,
+  MSQRT_PREC_BF16SPLIT = 1,
+  MSQRT_PREC_FP32 = 2,
+  MSQRT_PREC_FP64 = 3
+} msqrt_prec;
+
+/* AUTO tests for exact symmetry (Hermitian symmetry for complex input) and then
+ * uses Alg. 3; a non-positive low-precision eigenvalue escalates the
+ * precision and, if FP64 also sees one, falls back to the general path. */
+typedef enum { MSQRT_STRUCT_AUTO = 0, MSQRT_STRUCT_GENERAL = 1, MSQRT_STRUCT_HPD = 2 } msqrt_struct;
+
+typedef struct {
+  msqrt_prec prec;        /* default MSQRT_PREC_FP32 */
+  msqrt_struct structure; /* default MSQRT_STRUCT_AUTO */
+  int maxit;              /* maximum number of corrections, default 30 */
+  double tol;             /* stop when ||A - X^2||_F <= tol ||A||_F, default 1e-13 */
+  int blks;               /* minimal block size of the triangular solvers, default 32 */
+  int fallback;           /* 1: escalate BF16SPLIT -> FP32 -> FP64 on failure (default) */
+  int64_t batch;          /* number of matrices, default 1 */
+} msqrt_options;
+
+typedef struct {
+  int steps;                 /* corrections applied (max over the batch) */
+  double relres;             /* final ||A - X^2||_F / ||A||_F (max over the batch) */
+  double relres_hist[64];    /* residual after 0, 1, ... corrections (first matrix) */
+  int nhist;                 /* entries of relres_hist in use */
+  msqrt_prec prec_used;      /* precision of the factor that produced X */
+  msqrt_struct struct_used;  /* HPD or GENERAL */
+  int fallbacks;             /* number of precision escalations */
+  int scale_exp;             /* k of the exact scaling A / 4^k */
+  float predicted_steps[3];  /* selector prediction for BF16SPLIT, FP32, FP64 (AUTO only) */
+  float t_ms[12];            /* phase timers, see MSQRT_T_* */
+} msqrt_info;
+
+enum {
+  MSQRT_T_VALIDATE = 0, /* finiteness, symmetry, norm, scaling */
+  MSQRT_T_SELECT = 1,   /* selector features + inference */
+  MSQRT_T_REDUCE = 2,   /* tridiagonal / Hessenberg reduction */
+  MSQRT_T_EIG = 3,      /* tridiagonal eigensolver / Schur QR */
+  MSQRT_T_BACK = 4,     /* back-transformation of the Schur vectors */
+  MSQRT_T_X0 = 5,       /* triangular root and X_0 */
+  MSQRT_T_RESIDUAL = 6, /* all residual evaluations */
+  MSQRT_T_TRANSFORM = 7,/* Q^* R Q, including the SPD diagonal solve */
+  MSQRT_T_SOLVE = 8,    /* triangular Sylvester solves (general path) */
+  MSQRT_T_UPDATE = 9,   /* Q Y Q^* and the working-precision update */
+  MSQRT_T_TOTAL = 10
+};
+
+/* Fills *opt with the defaults listed in msqrt_options. */
+void msqrt_default_options(msqrt_options* opt);
+
+/* Low-precision Schur factorisation of A (Alg. 2 lines 1-2, Alg. 3 lines 1-2):
+ * HPD input -> spectral decomposition A/4^k ~ Q diag(s^2) Q^*;
+ * general input -> complex Schur form A/4^k ~ Q T Q^*, S = T^{1/2}.
+ * The precision is opt->prec (AUTO picks one).  On success *out owns Q, S, the
+ * scale exponent k and workspaces; release it with msqrt_factor_destroy.
+ * Errors: INVALID_ARG (n < 0, ld < n, NULL pointer with n > 0), NONFINITE,
+ * NO_PRINCIPAL (eigenvalue on R<=0 in this precision), OUT_OF_MEMORY, DEVICE. */
+msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
+                          int64_t lda, int64_t strideA, hipStream_t stream, msqrt_factor_t* out);
+
+/* Approximate-Newton refinement with a frozen factor (Alg. 2/3 loop, Sec. 2.1):
+ * X <- X + Q Y Q^*, S Y + Y S = Q^* (A - X^2) Q, until the relative residual is
+ * <= tol or maxit corrections were applied.  With init_from_factor != 0, X is
+ * first overwritten by X_0 = Q S Q^*; otherwise the caller's X is the start
+ * (it may be the root of a nearby matrix).  Never escalates the precision.
+ * dA/dX layout as above; A must be the matrix the factor was built from or a
+ * nearby one of the same size and structure. */
+msqrt_status msqrt_refine(msqrt_factor_t f, const void* dA, int64_t lda, int64_t strideA,
+                          void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
+                          double tol, hipStream_t stream, msqrt_info* info);
+
+/* Complete solve: factor, X_0, refinement, with precision escalation when
+ * opt->fallback is set.  If keep != NULL the factor is returned for reuse
+ * (e.g. by msqrt_sqrtm_backward); otherwise it is freed. */
+msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
+                         int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                         hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep);
+
+/* Reverse-mode derivative of X = sqrtm(A): given Gbar = dL/dX, returns
+ * G = dL/dA, the solution of X^* G + G X^* = Gbar (adjoint of the Frechet
+ * derivative; for HPD input X G + G X = Gbar).  Solved in the factor's Schur
+ * basis in low precision and refined with working-precision residuals, the
+ * same framework as the forward solve.  dX must be the root returned for the
+ * factor's matrix; all three buffers use `stride` between batch entries. */
+msqrt_status msqrt_sqrtm_backward(msqrt_factor_t f, const void* dX, int64_t ldx,
+                                  const void* dGbar, int64_t ldgb, void* dG, int64_t ldg,
+                                  int64_t stride, int maxit, double tol, hipStream_t stream,
+                                  msqrt_info* info);
+
+/* Releases a factor and its device memory.  NULL is ignored. */
+void msqrt_factor_destroy(msqrt_factor_t f);
+
+/* Human-readable name of a status code (static storage). */
+const char* msqrt_status_string(msqrt_status s);
+
+/* Last error message recorded by the calling thread (static storage). */
+const char* msqrt_last_error(void);
+
+/* Test hook: builds a factor from caller-provided Q (n x n) and S (length n for
+ * HPD, n x n upper triangular for GENERAL), column-major, in the precision
+ * `prec` (FP32 buffers hold float / complex64, FP64 buffers double /
+ * complex128).  on_device selects device or host pointers.  batch = 1. */
+msqrt_status msqrt_factor_wrap(msqrt_prec prec, msqrt_struct structure, msqrt_dtype dtype,
+                               int64_t n, const void* Q, const void* S, int on_device,
+                               msqrt_factor_t* out);
+
+/* Test hook: reads the factor's Q and S back to host buffers in the factor's
+ * own precision (layout as in msqrt_factor_wrap); the scale exponent goes to
+ * *scale_exp.  Either pointer may be NULL. */
+msqrt_status msqrt_factor_export(msqrt_factor_t f, void* Q, void* S, int* scale_exp);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSQRT_H */

@@ -1,0 +1,195 @@
+"""Mixed-precision principal matrix square root on MI355X (gfx950).
+
+Thin Python layer over the C-ABI in include/msqrt.h: torch supplies device
+memory and the current stream; every step of the computation runs in the HIP
+kernels of libmsqrt.so.
+
+    X, info = sqrtm(A)                 # A: cuda float64 (n, n) or (b, n, n)
+    X = sqrtm_autograd(A)              # differentiable (torch.autograd.Function)
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MsqrtError, check, lib
+
+__all__ = ["sqrtm", "sqrtm_autograd", "Factor", "factor", "refine", "factor_wrap", "MsqrtError",
+           "default_options"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_matrix(a: torch.Tensor, name: str):
+    if not a.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if a.dtype not in (torch.float64, torch.complex128):
+        raise ValueError(f"{name} must be float64 or complex128, got {a.dtype}")
+    if a.dim() not in (2, 3) or a.shape[-1] != a.shape[-2]:
+        raise ValueError(f"{name} must be (n, n) or (b, n, n)")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _dims(a: torch.Tensor):
+    n = a.shape[-1]
+    batch = a.shape[0] if a.dim() == 3 else 1
+    return n, batch, n * n
+
+
+def default_options(prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32, fallback=True,
+                    batch=1):
+    o = _lib.Options()
+    lib().msqrt_default_options(ctypes.byref(o))
+    o.prec = _lib.PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o.structure = _lib.STRUCT_NAMES[structure] if isinstance(structure, str) else int(structure)
+    o.maxit = int(maxit)
+    o.tol = float(tol)
+    o.blks = int(blks)
+    o.fallback = 1 if fallback else 0
+    o.batch = int(batch)
+    return o
+
+
+class Factor:
+    """Owns a msqrt_factor_t handle."""
+
+    def __init__(self, handle: int, n: int, batch: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.n = n
+        self.batch = batch
+
+    def close(self):
+        if self.handle and self.handle.value:
+            lib().msqrt_factor_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self, single: bool, structure: str = "hpd"):
+        """Host copies (Q, S, k) of the factor (test hook)."""
+        import numpy as np
+        n, b = self.n, self.batch
+        dt = np.float32 if single else np.float64
+        q = np.zeros((b, n, n), dtype=dt)
+        s = np.zeros((b, n) if structure == "hpd" else (b, n, n), dtype=dt)
+        k = ctypes.c_int(0)
+        check(lib().msqrt_factor_export(self.handle, q.ctypes.data_as(ctypes.c_void_p),
+                                        s.ctypes.data_as(ctypes.c_void_p), ctypes.byref(k)),
+              "msqrt_factor_export")
+        # buffers are column-major per batch entry
+        return np.ascontiguousarray(np.swapaxes(q, 1, 2)), s, k.value
+
+
+def factor(a: torch.Tensor, prec="fp32", structure="auto", blks=32) -> Factor:
+    _check_matrix(a, "A")
+    n, batch, nn = _dims(a)
+    o = default_options(prec=prec, structure=structure, blks=blks, batch=batch)
+    h = ctypes.c_void_p(0)
+    dt = _lib.COMPLEX128 if a.is_complex() else _lib.REAL64
+    check(lib().msqrt_factor(ctypes.byref(o), dt, n, ctypes.c_void_p(a.data_ptr()), n, nn,
+                             _stream(), ctypes.byref(h)), "msqrt_factor")
+    return Factor(h.value, n, batch)
+
+
+def factor_wrap(q, s, prec="fp32", structure="hpd") -> Factor:
+    """Builds a factor from host NumPy arrays Q (n x n) and S (test hook)."""
+    import numpy as np
+    single = prec == "fp32"
+    dt = np.float32 if single else np.float64
+    n = q.shape[0]
+    qf = np.asfortranarray(q, dtype=dt)
+    sf = np.asfortranarray(s, dtype=dt)
+    h = ctypes.c_void_p(0)
+    check(lib().msqrt_factor_wrap(_lib.PREC_NAMES[prec], _lib.STRUCT_NAMES[structure], _lib.REAL64, n,
+                                  qf.ctypes.data_as(ctypes.c_void_p), sf.ctypes.data_as(ctypes.c_void_p),
+                                  0, ctypes.byref(h)), "msqrt_factor_wrap")
+    return Factor(h.value, n, 1)
+
+
+def refine(f: Factor, a: torch.Tensor, x: torch.Tensor, init_from_factor=True, maxit=30, tol=1e-13,
+           allow_fail=False):
+    """Runs the refinement loop in place on x.  Returns the info dict."""
+    _check_matrix(a, "A")
+    _check_matrix(x, "X")
+    n, batch, nn = _dims(a)
+    info = _lib.Info()
+    st = lib().msqrt_refine(f.handle, ctypes.c_void_p(a.data_ptr()), n, nn,
+                            ctypes.c_void_p(x.data_ptr()), n, nn, 1 if init_from_factor else 0,
+                            int(maxit), float(tol), _stream(), ctypes.byref(info))
+    d = info.to_dict()
+    d["status"] = _lib.STATUS_NAMES.get(st, st)
+    if not allow_fail:
+        check(st, "msqrt_refine")
+    return d
+
+
+def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32,
+          fallback=True, keep_factor=False, allow_fail=False, out=None):
+    """Principal square root of a (batch of) matrices.  Returns (X, info) or
+    (X, info, factor) when keep_factor is set."""
+    _check_matrix(a, "A")
+    n, batch, nn = _dims(a)
+    x = torch.empty_like(a) if out is None else out
+    o = default_options(prec=prec, structure=structure, maxit=maxit, tol=tol, blks=blks,
+                        fallback=fallback, batch=batch)
+    info = _lib.Info()
+    h = ctypes.c_void_p(0)
+    dt = _lib.COMPLEX128 if a.is_complex() else _lib.REAL64
+    st = lib().msqrt_sqrtm(ctypes.byref(o), dt, n, ctypes.c_void_p(a.data_ptr()), n, nn,
+                           ctypes.c_void_p(x.data_ptr()), n, nn, _stream(), ctypes.byref(info),
+                           ctypes.byref(h) if keep_factor else None)
+    d = info.to_dict()
+    d["status"] = _lib.STATUS_NAMES.get(st, st)
+    if not allow_fail:
+        check(st, "msqrt_sqrtm")
+    if keep_factor:
+        return x, d, (Factor(h.value, n, batch) if h.value else None)
+    return x, d
+
+
+def sqrtm_backward(f: Factor, x: torch.Tensor, gbar: torch.Tensor, maxit=30, tol=1e-13):
+    _check_matrix(x, "X")
+    gbar = gbar.contiguous()
+    _check_matrix(gbar, "Gbar")
+    n, batch, nn = _dims(x)
+    g = torch.empty_like(gbar)
+    info = _lib.Info()
+    st = lib().msqrt_sqrtm_backward(f.handle, ctypes.c_void_p(x.data_ptr()), n,
+                                    ctypes.c_void_p(gbar.data_ptr()), n,
+                                    ctypes.c_void_p(g.data_ptr()), n, nn, int(maxit), float(tol),
+                                    _stream(), ctypes.byref(info))
+    check(st, "msqrt_sqrtm_backward")
+    return g, info.to_dict()
+
+
+class _SqrtmFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a, prec, tol, maxit):
+        x, info, f = sqrtm(a.contiguous(), prec=prec, tol=tol, maxit=maxit, keep_factor=True)
+        ctx.factor = f
+        ctx.tol = tol
+        ctx.maxit = maxit
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        g, _ = sqrtm_backward(ctx.factor, x, gx.contiguous(), maxit=ctx.maxit, tol=ctx.tol)
+        return g, None, None, None
+
+
+def sqrtm_autograd(a: torch.Tensor, prec="fp32", tol=1e-13, maxit=30) -> torch.Tensor:
+    """Differentiable principal square root (gradient: X G + G X = dL/dX for
+    symmetric positive definite A; X^H G + G X^H = dL/dX in general)."""
+    return _SqrtmFn.apply(a, prec, tol, maxit)

@@ -1,0 +1,142 @@
+// Elementwise and reduction kernels: validation, norms, casts, scaling.
+// All are HBM-bound; each thread handles a contiguous run within a column so
+// that a wave reads consecutive addresses.
+#include "kernels.hpp"
+
+namespace msqrt {
+
+namespace {
+
+constexpr int kEwThreads = 256;
+
+// One block per (column tile of 64 columns, batch).  Each thread walks rows
+// of its column slice; finiteness, exact symmetry (a_ij == a_ji) and the sum
+// of squares are accumulated.
+__global__ __launch_bounds__(kEwThreads) void validate_kernel(int n, const double* __restrict__ A,
+                                                              int64_t lda, int64_t sA,
+                                                              int check_sym, int* flags,
+                                                              double* partials) {
+  __shared__ double red[kEwThreads / kWave];
+  const int b = blockIdx.y;
+  const double* a = A + (int64_t)b * sA;
+  const int j0 = blockIdx.x * 64;
+  double ss = 0.0;
+  int bad = 0, asym = 0;
+  for (int j = j0; j < min(j0 + 64, n); ++j) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double v = a[i + (int64_t)j * lda];
+      if (!isfinite(v)) bad = 1;
+      ss += v * v;
+      if (check_sym && i > j && v != a[j + (int64_t)i * lda]) asym = 1;
+    }
+  }
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) partials[(int64_t)b * gridDim.x + blockIdx.x] = ss;
+  if (bad) atomicOr(&flags[b], 1);
+  if (asym) atomicOr(&flags[b], 2);
+}
+
+__global__ __launch_bounds__(kEwThreads) void reduce_sqrt_kernel(const double* __restrict__ p,
+                                                                 int count, double* out) {
+  __shared__ double red[kEwThreads / kWave];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s += p[(int64_t)b * count + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[b] = sqrt(s);
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kEwThreads) void cast_scale_kernel(int n, const double* __restrict__ A,
+                                                                int64_t lda, int64_t sA,
+                                                                const double* scale,
+                                                                TO* __restrict__ B, int64_t ldb,
+                                                                int64_t sB) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double sc = scale ? scale[b] : 1.0;
+  if (i < n) B[(int64_t)b * sB + i + (int64_t)j * ldb] = (TO)(sc * A[(int64_t)b * sA + i + (int64_t)j * lda]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void scale_cols_kernel(int n, const T* __restrict__ Q,
+                                                                int64_t ldq, int64_t sQ,
+                                                                const T* __restrict__ s, int64_t sS,
+                                                                T* __restrict__ W, int64_t ldw,
+                                                                int64_t sW) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) W[(int64_t)b * sW + i + (int64_t)j * ldw] = Q[(int64_t)b * sQ + i + (int64_t)j * ldq] * s[(int64_t)b * sS + j];
+}
+
+__global__ __launch_bounds__(kEwThreads) void scale_inplace_kernel(int n, double* X, int64_t ldx,
+                                                                   int64_t sX,
+                                                                   const double* scale) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(int64_t)b * sX + i + (int64_t)j * ldx] *= scale[b];
+}
+
+}  // namespace
+
+int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, int batch,
+                    int check_sym, int* flags, double* partials) {
+  const int nblk = (int)ceil_div(n, 64);
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(validate_kernel, dim3(nblk, batch), dim3(kEwThreads), 0, st, n, A, lda, sA,
+                     check_sym, flags, partials);
+  MSQRT_LAUNCH_CHECK();
+  return nblk;
+}
+
+void launch_reduce_sqrt(hipStream_t st, const double* partials, int count, int batch, double* out) {
+  hipLaunchKernelGGL(reduce_sqrt_kernel, dim3(batch), dim3(kEwThreads), 0, st, partials, count, out);
+  MSQRT_LAUNCH_CHECK();
+}
+
+void launch_cast_scale_f64_f32(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA,
+                               const double* scale, float* B, int64_t ldb, int64_t sB, int batch) {
+  if (n <= 0) return;
+  dim3 grid((unsigned)ceil_div(n, kEwThreads), n, batch);
+  hipLaunchKernelGGL(cast_scale_kernel<float>, grid, dim3(kEwThreads), 0, st, n, A, lda, sA, scale, B, ldb, sB);
+  MSQRT_LAUNCH_CHECK();
+}
+
+void launch_cast_scale_f64_f64(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA,
+                               const double* scale, double* B, int64_t ldb, int64_t sB, int batch) {
+  if (n <= 0) return;
+  dim3 grid((unsigned)ceil_div(n, kEwThreads), n, batch);
+  hipLaunchKernelGGL(cast_scale_kernel<double>, grid, dim3(kEwThreads), 0, st, n, A, lda, sA, scale, B, ldb, sB);
+  MSQRT_LAUNCH_CHECK();
+}
+
+void launch_copy_f64(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, double* B,
+                     int64_t ldb, int64_t sB, int batch) {
+  launch_cast_scale_f64_f64(st, n, A, lda, sA, nullptr, B, ldb, sB, batch);
+}
+
+template <typename T>
+void launch_scale_cols(hipStream_t st, int n, const T* Q, int64_t ldq, int64_t sQ, const T* s,
+                       int64_t sS, T* W, int64_t ldw, int64_t sW, int batch) {
+  if (n <= 0) return;
+  dim3 grid((unsigned)ceil_div(n, kEwThreads), n, batch);
+  hipLaunchKernelGGL(scale_cols_kernel<T>, grid, dim3(kEwThreads), 0, st, n, Q, ldq, sQ, s, sS, W, ldw, sW);
+  MSQRT_LAUNCH_CHECK();
+}
+template void launch_scale_cols<float>(hipStream_t, int, const float*, int64_t, int64_t,
+                                       const float*, int64_t, float*, int64_t, int64_t, int);
+template void launch_scale_cols<double>(hipStream_t, int, const double*, int64_t, int64_t,
+                                        const double*, int64_t, double*, int64_t, int64_t, int);
+
+void launch_scale_inplace(hipStream_t st, int n, double* X, int64_t ldx, int64_t sX,
+                          const double* scale, int batch) {
+  if (n <= 0) return;
+  dim3 grid((unsigned)ceil_div(n, kEwThreads), n, batch);
+  hipLaunchKernelGGL(scale_inplace_kernel, grid, dim3(kEwThreads), 0, st, n, X, ldx, sX, scale);
+  MSQRT_LAUNCH_CHECK();
+}
+
+}  // namespace msqrt

@@ -1,0 +1,153 @@
+// Factor object and the host-side pieces shared between the runtime files.
+#pragma once
+
+#include <vector>
+
+#include "../../include/msqrt.h"
+#include "common.hpp"
+
+namespace msqrt {
+
+// Owning device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (p && b <= bytes) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error{MSQRT_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+    bytes = b;
+  }
+  template <typename T>
+  T* ensure(int64_t count) {
+    alloc((size_t)count * sizeof(T));
+    return (T*)p;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+struct Factor {
+  int64_t n = 0, batch = 1;
+  msqrt_dtype dtype = MSQRT_REAL64;
+  msqrt_struct structure = MSQRT_STRUCT_HPD;
+  msqrt_prec prec = MSQRT_PREC_FP32;
+  int blks = 32;
+  std::vector<int> kexp;             // A_b is scaled by 4^-kexp[b]
+  std::vector<double> anorm;         // ||A_b||_F (unscaled)
+  std::vector<double> anorm_scaled;  // ||A_b / 4^k||_F
+  // The factor: Q (n x n per batch entry) and S (diagonal: n per entry;
+  // general: n x n upper triangular), in the factor precision.
+  DevBuf Q, S;
+  DevBuf scales;  // [3 * batch] doubles: 4^-k, 2^-k, 2^k
+  // refinement workspaces
+  DevBuf ws1, ws2, part, rnorm, active, best;
+  // factorisation workspaces
+  DevBuf fw1, fw2, fw3, fw4, fw5;
+
+  void upload_scales(hipStream_t st) {
+    const int64_t b = batch;
+    std::vector<double> h(3 * b);
+    anorm_scaled.assign(b, 0.0);
+    for (int64_t i = 0; i < b; ++i) {
+      const int k = kexp.empty() ? 0 : kexp[i];
+      h[i] = std::ldexp(1.0, -2 * k);
+      h[b + i] = std::ldexp(1.0, -k);
+      h[2 * b + i] = std::ldexp(1.0, k);
+      if ((int64_t)anorm.size() > i) anorm_scaled[i] = anorm[i] * h[i];
+    }
+    double* d = scales.ensure<double>(3 * b);
+    MSQRT_HIP(hipMemcpyAsync(d, h.data(), sizeof(double) * 3 * b, hipMemcpyHostToDevice, st));
+    MSQRT_HIP(hipStreamSynchronize(st));
+  }
+  const double* ascale_dev() const { return scales.as<double>(); }
+  const double* rscale_dev() const { return scales.as<double>() + batch; }
+  const double* uscale_dev() const { return scales.as<double>() + 2 * batch; }
+};
+
+// Phase timers (hipEvents on the call's stream, read at the next sync point).
+
+struct PhaseTimer {
+  hipStream_t st;
+  msqrt_info* info;
+  struct Pending { int phase; hipEvent_t a, b; };
+  std::vector<Pending> pend;
+  std::vector<hipEvent_t> pool;
+  int cur = -1;
+  hipEvent_t cur_ev = nullptr;
+  PhaseTimer(hipStream_t s, msqrt_info* i) : st(s), info(i) {}
+  ~PhaseTimer() {
+    for (auto& p : pend) { pool.push_back(p.a); pool.push_back(p.b); }
+    for (auto e : pool) hipEventDestroy(e);
+    if (cur_ev) hipEventDestroy(cur_ev);
+  }
+  hipEvent_t ev() {
+    hipEvent_t e;
+    if (!pool.empty()) { e = pool.back(); pool.pop_back(); return e; }
+    MSQRT_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void begin(int phase) {
+    if (!info) return;
+    end();
+    cur = phase;
+    cur_ev = ev();
+    MSQRT_HIP(hipEventRecord(cur_ev, st));
+  }
+  void end() {
+    if (!info || cur < 0) return;
+    hipEvent_t e = ev();
+    MSQRT_HIP(hipEventRecord(e, st));
+    pend.push_back({cur, cur_ev, e});
+    cur = -1;
+    cur_ev = nullptr;
+  }
+  // Call after a stream synchronisation.
+  void collect() {
+    if (!info) return;
+    for (auto& p : pend) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess && p.phase >= 0 && p.phase < 12)
+        info->t_ms[p.phase] += ms;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pend.clear();
+  }
+};
+
+// Validates A (finiteness, optional exact symmetry), computes ||A_b||_F and
+// the scale exponents into f.  Returns the OR of the per-entry flags
+// (bit0 non-finite, bit1 not symmetric).
+int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
+                  hipStream_t st);
+
+// Factorisation of the scaled input into f (Q, S, structure, prec).
+msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,
+                          int64_t sA, hipStream_t st, PhaseTimer* tm);
+// Precision choice for MSQRT_PREC_AUTO.
+msqrt_prec select_precision(const msqrt_options& o, msqrt_dtype dtype, int64_t n, const void* A,
+                            int64_t lda, int64_t sA, hipStream_t st, msqrt_info* info,
+                            PhaseTimer& tm);
+// Adjoint solve for msqrt_sqrtm_backward.
+msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gbar, int64_t ldgb,
+                      double* G, int64_t ldg, int64_t stride, int maxit, double tol,
+                      hipStream_t st, msqrt_info* info, PhaseTimer& tm);
+
+}  // namespace msqrt

@@ -1,0 +1,334 @@
+// MFMA GEMM for gfx950 with fused epilogues.
+//
+// C-tile 128 x 128 per workgroup of 256 threads (four wave64s in a 2 x 2
+// arrangement, 64 x 64 per wave), K-slab of 16 staged through LDS with the
+// next slab's global loads issued before the current slab's MFMAs.
+//   float : v_mfma_f32_32x32x2f32 (2 x 2 blocks of 32 x 32 per wave)
+//   double: v_mfma_f64_16x16x4f64 (4 x 4 blocks of 16 x 16 per wave)
+// Column-major operands; op(A) is M x K, op(B) is K x N; batches via strides.
+//
+// The epilogue functor receives every output element (i, j) exactly once and
+// returns a double that is summed over the workgroup (the residual epilogue
+// uses this for ||R||_F^2; the others return 0).  In "tri" mode only tiles
+// on or below the diagonal are launched (symmetric results) and the functor
+// is told to mirror the element to (j, i).
+#pragma once
+
+#include "common.hpp"
+
+namespace msqrt {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  static constexpr int TM = 32, TN = 32, TK = 2, NACC = 16, MB = 2, NB = 2;
+  typedef float acc_t __attribute__((ext_vector_type(16)));
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  // operand fragment coordinates of lane l
+  __device__ static inline int frag_mn(int l) { return l % 32; }
+  __device__ static inline int frag_k(int l) { return l / 32; }
+  // accumulator element r of lane l
+  __device__ static inline int c_row(int l, int r) { return 8 * (r / 4) + 4 * (l / 32) + (r % 4); }
+  __device__ static inline int c_col(int l, int) { return l % 32; }
+};
+
+template <>
+struct Mfma<double> {
+  static constexpr int TM = 16, TN = 16, TK = 4, NACC = 4, MB = 4, NB = 4;
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int frag_mn(int l) { return l % 16; }
+  __device__ static inline int frag_k(int l) { return l / 16; }
+  __device__ static inline int c_row(int l, int r) { return (l / 16) + 4 * r; }
+  __device__ static inline int c_col(int l, int) { return l % 16; }
+};
+
+struct GemmShape {
+  int M, N, K;
+  int64_t lda, ldb, sA, sB;
+  int tri;        // launch only tiles with tile_m >= tile_n
+  int tiles_m, tiles_n, ntiles, per_xcd;
+};
+
+constexpr int GBM = 128, GBN = 128, GBK = 16, GTHREADS = 256;
+
+// Maps the hardware workgroup id to a tile id so that each of the 8 XCDs
+// (workgroups are dispatched round-robin over XCDs) works on a contiguous
+// range of tiles, then the tile id to (tile_m, tile_n).
+__device__ inline bool gemm_tile_coords(const GemmShape& s, int& tm, int& tn) {
+  const int b = blockIdx.x;
+  const int id = (b % 8) * s.per_xcd + b / 8;
+  if (id >= s.ntiles) return false;
+  if (s.tri) {
+    // id -> (tm, tn), tm >= tn, row-major over the lower triangle of tiles.
+    int r = (int)((sqrt(8.0 * id + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= id) ++r;
+    while (r * (r + 1) / 2 > id) --r;
+    tm = r;
+    tn = id - r * (r + 1) / 2;
+    return true;
+  }
+  // Grouped ordering: 8 tile-rows per group, walking columns within a group.
+  const int GM = 8;
+  const int per_group = GM * s.tiles_n;
+  const int g = id / per_group;
+  const int first = g * GM;
+  const int gsz = min(s.tiles_m - first, GM);
+  const int w = id % per_group;
+  tm = first + w % gsz;
+  tn = w / gsz;
+  return true;
+}
+
+template <typename T, bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T* __restrict__ A,
+                                                           const T* __restrict__ B, Epi epi,
+                                                           double* __restrict__ partials) {
+  using M = Mfma<T>;
+  constexpr int PAD = 1;
+  __shared__ T As[GBK][GBM + PAD];
+  __shared__ T Bs[GBK][GBN + PAD];
+  __shared__ double red[GTHREADS / kWave];
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+
+  constexpr int EPT = GBM * GBK / GTHREADS;  // 8 elements per thread per operand
+  T ra[EPT], rb[EPT];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = t + GTHREADS * e;
+      int mm, kk;
+      if (!TA) { mm = idx % GBM; kk = idx / GBM; } else { kk = idx % GBK; mm = idx / GBK; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      T v = T(0);
+      if (gm < s.M && gk < s.K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = t + GTHREADS * e;
+      int nn, kk;
+      if (TB) { nn = idx % GBN; kk = idx / GBN; } else { kk = idx % GBK; nn = idx / GBK; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      T v = T(0);
+      if (gn < s.N && gk < s.K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
+      rb[e] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = t + GTHREADS * e;
+      int mm, kk;
+      if (!TA) { mm = idx % GBM; kk = idx / GBM; } else { kk = idx % GBK; mm = idx / GBK; }
+      As[kk][mm] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = t + GTHREADS * e;
+      int nn, kk;
+      if (TB) { nn = idx % GBN; kk = idx / GBN; } else { kk = idx % GBK; nn = idx / GBK; }
+      Bs[kk][nn] = rb[e];
+    }
+  };
+
+  typename M::acc_t acc[M::MB][M::NB];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = T(0);
+
+  if (s.K > 0) load(0);
+  for (int k0 = 0; k0 < s.K; k0 += GBK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + GBK < s.K) load(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += M::TK) {
+      T a[M::MB], b[M::NB];
+      const int fk = kk + M::frag_k(lane), fmn = M::frag_mn(lane);
+#pragma unroll
+      for (int i = 0; i < M::MB; ++i) a[i] = As[fk][wm * 64 + i * M::TM + fmn];
+#pragma unroll
+      for (int j = 0; j < M::NB; ++j) b[j] = Bs[fk][wn * 64 + j * M::TN + fmn];
+#pragma unroll
+      for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+        for (int j = 0; j < M::NB; ++j) acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+    }
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 64 + i * M::TM + M::c_row(lane, r);
+        const int gj = n0 + wn * 64 + j * M::TN + M::c_col(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues
+
+template <typename T>
+struct EpiStore {
+  static constexpr bool kReduces = false;
+  T* C;
+  int64_t ldc, sC;
+  T alpha, beta;
+  __device__ double operator()(int b, int i, int j, T v, bool mir) const {
+    T* c = C + (int64_t)b * sC;
+    T r = alpha * v;
+    if (beta != T(0)) r += beta * c[i + (int64_t)j * ldc];
+    c[i + (int64_t)j * ldc] = r;
+    if (mir) c[j + (int64_t)i * ldc] = r;
+    return 0.0;
+  }
+};
+
+// R = ascale * A - acc in float64; writes R_l = fl32(R) and returns R^2
+// (twice for mirrored off-diagonal elements).
+struct EpiResidual {
+  static constexpr bool kReduces = true;
+  const double* A;
+  int64_t lda, sA;
+  const double* ascale;  // per batch entry: 4^-k
+  float* R;
+  int64_t ldr, sR;
+  __device__ double operator()(int b, int i, int j, double v, bool mir) const {
+    const double r = ascale[b] * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
+    const float rl = (float)r;
+    float* rb = R + (int64_t)b * sR;
+    rb[i + (int64_t)j * ldr] = rl;
+    if (mir) rb[j + (int64_t)i * ldr] = rl;
+    return mir ? 2.0 * r * r : r * r;
+  }
+};
+
+// Same residual in float64 but keeping R in float64 (fixed-FP64 path).
+struct EpiResidual64 {
+  static constexpr bool kReduces = true;
+  const double* A;
+  int64_t lda, sA;
+  const double* ascale;
+  double* R;
+  int64_t ldr, sR;
+  __device__ double operator()(int b, int i, int j, double v, bool mir) const {
+    const double r = ascale[b] * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
+    double* rb = R + (int64_t)b * sR;
+    rb[i + (int64_t)j * ldr] = r;
+    if (mir) rb[j + (int64_t)i * ldr] = r;
+    return mir ? 2.0 * r * r : r * r;
+  }
+};
+
+// SPD correction solve fused into the Q^T (R Q) product (Alg. 3):
+// y_ij = acc_ij / (s_i + s_j), in the factor precision T.
+template <typename T>
+struct EpiDiagSylv {
+  static constexpr bool kReduces = false;
+  const T* s;
+  int64_t sS;
+  T* Y;
+  int64_t ldy, sY;
+  __device__ double operator()(int b, int i, int j, T v, bool mir) const {
+    const T* sb = s + (int64_t)b * sS;
+    const T y = v / (sb[i] + sb[j]);
+    T* yb = Y + (int64_t)b * sY;
+    yb[i + (int64_t)j * ldy] = y;
+    if (mir) yb[j + (int64_t)i * ldy] = y;
+    return 0.0;
+  }
+};
+
+// Working-precision update X += fl64(acc) fused into the last product of
+// Q Y Q^T (Alg. 2/3, last line of the loop).
+template <typename T>
+struct EpiUpdate {
+  static constexpr bool kReduces = false;
+  double* X;
+  int64_t ldx, sX;
+  const int* active;  // per batch entry; NULL = all active
+  __device__ double operator()(int b, int i, int j, T v, bool mir) const {
+    if (active && !active[b]) return 0.0;
+    double* xb = X + (int64_t)b * sX;
+    const double d = (double)v;
+    xb[i + (int64_t)j * ldx] += d;
+    if (mir) xb[j + (int64_t)i * ldx] += d;
+    return 0.0;
+  }
+};
+
+// X = fl64(acc) (initial iterate X_0 = Q S Q^T).
+template <typename T>
+struct EpiSetF64 {
+  static constexpr bool kReduces = false;
+  double* X;
+  int64_t ldx, sX;
+  __device__ double operator()(int b, int i, int j, T v, bool mir) const {
+    double* xb = X + (int64_t)b * sX;
+    const double d = (double)v;
+    xb[i + (int64_t)j * ldx] = d;
+    if (mir) xb[j + (int64_t)i * ldx] = d;
+    return 0.0;
+  }
+};
+
+// Host-side shape setup shared by the launchers.
+inline GemmShape make_shape(int M, int N, int K, int64_t lda, int64_t ldb, int64_t sA, int64_t sB,
+                            bool tri) {
+  GemmShape s;
+  s.M = M; s.N = N; s.K = K; s.lda = lda; s.ldb = ldb; s.sA = sA; s.sB = sB;
+  s.tri = tri ? 1 : 0;
+  s.tiles_m = (int)ceil_div(M, GBM);
+  s.tiles_n = (int)ceil_div(N, GBN);
+  s.ntiles = tri ? s.tiles_m * (s.tiles_m + 1) / 2 : s.tiles_m * s.tiles_n;
+  s.per_xcd = (int)ceil_div(s.ntiles, 8);
+  return s;
+}
+
+template <typename T, class Epi>
+void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A, const T* B,
+                 const Epi& epi, double* partials, int batch) {
+  if (s.M <= 0 || s.N <= 0 || batch <= 0) return;
+  dim3 grid(8 * s.per_xcd, batch), block(GTHREADS);
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  else hipLaunchKernelGGL((gemm_kernel<T, true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  MSQRT_LAUNCH_CHECK();
+}
+
+}  // namespace msqrt

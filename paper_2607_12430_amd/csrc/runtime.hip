@@ -1,0 +1,455 @@
+// Host runtime and C-ABI of the msqrt library: factor objects, validation and
+// scaling, the refinement loop of Alg. 2/3 and precision escalation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/msqrt.h"
+#include "factor.hpp"
+#include "kernels.hpp"
+
+namespace msqrt {
+
+thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Convergence bookkeeping (stopping rule of Alg. 2 plus the divergence /
+// stagnation reading of the paper's remark that the iteration diverges for
+// too ill-conditioned inputs).
+
+enum class Verdict { Continue, Converged, Diverged, Stagnated };
+
+static Verdict judge(const std::vector<double>& h, double tol) {
+  const double r = h.back();
+  if (!std::isfinite(r)) return Verdict::Diverged;
+  if (r <= tol) return Verdict::Converged;
+  if (r > 10.0 * h.front()) return Verdict::Diverged;
+  const size_t k = h.size();
+  if (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) return Verdict::Diverged;
+  if (k >= 3 && h[k - 1] > 0.9 * h[k - 2] && h[k - 2] > 0.9 * h[k - 3]) return Verdict::Stagnated;
+  return Verdict::Continue;
+}
+
+// ---------------------------------------------------------------------------
+// Refinement for HPD (real SPD) factors: Alg. 3 loop.  T is the factor
+// precision (float for FP32, double for FP64).
+
+template <typename T>
+static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, double* X,
+                               int64_t ldx, int64_t sX, int init, int maxit, double tol,
+                               hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  const int n = (int)f->n, batch = (int)f->batch;
+  const int64_t nn = (int64_t)n * n;
+  const T* Q = f->Q.as<T>();
+  const T* s = f->S.as<T>();
+  T* W1 = f->ws1.ensure<T>(nn * batch);
+  T* W2 = f->ws2.ensure<T>(nn * batch);
+  const int ntile_est = (int)(ceil_div(n, 128) * (ceil_div(n, 128) + 1) / 2);
+  double* part = f->part.ensure<double>((int64_t)ntile_est * batch + 64);
+  double* rn = f->rnorm.ensure<double>(batch);
+  int* active = f->active.ensure<int>(batch);
+  double* best = nullptr;
+
+  if (init) {
+    tm.begin(MSQRT_T_X0);
+    // X_0 = (Q diag(s)) Q^T in the factor precision, stored in float64.
+    launch_scale_cols<T>(st, n, Q, n, nn, s, n, W1, n, nn, batch);
+    gemm_set_f64<T>(st, false, true, n, n, W1, n, nn, Q, n, nn, X, ldx, sX, batch, true);
+  }
+
+  std::vector<std::vector<double>> hist(batch);
+  std::vector<int> done(batch, 0), steps(batch, 0);
+  std::vector<Verdict> verdict(batch, Verdict::Continue);
+  std::vector<double> host_rn(batch), best_r(batch, INFINITY);
+  std::vector<int> host_active(batch, 1);
+  bool need_best = false;
+
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    int ntiles;
+    if (std::is_same<T, float>::value)
+      ntiles = gemm_residual(st, n, X, ldx, sX, A, lda, sA, f->ascale_dev(), (float*)W1, nullptr, n,
+                             nn, part, batch, true);
+    else
+      ntiles = gemm_residual(st, n, X, ldx, sX, A, lda, sA, f->ascale_dev(), nullptr, (double*)W1,
+                             n, nn, part, batch, true);
+    launch_reduce_sqrt(st, part, ntiles, batch, rn);
+    MSQRT_HIP(hipMemcpyAsync(host_rn.data(), rn, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    tm.end();
+    MSQRT_HIP(hipStreamSynchronize(st));
+    tm.collect();
+    bool all_done = true;
+    for (int b = 0; b < batch; ++b) {
+      if (done[b]) continue;
+      const double r = host_rn[b] / f->anorm_scaled[b];
+      hist[b].push_back(r);
+      Verdict v = judge(hist[b], tol);
+      if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+      if (v != Verdict::Continue) {
+        done[b] = 1;
+        verdict[b] = v;
+        host_active[b] = 0;
+      } else {
+        all_done = false;
+      }
+    }
+    if (all_done) break;
+    // Keep the best iterate of every entry that is still being refined, so a
+    // diverging entry can return it.
+    for (int b = 0; b < batch; ++b)
+      if (!done[b] && hist[b].back() < best_r[b]) {
+        best_r[b] = hist[b].back();
+        need_best = true;
+      }
+    if (need_best) {
+      if (!best) best = f->best.ensure<double>(nn * batch);
+      for (int b = 0; b < batch; ++b)
+        if (!done[b] && hist[b].back() == best_r[b])
+          launch_copy_f64(st, n, X + b * sX, ldx, 0, best + b * nn, n, 0, 1);
+      need_best = false;
+    }
+    MSQRT_HIP(hipMemcpyAsync(active, host_active.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st));
+    // Schur-basis transform and diagonal solve (Alg. 3):
+    //   W2 = R_l Q;  Y = (Q^T W2) ./ (s_i + s_j)  -> W1
+    tm.begin(MSQRT_T_TRANSFORM);
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, false, false, n, n, n, (const float*)W1, n, nn, (const float*)Q, n, nn,
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+    else
+      gemm_store_f64(st, false, false, n, n, n, (const double*)W1, n, nn, (const double*)Q, n, nn,
+                     (double*)W2, n, nn, 1.0, 0.0, batch, false);
+    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, true);
+    // Back-transform and working-precision update:  V = Q Y -> W2;  X += V Q^T
+    tm.begin(MSQRT_T_UPDATE);
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, false, false, n, n, n, (const float*)Q, n, nn, (const float*)W1, n, nn,
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+    else
+      gemm_store_f64(st, false, false, n, n, n, (const double*)Q, n, nn, (const double*)W1, n, nn,
+                     (double*)W2, n, nn, 1.0, 0.0, batch, false);
+    gemm_update<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, X, ldx, sX, active, batch, true);
+    tm.end();
+    for (int b = 0; b < batch; ++b)
+      if (!done[b]) steps[b]++;
+  }
+
+  // Restore the best iterate where the refinement failed.
+  msqrt_status status = MSQRT_OK;
+  int max_steps = 0;
+  double max_r = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    max_steps = std::max(max_steps, steps[b]);
+    double final_r = hist[b].back();
+    if (verdict[b] != Verdict::Converged) {
+      if (best && best_r[b] < final_r) {
+        launch_copy_f64(st, n, best + b * nn, n, 0, X + b * sX, ldx, 0, 1);
+        final_r = best_r[b];
+      }
+      msqrt_status sb = verdict[b] == Verdict::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
+      if (status == MSQRT_OK || sb == MSQRT_ERR_DIVERGED) status = sb;
+    }
+    max_r = std::max(max_r, std::isfinite(final_r) ? final_r : INFINITY);
+  }
+  if (info) {
+    info->steps = max_steps;
+    info->relres = max_r;
+    info->nhist = (int)std::min<size_t>(64, hist[0].size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[0][k];
+  }
+  return status;
+}
+
+msqrt_status refine(Factor* f, const double* A, int64_t lda, int64_t sA, double* X, int64_t ldx,
+                    int64_t sX, int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
+                    PhaseTimer& tm) {
+  if (f->structure == MSQRT_STRUCT_HPD) {
+    if (f->prec == MSQRT_PREC_FP64)
+      return refine_hpd<double>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
+    return refine_hpd<float>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
+  }
+  throw Error{MSQRT_ERR_UNSUPPORTED, "general (non-HPD) refinement is not available in this build"};
+}
+
+// Computes ||A_b||_F and the scale exponents k_b = round(log4(||A_b||_F / sqrt(n)))
+// into the factor; also validates finiteness / symmetry.  Returns flags.
+int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
+                         hipStream_t st) {
+  const int n = (int)f->n, batch = (int)f->batch;
+  int* flags = f->active.ensure<int>(batch);
+  const int nblk = (int)ceil_div(n, 64);
+  double* part = f->part.ensure<double>((int64_t)nblk * batch + 64);
+  double* rn = f->rnorm.ensure<double>(batch);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
+  launch_validate(st, n, A, lda, sA, batch, check_sym ? 1 : 0, flags, part);
+  launch_reduce_sqrt(st, part, nblk, batch, rn);
+  std::vector<int> hf(batch);
+  std::vector<double> hn(batch);
+  MSQRT_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipMemcpyAsync(hn.data(), rn, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  int agg = 0;
+  f->kexp.assign(batch, 0);
+  f->anorm.assign(batch, 0.0);
+  for (int b = 0; b < batch; ++b) {
+    agg |= hf[b];
+    f->anorm[b] = hn[b];
+    int k = 0;
+    if (hn[b] > 0 && std::isfinite(hn[b])) k = (int)std::lround(std::log(hn[b] / std::sqrt((double)n)) / std::log(4.0));
+    f->kexp[b] = k;
+  }
+  f->upload_scales(st);
+  return agg;
+}
+
+}  // namespace msqrt
+
+using namespace msqrt;
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+#define MSQRT_API_BEGIN try {
+#define MSQRT_API_END                                                                   \
+  }                                                                                     \
+  catch (const Error& e) {                                                              \
+    set_last_error(e.msg);                                                              \
+    return (msqrt_status)e.status;                                                      \
+  }                                                                                     \
+  catch (const std::bad_alloc&) {                                                       \
+    set_last_error("host allocation failed");                                           \
+    return MSQRT_ERR_OUT_OF_MEMORY;                                                     \
+  }                                                                                     \
+  catch (...) {                                                                         \
+    set_last_error("unknown error");                                                    \
+    return MSQRT_ERR_DEVICE;                                                            \
+  }
+
+extern "C" {
+
+void msqrt_default_options(msqrt_options* o) {
+  if (!o) return;
+  o->prec = MSQRT_PREC_FP32;
+  o->structure = MSQRT_STRUCT_AUTO;
+  o->maxit = 30;
+  o->tol = 1e-13;
+  o->blks = 32;
+  o->fallback = 1;
+  o->batch = 1;
+}
+
+const char* msqrt_status_string(msqrt_status s) {
+  switch (s) {
+    case MSQRT_OK: return "ok";
+    case MSQRT_ERR_INVALID_ARG: return "invalid argument";
+    case MSQRT_ERR_NONFINITE: return "non-finite input";
+    case MSQRT_ERR_NO_PRINCIPAL: return "no principal square root (eigenvalue on R<=0)";
+    case MSQRT_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case MSQRT_ERR_DIVERGED: return "refinement diverged";
+    case MSQRT_ERR_DEVICE: return "device error";
+    case MSQRT_ERR_OUT_OF_MEMORY: return "out of memory";
+    case MSQRT_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* msqrt_last_error(void) { return g_last_error.c_str(); }
+
+void msqrt_factor_destroy(msqrt_factor_t f) { delete reinterpret_cast<Factor*>(f); }
+
+static msqrt_status check_common(msqrt_dtype dtype, int64_t n, const void* A, int64_t lda,
+                                 int64_t batch) {
+  if (n < 0 || batch < 1 || (n > 0 && (A == nullptr || lda < n))) {
+    set_last_error("invalid size, pointer or leading dimension");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (n > (int64_t)1 << 30) {
+    set_last_error("n too large");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (dtype != MSQRT_REAL64 && dtype != MSQRT_COMPLEX128) {
+    set_last_error("unknown dtype");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  return MSQRT_OK;
+}
+
+msqrt_status msqrt_factor_wrap(msqrt_prec prec, msqrt_struct structure, msqrt_dtype dtype,
+                               int64_t n, const void* Qp, const void* Sp, int on_device,
+                               msqrt_factor_t* out) {
+  MSQRT_API_BEGIN
+  if (!out || n < 1 || !Qp || !Sp) {
+    set_last_error("invalid argument");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (dtype != MSQRT_REAL64 || structure != MSQRT_STRUCT_HPD) {
+    set_last_error("factor_wrap supports real HPD factors in this build");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  if (prec != MSQRT_PREC_FP32 && prec != MSQRT_PREC_FP64) {
+    set_last_error("factor_wrap: prec must be FP32 or FP64");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  std::unique_ptr<Factor> f(new Factor());
+  f->n = n; f->batch = 1; f->dtype = dtype; f->structure = structure; f->prec = prec;
+  const size_t es = prec == MSQRT_PREC_FP64 ? 8 : 4;
+  f->Q.alloc(es * n * n);
+  f->S.alloc(es * n);
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  MSQRT_HIP(hipMemcpy(f->Q.p, Qp, es * n * n, kind));
+  MSQRT_HIP(hipMemcpy(f->S.p, Sp, es * n, kind));
+  f->kexp.assign(1, 0);
+  f->anorm.assign(1, 0.0);
+  f->upload_scales(nullptr);
+  MSQRT_HIP(hipDeviceSynchronize());
+  *out = reinterpret_cast<msqrt_factor_t>(f.release());
+  return MSQRT_OK;
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_factor_export(msqrt_factor_t fh, void* Qh, void* Sh, int* scale_exp) {
+  MSQRT_API_BEGIN
+  Factor* f = reinterpret_cast<Factor*>(fh);
+  if (!f) return MSQRT_ERR_INVALID_ARG;
+  const size_t es = f->prec == MSQRT_PREC_FP64 ? 8 : 4;
+  const int64_t n = f->n;
+  MSQRT_HIP(hipDeviceSynchronize());
+  if (Qh) MSQRT_HIP(hipMemcpy(Qh, f->Q.p, es * n * n * f->batch, hipMemcpyDeviceToHost));
+  if (Sh) MSQRT_HIP(hipMemcpy(Sh, f->S.p, es * n * f->batch, hipMemcpyDeviceToHost));
+  if (scale_exp) *scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+  return MSQRT_OK;
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_t strideA,
+                          void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
+                          double tol, hipStream_t stream, msqrt_info* info) {
+  MSQRT_API_BEGIN
+  Factor* f = reinterpret_cast<Factor*>(fh);
+  if (!f || !dA || !dX || lda < f->n || ldx < f->n || maxit < 0 || !(tol >= 0)) {
+    set_last_error("msqrt_refine: invalid argument");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (f->batch > 1 && (strideA < lda * f->n || strideX < ldx * f->n)) {
+    set_last_error("msqrt_refine: batch strides too small");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (info) { std::memset(info, 0, sizeof(*info)); info->prec_used = f->prec; info->struct_used = f->structure; }
+  PhaseTimer tm(stream, info);
+  // ||A||_F of the (scaled) matrix the refinement measures against.  The
+  // factor's scale exponents are kept; the norm is recomputed because A may be
+  // a nearby matrix.
+  {
+    std::vector<int> k = f->kexp;
+    analyse_input(f, (const double*)dA, lda, strideA, false, stream);
+    f->kexp = k;
+    f->upload_scales(stream);
+  }
+  for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
+  double* X = (double*)dX;
+  // Refinement runs on the scaled problem A/4^k: bring X to that scale.
+  launch_scale_inplace(stream, (int)f->n, X, ldx, strideX, f->rscale_dev(), (int)f->batch);
+  msqrt_status s = refine(f, (const double*)dA, lda, strideA, X, ldx, strideX, init_from_factor,
+                          maxit, tol, stream, info, tm);
+  launch_scale_inplace(stream, (int)f->n, X, ldx, strideX, f->uscale_dev(), (int)f->batch);
+  MSQRT_HIP(hipStreamSynchronize(stream));
+  tm.collect();
+  if (info) info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+  return s;
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
+                          int64_t lda, int64_t strideA, hipStream_t stream, msqrt_factor_t* out) {
+  MSQRT_API_BEGIN
+  msqrt_options o;
+  msqrt_default_options(&o);
+  if (opt) o = *opt;
+  msqrt_status cs = check_common(dtype, n, dA, lda, o.batch);
+  if (cs != MSQRT_OK) return cs;
+  if (!out) return MSQRT_ERR_INVALID_ARG;
+  std::unique_ptr<Factor> f(new Factor());
+  f->n = n; f->batch = o.batch; f->dtype = dtype; f->blks = o.blks;
+  msqrt_status st = build_factor(f.get(), o, (const double*)dA, lda, strideA, stream, nullptr);
+  if (st != MSQRT_OK) return st;
+  *out = reinterpret_cast<msqrt_factor_t>(f.release());
+  return MSQRT_OK;
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
+                         int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                         hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep) {
+  MSQRT_API_BEGIN
+  msqrt_options o;
+  msqrt_default_options(&o);
+  if (opt) o = *opt;
+  msqrt_status cs = check_common(dtype, n, dA, lda, o.batch);
+  if (cs != MSQRT_OK) return cs;
+  if (n > 0 && (!dX || ldx < n)) return MSQRT_ERR_INVALID_ARG;
+  if (o.batch > 1 && (strideA < lda * n || strideX < ldx * n)) {
+    set_last_error("batch strides too small");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (keep) *keep = nullptr;
+  if (n == 0) return MSQRT_OK;
+  PhaseTimer tm(stream, info);
+
+  msqrt_prec prec = o.prec;
+  if (prec == MSQRT_PREC_AUTO) prec = select_precision(o, dtype, n, dA, lda, strideA, stream, info, tm);
+  msqrt_status last = MSQRT_ERR_DEVICE;
+  int fallbacks = 0;
+  for (;;) {
+    std::unique_ptr<Factor> f(new Factor());
+    f->n = n; f->batch = o.batch; f->dtype = dtype; f->blks = o.blks;
+    msqrt_options oo = o;
+    oo.prec = prec;
+    msqrt_status st = build_factor(f.get(), oo, (const double*)dA, lda, strideA, stream, &tm);
+    if (st == MSQRT_OK) {
+      for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
+      st = refine(f.get(), (const double*)dA, lda, strideA, (double*)dX, ldx, strideX, 1, o.maxit,
+                  o.tol, stream, info, tm);
+      tm.begin(MSQRT_T_VALIDATE);
+      launch_scale_inplace(stream, (int)n, (double*)dX, ldx, strideX, f->uscale_dev(), (int)o.batch);
+      tm.end();
+      MSQRT_HIP(hipStreamSynchronize(stream));
+      tm.collect();
+      if (info) { info->prec_used = prec; info->struct_used = f->structure; info->scale_exp = f->kexp[0]; }
+    }
+    last = st;
+    const bool retryable = st == MSQRT_ERR_DIVERGED || st == MSQRT_ERR_NOT_CONVERGED ||
+                           st == MSQRT_ERR_NO_PRINCIPAL;
+    if (st == MSQRT_OK || !o.fallback || !retryable || prec == MSQRT_PREC_FP64) {
+      if (keep && st == MSQRT_OK) *keep = reinterpret_cast<msqrt_factor_t>(f.release());
+      break;
+    }
+    prec = prec == MSQRT_PREC_BF16SPLIT ? MSQRT_PREC_FP32 : MSQRT_PREC_FP64;
+    ++fallbacks;
+  }
+  if (info) info->fallbacks = fallbacks;
+  return last;
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_sqrtm_backward(msqrt_factor_t fh, const void* dX, int64_t ldx,
+                                  const void* dGbar, int64_t ldgb, void* dG, int64_t ldg,
+                                  int64_t stride, int maxit, double tol, hipStream_t stream,
+                                  msqrt_info* info) {
+  MSQRT_API_BEGIN
+  Factor* f = reinterpret_cast<Factor*>(fh);
+  if (!f || !dX || !dGbar || !dG || ldx < f->n || ldgb < f->n || ldg < f->n || maxit < 0) {
+    set_last_error("msqrt_sqrtm_backward: invalid argument");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  PhaseTimer tm(stream, info);
+  return backward(f, (const double*)dX, ldx, (const double*)dGbar, ldgb, (double*)dG, ldg, stride,
+                  maxit, tol, stream, info, tm);
+  MSQRT_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/msqrt.h (no compute call: runs without a GPU)."""
+
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "msqrt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(msqrt_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_four_calls():
+    names = declared_symbols()
+    for required in ("msqrt_factor", "msqrt_sqrtm", "msqrt_refine", "msqrt_sqrtm_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2607_12430_amd import _lib
+    lib = _lib.lib()
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.EXPORTED) == set(declared_symbols())
+
+
+def test_status_strings_and_invalid_args_without_device():
+    import ctypes
+    from paper_2607_12430_amd import _lib
+    lib = _lib.lib()
+    for s in range(9):
+        assert lib.msqrt_status_string(s)
+    o = _lib.Options()
+    lib.msqrt_default_options(ctypes.byref(o))
+    assert o.maxit == 30 and abs(o.tol - 1e-13) < 1e-30 and o.blks == 32 and o.batch == 1
+    h = ctypes.c_void_p(0)
+    # negative n is rejected before any device work
+    st = lib.msqrt_factor(ctypes.byref(o), 0, -1, None, 1, 1, None, ctypes.byref(h))
+    assert st == _lib.INVALID_ARG
+    lib.msqrt_factor_destroy(None)
