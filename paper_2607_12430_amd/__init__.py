@@ -172,6 +172,36 @@ def sqrtm_backward(f: Factor, x: torch.Tensor, gbar: torch.Tensor, maxit=30, tol
     return g, info.to_dict()
 
 
+def test_sytrd(a, prec="fp32"):
+    """Test hook: (d, e, tau) of the on-device tridiagonalisation of host A."""
+    import numpy as np
+    dt = np.float32 if prec == "fp32" else np.float64
+    a = np.asfortranarray(a, dtype=dt)
+    n = a.shape[0]
+    d = np.zeros(n, dt)
+    e = np.zeros(max(n - 1, 1), dt)
+    tau = np.zeros(max(n - 1, 1), dt)
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().msqrt_test_sytrd(_lib.PREC_NAMES[prec], n, vp(a), vp(d), vp(e), vp(tau)),
+          "msqrt_test_sytrd")
+    return d, e[: n - 1], tau[: n - 1]
+
+
+def test_stedc(d, e, prec="fp32"):
+    """Test hook: (lam, Z) of the on-device divide-and-conquer eigensolver."""
+    import numpy as np
+    dt = np.float32 if prec == "fp32" else np.float64
+    n = len(d)
+    d = np.ascontiguousarray(d, dtype=dt)
+    e = np.ascontiguousarray(np.concatenate([np.asarray(e, dt), np.zeros(1, dt)]))
+    lam = np.zeros(n, np.float64)
+    z = np.zeros((n, n), dt, order="F")
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().msqrt_test_stedc(_lib.PREC_NAMES[prec], n, vp(d), vp(e), vp(lam), vp(z)),
+          "msqrt_test_stedc")
+    return lam, z
+
+
 class _SqrtmFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, a, prec, tol, maxit):

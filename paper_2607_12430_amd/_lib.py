@@ -30,7 +30,7 @@ PHASES = ["validate", "select", "reduce", "eig", "back", "x0", "residual", "tran
 EXPORTED = [
     "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_sqrtm",
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
-    "msqrt_factor_wrap", "msqrt_factor_export",
+    "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_stedc",
 ]
 
 
@@ -103,8 +103,11 @@ def lib():
     L.msqrt_last_error.restype = ctypes.c_char_p
     L.msqrt_factor_wrap.argtypes = [ci, ci, ci, i64, vp, vp, ci, ctypes.POINTER(vp)]
     L.msqrt_factor_export.argtypes = [vp, vp, vp, ctypes.POINTER(ci)]
+    L.msqrt_test_sytrd.argtypes = [ci, i64, vp, vp, vp, vp]
+    L.msqrt_test_stedc.argtypes = [ci, i64, vp, vp, vp, vp]
     for name in ("msqrt_factor", "msqrt_refine", "msqrt_sqrtm", "msqrt_sqrtm_backward",
-                 "msqrt_factor_wrap", "msqrt_factor_export"):
+                 "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
+                 "msqrt_test_stedc"):
         getattr(L, name).restype = ci
     _lib = L
     return L

@@ -1,16 +1,117 @@
 // Factorisation driver: validation, scaling, structure detection and the
 // low-precision Schur / spectral decomposition of Alg. 2 / Alg. 3.
 #include <cmath>
+#include <vector>
 
 #include "factor.hpp"
 #include "kernels.hpp"
+#include "tridiag.hpp"
+#include "../../include/msqrt_testing.h"
 
 namespace msqrt {
 
+namespace {
+
+// s_i = sqrt(lam_i) in the factor precision; out[0] = min lam (float64).
+template <typename T>
+__global__ __launch_bounds__(256) void finish_hpd_kernel(int n, const double* lam, T* s,
+                                                         double* minlam) {
+  __shared__ double red[4];
+  double mn = INFINITY;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double l = lam[i];
+    mn = fmin(mn, l);
+    s[i] = (T)sqrt(fmax(l, 0.0));
+  }
+  mn = -block_max(-mn, red);
+  if (threadIdx.x == 0) *minlam = mn;
+}
+
+template <typename T>
+void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t st,
+                PhaseTimer* tm, std::vector<double>& minlam) {
+  const int n = (int)f->n, batch = (int)f->batch;
+  const int64_t nn = (int64_t)n * n;
+  T* Q = f->Q.ensure<T>(nn * batch);
+  T* S = f->S.ensure<T>((int64_t)n * batch);
+  T* Aw = f->fw1.ensure<T>(nn);
+  T* d = f->fw2.ensure<T>(3 * (int64_t)n + 8);
+  T* e = d + n;
+  T* tau = e + n;
+  double* lam = f->fw3.ensure<double>(n + 8);
+  double* mins = f->fw4.ensure<double>(batch);
+  SytrdWork sw;
+  StedcWork ew;
+  OrmtrWork ow;
+  for (int b = 0; b < batch; ++b) {
+    if (tm) tm->begin(MSQRT_T_REDUCE);
+    if (std::is_same<T, float>::value)
+      launch_cast_scale_f64_f32(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (float*)Aw, n, 0, 1);
+    else
+      launch_cast_scale_f64_f64(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (double*)Aw, n, 0, 1);
+    sytrd<T>(st, n, Aw, d, e, tau, sw);
+    if (tm) tm->begin(MSQRT_T_EIG);
+    stedc<T>(st, n, d, e, lam, Q + b * nn, ew);
+    if (tm) tm->begin(MSQRT_T_BACK);
+    ormtr<T>(st, n, Aw, tau, Q + b * nn, ow);
+    hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(1), dim3(256), 0, st, n, (const double*)lam,
+                       S + (int64_t)b * n, mins + b);
+    MSQRT_LAUNCH_CHECK();
+    if (tm) tm->end();
+  }
+  minlam.resize(batch);
+  MSQRT_HIP(hipMemcpyAsync(minlam.data(), mins, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  if (tm) tm->collect();
+  // the sytrd barrier error flag
+  unsigned flag[2] = {0, 0};
+  if (sw.bar.p) {
+    MSQRT_HIP(hipMemcpy(flag, sw.bar.p, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag[1]) throw Error{MSQRT_ERR_DEVICE, "tridiagonal reduction: grid barrier timed out"};
+  }
+}
+
+}  // namespace
+
 msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,
                           int64_t sA, hipStream_t st, PhaseTimer* tm) {
-  (void)o; (void)A; (void)lda; (void)sA; (void)st; (void)tm; (void)f;
-  throw Error{MSQRT_ERR_UNSUPPORTED, "on-device factorisation is not available in this build"};
+  if (f->dtype != MSQRT_REAL64) {
+    set_last_error("complex input is not available in this build");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  if (o.prec != MSQRT_PREC_FP32 && o.prec != MSQRT_PREC_FP64 && o.prec != MSQRT_PREC_BF16SPLIT) {
+    set_last_error("invalid precision");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (tm) tm->begin(MSQRT_T_VALIDATE);
+  const bool want_sym_check = o.structure != MSQRT_STRUCT_GENERAL;
+  const int flags = analyse_input(f, A, lda, sA, want_sym_check, st);
+  if (tm) tm->end();
+  if (flags & 1) {
+    set_last_error("input contains Inf or NaN");
+    return MSQRT_ERR_NONFINITE;
+  }
+  msqrt_struct sc = o.structure;
+  if (sc == MSQRT_STRUCT_AUTO) sc = (flags & 2) ? MSQRT_STRUCT_GENERAL : MSQRT_STRUCT_HPD;
+  if (sc == MSQRT_STRUCT_HPD && (flags & 2)) {
+    set_last_error("structure HPD requested but the input is not exactly symmetric");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (sc == MSQRT_STRUCT_GENERAL) {
+    set_last_error("the general (non-symmetric) path is not available in this build");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  f->structure = sc;
+  f->prec = o.prec == MSQRT_PREC_FP64 ? MSQRT_PREC_FP64 : MSQRT_PREC_FP32;
+  std::vector<double> minlam;
+  if (f->prec == MSQRT_PREC_FP64) factor_hpd<double>(f, A, lda, sA, st, tm, minlam);
+  else factor_hpd<float>(f, A, lda, sA, st, tm, minlam);
+  for (double l : minlam)
+    if (!(l > 0.0)) {
+      set_last_error("a computed eigenvalue is not positive in this precision");
+      return MSQRT_ERR_NO_PRINCIPAL;
+    }
+  return MSQRT_OK;
 }
 
 msqrt_prec select_precision(const msqrt_options& o, msqrt_dtype dtype, int64_t n, const void* A,
@@ -29,3 +130,71 @@ msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gba
 }
 
 }  // namespace msqrt
+
+// ---------------------------------------------------------------------------
+// Test hooks (include/msqrt_testing.h).
+
+using namespace msqrt;
+
+namespace {
+template <typename T>
+void test_sytrd_impl(int n, const void* A, void* d, void* e, void* tau) {
+  DevBuf a, dd;
+  T* da = a.ensure<T>((int64_t)n * n);
+  T* dv = dd.ensure<T>(3 * (int64_t)n + 8);
+  MSQRT_HIP(hipMemcpy(da, A, sizeof(T) * n * n, hipMemcpyHostToDevice));
+  SytrdWork sw;
+  sytrd<T>(nullptr, n, da, dv, dv + n, dv + 2 * n, sw);
+  MSQRT_HIP(hipDeviceSynchronize());
+  MSQRT_HIP(hipMemcpy(d, dv, sizeof(T) * n, hipMemcpyDeviceToHost));
+  if (n > 1) {
+    MSQRT_HIP(hipMemcpy(e, dv + n, sizeof(T) * (n - 1), hipMemcpyDeviceToHost));
+    MSQRT_HIP(hipMemcpy(tau, dv + 2 * n, sizeof(T) * (n - 1), hipMemcpyDeviceToHost));
+  }
+  unsigned flag[2] = {0, 0};
+  if (sw.bar.p) MSQRT_HIP(hipMemcpy(flag, sw.bar.p, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag[1]) throw Error{MSQRT_ERR_DEVICE, "grid barrier timed out"};
+}
+template <typename T>
+void test_stedc_impl(int n, const void* d, const void* e, double* lam, void* Z) {
+  DevBuf dd, z, l;
+  T* dv = dd.ensure<T>(2 * (int64_t)n + 8);
+  T* dz = z.ensure<T>((int64_t)n * n);
+  double* dl = l.ensure<double>(n);
+  MSQRT_HIP(hipMemcpy(dv, d, sizeof(T) * n, hipMemcpyHostToDevice));
+  if (n > 1) MSQRT_HIP(hipMemcpy(dv + n, e, sizeof(T) * (n - 1), hipMemcpyHostToDevice));
+  StedcWork ew;
+  stedc<T>(nullptr, n, dv, dv + n, dl, dz, ew);
+  MSQRT_HIP(hipDeviceSynchronize());
+  MSQRT_HIP(hipMemcpy(lam, dl, sizeof(double) * n, hipMemcpyDeviceToHost));
+  MSQRT_HIP(hipMemcpy(Z, dz, sizeof(T) * n * n, hipMemcpyDeviceToHost));
+}
+}  // namespace
+
+extern "C" msqrt_status msqrt_test_sytrd(msqrt_prec prec, int64_t n, const void* A, void* d,
+                                         void* e, void* tau) {
+  try {
+    if (n < 1 || !A || !d || !e || !tau) return MSQRT_ERR_INVALID_ARG;
+    if (prec == MSQRT_PREC_FP64) test_sytrd_impl<double>((int)n, A, d, e, tau);
+    else if (prec == MSQRT_PREC_FP32) test_sytrd_impl<float>((int)n, A, d, e, tau);
+    else return MSQRT_ERR_INVALID_ARG;
+    return MSQRT_OK;
+  } catch (const Error& err) {
+    set_last_error(err.msg);
+    return (msqrt_status)err.status;
+  }
+}
+
+extern "C" msqrt_status msqrt_test_stedc(msqrt_prec prec, int64_t n, const void* d, const void* e,
+                                         double* lam, void* Z) {
+  try {
+    if (n < 1 || !d || !lam || !Z) return MSQRT_ERR_INVALID_ARG;
+    if (prec == MSQRT_PREC_FP64) test_stedc_impl<double>((int)n, d, e, lam, Z);
+    else if (prec == MSQRT_PREC_FP32) test_stedc_impl<float>((int)n, d, e, lam, Z);
+    else return MSQRT_ERR_INVALID_ARG;
+    return MSQRT_OK;
+  } catch (const Error& err) {
+    set_last_error(err.msg);
+    return (msqrt_status)err.status;
+  }
+}

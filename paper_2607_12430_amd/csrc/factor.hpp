@@ -8,6 +8,11 @@
 
 namespace msqrt {
 
+// Process-wide cache of device allocations keyed by (device, size), so that
+// repeated solves of the same size do not pay for hipMalloc / hipFree.
+void* pool_alloc(size_t bytes);
+void pool_free(void* p, size_t bytes);
+
 // Owning device allocation that only grows.
 struct DevBuf {
   void* p = nullptr;
@@ -16,21 +21,18 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, bytes);
   }
   void alloc(size_t b) {
     if (p && b <= bytes) return;
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, bytes);
     p = nullptr;
     bytes = 0;
     if (b == 0) return;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw Error{MSQRT_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(b) + " bytes failed"};
-    }
-    bytes = b;
+    // round up to 1 MiB granules above 1 MiB so near sizes share cache entries
+    const size_t g = b > (1u << 20) ? ((b + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1)) : ((b + 255) & ~(size_t)255);
+    p = pool_alloc(g);
+    bytes = g;
   }
   template <typename T>
   T* ensure(int64_t count) {

@@ -20,6 +20,22 @@ void gemm_store_f64(hipStream_t st, bool ta, bool tb, int M, int N, int K, const
   launch_gemm<double>(st, ta, tb, s, A, B, e, nullptr, batch);
 }
 
+template <typename T>
+void gemm_store_splitk(hipStream_t st, bool ta, bool tb, int M, int N, int K, int K_last,
+                       const T* A, int64_t lda, int64_t sA, const T* B, int64_t ldb, int64_t sB,
+                       T* C, int64_t ldc, int64_t sC, int splits) {
+  GemmShape s = make_shape(M, N, K, lda, ldb, sA, sB, false);
+  s.K_last = K_last;
+  EpiStore<T> e{C, ldc, sC, T(1), T(0)};
+  launch_gemm<T>(st, ta, tb, s, A, B, e, nullptr, splits);
+}
+template void gemm_store_splitk<float>(hipStream_t, bool, bool, int, int, int, int, const float*,
+                                       int64_t, int64_t, const float*, int64_t, int64_t, float*,
+                                       int64_t, int64_t, int);
+template void gemm_store_splitk<double>(hipStream_t, bool, bool, int, int, int, int, const double*,
+                                        int64_t, int64_t, const double*, int64_t, int64_t, double*,
+                                        int64_t, int64_t, int);
+
 int gemm_residual(hipStream_t st, int n, const double* X, int64_t ldx, int64_t sX,
                   const double* A, int64_t lda, int64_t sA, const double* ascale, float* Rl,
                   double* R64, int64_t ldr, int64_t sR, double* partials, int batch, bool sym) {

@@ -51,6 +51,7 @@ struct Mfma<double> {
 
 struct GemmShape {
   int M, N, K;
+  int K_last;     // K of the last batch entry (split-K over a ragged range)
   int64_t lda, ldb, sA, sB;
   int tri;        // launch only tiles with tile_m >= tile_n
   int tiles_m, tiles_n, ntiles, per_xcd;
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
   int tm, tn;
   if (!gemm_tile_coords(s, tm, tn)) return;
   const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
   A += (int64_t)batch * s.sA;
   B += (int64_t)batch * s.sB;
   const int m0 = tm * GBM, n0 = tn * GBN;
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
       if (!TA) { mm = idx % GBM; kk = idx / GBM; } else { kk = idx % GBK; mm = idx / GBK; }
       const int gm = m0 + mm, gk = k0 + kk;
       T v = T(0);
-      if (gm < s.M && gk < s.K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
+      if (gm < s.M && gk < K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
       ra[e] = v;
     }
 #pragma unroll
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
       if (TB) { nn = idx % GBN; kk = idx / GBN; } else { kk = idx % GBK; nn = idx / GBK; }
       const int gn = n0 + nn, gk = k0 + kk;
       T v = T(0);
-      if (gn < s.N && gk < s.K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
+      if (gn < s.N && gk < K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
       rb[e] = v;
     }
   };
@@ -155,12 +157,12 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
 #pragma unroll
       for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = T(0);
 
-  if (s.K > 0) load(0);
-  for (int k0 = 0; k0 < s.K; k0 += GBK) {
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += GBK) {
     __syncthreads();
     store();
     __syncthreads();
-    if (k0 + GBK < s.K) load(k0 + GBK);
+    if (k0 + GBK < K) load(k0 + GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += M::TK) {
       T a[M::MB], b[M::NB];
@@ -310,7 +312,7 @@ struct EpiSetF64 {
 inline GemmShape make_shape(int M, int N, int K, int64_t lda, int64_t ldb, int64_t sA, int64_t sB,
                             bool tri) {
   GemmShape s;
-  s.M = M; s.N = N; s.K = K; s.lda = lda; s.ldb = ldb; s.sA = sA; s.sB = sB;
+  s.M = M; s.N = N; s.K = K; s.K_last = K; s.lda = lda; s.ldb = ldb; s.sA = sA; s.sB = sB;
   s.tri = tri ? 1 : 0;
   s.tiles_m = (int)ceil_div(M, GBM);
   s.tiles_n = (int)ceil_div(N, GBN);

@@ -39,6 +39,12 @@ void gemm_store_f32(hipStream_t st, bool ta, bool tb, int M, int N, int K, const
 void gemm_store_f64(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C,
                     int64_t ldc, int64_t sC, double alpha, double beta, int batch, bool tri);
+// Split-K partial products: C_b = op(A_b) op(B_b) with A_b = A + b*sA,
+// B_b = B + b*sB, C_b = C + b*sC, K for every entry but the last (K_last).
+template <typename T>
+void gemm_store_splitk(hipStream_t st, bool ta, bool tb, int M, int N, int K, int K_last,
+                       const T* A, int64_t lda, int64_t sA, const T* B, int64_t ldb, int64_t sB,
+                       T* C, int64_t ldc, int64_t sC, int splits);
 // Residual R = ascale * A - X X (float64); writes R as float (Rl) or double
 // (R64), partials[b * ntiles + tile] = sum of R^2.  Returns ntiles.
 int gemm_residual(hipStream_t st, int n, const double* X, int64_t ldx, int64_t sX,

@@ -1,0 +1,145 @@
+// Back-transformation Q = H_0 H_1 ... H_{n-2} Z of the tridiagonal
+// eigenvectors (completing the spectral decomposition A = Q diag(lam) Q^T).
+//
+// Reflectors are grouped in blocks of kBlk = 128: H_B ... H_{B+127} =
+// I - V T V^T (compact WY, T upper triangular from the Gram matrix V^T V).
+// VT = V T is formed once per block; the blocks are then applied from the
+// last to the first as  Z(B+1:, :) -= VT (V^T Z(B+1:, :)),  the inner product
+// V^T Z as a split-K MFMA GEMM (partials over row chunks, summed in a fixed
+// order, so results are reproducible) and the update as one MFMA GEMM.
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "tridiag.hpp"
+
+namespace msqrt {
+
+namespace {
+
+constexpr int kBlk = 128;
+
+// Zero the rows above each explicit reflector (v_j(i) = 0 for i <= j) so that
+// full-height products can be used; the unit entry v_j(j+1) = 1 is already
+// stored.
+template <typename T>
+__global__ void clean_reflectors(int n, T* V) {
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i <= j && i < n; i += blockDim.x) V[i + (int64_t)j * n] = T(0);
+}
+
+// T factor of one block from its Gram matrix G = V^T V (forward, columnwise):
+// T(i,i) = tau_i,  T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i).
+template <typename T>
+__global__ __launch_bounds__(kBlk) void larft_kernel(int nb_total, const T* G, const T* tau,
+                                                     T* Tm) {
+  const int blk = blockIdx.x;
+  const int B = blk * kBlk;
+  const int nbk = min(kBlk, nb_total - B);
+  const T* g = G + (int64_t)blk * kBlk * kBlk;
+  T* t = Tm + (int64_t)blk * kBlk * kBlk;
+  const int r = threadIdx.x;
+  __shared__ T col[kBlk];
+  for (int c = 0; c < kBlk; ++c) t[r + (int64_t)c * kBlk] = T(0);
+  __syncthreads();
+  for (int i = 0; i < nbk; ++i) {
+    const T ti = tau[B + i];
+    // col = G(0:i, i)
+    if (r < i) col[r] = g[r + (int64_t)i * kBlk];
+    __syncthreads();
+    if (r < i) {
+      T acc = T(0);
+      for (int c = r; c < i; ++c) acc += t[r + (int64_t)c * kBlk] * col[c];
+      t[r + (int64_t)i * kBlk] = -ti * acc;
+    }
+    if (r == i) t[i + (int64_t)i * kBlk] = ti;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void sum_partials(int count, int splits, const T* P, int64_t stride, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  T s = T(0);
+  for (int q = 0; q < splits; ++q) s += P[i + q * stride];
+  out[i] = s;
+}
+
+}  // namespace
+
+template <typename T>
+void ormtr(hipStream_t st, int n, const T* Vc, const T* tau, T* Z, OrmtrWork& w) {
+  const int nref = n - 1;  // reflectors 0..n-2
+  if (nref <= 0) return;
+  T* V = const_cast<T*>(Vc);
+  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n), dim3(256), 0, st, n, V);
+  MSQRT_LAUNCH_CHECK();
+  const int nblk = (int)ceil_div(nref, kBlk);
+  T* G = w.gram.ensure<T>((int64_t)nblk * kBlk * kBlk * 2);
+  T* Tm = G + (int64_t)nblk * kBlk * kBlk;
+  T* VT = w.VT.ensure<T>((int64_t)nblk * kBlk * n);
+  // Gram matrices of all blocks (full height: rows above a reflector are 0).
+  const int full = nref / kBlk;
+  auto gemm = [&](bool ta, bool tb, int M, int N, int K, const T* A, int64_t lda, int64_t sA,
+                  const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, T alpha,
+                  T beta, int batch) {
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, ta, tb, M, N, K, (const float*)A, lda, sA, (const float*)B, ldb, sB,
+                     (float*)C, ldc, sC, (float)alpha, (float)beta, batch, false);
+    else
+      gemm_store_f64(st, ta, tb, M, N, K, (const double*)A, lda, sA, (const double*)B, ldb, sB,
+                     (double*)C, ldc, sC, (double)alpha, (double)beta, batch, false);
+  };
+  MSQRT_HIP(hipMemsetAsync(G, 0, sizeof(T) * (size_t)nblk * kBlk * kBlk, st));
+  if (full > 0)
+    gemm(true, false, kBlk, kBlk, n, V, n, (int64_t)kBlk * n, V, n, (int64_t)kBlk * n, G, kBlk,
+         (int64_t)kBlk * kBlk, T(1), T(0), full);
+  if (full < nblk) {
+    const int nbk = nref - full * kBlk;
+    const T* Vb = V + (int64_t)full * kBlk * n;
+    gemm(true, false, nbk, nbk, n, Vb, n, 0, Vb, n, 0, G + (int64_t)full * kBlk * kBlk, kBlk, 0,
+         T(1), T(0), 1);
+  }
+  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kBlk), 0, st, nref, (const T*)G, tau, Tm);
+  MSQRT_LAUNCH_CHECK();
+  // VT_b = V_b T_b (n x nbk)
+  if (full > 0)
+    gemm(false, false, n, kBlk, kBlk, V, n, (int64_t)kBlk * n, Tm, kBlk, (int64_t)kBlk * kBlk, VT,
+         n, (int64_t)kBlk * n, T(1), T(0), full);
+  if (full < nblk) {
+    const int nbk = nref - full * kBlk;
+    gemm(false, false, n, nbk, nbk, V + (int64_t)full * kBlk * n, n, 0,
+         Tm + (int64_t)full * kBlk * kBlk, kBlk, 0, VT + (int64_t)full * kBlk * n, n, 0, T(1),
+         T(0), 1);
+  }
+  // Apply the blocks, last to first.
+  const int splits_max = 16;
+  T* Wp = w.Wpart.ensure<T>((int64_t)splits_max * kBlk * n);
+  T* W = w.W.ensure<T>((int64_t)kBlk * n);
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int B = b * kBlk;
+    const int nbk = std::min(kBlk, nref - B);
+    const int r0 = B + 1;
+    const int rows = n - r0;
+    const T* Vb = V + (int64_t)B * n;
+    int splits = (int)std::min<int64_t>(splits_max, std::max<int64_t>(1, ceil_div(rows, 256)));
+    const int chunk = (int)ceil_div(rows, splits);
+    splits = (int)ceil_div(rows, chunk);
+    const int klast = rows - (splits - 1) * chunk;
+    // Wp[q] = V_b(rows chunk q)^T Z(rows chunk q, :)   (nbk x n each)
+    gemm_store_splitk<T>(st, true, false, nbk, n, chunk, klast, Vb + r0, n, chunk, Z + r0, n,
+                         chunk, Wp, nbk, (int64_t)nbk * n, splits);
+    const int cnt = nbk * n;
+    hipLaunchKernelGGL(sum_partials<T>, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, cnt,
+                       splits, (const T*)Wp, (int64_t)nbk * n, W);
+    MSQRT_LAUNCH_CHECK();
+    // Z(r0:, :) -= VT_b(r0:, :) W
+    gemm(false, false, rows, n, nbk, VT + (int64_t)b * kBlk * n + r0, n, 0, W, nbk, 0, Z + r0, n,
+         0, T(-1), T(1), 1);
+  }
+}
+
+template void ormtr<float>(hipStream_t, int, const float*, const float*, float*, OrmtrWork&);
+template void ormtr<double>(hipStream_t, int, const double*, const double*, double*, OrmtrWork&);
+
+}  // namespace msqrt

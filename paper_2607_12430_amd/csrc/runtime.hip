@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +17,53 @@ namespace msqrt {
 
 thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Device allocation cache.
+
+namespace {
+std::mutex g_pool_mu;
+std::multimap<std::pair<int, size_t>, void*> g_pool;
+}  // namespace
+
+void* pool_alloc(size_t bytes) {
+  int dev = 0;
+  MSQRT_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find({dev, bytes});
+    if (it != g_pool.end()) {
+      void* p = it->second;
+      g_pool.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // release the cache and retry once
+    {
+      std::lock_guard<std::mutex> lk(g_pool_mu);
+      for (auto& kv : g_pool) (void)hipFree(kv.second);
+      g_pool.clear();
+    }
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{MSQRT_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+  }
+  return p;
+}
+
+void pool_free(void* p, size_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool.insert({{dev, bytes}, p});
+}
 
 // ---------------------------------------------------------------------------
 // Convergence bookkeeping (stopping rule of Alg. 2 plus the divergence /

@@ -1,0 +1,650 @@
+// Divide-and-conquer eigensolver for a symmetric tridiagonal matrix
+// (Cuppen's tearing, deflation, secular equation, Gu-Eisenstat eigenvectors).
+//
+// All scalar work (eigenvalues, secular roots, deflation) is float64 on the
+// device; the eigenvector matrices and the merge products use the factor
+// precision T on the MFMA GEMM.  Every merge of a level is processed by the
+// same launches: one workgroup per merge for the deflation scan, one wave per
+// secular root, one GEMM per merge for the eigenvector update.
+//
+// Merge of two solved halves (T1' = Q1 D1 Q1^T, T2' = Q2 D2 Q2^T) coupled by
+// beta:  T = diag(Q1, Q2) (D + rho z z^T) diag(Q1, Q2)^T with
+// z = [last row of Q1, sign(beta) first row of Q2] / sqrt(2), rho = 2|beta|.
+// The merged eigenvectors are diag(Q1, Q2) (after the deflation rotations)
+// times M, where M holds the normalised vectors z_i / (d_i - lambda_j) of the
+// non-deflated secular problem and unit columns for deflated entries, both
+// placed in ascending order of the merged eigenvalues.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tridiag.hpp"
+
+namespace msqrt {
+
+namespace {
+
+constexpr int kLeaf = 32;
+
+struct MergeDesc {
+  int s, n1, m;  // start, left size, total size
+};
+
+// Per-position metadata arrays (all length n, indexed by s + local index).
+struct Meta {
+  double* dl;      // non-deflated poles, ascending
+  double* zl;      // their z components
+  int* cl;         // their original local column
+  double* defd;    // deflated eigenvalues, ascending
+  int* defc;       // their original local column
+  int* rota;       // rotation list: columns a, b
+  int* rotb;
+  double* rotc;
+  double* rots;
+  int* kcnt;       // per merge: k, number of deflated, number of rotations
+  double* rho;     // per merge
+  int* org;        // per root: origin pole index
+  double* tau;     // per root: lambda - d_org
+  double* lamr;    // per root: lambda
+  double* zhat;    // per non-deflated index: recomputed z
+  double* tmpd;    // scratch (sorted d), length n
+  double* tmpz;    // scratch (sorted z)
+  int* tmpc;       // scratch (sorted columns)
+};
+
+// ---------------------------------------------------------------------------
+// Tearing: for every split point q, d[q-1] -= |e[q-1]| and d[q] -= |e[q-1]|.
+
+__global__ void tear_kernel(int nsplit, const int* splits, double* d, const double* e) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsplit) return;
+  const int q = splits[t];
+  const double b = fabs(e[q - 1]);
+  d[q - 1] -= b;
+  d[q] -= b;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf eigensolver: implicit symmetric QR with Wilkinson shifts on a leaf of
+// size L <= 32.  One wave per leaf; every lane runs the scalar recurrence
+// redundantly (identical values) and lane r applies the rotations to row r of
+// the eigenvector block.
+
+template <typename T>
+__global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const int* leaf_size,
+                                                  const double* dg, const double* eg, double* lam,
+                                                  T* Z, int n) {
+  __shared__ double d[kLeaf], e[kLeaf], Zl[kLeaf][kLeaf + 1];
+  const int lf = blockIdx.x, lane = threadIdx.x;
+  const int s = leaf_start[lf], L = leaf_size[lf];
+  if (lane < L) {
+    d[lane] = dg[s + lane];
+    e[lane] = (lane + 1 < L) ? eg[s + lane] : 0.0;
+    for (int c = 0; c < L; ++c) Zl[lane][c] = (c == lane) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double eps = 1.1102230246251565e-16;
+  int hi = L - 1, iters = 0;
+  while (hi > 0 && iters < 60 * kLeaf) {
+    int lo = hi;
+    while (lo > 0) {
+      if (fabs(e[lo - 1]) <= eps * (fabs(d[lo - 1]) + fabs(d[lo]))) break;
+      --lo;
+    }
+    if (lo == hi) { --hi; continue; }
+    ++iters;
+    const double dd = (d[hi - 1] - d[hi]) * 0.5;
+    const double b2 = e[hi - 1] * e[hi - 1];
+    const double den = dd + copysign(sqrt(dd * dd + b2), dd);
+    const double mu = (den == 0.0) ? d[hi] : d[hi] - b2 / den;
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = hypot(x, z);
+      const double c = (r == 0.0) ? 1.0 : x / r;
+      const double sn = (r == 0.0) ? 0.0 : z / r;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      const double ekm = (k > lo) ? r : 0.0;
+      const double nd0 = c * c * dk + 2.0 * c * sn * ek + sn * sn * dk1;
+      const double nd1 = sn * sn * dk - 2.0 * c * sn * ek + c * c * dk1;
+      const double ne = c * sn * (dk1 - dk) + (c * c - sn * sn) * ek;
+      double nx = 0.0, nz = 0.0, nek1 = 0.0;
+      if (k + 1 < hi) {
+        nx = ne;
+        nz = sn * e[k + 1];
+        nek1 = c * e[k + 1];
+      }
+      __syncthreads();
+      if (lane == 0) {
+        if (k > lo) e[k - 1] = ekm;
+        d[k] = nd0;
+        d[k + 1] = nd1;
+        e[k] = ne;
+        if (k + 1 < hi) e[k + 1] = nek1;
+      }
+      if (lane < L) {
+        const double qa = Zl[lane][k], qb = Zl[lane][k + 1];
+        Zl[lane][k] = c * qa + sn * qb;
+        Zl[lane][k + 1] = -sn * qa + c * qb;
+      }
+      __syncthreads();
+      x = nx;
+      z = nz;
+    }
+    if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) e[hi - 1] = 0.0;
+    __syncthreads();
+  }
+  // Ascending order: rank of eigenvalue c (ties by index).
+  __shared__ int rank[kLeaf];
+  if (lane < L) {
+    int r = 0;
+    for (int i = 0; i < L; ++i) r += (d[i] < d[lane]) || (d[i] == d[lane] && i < lane);
+    rank[lane] = r;
+  }
+  __syncthreads();
+  if (lane < L) {
+    lam[s + rank[lane]] = d[lane];
+    for (int c = 0; c < L; ++c) Z[(int64_t)(s + lane) + (int64_t)(s + rank[c]) * n] = (T)Zl[lane][c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Merge preparation: z vector, merge of the two sorted halves, deflation scan.
+// One workgroup per merge.
+
+template <typename T>
+__global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, const double* eg,
+                                                         const double* lam, const T* Z, int n,
+                                                         Meta mt) {
+  const MergeDesc g = md[blockIdx.x];
+  const int s = g.s, n1 = g.n1, m = g.m, n2 = m - n1;
+  const double beta = eg[s + n1 - 1];
+  const double sgn = beta >= 0.0 ? 1.0 : -1.0;
+  const double rho = 2.0 * fabs(beta);
+  const double r2 = 0.7071067811865476;
+  __shared__ double red[4];
+  // merge-path placement of the two ascending halves
+  double dmax = 0.0, zmax = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    double di, zi;
+    int pos;
+    if (i < n1) {
+      di = lam[s + i];
+      zi = r2 * (double)Z[(int64_t)(s + n1 - 1) + (int64_t)(s + i) * n];
+      int lo = 0, hi = n2;  // count right values < di
+      while (lo < hi) { const int mid = (lo + hi) / 2; if (lam[s + n1 + mid] < di) lo = mid + 1; else hi = mid; }
+      pos = i + lo;
+    } else {
+      const int jr = i - n1;
+      di = lam[s + i];
+      zi = sgn * r2 * (double)Z[(int64_t)(s + n1) + (int64_t)(s + i) * n];
+      int lo = 0, hi = n1;  // count left values <= di
+      while (lo < hi) { const int mid = (lo + hi) / 2; if (lam[s + mid] <= di) lo = mid + 1; else hi = mid; }
+      pos = jr + lo;
+    }
+    mt.tmpd[s + pos] = di;
+    mt.tmpz[s + pos] = zi;
+    mt.tmpc[s + pos] = i;
+    dmax = fmax(dmax, fabs(di));
+    zmax = fmax(zmax, fabs(zi));
+  }
+  dmax = block_max(dmax, red);
+  zmax = block_max(zmax, red);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double eps = 1.1102230246251565e-16;
+  const double tol = 8.0 * eps * fmax(dmax, zmax);
+  double* d = mt.tmpd + s;
+  double* z = mt.tmpz + s;
+  int* c = mt.tmpc + s;
+  int k = 0, nd = 0, nr = 0, pj = -1;
+  for (int j = 0; j < m; ++j) {
+    if (rho * fabs(z[j]) <= tol) {
+      mt.defd[s + nd] = d[j];
+      mt.defc[s + nd] = c[j];
+      ++nd;
+      continue;
+    }
+    if (pj < 0) { pj = j; continue; }
+    double sn = z[pj], cs = z[j];
+    const double tau = hypot(cs, sn);
+    const double t = d[j] - d[pj];
+    cs /= tau;
+    sn = -sn / tau;
+    if (fabs(t * cs * sn) <= tol) {
+      // Rotate columns pj, j so that z[pj] vanishes; pj deflates.
+      z[j] = tau;
+      z[pj] = 0.0;
+      mt.rota[s + nr] = c[pj];
+      mt.rotb[s + nr] = c[j];
+      mt.rotc[s + nr] = cs;
+      mt.rots[s + nr] = sn;
+      ++nr;
+      const double tt = d[pj] * cs * cs + d[j] * sn * sn;
+      d[j] = d[pj] * sn * sn + d[j] * cs * cs;
+      d[pj] = tt;
+      mt.defd[s + nd] = d[pj];
+      mt.defc[s + nd] = c[pj];
+      ++nd;
+      pj = j;
+    } else {
+      mt.dl[s + k] = d[pj];
+      mt.zl[s + k] = z[pj];
+      mt.cl[s + k] = c[pj];
+      ++k;
+      pj = j;
+    }
+  }
+  if (pj >= 0) {
+    mt.dl[s + k] = d[pj];
+    mt.zl[s + k] = z[pj];
+    mt.cl[s + k] = c[pj];
+    ++k;
+  }
+  // deflated values ascending (insertion sort; the list is nearly sorted)
+  for (int a = 1; a < nd; ++a) {
+    const double v = mt.defd[s + a];
+    const int cv = mt.defc[s + a];
+    int b = a - 1;
+    while (b >= 0 && mt.defd[s + b] > v) {
+      mt.defd[s + b + 1] = mt.defd[s + b];
+      mt.defc[s + b + 1] = mt.defc[s + b];
+      --b;
+    }
+    mt.defd[s + b + 1] = v;
+    mt.defc[s + b + 1] = cv;
+  }
+  mt.kcnt[3 * blockIdx.x + 0] = k;
+  mt.kcnt[3 * blockIdx.x + 1] = nd;
+  mt.kcnt[3 * blockIdx.x + 2] = nr;
+  mt.rho[blockIdx.x] = rho;
+}
+
+// Deflation rotations on the rows of each merge block (one thread per row).
+template <typename T>
+__global__ void merge_rot_kernel(const MergeDesc* md, int nmerge_rows, const int* row_merge,
+                                 Meta mt, T* Z, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nmerge_rows) return;
+  const int b = row_merge[r];
+  if (b < 0) return;
+  const MergeDesc g = md[b];
+  const int nr = mt.kcnt[3 * b + 2];
+  for (int q = 0; q < nr; ++q) {
+    const int ca = g.s + mt.rota[g.s + q], cb = g.s + mt.rotb[g.s + q];
+    const double c = mt.rotc[g.s + q], sn = mt.rots[g.s + q];
+    const double x = (double)Z[(int64_t)r + (int64_t)ca * n], y = (double)Z[(int64_t)r + (int64_t)cb * n];
+    Z[(int64_t)r + (int64_t)ca * n] = (T)(c * x + sn * y);
+    Z[(int64_t)r + (int64_t)cb * n] = (T)(c * y - sn * x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Secular equation 1/rho + sum_i z_i^2 / (d_i - lambda) = 0, one wave per
+// root j (root j lies in (d_j, d_{j+1}), the last one in (d_k, d_k + rho)).
+// The root is represented as lambda = d_org + tau with org the nearer pole so
+// that d_i - lambda = (d_i - d_org) - tau is computed to high relative
+// accuracy.  Iteration: a two-pole rational model fitted to the value and the
+// derivatives of the left and right partial sums (Gragg's scheme), solved as
+// a quadratic, safeguarded by a bracket that is bisected whenever the model
+// step leaves it.
+
+__device__ inline void secular_eval(const double* dl, const double* zl, int k, int org, int j,
+                                    double tau, int lane, double& psi, double& phi, double& dpsi,
+                                    double& dphi) {
+  psi = phi = dpsi = dphi = 0.0;
+  const double dorg = dl[org];
+  for (int i = lane; i < k; i += kWave) {
+    const double del = (dl[i] - dorg) - tau;
+    const double w = zl[i] / del;
+    if (i <= j) { psi += zl[i] * w; dpsi += w * w; }
+    else { phi += zl[i] * w; dphi += w * w; }
+  }
+  psi = wave_sum(psi);
+  phi = wave_sum(phi);
+  dpsi = wave_sum(dpsi);
+  dphi = wave_sum(dphi);
+}
+
+__global__ __launch_bounds__(64) void secular_kernel(const MergeDesc* md, const int* pos_merge,
+                                                     Meta mt, int n) {
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = pos_merge[w];
+  if (b < 0) return;
+  const MergeDesc g = md[b];
+  const int j = w - g.s;
+  const int k = mt.kcnt[3 * b];
+  if (j >= k) return;
+  const double* dl = mt.dl + g.s;
+  const double* zl = mt.zl + g.s;
+  const double rho = mt.rho[b];
+  const double eps = 1.1102230246251565e-16;
+  int org;
+  double lo, hi, tau;
+  if (k == 1) {
+    if (lane == 0) {
+      mt.org[g.s + j] = 0;
+      mt.tau[g.s + j] = rho * zl[0] * zl[0];
+      mt.lamr[g.s + j] = dl[0] + rho * zl[0] * zl[0];
+    }
+    return;
+  }
+  if (j < k - 1) {
+    const double gap = dl[j + 1] - dl[j];
+    // f at the midpoint decides the nearer pole
+    double psi, phi, dpsi, dphi;
+    secular_eval(dl, zl, k, j, j, 0.5 * gap, lane, psi, phi, dpsi, dphi);
+    const double fmid = 1.0 / rho + psi + phi;
+    if (fmid >= 0.0) { org = j; lo = 0.0; hi = 0.5 * gap; }
+    else { org = j + 1; lo = -0.5 * gap; hi = 0.0; }
+  } else {
+    org = k - 1;
+    double zz = 0.0;
+    for (int i = lane; i < k; i += kWave) zz += zl[i] * zl[i];
+    zz = wave_sum(zz);
+    lo = 0.0;
+    hi = rho * zz * (1.0 + 4.0 * eps) + 1e-300;
+  }
+  tau = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    double psi, phi, dpsi, dphi;
+    secular_eval(dl, zl, k, org, j, tau, lane, psi, phi, dpsi, dphi);
+    const double f = 1.0 / rho + psi + phi;
+    if (f == 0.0) break;
+    if (f < 0.0) lo = tau; else hi = tau;
+    // convergence: |f| below the rounding level of its terms, or bracket tight
+    const double erret = 8.0 * (phi - psi) + 2.0 / rho + fabs(tau) * (dpsi + dphi);
+    if (fabs(f) <= eps * erret * 4.0) break;
+    if (hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+    // model poles relative to the current point
+    const double dorg = dl[org];
+    const double a0 = (dl[j] - dorg) - tau;  // < 0
+    double step_tau;
+    bool ok = false;
+    if (j < k - 1) {
+      const double b0 = (dl[j + 1] - dorg) - tau;  // > 0
+      const double s1 = a0 * a0 * dpsi, s2 = b0 * b0 * dphi;
+      const double c0 = f - a0 * dpsi - b0 * dphi;
+      // c0 eta^2 - B eta + C = 0, eta in (a0, b0)
+      const double B = c0 * (a0 + b0) + s1 + s2;
+      const double C = c0 * a0 * b0 + s1 * b0 + s2 * a0;
+      double eta = 0.0;
+      if (c0 == 0.0) {
+        if (B != 0.0) { eta = C / B; ok = true; }
+      } else {
+        const double disc = B * B - 4.0 * c0 * C;
+        if (disc >= 0.0) {
+          const double q = 0.5 * (B + copysign(sqrt(disc), B));
+          const double e1 = q / c0, e2 = (q != 0.0) ? C / q : e1;
+          if (e1 > a0 && e1 < b0) { eta = e1; ok = true; }
+          else if (e2 > a0 && e2 < b0) { eta = e2; ok = true; }
+        }
+      }
+      step_tau = tau + eta;
+    } else {
+      const double s1 = a0 * a0 * dpsi;
+      const double c0 = f - a0 * dpsi;
+      double eta = 0.0;
+      if (c0 > 0.0) { eta = a0 + s1 / c0; ok = true; }
+      step_tau = tau + eta;
+    }
+    if (!ok || !(step_tau > lo && step_tau < hi)) {
+      // bisection (geometric when the bracket excludes zero)
+      if (lo > 0.0 && hi > 0.0 && hi > 4.0 * lo) step_tau = sqrt(lo * hi);
+      else if (lo < 0.0 && hi < 0.0 && lo < 4.0 * hi) step_tau = -sqrt(lo * hi);
+      else step_tau = 0.5 * (lo + hi);
+    }
+    if (step_tau == tau) break;
+    tau = step_tau;
+  }
+  if (lane == 0) {
+    mt.org[g.s + j] = org;
+    mt.tau[g.s + j] = tau;
+    mt.lamr[g.s + j] = dl[org] + tau;
+  }
+}
+
+// Gu-Eisenstat: z_i recomputed from the computed roots so that the computed
+// eigenvectors are numerically orthogonal:
+//   zhat_i^2 = (lambda_i - d_i)/rho * prod_{j != i} (lambda_j - d_i)/(d_j - d_i).
+__global__ void lowner_kernel(const MergeDesc* md, const int* pos_merge, Meta mt, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int b = pos_merge[p];
+  if (b < 0) return;
+  const MergeDesc g = md[b];
+  const int i = p - g.s;
+  const int k = mt.kcnt[3 * b];
+  if (i >= k) return;
+  const double* dl = mt.dl + g.s;
+  const double di = dl[i];
+  double prod = ((dl[mt.org[g.s + i]] - di) + mt.tau[g.s + i]) / mt.rho[b];
+  for (int j = 0; j < k; ++j) {
+    if (j == i) continue;
+    const double lj_di = (dl[mt.org[g.s + j]] - di) + mt.tau[g.s + j];
+    prod *= lj_di / (dl[j] - di);
+  }
+  const double zh = sqrt(fmax(prod, 0.0));
+  mt.zhat[g.s + i] = mt.zl[g.s + i] >= 0.0 ? zh : -zh;
+}
+
+// Columns of M: secular eigenvectors (normalised) and unit vectors for the
+// deflated entries, at the rank of their eigenvalue; new eigenvalue array.
+template <typename T>
+__global__ __launch_bounds__(64) void vectors_kernel(const MergeDesc* md, const int* pos_merge,
+                                                     Meta mt, T* M, double* lam_new, int n) {
+  const int w = blockIdx.x, lane = threadIdx.x;
+  const int b = pos_merge[w];
+  if (b < 0) return;
+  const MergeDesc g = md[b];
+  const int q = w - g.s;
+  const int k = mt.kcnt[3 * b], nd = mt.kcnt[3 * b + 1];
+  T* Mb = M + (int64_t)g.s * n;  // m x m, ld m
+  const int m = g.m;
+  if (q < k) {
+    const int j = q;
+    const double* dl = mt.dl + g.s;
+    const double dorg = dl[mt.org[g.s + j]], tau = mt.tau[g.s + j];
+    const double lj = mt.lamr[g.s + j];
+    double nrm = 0.0;
+    for (int i = lane; i < k; i += kWave) {
+      const double v = mt.zhat[g.s + i] / ((dl[i] - dorg) - tau);
+      nrm += v * v;
+    }
+    nrm = sqrt(wave_sum(nrm));
+    // rank among deflated values (strictly smaller)
+    int lo = 0, hi = nd;
+    while (lo < hi) { const int mid = (lo + hi) / 2; if (mt.defd[g.s + mid] < lj) lo = mid + 1; else hi = mid; }
+    const int col = j + lo;
+    for (int i = lane; i < k; i += kWave) {
+      const double v = mt.zhat[g.s + i] / ((dl[i] - dorg) - tau) / nrm;
+      Mb[mt.cl[g.s + i] + (int64_t)col * m] = (T)v;
+    }
+    if (lane == 0) lam_new[g.s + col] = lj;
+  } else if (q < k + nd) {
+    const int t = q - k;
+    const double v = mt.defd[g.s + t];
+    int lo = 0, hi = k;  // roots <= v
+    while (lo < hi) { const int mid = (lo + hi) / 2; if (mt.lamr[g.s + mid] <= v) lo = mid + 1; else hi = mid; }
+    const int col = t + lo;
+    if (lane == 0) {
+      Mb[mt.defc[g.s + t] + (int64_t)col * m] = T(1);
+      lam_new[g.s + col] = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void cast_tridiag(int n, const T* d, const T* e, double* dd, double* ee) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    dd[i] = (double)d[i];
+    ee[i] = (i + 1 < n) ? (double)e[i] : 0.0;
+  }
+}
+
+// Copies the diagonal block [r0, r0+sz) of Za (and its eigenvalues) to Zb.
+template <typename T>
+__global__ void copy_block(int n, int r0, int sz, const T* Za, T* Zb, const double* la,
+                           double* lb) {
+  const int c = r0 + blockIdx.x;
+  for (int i = threadIdx.x; i < sz; i += blockDim.x)
+    Zb[(int64_t)(r0 + i) + (int64_t)c * n] = Za[(int64_t)(r0 + i) + (int64_t)c * n];
+  if (threadIdx.x == 0) lb[c] = la[c];
+}
+
+template <typename T>
+__global__ void copy_mat(int n, const T* a, T* b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)n * n) b[i] = a[i];
+}
+
+}  // namespace
+
+template <typename T>
+void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, StedcWork& w) {
+  if (n <= 0) return;
+  const int64_t nn = (int64_t)n * n;
+  double* dd = w.dd.ensure<double>(n);
+  double* ee = w.ee.ensure<double>(n);
+  hipLaunchKernelGGL(cast_tridiag<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, d, e, dd, ee);
+  MSQRT_LAUNCH_CHECK();
+
+  // Static recursion tree: halve until the pieces are at most kLeaf.
+  std::vector<std::vector<MergeDesc>> levels;  // levels[0] = leaves' parents ... top
+  std::vector<std::pair<int, int>> cur{{0, n}};
+  std::vector<std::vector<std::pair<int, int>>> tree{cur};
+  while (true) {
+    bool split = false;
+    std::vector<std::pair<int, int>> nxt;
+    for (auto& pr : tree.back()) {
+      if (pr.second > kLeaf) {
+        const int h = pr.second / 2;
+        nxt.push_back({pr.first, h});
+        nxt.push_back({pr.first + h, pr.second - h});
+        split = true;
+      } else {
+        nxt.push_back(pr);
+      }
+    }
+    if (!split) break;
+    tree.push_back(nxt);
+  }
+  // leaves = tree.back(); merges: for level L from deepest-1 up to 0, every
+  // node of tree[L] that was split.
+  const auto& leaves = tree.back();
+  std::vector<int> lst, lsz, splits;
+  for (auto& pr : leaves) { lst.push_back(pr.first); lsz.push_back(pr.second); }
+  // Nodes of a tree level that are not split are already solved leaves; they
+  // are carried unchanged through that level's merge step.
+  std::vector<std::vector<std::pair<int, int>>> carried;
+  for (size_t li = 0; li + 1 < tree.size(); ++li) {
+    std::vector<MergeDesc> lv;
+    std::vector<std::pair<int, int>> cv;
+    for (auto& pr : tree[li]) {
+      if (pr.second > kLeaf) {
+        const int h = pr.second / 2;
+        lv.push_back({pr.first, h, pr.second});
+        splits.push_back(pr.first + h);
+      } else {
+        cv.push_back(pr);
+      }
+    }
+    levels.push_back(lv);
+    carried.push_back(cv);
+  }
+  std::reverse(levels.begin(), levels.end());  // bottom-up
+  std::reverse(carried.begin(), carried.end());
+
+  // device metadata
+  const int nl = (int)lst.size();
+  int* dmeta = w.meta.ensure<int>(2 * nl + (int64_t)splits.size() + 4 * n + 8);
+  int* dlst = dmeta;
+  int* dlsz = dmeta + nl;
+  int* dspl = dmeta + 2 * nl;
+  int* pos_merge = dspl + splits.size();
+  std::vector<int> hmeta(2 * nl + splits.size());
+  std::copy(lst.begin(), lst.end(), hmeta.begin());
+  std::copy(lsz.begin(), lsz.end(), hmeta.begin() + nl);
+  std::copy(splits.begin(), splits.end(), hmeta.begin() + 2 * nl);
+  MSQRT_HIP(hipMemcpyAsync(dmeta, hmeta.data(), sizeof(int) * hmeta.size(), hipMemcpyHostToDevice, st));
+  if (!splits.empty()) {
+    hipLaunchKernelGGL(tear_kernel, dim3((unsigned)ceil_div(splits.size(), 64)), dim3(64), 0, st,
+                       (int)splits.size(), dspl, dd, ee);
+    MSQRT_LAUNCH_CHECK();
+  }
+  T* Za = Z;
+  T* Zb = w.Z2.ensure<T>(nn);
+  MSQRT_HIP(hipMemsetAsync(Za, 0, sizeof(T) * nn, st));
+  MSQRT_HIP(hipMemsetAsync(Zb, 0, sizeof(T) * nn, st));
+  double* lamA = lam;
+  double* lamB = w.lam.ensure<double>(n);
+  hipLaunchKernelGGL(leaf_kernel<T>, dim3(nl), dim3(64), 0, st, dlst, dlsz, dd, ee, lamA, Za, n);
+  MSQRT_LAUNCH_CHECK();
+  if (levels.empty()) return;
+
+  // metadata buffers
+  Meta mt;
+  double* fb = w.roots.ensure<double>((int64_t)12 * n + 16);
+  int* ib = w.rot.ensure<int>((int64_t)10 * n + 16);
+  mt.dl = fb; mt.zl = fb + n; mt.defd = fb + 2 * n; mt.rotc = fb + 3 * n; mt.rots = fb + 4 * n;
+  mt.tau = fb + 5 * n; mt.lamr = fb + 6 * n; mt.zhat = fb + 7 * n; mt.tmpd = fb + 8 * n;
+  mt.tmpz = fb + 9 * n; mt.rho = fb + 10 * n;
+  mt.cl = ib; mt.defc = ib + n; mt.rota = ib + 2 * n; mt.rotb = ib + 3 * n; mt.org = ib + 4 * n;
+  mt.tmpc = ib + 5 * n; mt.kcnt = ib + 6 * n;
+  MergeDesc* dmd = (MergeDesc*)w.zhat.ensure<int>((int64_t)3 * n + 16);
+  T* M = w.M.ensure<T>(nn);
+
+  std::vector<int> posm(n);
+  for (size_t L = 0; L < levels.size(); ++L) {
+    const auto& lv = levels[L];
+    const int nm = (int)lv.size();
+    std::fill(posm.begin(), posm.end(), -1);
+    for (int b = 0; b < nm; ++b)
+      for (int i = 0; i < lv[b].m; ++i) posm[lv[b].s + i] = b;
+    MSQRT_HIP(hipMemcpyAsync(dmd, lv.data(), sizeof(MergeDesc) * nm, hipMemcpyHostToDevice, st));
+    MSQRT_HIP(hipMemcpyAsync(pos_merge, posm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(merge_prep_kernel<T>, dim3(nm), dim3(256), 0, st, dmd, ee, lamA, Za, n, mt);
+    MSQRT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(merge_rot_kernel<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, dmd, n,
+                       pos_merge, mt, Za, n);
+    MSQRT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(secular_kernel, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, n);
+    MSQRT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lowner_kernel, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, dmd, pos_merge, mt, n);
+    MSQRT_LAUNCH_CHECK();
+    MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn, st));
+    hipLaunchKernelGGL(vectors_kernel<T>, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);
+    MSQRT_LAUNCH_CHECK();
+    for (int b = 0; b < nm; ++b) {
+      const MergeDesc& g = lv[b];
+      const T* Ablk = Za + g.s + (int64_t)g.s * n;
+      T* Cblk = Zb + g.s + (int64_t)g.s * n;
+      const T* Mb = M + (int64_t)g.s * n;
+      if (std::is_same<T, float>::value)
+        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, 0, (const float*)Mb,
+                       g.m, 0, (float*)Cblk, n, 0, 1.f, 0.f, 1, false);
+      else
+        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, 0, (const double*)Mb,
+                       g.m, 0, (double*)Cblk, n, 0, 1.0, 0.0, 1, false);
+    }
+    for (auto& pr : carried[L]) {
+      hipLaunchKernelGGL(copy_block<T>, dim3((unsigned)pr.second), dim3(64), 0, st, n, pr.first,
+                         pr.second, (const T*)Za, Zb, (const double*)lamA, lamB);
+      MSQRT_LAUNCH_CHECK();
+    }
+    std::swap(Za, Zb);
+    std::swap(lamA, lamB);
+  }
+  if (Za != Z) {
+    hipLaunchKernelGGL(copy_mat<T>, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, n, (const T*)Za, Z);
+    MSQRT_LAUNCH_CHECK();
+  }
+  if (lamA != lam) MSQRT_HIP(hipMemcpyAsync(lam, lamA, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+}
+
+template void stedc<float>(hipStream_t, int, const float*, const float*, double*, float*, StedcWork&);
+template void stedc<double>(hipStream_t, int, const double*, const double*, double*, double*, StedcWork&);
+
+}  // namespace msqrt
