@@ -1,0 +1,173 @@
+"""Benchmark: principal square roots per second of a real SPD matrix, n=4096,
+kappa=1e4, with the mixed-precision method (float32 spectral decomposition +
+float64 approximate-Newton refinement, Alg. 3) beside the plain float64 Schur
+method on the same GPU.  Every timed call is a complete msqrt_sqrtm (factor,
+X_0, refinement, final residual check to 1e-13) with A already in HBM.
+
+Prints one JSON line (see the measurement section of the design doc).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"gemm_f32": (157.3, "TFLOP/s"), "gemm_f64": (78.6, "TFLOP/s")}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=4096)
+    p.add_argument("--kappa", type=float, default=1e4)
+    p.add_argument("--seed", type=int, default=3)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-fp64", action="store_true", help="skip the fixed-FP64 comparator")
+    p.add_argument("--cpu-n", type=int, default=1536)
+    return p.parse_args()
+
+
+def time_solves(msq, torch, a, prec, steps, warmup):
+    x = torch.empty_like(a)
+    info = None
+    for _ in range(warmup):
+        _, info = msq.sqrtm(a, prec=prec, tol=1e-13, fallback=False, out=x)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = msq.sqrtm(a, prec=prec, tol=1e-13, fallback=False, out=x)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0), x, infos
+
+
+def gpu_relres(torch, x, a):
+    r = torch.linalg.matrix_norm(x @ x - a) / torch.linalg.matrix_norm(a)
+    return float(r)
+
+
+def cpu_baseline(n_cpu, n, kappa, seed):
+    import oracle
+    import workloads as W
+    a, _, _ = W.spd(n_cpu, kappa, seed)
+    t0 = time.perf_counter()
+    oracle.sqrtm_spd(a)
+    dt = time.perf_counter() - t0
+    scale = (n / n_cpu) ** 3
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle float64 SPD route (Householder tridiagonalisation + implicit QL, "
+                   f"X = Q diag(lam^1/2) Q^T), one solve at n={n_cpu}, kappa={kappa:g}, "
+                   f"{dt:.2f} s, scaled by (n/{n_cpu})^3 to n={n}"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2607_12430_amd as msq
+    from paper_2607_12430_amd import _lib
+    import workloads as W
+
+    n, kappa = args.n, args.kappa
+    a_h, _, _ = W.spd(n, kappa, args.seed)
+    a = torch.from_numpy(np.ascontiguousarray(a_h)).cuda()
+    torch.cuda.synchronize()
+
+    # ---- mixed precision (timed; kernel-class timing on)
+    _lib.profile_enable(False)
+    for _ in range(args.warmup):
+        msq.sqrtm(a, prec="fp32", tol=1e-13, fallback=False)
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    dt_mixed, x, infos = time_solves(msq, torch, a, "fp32", args.steps, 0)
+    stats = _lib.profile_stats()
+    _lib.profile_enable(False)
+    rr_mixed = gpu_relres(torch, x, a)
+    steps_mixed = infos[-1]["steps"]
+    phases = infos[-1]["t_ms"]
+
+    # ---- fixed FP64 Schur method on the same GPU
+    fp64 = None
+    if not args.no_fp64:
+        dt64, x64, infos64 = time_solves(msq, torch, a, "fp64", args.steps, args.warmup)
+        fp64 = {"solves_per_s": args.steps / dt64, "ms_per_solve": 1e3 * dt64 / args.steps,
+                "relres": gpu_relres(torch, x64, a), "steps": infos64[-1]["steps"],
+                "phases_ms": {k: round(v, 3) for k, v in infos64[-1]["t_ms"].items()}}
+
+    # ---- roofline of the dominant kernel class (live HIP-event timing)
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    cls, st = dom
+    if cls.startswith("gemm"):
+        peak, unit = PEAK[cls]
+        achieved = st["flops"] / (st["ms"] * 1e-3) / 1e12
+        bound = "mfma"
+    else:
+        peak, unit = HBM_PEAK_GBS, "GB/s"
+        achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+        bound = "hbm"
+    roof = {"bound": bound, "kernel": cls, "achieved": round(achieved, 3), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+            "launches_per_solve": st["launches"] / args.steps,
+            "avg_launch_ms": round(st["ms"] / st["launches"], 5)}
+    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in stats.items()}
+    gemm32 = stats.get("gemm_f32")
+    gemm64 = stats.get("gemm_f64")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_n, n, kappa, args.seed)
+
+    value = args.steps / dt_mixed
+    out = {
+        "metric": "sqrtm solves/s at n=4096, mixed vs FP64 Schur, relres<=1e-13; % matrix peak",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt_mixed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factor+transforms, f64 residual+update",
+        "data": "synthetic",
+        "config": {"workload": f"spd_n{n}_kappa{kappa:g}", "n": n, "kappa": kappa,
+                   "seed": args.seed, "tol": 1e-13, "eigs": "log-uniform, endpoints pinned"},
+        "relres": rr_mixed,
+        "refinement_steps": steps_mixed,
+        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "kernel_ms_per_solve": kernel_ms,
+        "fp64_schur": fp64,
+        "speedup_vs_fp64": (round(value / fp64["solves_per_s"], 4) if fp64 else None),
+        "gemm_f32_tflops": (round(gemm32["flops"] / (gemm32["ms"] * 1e-3) / 1e12, 2) if gemm32 else None),
+        "gemm_f64_tflops": (round(gemm64["flops"] / (gemm64["ms"] * 1e-3) / 1e12, 2) if gemm64 else None),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,20 @@ const char* msqrt_status_string(msqrt_status s);
 /* Last error message recorded by the calling thread (static storage). */
 const char* msqrt_last_error(void);
 
+/* Kernel-class timing for measurement tools.  msqrt_profile_enable(1) clears
+ * the counters and starts recording a pair of hipEvents on the launch stream
+ * around every launch of an instrumented kernel class ("gemm_f32",
+ * "gemm_f64", "sytrd_panel_f32", "sytrd_panel_f64", ...), together with the
+ * launch's algorithmic flop and byte counts; 0 stops recording.
+ * msqrt_profile_query returns 0 and the accumulated launches, time (ms),
+ * flops and bytes of one class (1 if the class was never launched).
+ * msqrt_profile_list writes the comma-separated class names into buf and
+ * returns the full length.  Querying waits for the recorded events. */
+void msqrt_profile_enable(int on);
+int msqrt_profile_query(const char* kernel_class, int64_t* launches, double* total_ms,
+                        double* flops, double* bytes);
+int msqrt_profile_list(char* buf, int buflen);
+
 /* Test hook: builds a factor from caller-provided Q (n x n) and S (length n for
  * HPD, n x n upper triangular for GENERAL), column-major, in the precision
  * `prec` (FP32 buffers hold float / complex64, FP64 buffers double /

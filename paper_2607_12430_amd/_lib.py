@@ -31,6 +31,7 @@ EXPORTED = [
     "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_sqrtm",
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_stedc",
+    "msqrt_profile_enable", "msqrt_profile_query", "msqrt_profile_list",
 ]
 
 
@@ -103,6 +104,13 @@ def lib():
     L.msqrt_last_error.restype = ctypes.c_char_p
     L.msqrt_factor_wrap.argtypes = [ci, ci, ci, i64, vp, vp, ci, ctypes.POINTER(vp)]
     L.msqrt_factor_export.argtypes = [vp, vp, vp, ctypes.POINTER(ci)]
+    L.msqrt_profile_enable.argtypes = [ci]
+    L.msqrt_profile_enable.restype = None
+    L.msqrt_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(cd),
+                                      ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    L.msqrt_profile_query.restype = ci
+    L.msqrt_profile_list.argtypes = [ctypes.c_char_p, ci]
+    L.msqrt_profile_list.restype = ci
     L.msqrt_test_sytrd.argtypes = [ci, i64, vp, vp, vp, vp]
     L.msqrt_test_stedc.argtypes = [ci, i64, vp, vp, vp, vp]
     for name in ("msqrt_factor", "msqrt_refine", "msqrt_sqrtm", "msqrt_sqrtm_backward",
@@ -125,3 +133,22 @@ def check(status, where, allow=()):
     if status != OK and status not in allow:
         raise MsqrtError(status, where)
     return status
+
+
+def profile_enable(on: bool):
+    lib().msqrt_profile_enable(1 if on else 0)
+
+
+def profile_stats():
+    """{kernel_class: dict(launches, ms, flops, bytes)} recorded since enable."""
+    L = lib()
+    buf = ctypes.create_string_buffer(4096)
+    L.msqrt_profile_list(buf, 4096)
+    out = {}
+    for cls in filter(None, buf.value.decode().split(",")):
+        n = ctypes.c_int64(0)
+        ms, fl, by = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        if L.msqrt_profile_query(cls.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                 ctypes.byref(by)) == 0:
+            out[cls] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out

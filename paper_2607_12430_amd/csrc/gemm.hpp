@@ -15,6 +15,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace msqrt {
 
@@ -326,11 +327,19 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
                  const Epi& epi, double* partials, int batch) {
   if (s.M <= 0 || s.N <= 0 || batch <= 0) return;
   dim3 grid(8 * s.per_xcd, batch), block(GTHREADS);
+  const int tok = prof_begin(st);
   if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   else hipLaunchKernelGGL((gemm_kernel<T, true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   MSQRT_LAUNCH_CHECK();
+  if (tok >= 0) {
+    // algorithmic work: 2 M N K per entry, or the lower triangle only for
+    // symmetric outputs
+    const double outs = s.tri ? 0.5 * (double)s.N * (s.N + 1) : (double)s.M * s.N;
+    const double kk = (double)s.K * (batch - 1) + s.K_last;
+    prof_end(tok, st, sizeof(T) == 4 ? "gemm_f32" : "gemm_f64", 2.0 * outs * kk, 0.0);
+  }
 }
 
 }  // namespace msqrt

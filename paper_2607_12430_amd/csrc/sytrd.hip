@@ -19,14 +19,15 @@
 // After the panel: A22 -= [V W] [W V]^T on the MFMA GEMM (symmetric output).
 #include "gemm.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 #include "tridiag.hpp"
 
 namespace msqrt {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kMaxTs = 1024;  // max tile size handled by one workgroup
+constexpr int kThreads = 1024;
+constexpr int kMaxTs = 256;  // max tile size handled by one workgroup
 constexpr int kNbMax = 32;
 
 // Two-level grid barrier: 16 workgroups per group counter, then one top
@@ -77,11 +78,11 @@ __device__ inline void grid_barrier(unsigned* bar, int G) {
 template <typename T>
 struct PanelArgs {
   int n, p, nb;  // matrix size, first column of the panel, panel width
-  int TR;        // tiles per dimension; G = TR * TR workgroups
-  int r0, ts;    // tile grid origin (p + 1) and tile size
+  int TR;        // tiles per dimension; G = TR (TR + 1) / 2 workgroups (lower triangle)
+  int r0, ts;    // tile grid origin (p + 1) and tile size (<= kMaxTs)
   T* A;          // n x n, ld n, full symmetric storage
-  T* VW;         // n x 2nb: [V W]
-  T* WV;         // n x 2nb: [W V]
+  T* VW;         // n x 2 kNbMax: [V W]
+  T* WV;         // n x 2 kNbMax: [W V]
   T* d;
   T* e;
   T* tau;
@@ -91,32 +92,116 @@ struct PanelArgs {
   unsigned* bar;
 };
 
+// Tile product of one lower-triangular tile (I x K, I >= K) with the current
+// u: zI = A(I, K) uK (all tiles) and zK = A(I, K)^T uI (off-diagonal tiles),
+// masked to rows/columns >= jmin.  Wave w takes columns [16w, 16w+16) of the
+// tile, lane l rows l, l+64, ...; all loads of a 16-column chunk are issued
+// before any is used, so every wave of the workgroup has its whole share of
+// the tile in flight at once.  Row partials stay in zi (NP passes of RPL rows
+// per lane); column partials are reduced over the wave and added to zK.
+template <typename T, int RPL, int NP>
+__device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0,
+                                    int nK, int jmin, bool offdiag, const T* uI, const T* uK,
+                                    T (&zi)[NP][RPL], T* zK, int tid) {
+  constexpr int CW = sizeof(T) == 4 ? 16 : 8;            // columns per chunk
+  constexpr int NCH = kMaxTs / (CW * (kThreads / kWave));  // chunks per wave
+  const int wave = tid / kWave, lane = tid % kWave;
+#pragma unroll
+  for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) zi[ps][q] = T(0);
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int cb = (ch * (kThreads / kWave) + wave) * CW;
+    if (cb >= nK) break;
+    // Columns below jmin or past the tile are skipped (wave-uniform test).
+    const int cfirst = max(cb, jmin - K0);
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) {
+      const int rb = ps * RPL * kWave;
+      T v[CW][RPL];
+      int rowoff[RPL];
+      bool rowok[RPL];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = rb + lane + q * kWave;
+        rowok[q] = r < nI && (I0 + r) >= jmin;
+        rowoff[q] = rowok[q] ? I0 + r : I0;
+      }
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const int k = cb + c;
+        const bool colok = k < nK && k >= cfirst;
+        const T* colp = A + (int64_t)(K0 + (colok ? k : cb)) * ld;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) v[c][q] = (colok && rowok[q]) ? colp[rowoff[q]] : T(0);
+      }
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const T uk = (cb + c < nK) ? uK[cb + c] : T(0);
+        T zk = T(0);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = rb + lane + q * kWave;
+          zi[ps][q] += v[c][q] * uk;
+          if (offdiag) zk += v[c][q] * ((r < nI) ? uI[r] : T(0));
+        }
+        if (offdiag) {
+          zk = wave_sum(zk);
+          if (lane == 0 && cb + c < nK) zK[cb + c] += zk;
+        }
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
-  const int n = a.n, nb = a.nb, TR = a.TR, G = TR * TR;
-  const int blk = blockIdx.x, bi = blk % TR, bj = blk / TR;
-  const int I0 = a.r0 + bi * a.ts, I1 = min(n, I0 + a.ts);
-  const int K0 = a.r0 + bj * a.ts, K1 = min(n, K0 + a.ts);
+  constexpr int RPL = sizeof(T) == 4 ? 4 : 2;
+  const int n = a.n, nb = a.nb, TR = a.TR, G = TR * (TR + 1) / 2;
+  const int blk = blockIdx.x;
+  int bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+  while (bi * (bi + 1) / 2 > blk) --bi;
+  const int bj = blk - bi * (bi + 1) / 2;
+  const bool diag = bi == bj, offdiag = !diag;
+  const int I0 = a.r0 + bi * a.ts, I1 = max(I0, min(n, I0 + a.ts));
+  const int K0 = a.r0 + bj * a.ts, K1 = max(K0, min(n, K0 + a.ts));
+  const int nI = I1 - I0, nK = K1 - K0;
   const int tid = threadIdx.x;
   const int64_t ld = n;
   const int p = a.p;
   T* A = a.A;
 
-  __shared__ T uI[kMaxTs], uK[kMaxTs];
-  __shared__ T vI[kMaxTs], wI[kMaxTs], vK[kMaxTs], wK[kMaxTs];  // newest column's v, w
-  // Pivot rows r = p+1+q (q < nb) of V and W for all panel columns, and their
-  // u for the current column: every workgroup keeps its own copy, so no value
-  // written by another workgroup in the current phase is ever read.
+  // Panel columns of this workgroup's rows: PVI[t][r] = V(I0 + r, t), etc.
+  extern __shared__ unsigned char smem_raw[];
+  T* PVI = reinterpret_cast<T*>(smem_raw);
+  T* PWI = PVI + nb * kMaxTs;
+  T* PVK = PWI + nb * kMaxTs;
+  T* PWK = PVK + nb * kMaxTs;
+  __shared__ T uI[kMaxTs], uK[kMaxTs], zKs[kMaxTs];
+  // zred (row partials of the tile product, before the barrier) and the
+  // gathered partial sums (after it) share one buffer.
+  constexpr int kZredBytes = (kThreads / kWave / 2) * kMaxTs * (int)sizeof(T);
+  constexpr int kGathBytes = (3 * 136 + 16 * 2 * kNbMax) * 8;
+  __shared__ double scratch[(kZredBytes > kGathBytes ? kZredBytes : kGathBytes) / 8];
+  T* zred = reinterpret_cast<T*>(scratch);
+  double (*spl)[136] = reinterpret_cast<double (*)[136]>(scratch);
+  double* vpl = scratch + 3 * 136;
+  // Pivot rows r = p+1+q (q < nb) of V and W and their u for the current
+  // column: every workgroup keeps its own copy, so no value written by another
+  // workgroup in the current phase is ever read.
   __shared__ T PV[kNbMax][kNbMax + 1], PW[kNbMax][kNbMax + 1], PU[kNbMax];
   __shared__ T VTv[kNbMax], WTv[kNbMax];
   __shared__ double red[kThreads / kWave];
   __shared__ double sc[8];
+  __shared__ T acI[kMaxTs], acK[kMaxTs], acP[kNbMax];  // A(:, j+1) on rows I, K, pivots
+  __shared__ T yzI[kMaxTs], yzK[kMaxTs], yzP[kNbMax];  // (A22 u) on rows I, K, pivots
 
   // ---- prologue: u for the first column of the panel
   {
     const int j = p;
-    for (int r = tid; r < I1 - I0; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (int64_t)j * ld] : T(0);
-    for (int r = tid; r < K1 - K0; r += kThreads) uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] : T(0);
+    for (int r = tid; r < nI; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (int64_t)j * ld] : T(0);
+    for (int r = tid; r < nK; r += kThreads) uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] : T(0);
     for (int q = tid; q < nb; q += kThreads) PU[q] = (p + 1 + q < n) ? A[p + 1 + q + (int64_t)j * ld] : T(0);
   }
   __syncthreads();
@@ -124,38 +209,65 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   for (int jj = 0; jj < nb; ++jj) {
     const int j = p + jj;
     const int buf = jj & 1;
-    // ---- tile product z_I = A(I, K) u_K and partial u_I^T z_I
-    double s_uAu = 0.0;
+    // ---- column j+1 of A (a1 for the product, base of the next u), issued
+    // together with the tile loads
+    T acv_i = T(0), acv_k = T(0), acv_p = T(0);
+    if (tid < nI) acv_i = A[I0 + tid + (int64_t)(j + 1) * ld];
+    if (tid < nK) acv_k = A[K0 + tid + (int64_t)(j + 1) * ld];
+    if (tid < nb && p + 1 + tid < n) acv_p = A[p + 1 + tid + (int64_t)(j + 1) * ld];
+    // ---- tile product; the 16 waves' row partials are folded onto 8 slots
+    for (int r = tid; r < nK; r += kThreads) zKs[r] = T(0);
+    __syncthreads();
     {
-      const int kb = max(K0, j + 1);
-      for (int r = tid; r < I1 - I0; r += kThreads) {
-        const int i = I0 + r;
-        T z = T(0);
-        if (i >= j + 1) {
-          const T* col = A + i;
-#pragma unroll 8
-          for (int k = kb; k < K1; ++k) z += col[(int64_t)k * ld] * uK[k - K0];
-        }
-        a.ypart[((int64_t)buf * TR + bj) * n + i] = z;
-        s_uAu += (double)uI[r] * (double)z;
+      constexpr int NP = kMaxTs / (RPL * kWave);
+      T zi[NP][RPL];
+      tile_product<T, RPL, NP>(A, ld, I0, nI, K0, nK, j + 1, offdiag, uI, uK, zi, zKs, tid);
+      const int wave = tid / kWave, lane = tid % kWave;
+      if (wave < 8) {
+#pragma unroll
+        for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) zred[wave * kMaxTs + ps * RPL * kWave + lane + q * kWave] = zi[ps][q];
       }
+      __syncthreads();
+      if (wave >= 8) {
+#pragma unroll
+        for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) zred[(wave - 8) * kMaxTs + ps * RPL * kWave + lane + q * kWave] += zi[ps][q];
+      }
+      if (tid < nI) acI[tid] = acv_i;
+      if (tid < nK) acK[tid] = acv_k;
+      if (tid < nb) acP[tid] = acv_p;
+      __syncthreads();
     }
+    // zI = sum over the 8 slots; publish partial products and u^T A u
+    double s_uAu = 0.0;
+    for (int r = tid; r < nI; r += kThreads) {
+      T z = T(0);
+#pragma unroll
+      for (int w = 0; w < 8; ++w) z += zred[w * kMaxTs + r];
+      a.ypart[((int64_t)buf * TR + bj) * n + I0 + r] = z;
+      s_uAu += (double)uI[r] * (double)z;
+    }
+    if (offdiag)
+      for (int r = tid; r < nK; r += kThreads) a.ypart[((int64_t)buf * TR + bi) * n + K0 + r] = zKs[r];
     s_uAu = block_sum(s_uAu, red);
-    // ---- row-owner partials (bj == 0): ||u(2:)||^2, u^T a1, V^T u, W^T u
+    if (offdiag) s_uAu *= 2.0;
+    // ---- row-owner partials (diagonal tiles): ||u(2:)||^2, u^T a1, V^T u, W^T u
     double s_sig = 0.0, s_ua1 = 0.0;
-    if (bj == 0) {
-      for (int r = tid; r < I1 - I0; r += kThreads) {
+    if (diag) {
+      for (int r = tid; r < nI; r += kThreads) {
         const int i = I0 + r;
         const double u = (double)uI[r];
         if (i >= j + 2) s_sig += u * u;
-        if (i >= j + 1) s_ua1 += u * (double)A[i + (int64_t)(j + 1) * ld];
+        if (i >= j + 1) s_ua1 += u * (double)acI[r];
       }
-      // 2 jj dot products over the rows of I: wave w takes columns w, w+4, ...
       const int wave = tid / kWave, lane = tid % kWave;
       for (int c = wave; c < 2 * jj; c += kThreads / kWave) {
-        const int col = c < jj ? c : nb + (c - jj);
+        const T* col = c < jj ? (PVI + c * kMaxTs) : (PWI + (c - jj) * kMaxTs);
         double s = 0.0;
-        for (int r = lane; r < I1 - I0; r += kWave) s += (double)a.VW[I0 + r + (int64_t)col * ld] * (double)uI[r];
+        for (int r = lane; r < nI; r += kWave) s += (double)col[r] * (double)uI[r];
         s = wave_sum(s);
         if (lane == 0) a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c] = s;
       }
@@ -170,38 +282,75 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
       // before the barrier: owners overwrite column j right after it.
       double dj = (double)A[j + (int64_t)j * ld];
-      if (jj > 0)
-        for (int t = 0; t < jj; ++t) dj -= 2.0 * (double)PV[jj - 1][t] * (double)PW[jj - 1][t];
+      for (int t = 0; t < jj; ++t) dj -= 2.0 * (double)PV[jj - 1][t] * (double)PW[jj - 1][t];
       sc[0] = dj;
       sc[3] = (double)PU[jj];
     }
 
     grid_barrier(a.bar, G);
 
-    // ---- reflector scalars (every workgroup, redundantly)
-    if (tid == 0) {
+    // ---- gather the partial sums of all workgroups into LDS in parallel
+    // (one load per thread), then reduce them there.
+    for (int b = tid; b < G; b += kThreads) {
+      const double* spb = a.sp + ((int64_t)buf * G + b) * 4;
+      spl[0][b] = spb[0];
+      spl[1][b] = spb[1];
+      spl[2][b] = spb[2];
+    }
+    for (int x = tid; x < TR * 2 * jj; x += kThreads) {
+      const int b = x / (2 * jj), c2 = x % (2 * jj);
+      vpl[x] = a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + c2];
+    }
+    // (A22 u)_i = sum of the TR partial products of row i, for the rows of I,
+    // K and the pivot rows: all loads of a row issued together.
+    {
+      auto rowsum = [&](int i) -> T {
+        T yv[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) yv[b] = (b < TR) ? a.ypart[((int64_t)buf * TR + b) * n + i] : T(0);
+        T z = T(0);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) z += yv[b];
+        return z;
+      };
+      if (tid < nI) yzI[tid] = (I0 + tid >= j + 1) ? rowsum(I0 + tid) : T(0);
+      if (offdiag && tid < nK) yzK[tid] = (K0 + tid >= j + 1) ? rowsum(K0 + tid) : T(0);
+      if (tid >= kThreads - kNbMax) {
+        const int q = tid - (kThreads - kNbMax);
+        const int r = p + 1 + q;
+        yzP[q] = (q < nb && r >= j + 1 && r < n) ? rowsum(r) : T(0);
+      }
+    }
+    __syncthreads();
+    if (tid < kWave) {
       double uAu = 0.0, sig = 0.0, ua1 = 0.0;
-      for (int b = 0; b < G; ++b) uAu += a.sp[((int64_t)buf * G + b) * 4 + 0];
-      for (int b = 0; b < TR; ++b) {
-        sig += a.sp[((int64_t)buf * G + b) * 4 + 1];
-        ua1 += a.sp[((int64_t)buf * G + b) * 4 + 2];
+      for (int b = tid; b < G; b += kWave) uAu += spl[0][b];
+      for (int t = tid; t < TR; t += kWave) {
+        const int b = t * (t + 1) / 2 + t;  // diagonal tile (t, t)
+        sig += spl[1][b];
+        ua1 += spl[2][b];
       }
-      const double alpha = sc[3];
-      double beta, tau, c;
-      if (sig == 0.0) {
-        beta = alpha; tau = 0.0; c = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-        tau = (beta - alpha) / beta;
-        c = 1.0 / (alpha - beta);
+      uAu = wave_sum(uAu);
+      sig = wave_sum(sig);
+      ua1 = wave_sum(ua1);
+      if (tid == 0) {
+        const double alpha = sc[3];
+        double beta, tau, c;
+        if (sig == 0.0) {
+          beta = alpha; tau = 0.0; c = 0.0;
+        } else {
+          beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+          tau = (beta - alpha) / beta;
+          c = 1.0 / (alpha - beta);
+        }
+        if (blk == 0) {
+          a.d[j] = (T)sc[0];
+          a.e[j] = (T)beta;
+          a.tau[j] = (T)tau;
+        }
+        sc[0] = uAu; sc[1] = sig; sc[2] = ua1;
+        sc[4] = beta; sc[5] = tau; sc[6] = c;
       }
-      if (blk == 0) {
-        a.d[j] = (T)sc[0];
-        a.e[j] = (T)beta;
-        a.tau[j] = (T)tau;
-      }
-      sc[0] = uAu; sc[1] = sig; sc[2] = ua1;
-      sc[4] = beta; sc[5] = tau; sc[6] = c;
     }
     __syncthreads();
     const double beta = sc[4], tau = sc[5], c = sc[6];
@@ -209,15 +358,15 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     for (int t = tid; t < jj; t += kThreads) {
       double vtu = 0.0, wtu = 0.0;
       for (int b = 0; b < TR; ++b) {
-        vtu += a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + t];
-        wtu += a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + jj + t];
+        vtu += vpl[b * 2 * jj + t];
+        wtu += vpl[b * 2 * jj + jj + t];
       }
       VTv[t] = (T)(c * (vtu - beta * (double)PV[jj][t]));
       WTv[t] = (T)(c * (wtu - beta * (double)PW[jj][t]));
     }
     __syncthreads();
     if (tid == 0) {
-      const double a11 = (double)A[j + 1 + (int64_t)(j + 1) * ld];
+      const double a11 = (double)acP[jj];
       const double vAv = c * c * (sc[0] - 2.0 * beta * sc[2] + beta * beta * a11);
       double vw = 0.0;
       for (int t = 0; t < jj; ++t) vw += (double)VTv[t] * (double)WTv[t];
@@ -227,19 +376,16 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     const double wv = sc[7];
     const bool zero_refl = (sc[1] == 0.0);
 
-    // y_i, v_i, w_i of the current column for a row i >= j+1 (u_i given).
-    auto finish_row = [&](int i, T ui, T& vi, T& wi) {
+    // y_i, v_i, w_i of the current column for a row i >= j+1, given u_i,
+    // (A22 u)_i, a1_i = A(i, j+1) and the row's panel coefficients.
+    auto finish = [&](int i, T ui, T yzi, T a1i, auto Vt, auto Wt, T& vi, T& wi) {
       if (zero_refl) {
         vi = (i == j + 1) ? T(1) : T(0);
         wi = T(0);
         return;
       }
-      double yz = 0.0;
-      for (int b = 0; b < TR; ++b) yz += (double)a.ypart[((int64_t)buf * TR + b) * n + i];
-      double y = c * (yz - beta * (double)A[i + (int64_t)(j + 1) * ld]);
-      for (int t = 0; t < jj; ++t)
-        y -= (double)a.VW[i + (int64_t)t * ld] * (double)WTv[t] +
-             (double)a.VW[i + (int64_t)(nb + t) * ld] * (double)VTv[t];
+      double y = c * ((double)yzi - beta * (double)a1i);
+      for (int t = 0; t < jj; ++t) y -= (double)Vt(t) * (double)WTv[t] + (double)Wt(t) * (double)VTv[t];
       const double v = (i == j + 1) ? 1.0 : c * (double)ui;
       vi = (T)v;
       wi = (T)(tau * y - 0.5 * tau * wv * v);
@@ -249,56 +395,67 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     for (int q = jj + tid; q < nb; q += kThreads) {
       const int r = p + 1 + q;
       T vi = T(0), wi = T(0);
-      if (r < n) finish_row(r, PU[q], vi, wi);
+      if (r < n) finish(r, PU[q], yzP[q], acP[q], [&](int t) { return PV[q][t]; }, [&](int t) { return PW[q][t]; }, vi, wi);
       PV[q][jj] = vi;
       PW[q][jj] = wi;
     }
-    // Rows of I and K; owners (bj == 0) publish V, W and the explicit
-    // reflector column A(:, j).
-    for (int r = tid; r < I1 - I0; r += kThreads) {
+    // Rows of I (and K); the diagonal tile's workgroup owns its rows and
+    // publishes V, W and the explicit reflector column A(:, j).
+    for (int r = tid; r < nI; r += kThreads) {
       const int i = I0 + r;
       T vi = T(0), wi = T(0);
-      if (i >= j + 1) finish_row(i, uI[r], vi, wi);
-      vI[r] = vi;
-      wI[r] = wi;
-      if (bj == 0) {
+      if (i >= j + 1)
+        finish(i, uI[r], yzI[r], acI[r], [&](int t) { return PVI[t * kMaxTs + r]; }, [&](int t) { return PWI[t * kMaxTs + r]; }, vi, wi);
+      PVI[jj * kMaxTs + r] = vi;
+      PWI[jj * kMaxTs + r] = wi;
+      if (diag) {
         a.VW[i + (int64_t)jj * ld] = vi;
-        a.VW[i + (int64_t)(nb + jj) * ld] = wi;
+        a.VW[i + (int64_t)(kNbMax + jj) * ld] = wi;
         a.WV[i + (int64_t)jj * ld] = wi;
-        a.WV[i + (int64_t)(nb + jj) * ld] = vi;
+        a.WV[i + (int64_t)(kNbMax + jj) * ld] = vi;
         A[i + (int64_t)j * ld] = vi;
       }
     }
-    for (int r = tid; r < K1 - K0; r += kThreads) {
-      const int i = K0 + r;
-      T vi = T(0), wi = T(0);
-      if (i >= j + 1) finish_row(i, uK[r], vi, wi);
-      vK[r] = vi;
-      wK[r] = wi;
-    }
+    if (offdiag)
+      for (int r = tid; r < nK; r += kThreads) {
+        const int i = K0 + r;
+        T vi = T(0), wi = T(0);
+        if (i >= j + 1)
+          finish(i, uK[r], yzK[r], acK[r], [&](int t) { return PVK[t * kMaxTs + r]; }, [&](int t) { return PWK[t * kMaxTs + r]; }, vi, wi);
+        PVK[jj * kMaxTs + r] = vi;
+        PWK[jj * kMaxTs + r] = wi;
+      }
     __syncthreads();
     if (jj + 1 == nb) break;
     // ---- next column jn = j+1: u_i = A(i, jn) - sum_{t <= jj} V(i,t) W(jn,t) + W(i,t) V(jn,t)
     // with row jn's coefficients = pivot row jj.
     const int jn = j + 1;
-    auto upd = [&](int i, T vnew, T wnew) -> T {
-      T u = A[i + (int64_t)jn * ld];
-      for (int t = 0; t < jj; ++t)
-        u -= a.VW[i + (int64_t)t * ld] * PW[jj][t] + a.VW[i + (int64_t)(nb + t) * ld] * PV[jj][t];
-      return u - (vnew * PW[jj][jj] + wnew * PV[jj][jj]);
-    };
-    for (int r = tid; r < I1 - I0; r += kThreads) {
+    for (int r = tid; r < nI; r += kThreads) {
       const int i = I0 + r;
-      uI[r] = (i >= jn + 1) ? upd(i, vI[r], wI[r]) : T(0);
+      T u = T(0);
+      if (i >= jn + 1) {
+        u = acI[r];
+        for (int t = 0; t <= jj; ++t) u -= PVI[t * kMaxTs + r] * PW[jj][t] + PWI[t * kMaxTs + r] * PV[jj][t];
+      }
+      uI[r] = u;
     }
-    for (int r = tid; r < K1 - K0; r += kThreads) {
-      const int i = K0 + r;
-      uK[r] = (i >= jn + 1) ? upd(i, vK[r], wK[r]) : T(0);
+    if (offdiag) {
+      for (int r = tid; r < nK; r += kThreads) {
+        const int i = K0 + r;
+        T u = T(0);
+        if (i >= jn + 1) {
+          u = acK[r];
+          for (int t = 0; t <= jj; ++t) u -= PVK[t * kMaxTs + r] * PW[jj][t] + PWK[t * kMaxTs + r] * PV[jj][t];
+        }
+        uK[r] = u;
+      }
+    } else {
+      for (int r = tid; r < nK; r += kThreads) uK[r] = uI[r];  // same rows (written above by the same thread)
     }
     for (int q = jj + 1 + tid; q < nb; q += kThreads) {
       const int r = p + 1 + q;
       if (r >= n) { PU[q] = T(0); continue; }
-      T u = A[r + (int64_t)jn * ld];
+      T u = acP[q];
       for (int t = 0; t <= jj; ++t) u -= PV[q][t] * PW[jj][t] + PW[q][t] * PV[jj][t];
       PU[q] = u;
     }
@@ -322,9 +479,20 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
     MSQRT_LAUNCH_CHECK();
     return;
   }
-  const int nb = kNbMax;
-  T* VW = w.VW.ensure<T>((int64_t)n * 2 * nb);
-  T* WV = w.WV.ensure<T>((int64_t)n * 2 * nb);
+  if (n - 1 > 16 * kMaxTs)
+    throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal reduction supports n <= 4097 in this build"};
+  // Panel width: the LDS cache holds 4 * nb * kMaxTs values (at most 128 KiB).
+  const int lds_budget = sizeof(T) == 4 ? 128 * 1024 : 96 * 1024;
+  const int nb = std::min(kNbMax, (int)(lds_budget / (4 * kMaxTs * (int)sizeof(T))));
+  const size_t dyn_lds = (size_t)4 * nb * kMaxTs * sizeof(T);
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    MSQRT_HIP(hipFuncSetAttribute((const void*)sytrd_panel_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
+    attr_set[sizeof(T) == 8] = true;
+  }
+  T* VW = w.VW.ensure<T>((int64_t)n * 2 * kNbMax);
+  T* WV = w.WV.ensure<T>((int64_t)n * 2 * kNbMax);
   T* ypart = w.ypart.ensure<T>((int64_t)2 * 16 * n);
   double* sp = w.sp.ensure<double>((int64_t)2 * 256 * 4);
   double* vp = w.vp.ensure<double>((int64_t)2 * 16 * 2 * kNbMax);
@@ -333,25 +501,37 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
   for (int p = 0; p < n - 1; p += nb) {
     const int nbe = std::min(nb, n - 1 - p);
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
-    const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, 128)));
+    const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
     const int ts = (int)ceil_div(m, TR);
-    if (ts > kMaxTs) throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal reduction supports n <= 16385"};
-    MSQRT_HIP(hipMemsetAsync(VW, 0, sizeof(T) * n * 2 * nb, st));
-    MSQRT_HIP(hipMemsetAsync(WV, 0, sizeof(T) * n * 2 * nb, st));
+    MSQRT_HIP(hipMemsetAsync(VW, 0, sizeof(T) * n * 2 * kNbMax, st));
+    MSQRT_HIP(hipMemsetAsync(WV, 0, sizeof(T) * n * 2 * kNbMax, st));
     PanelArgs<T> pa{n, p, nbe, TR, p + 1, ts, A, VW, WV, d, e, tau, ypart, sp, vp, bar};
     void* args[] = {&pa};
-    MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(TR * TR),
-                                         dim3(kThreads), args, 0, st));
+    const int G = TR * (TR + 1) / 2;
+    const int tok = prof_begin(st);
+    MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G),
+                                         dim3(kThreads), args, dyn_lds, st));
+    if (tok >= 0) {
+      // algorithmic traffic: one read of the symmetric trailing matrix (lower
+      // triangle) per column for its product with the reflector
+      double bytes = 0.0;
+      for (int jj = 0; jj < nbe; ++jj) {
+        const double mj = (double)(n - 1 - (p + jj));
+        bytes += 0.5 * mj * (mj + 1.0) * sizeof(T);
+      }
+      prof_end(tok, st, sizeof(T) == 4 ? "sytrd_panel_f32" : "sytrd_panel_f64",
+               4.0 * 0.5 * (double)m * m * nbe, bytes);
+    }
     // Trailing update A(q:n, q:n) -= [V W] [W V]^T, q = p + nbe.
     const int q = p + nbe;
     if (q < n) {
       const int mt = n - q;
       if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, true, mt, mt, 2 * nb, (const float*)(VW + q), n, 0,
+        gemm_store_f32(st, false, true, mt, mt, 2 * kNbMax, (const float*)(VW + q), n, 0,
                        (const float*)(WV + q), n, 0, (float*)(A + q + (int64_t)q * n), n, 0, -1.f,
                        1.f, 1, true);
       else
-        gemm_store_f64(st, false, true, mt, mt, 2 * nb, (const double*)(VW + q), n, 0,
+        gemm_store_f64(st, false, true, mt, mt, 2 * kNbMax, (const double*)(VW + q), n, 0,
                        (const double*)(WV + q), n, 0, (double*)(A + q + (int64_t)q * n), n, 0,
                        -1.0, 1.0, 1, true);
     }
