@@ -9,25 +9,49 @@ namespace {
 
 constexpr int kEwThreads = 256;
 
-// One block per (column tile of 64 columns, batch).  Each thread walks rows
-// of its column slice; finiteness, exact symmetry (a_ij == a_ji) and the sum
-// of squares are accumulated.
+// One block per 32 x 32 tile (lower triangle of tiles) and batch entry: reads
+// the tile and its mirror with coalesced loads, compares through LDS, and
+// accumulates finiteness, exact symmetry (a_ij == a_ji) and the sum of squares
+// (off-diagonal tiles count both copies).
 __global__ __launch_bounds__(kEwThreads) void validate_kernel(int n, const double* __restrict__ A,
                                                               int64_t lda, int64_t sA,
                                                               int check_sym, int* flags,
                                                               double* partials) {
   __shared__ double red[kEwThreads / kWave];
+  __shared__ double tT[32][33];
   const int b = blockIdx.y;
   const double* a = A + (int64_t)b * sA;
-  const int j0 = blockIdx.x * 64;
+  const int id = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * id + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= id) ++ti;
+  while (ti * (ti + 1) / 2 > id) --ti;
+  const int tj = id - ti * (ti + 1) / 2;
+  const int i0 = ti * 32, j0 = tj * 32;
+  const int lx = threadIdx.x % 32, ly = threadIdx.x / 32;  // 32 x 8
   double ss = 0.0;
   int bad = 0, asym = 0;
-  for (int j = j0; j < min(j0 + 64, n); ++j) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double v = a[i + (int64_t)j * lda];
+  // mirror tile (rows j0.., cols i0..) into LDS, transposed
+  if (ti != tj) {
+    for (int c = ly; c < 32; c += 8) {
+      const int row = j0 + lx, col = i0 + c;
+      tT[c][lx] = (row < n && col < n) ? a[row + (int64_t)col * lda] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int c = ly; c < 32; c += 8) {
+    const int row = i0 + lx, col = j0 + c;
+    if (row < n && col < n) {
+      const double v = a[row + (int64_t)col * lda];
       if (!isfinite(v)) bad = 1;
-      ss += v * v;
-      if (check_sym && i > j && v != a[j + (int64_t)i * lda]) asym = 1;
+      if (ti == tj) {
+        ss += v * v;
+        if (check_sym && row > col && v != a[col + (int64_t)row * lda]) asym = 1;
+      } else {
+        const double w = tT[lx][c];  // a(col, row)
+        if (!isfinite(w)) bad = 1;
+        ss += v * v + w * w;
+        if (check_sym && v != w) asym = 1;
+      }
     }
   }
   ss = block_sum(ss, red);
@@ -84,7 +108,8 @@ __global__ __launch_bounds__(kEwThreads) void scale_inplace_kernel(int n, double
 
 int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, int batch,
                     int check_sym, int* flags, double* partials) {
-  const int nblk = (int)ceil_div(n, 64);
+  const int nt = (int)ceil_div(n, 32);
+  const int nblk = nt * (nt + 1) / 2;
   if (n <= 0) return 0;
   hipLaunchKernelGGL(validate_kernel, dim3(nblk, batch), dim3(kEwThreads), 0, st, n, A, lda, sA,
                      check_sym, flags, partials);

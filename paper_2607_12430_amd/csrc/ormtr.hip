@@ -38,22 +38,23 @@ __global__ __launch_bounds__(kBlk) void larft_kernel(int nb_total, const T* G, c
   const T* g = G + (int64_t)blk * kBlk * kBlk;
   T* t = Tm + (int64_t)blk * kBlk * kBlk;
   const int r = threadIdx.x;
+  // Row r of T lives in LDS (padded to avoid bank conflicts on columns).
+  __shared__ T tl[kBlk][kBlk + 1];
   __shared__ T col[kBlk];
-  for (int c = 0; c < kBlk; ++c) t[r + (int64_t)c * kBlk] = T(0);
+  for (int c = 0; c < kBlk; ++c) tl[r][c] = T(0);
   __syncthreads();
   for (int i = 0; i < nbk; ++i) {
-    const T ti = tau[B + i];
-    // col = G(0:i, i)
     if (r < i) col[r] = g[r + (int64_t)i * kBlk];
     __syncthreads();
     if (r < i) {
       T acc = T(0);
-      for (int c = r; c < i; ++c) acc += t[r + (int64_t)c * kBlk] * col[c];
-      t[r + (int64_t)i * kBlk] = -ti * acc;
+      for (int c = r; c < i; ++c) acc += tl[r][c] * col[c];
+      tl[r][i] = -tau[B + i] * acc;
     }
-    if (r == i) t[i + (int64_t)i * kBlk] = ti;
+    if (r == i) tl[i][i] = tau[B + i];
     __syncthreads();
   }
+  for (int c = 0; c < kBlk; ++c) t[r + (int64_t)c * kBlk] = tl[r][c];
 }
 
 template <typename T>

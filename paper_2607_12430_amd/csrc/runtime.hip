@@ -229,7 +229,8 @@ int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool chec
                          hipStream_t st) {
   const int n = (int)f->n, batch = (int)f->batch;
   int* flags = f->active.ensure<int>(batch);
-  const int nblk = (int)ceil_div(n, 64);
+  const int nt = (int)ceil_div(n, 32);
+  const int nblk = nt * (nt + 1) / 2;
   double* part = f->part.ensure<double>((int64_t)nblk * batch + 64);
   double* rn = f->rnorm.ensure<double>(batch);
   MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));

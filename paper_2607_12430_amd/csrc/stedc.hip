@@ -114,26 +114,24 @@ __global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const i
         nz = sn * e[k + 1];
         nek1 = c * e[k + 1];
       }
-      __syncthreads();
-      if (lane == 0) {
-        if (k > lo) e[k - 1] = ekm;
-        d[k] = nd0;
-        d[k + 1] = nd1;
-        e[k] = ne;
-        if (k + 1 < hi) e[k + 1] = nek1;
-      }
+      // Every lane computed the same scalars and writes them itself, so each
+      // lane's later reads depend only on its own writes (no barrier).
+      if (k > lo) e[k - 1] = ekm;
+      d[k] = nd0;
+      d[k + 1] = nd1;
+      e[k] = ne;
+      if (k + 1 < hi) e[k + 1] = nek1;
       if (lane < L) {
         const double qa = Zl[lane][k], qb = Zl[lane][k + 1];
         Zl[lane][k] = c * qa + sn * qb;
         Zl[lane][k + 1] = -sn * qa + c * qb;
       }
-      __syncthreads();
       x = nx;
       z = nz;
     }
     if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) e[hi - 1] = 0.0;
-    __syncthreads();
   }
+  __syncthreads();
   // Ascending order: rank of eigenvalue c (ties by index).
   __shared__ int rank[kLeaf];
   if (lane < L) {
@@ -191,73 +189,90 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, co
   dmax = block_max(dmax, red);
   zmax = block_max(zmax, red);
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double eps = 1.1102230246251565e-16;
-  const double tol = 8.0 * eps * fmax(dmax, zmax);
-  double* d = mt.tmpd + s;
-  double* z = mt.tmpz + s;
-  int* c = mt.tmpc + s;
-  int k = 0, nd = 0, nr = 0, pj = -1;
-  for (int j = 0; j < m; ++j) {
-    if (rho * fabs(z[j]) <= tol) {
-      mt.defd[s + nd] = d[j];
-      mt.defc[s + nd] = c[j];
-      ++nd;
-      continue;
+  // Stage the sorted (d, z, column) triples in LDS for the sequential scan;
+  // outputs go straight to global memory (stores only).
+  extern __shared__ unsigned char lds_raw[];
+  double* d = reinterpret_cast<double*>(lds_raw);
+  double* z = d + m;
+  int* c = reinterpret_cast<int*>(z + m);
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    d[i] = mt.tmpd[s + i];
+    z[i] = mt.tmpz[s + i];
+    c[i] = mt.tmpc[s + i];
+  }
+  __syncthreads();
+  __shared__ int counts[3];
+  if (threadIdx.x == 0) {
+    const double eps = 1.1102230246251565e-16;
+    const double tol = 8.0 * eps * fmax(dmax, zmax);
+    int k = 0, nd = 0, nr = 0, pj = -1;
+    double dp = 0.0, zp = 0.0;
+    int cp = 0;
+    for (int j = 0; j < m; ++j) {
+      const double dj = d[j], zj = z[j];
+      const int cj = c[j];
+      if (rho * fabs(zj) <= tol) {
+        mt.defd[s + nd] = dj;
+        mt.defc[s + nd] = cj;
+        ++nd;
+        continue;
+      }
+      if (pj < 0) { pj = j; dp = dj; zp = zj; cp = cj; continue; }
+      double sn = zp, cs = zj;
+      const double tau = hypot(cs, sn);
+      const double t = dj - dp;
+      cs /= tau;
+      sn = -sn / tau;
+      if (fabs(t * cs * sn) <= tol) {
+        // Rotate columns pj, j so that z[pj] vanishes; pj deflates.
+        mt.rota[s + nr] = cp;
+        mt.rotb[s + nr] = cj;
+        mt.rotc[s + nr] = cs;
+        mt.rots[s + nr] = sn;
+        ++nr;
+        const double tt = dp * cs * cs + dj * sn * sn;
+        const double dnew = dp * sn * sn + dj * cs * cs;
+        mt.defd[s + nd] = tt;
+        mt.defc[s + nd] = cp;
+        ++nd;
+        pj = j; dp = dnew; zp = tau; cp = cj;
+      } else {
+        mt.dl[s + k] = dp;
+        mt.zl[s + k] = zp;
+        mt.cl[s + k] = cp;
+        ++k;
+        pj = j; dp = dj; zp = zj; cp = cj;
+      }
     }
-    if (pj < 0) { pj = j; continue; }
-    double sn = z[pj], cs = z[j];
-    const double tau = hypot(cs, sn);
-    const double t = d[j] - d[pj];
-    cs /= tau;
-    sn = -sn / tau;
-    if (fabs(t * cs * sn) <= tol) {
-      // Rotate columns pj, j so that z[pj] vanishes; pj deflates.
-      z[j] = tau;
-      z[pj] = 0.0;
-      mt.rota[s + nr] = c[pj];
-      mt.rotb[s + nr] = c[j];
-      mt.rotc[s + nr] = cs;
-      mt.rots[s + nr] = sn;
-      ++nr;
-      const double tt = d[pj] * cs * cs + d[j] * sn * sn;
-      d[j] = d[pj] * sn * sn + d[j] * cs * cs;
-      d[pj] = tt;
-      mt.defd[s + nd] = d[pj];
-      mt.defc[s + nd] = c[pj];
-      ++nd;
-      pj = j;
-    } else {
-      mt.dl[s + k] = d[pj];
-      mt.zl[s + k] = z[pj];
-      mt.cl[s + k] = c[pj];
+    if (pj >= 0) {
+      mt.dl[s + k] = dp;
+      mt.zl[s + k] = zp;
+      mt.cl[s + k] = cp;
       ++k;
-      pj = j;
+    }
+    counts[0] = k; counts[1] = nd; counts[2] = nr;
+    mt.kcnt[3 * blockIdx.x + 0] = k;
+    mt.kcnt[3 * blockIdx.x + 1] = nd;
+    mt.kcnt[3 * blockIdx.x + 2] = nr;
+    mt.rho[blockIdx.x] = rho;
+  }
+  __syncthreads();
+  // Deflated values in ascending order: rank sort in LDS (ties by index).
+  const int nd = counts[1];
+  if (nd > 1) {
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      d[i] = mt.defd[s + i];
+      c[i] = mt.defc[s + i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      const double v = d[i];
+      int r = 0;
+      for (int q = 0; q < nd; ++q) r += (d[q] < v) || (d[q] == v && q < i);
+      mt.defd[s + r] = v;
+      mt.defc[s + r] = c[i];
     }
   }
-  if (pj >= 0) {
-    mt.dl[s + k] = d[pj];
-    mt.zl[s + k] = z[pj];
-    mt.cl[s + k] = c[pj];
-    ++k;
-  }
-  // deflated values ascending (insertion sort; the list is nearly sorted)
-  for (int a = 1; a < nd; ++a) {
-    const double v = mt.defd[s + a];
-    const int cv = mt.defc[s + a];
-    int b = a - 1;
-    while (b >= 0 && mt.defd[s + b] > v) {
-      mt.defd[s + b + 1] = mt.defd[s + b];
-      mt.defc[s + b + 1] = mt.defc[s + b];
-      --b;
-    }
-    mt.defd[s + b + 1] = v;
-    mt.defc[s + b + 1] = cv;
-  }
-  mt.kcnt[3 * blockIdx.x + 0] = k;
-  mt.kcnt[3 * blockIdx.x + 1] = nd;
-  mt.kcnt[3 * blockIdx.x + 2] = nr;
-  mt.rho[blockIdx.x] = rho;
 }
 
 // Deflation rotations on the rows of each merge block (one thread per row).
@@ -408,9 +423,9 @@ __global__ __launch_bounds__(64) void secular_kernel(const MergeDesc* md, const 
 // Gu-Eisenstat: z_i recomputed from the computed roots so that the computed
 // eigenvectors are numerically orthogonal:
 //   zhat_i^2 = (lambda_i - d_i)/rho * prod_{j != i} (lambda_j - d_i)/(d_j - d_i).
-__global__ void lowner_kernel(const MergeDesc* md, const int* pos_merge, Meta mt, int n) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+__global__ __launch_bounds__(64) void lowner_kernel(const MergeDesc* md, const int* pos_merge,
+                                                    Meta mt, int n) {
+  const int p = blockIdx.x, lane = threadIdx.x;
   const int b = pos_merge[p];
   if (b < 0) return;
   const MergeDesc g = md[b];
@@ -419,14 +434,18 @@ __global__ void lowner_kernel(const MergeDesc* md, const int* pos_merge, Meta mt
   if (i >= k) return;
   const double* dl = mt.dl + g.s;
   const double di = dl[i];
-  double prod = ((dl[mt.org[g.s + i]] - di) + mt.tau[g.s + i]) / mt.rho[b];
-  for (int j = 0; j < k; ++j) {
-    if (j == i) continue;
+  double prod = 1.0;
+  for (int j = lane; j < k; j += kWave) {
     const double lj_di = (dl[mt.org[g.s + j]] - di) + mt.tau[g.s + j];
-    prod *= lj_di / (dl[j] - di);
+    prod *= (j == i) ? lj_di / mt.rho[b] : lj_di / (dl[j] - di);
   }
-  const double zh = sqrt(fmax(prod, 0.0));
-  mt.zhat[g.s + i] = mt.zl[g.s + i] >= 0.0 ? zh : -zh;
+  // product over the wave
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) prod *= __shfl_xor(prod, off, kWave);
+  if (lane == 0) {
+    const double zh = sqrt(fmax(prod, 0.0));
+    mt.zhat[g.s + i] = mt.zl[g.s + i] >= 0.0 ? zh : -zh;
+  }
 }
 
 // Columns of M: secular eigenvectors (normalised) and unit vectors for the
@@ -596,6 +615,12 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
   MergeDesc* dmd = (MergeDesc*)w.zhat.ensure<int>((int64_t)3 * n + 16);
   T* M = w.M.ensure<T>(nn);
 
+  static bool prep_attr[2] = {false, false};
+  if (!prep_attr[sizeof(T) == 8]) {
+    MSQRT_HIP(hipFuncSetAttribute((const void*)merge_prep_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
+    prep_attr[sizeof(T) == 8] = true;
+  }
   std::vector<int> posm(n);
   for (size_t L = 0; L < levels.size(); ++L) {
     const auto& lv = levels[L];
@@ -605,14 +630,18 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
       for (int i = 0; i < lv[b].m; ++i) posm[lv[b].s + i] = b;
     MSQRT_HIP(hipMemcpyAsync(dmd, lv.data(), sizeof(MergeDesc) * nm, hipMemcpyHostToDevice, st));
     MSQRT_HIP(hipMemcpyAsync(pos_merge, posm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(merge_prep_kernel<T>, dim3(nm), dim3(256), 0, st, dmd, ee, lamA, Za, n, mt);
+    int mmax = 0;
+    for (auto& g : lv) mmax = std::max(mmax, g.m);
+    const size_t prep_lds = (size_t)mmax * (2 * sizeof(double) + sizeof(int));
+    if (prep_lds > 140 * 1024) throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal eigensolver supports n <= 7000"};
+    hipLaunchKernelGGL(merge_prep_kernel<T>, dim3(nm), dim3(256), prep_lds, st, dmd, ee, lamA, Za, n, mt);
     MSQRT_LAUNCH_CHECK();
     hipLaunchKernelGGL(merge_rot_kernel<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, dmd, n,
                        pos_merge, mt, Za, n);
     MSQRT_LAUNCH_CHECK();
     hipLaunchKernelGGL(secular_kernel, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, n);
     MSQRT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(lowner_kernel, dim3((unsigned)ceil_div(n, 128)), dim3(128), 0, st, dmd, pos_merge, mt, n);
+    hipLaunchKernelGGL(lowner_kernel, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, n);
     MSQRT_LAUNCH_CHECK();
     MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn, st));
     hipLaunchKernelGGL(vectors_kernel<T>, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);

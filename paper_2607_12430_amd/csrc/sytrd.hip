@@ -81,8 +81,8 @@ struct PanelArgs {
   int TR;        // tiles per dimension; G = TR (TR + 1) / 2 workgroups (lower triangle)
   int r0, ts;    // tile grid origin (p + 1) and tile size (<= kMaxTs)
   T* A;          // n x n, ld n, full symmetric storage
-  T* VW;         // n x 2 kNbMax: [V W]
-  T* WV;         // n x 2 kNbMax: [W V]
+  T* VW;         // n x 2 nb: [V W], rows >= p+1 written by the panel
+  T* WV;         // n x 2 nb: [W V]
   T* d;
   T* e;
   T* tau;
@@ -410,9 +410,9 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       PWI[jj * kMaxTs + r] = wi;
       if (diag) {
         a.VW[i + (int64_t)jj * ld] = vi;
-        a.VW[i + (int64_t)(kNbMax + jj) * ld] = wi;
+        a.VW[i + (int64_t)(nb + jj) * ld] = wi;
         a.WV[i + (int64_t)jj * ld] = wi;
-        a.WV[i + (int64_t)(kNbMax + jj) * ld] = vi;
+        a.WV[i + (int64_t)(nb + jj) * ld] = vi;
         A[i + (int64_t)j * ld] = vi;
       }
     }
@@ -503,8 +503,6 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
     const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
     const int ts = (int)ceil_div(m, TR);
-    MSQRT_HIP(hipMemsetAsync(VW, 0, sizeof(T) * n * 2 * kNbMax, st));
-    MSQRT_HIP(hipMemsetAsync(WV, 0, sizeof(T) * n * 2 * kNbMax, st));
     PanelArgs<T> pa{n, p, nbe, TR, p + 1, ts, A, VW, WV, d, e, tau, ypart, sp, vp, bar};
     void* args[] = {&pa};
     const int G = TR * (TR + 1) / 2;
@@ -527,11 +525,11 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
     if (q < n) {
       const int mt = n - q;
       if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, true, mt, mt, 2 * kNbMax, (const float*)(VW + q), n, 0,
+        gemm_store_f32(st, false, true, mt, mt, 2 * nbe, (const float*)(VW + q), n, 0,
                        (const float*)(WV + q), n, 0, (float*)(A + q + (int64_t)q * n), n, 0, -1.f,
                        1.f, 1, true);
       else
-        gemm_store_f64(st, false, true, mt, mt, 2 * kNbMax, (const double*)(VW + q), n, 0,
+        gemm_store_f64(st, false, true, mt, mt, 2 * nbe, (const double*)(VW + q), n, 0,
                        (const double*)(WV + q), n, 0, (double*)(A + q + (int64_t)q * n), n, 0,
                        -1.0, 1.0, 1, true);
     }
