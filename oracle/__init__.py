@@ -219,6 +219,16 @@ def adjoint(x, gbar):
     return np.asfortranarray(g.real) if is_real else g
 
 
+def adjoint_spd(q, lam, gbar):
+    """Closed form of the adjoint for X = Q diag(lam^1/2) Q^T (SPD): in the
+    eigenbasis X G + G X = Gbar is diagonal, g_ij = (Q^T Gbar Q)_ij /
+    (lam_i^1/2 + lam_j^1/2)."""
+    s = np.sqrt(np.asarray(lam, dtype=np.float64))
+    q = np.asarray(q, dtype=np.float64)
+    h = (q.T @ np.asarray(gbar, dtype=np.float64) @ q) / (s[:, None] + s[None, :])
+    return q @ h @ q.T
+
+
 def kron_adjoint(x, gbar):
     """Brute force for X^H G + G X^H = Gbar: (I kron X^H + conj(X) kron I) vec G."""
     x = np.asarray(x, dtype=np.complex128)

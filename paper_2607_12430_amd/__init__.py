@@ -137,6 +137,8 @@ def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, b
           fallback=True, keep_factor=False, allow_fail=False, out=None):
     """Principal square root of a (batch of) matrices.  Returns (X, info) or
     (X, info, factor) when keep_factor is set."""
+    if isinstance(a, torch.Tensor) and not a.is_contiguous():
+        a = a.contiguous()
     _check_matrix(a, "A")
     n, batch, nn = _dims(a)
     x = torch.empty_like(a) if out is None else out

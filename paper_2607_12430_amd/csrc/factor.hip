@@ -121,14 +121,6 @@ msqrt_prec select_precision(const msqrt_options& o, msqrt_dtype dtype, int64_t n
   return MSQRT_PREC_FP32;
 }
 
-msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gbar, int64_t ldgb,
-                      double* G, int64_t ldg, int64_t stride, int maxit, double tol,
-                      hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
-  (void)f; (void)X; (void)ldx; (void)Gbar; (void)ldgb; (void)G; (void)ldg; (void)stride;
-  (void)maxit; (void)tol; (void)st; (void)info; (void)tm;
-  throw Error{MSQRT_ERR_UNSUPPORTED, "backward is not available in this build"};
-}
-
 }  // namespace msqrt
 
 // ---------------------------------------------------------------------------

@@ -52,6 +52,21 @@ int gemm_residual(hipStream_t st, int n, const double* X, int64_t ldx, int64_t s
   return s.ntiles;
 }
 
+int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda_, int64_t sXa,
+                          const double* Xb, int64_t ldb_, int64_t sXb, const double* C,
+                          int64_t ldc, int64_t sC, float* Rl, double* R64, int64_t ldr, int64_t sR,
+                          double* partials, int batch) {
+  GemmShape s = make_shape(n, n, n, lda_, ldb_, sXa, sXb, false);
+  if (Rl) {
+    EpiResidual e{C, ldc, sC, nullptr, Rl, ldr, sR};
+    launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
+  } else {
+    EpiResidual64 e{C, ldc, sC, nullptr, R64, ldr, sR};
+    launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
+  }
+  return s.ntiles;
+}
+
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,
                    const T* B, int64_t ldb, int64_t sB, const T* s, int64_t sS, T* Y, int64_t ldy,

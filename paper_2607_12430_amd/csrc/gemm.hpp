@@ -231,7 +231,7 @@ struct EpiResidual {
   float* R;
   int64_t ldr, sR;
   __device__ double operator()(int b, int i, int j, double v, bool mir) const {
-    const double r = ascale[b] * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
+    const double r = (ascale ? ascale[b] : 1.0) * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
     const float rl = (float)r;
     float* rb = R + (int64_t)b * sR;
     rb[i + (int64_t)j * ldr] = rl;
@@ -249,7 +249,7 @@ struct EpiResidual64 {
   double* R;
   int64_t ldr, sR;
   __device__ double operator()(int b, int i, int j, double v, bool mir) const {
-    const double r = ascale[b] * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
+    const double r = (ascale ? ascale[b] : 1.0) * A[(int64_t)b * sA + i + (int64_t)j * lda] - v;
     double* rb = R + (int64_t)b * sR;
     rb[i + (int64_t)j * ldr] = r;
     if (mir) rb[j + (int64_t)i * ldr] = r;

@@ -50,6 +50,12 @@ void gemm_store_splitk(hipStream_t st, bool ta, bool tb, int M, int N, int K, in
 int gemm_residual(hipStream_t st, int n, const double* X, int64_t ldx, int64_t sX,
                   const double* A, int64_t lda, int64_t sA, const double* ascale, float* Rl,
                   double* R64, int64_t ldr, int64_t sR, double* partials, int batch, bool sym);
+// R = C - Xa Xb (general product, float64); R as float (Rl) or double (R64),
+// partials[b * ntiles + tile] = sum of R^2.  Returns ntiles.
+int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda, int64_t sXa,
+                          const double* Xb, int64_t ldb, int64_t sXb, const double* C,
+                          int64_t ldc, int64_t sC, float* Rl, double* R64, int64_t ldr, int64_t sR,
+                          double* partials, int batch);
 // Y = (op(A) op(B)) ./ (s_i + s_j)
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,

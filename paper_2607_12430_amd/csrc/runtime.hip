@@ -223,6 +223,159 @@ msqrt_status refine(Factor* f, const double* A, int64_t lda, int64_t sA, double*
   throw Error{MSQRT_ERR_UNSUPPORTED, "general (non-HPD) refinement is not available in this build"};
 }
 
+// ---------------------------------------------------------------------------
+// Backward: the adjoint of the Frechet derivative of the square root,
+// X G + G X = Gbar (X symmetric), solved in the factor's eigenbasis in low
+// precision and refined with float64 residuals -- the correction framework
+// of Sec. 2 applied to this linear equation.  The factor belongs to A/4^k,
+// whose root is X_s = X 2^-k; X_s G' + G' X_s = Gbar gives G = 2^-k G'.
+
+template <typename T>
+static msqrt_status backward_hpd(Factor* f, const double* X, int64_t ldx, const double* Gbar,
+                                 int64_t ldgb, double* G, int64_t ldg, int64_t stride, int maxit,
+                                 double tol, hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  const int n = (int)f->n, batch = (int)f->batch;
+  const int64_t nn = (int64_t)n * n;
+  const T* Q = f->Q.as<T>();
+  const T* s = f->S.as<T>();
+  double* Xs = f->best.ensure<double>(2 * nn * batch);  // scaled X, then T1
+  double* T1 = Xs + nn * batch;
+  T* W1 = f->ws1.ensure<T>(nn * batch);
+  T* W2 = f->ws2.ensure<T>(nn * batch);
+  const int ntile = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  const int nt32 = (int)ceil_div(n, 32);
+  double* part = f->part.ensure<double>((int64_t)std::max(ntile, nt32 * (nt32 + 1) / 2) * batch + 64);
+  double* rn = f->rnorm.ensure<double>(2 * batch);
+  int* flags = f->active.ensure<int>(batch);
+  // ||Gbar||_F per entry (and finiteness)
+  tm.begin(MSQRT_T_VALIDATE);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
+  const int nblk = launch_validate(st, n, Gbar, ldgb, stride, batch, 0, flags, part);
+  launch_reduce_sqrt(st, part, nblk, batch, rn + batch);
+  std::vector<double> gnorm(batch);
+  std::vector<int> hflags(batch);
+  MSQRT_HIP(hipMemcpyAsync(gnorm.data(), rn + batch, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipMemcpyAsync(hflags.data(), flags, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  launch_cast_scale_f64_f64(st, n, X, ldx, stride, f->rscale_dev(), Xs, n, nn, batch);
+  tm.end();
+  MSQRT_HIP(hipStreamSynchronize(st));
+  tm.collect();
+  for (int b = 0; b < batch; ++b)
+    if (hflags[b] & 1) {
+      set_last_error("Gbar contains Inf or NaN");
+      return MSQRT_ERR_NONFINITE;
+    }
+  std::vector<std::vector<double>> hist(batch);
+  std::vector<int> done(batch, 0), steps(batch, 0);
+  std::vector<Verdict> verdict(batch, Verdict::Continue);
+  std::vector<double> host_rn(batch);
+  for (int it = 0;; ++it) {
+    if (it == 0) {
+      // G = 0: the residual is Gbar itself
+      tm.begin(MSQRT_T_RESIDUAL);
+      if (std::is_same<T, float>::value)
+        launch_cast_scale_f64_f32(st, n, Gbar, ldgb, stride, nullptr, (float*)W1, n, nn, batch);
+      else
+        launch_cast_scale_f64_f64(st, n, Gbar, ldgb, stride, nullptr, (double*)W1, n, nn, batch);
+      for (int b = 0; b < batch; ++b) {
+        hist[b].push_back(gnorm[b] > 0.0 ? 1.0 : 0.0);
+        if (gnorm[b] == 0.0) { done[b] = 1; verdict[b] = Verdict::Converged; }
+      }
+    } else {
+      // R = Gbar - X_s G - G X_s  (float64), written as the float R_l
+      tm.begin(MSQRT_T_RESIDUAL);
+      launch_copy_f64(st, n, Gbar, ldgb, stride, T1, n, nn, batch);
+      gemm_store_f64(st, false, false, n, n, n, Xs, n, nn, G, ldg, stride, T1, n, nn, -1.0, 1.0,
+                     batch, false);
+      int nt;
+      if (std::is_same<T, float>::value)
+        nt = gemm_residual_general(st, n, G, ldg, stride, Xs, n, nn, T1, n, nn, (float*)W1, nullptr,
+                                   n, nn, part, batch);
+      else
+        nt = gemm_residual_general(st, n, G, ldg, stride, Xs, n, nn, T1, n, nn, nullptr,
+                                   (double*)W1, n, nn, part, batch);
+      launch_reduce_sqrt(st, part, nt, batch, rn);
+      MSQRT_HIP(hipMemcpyAsync(host_rn.data(), rn, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+      tm.end();
+      MSQRT_HIP(hipStreamSynchronize(st));
+      tm.collect();
+      for (int b = 0; b < batch; ++b) {
+        if (done[b]) continue;
+        hist[b].push_back(host_rn[b] / gnorm[b]);
+        Verdict v = judge(hist[b], tol);
+        if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+        if (v != Verdict::Continue) { done[b] = 1; verdict[b] = v; }
+      }
+    }
+    bool all_done = true;
+    for (int b = 0; b < batch; ++b) all_done = all_done && done[b];
+    if (all_done && it > 0) break;
+    // correction in the eigenbasis:  G (+)= Q [(Q^T R Q) ./ (s_i + s_j)] Q^T
+    tm.begin(MSQRT_T_TRANSFORM);
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, false, false, n, n, n, (const float*)W1, n, nn, (const float*)Q, n, nn,
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+    else
+      gemm_store_f64(st, false, false, n, n, n, (const double*)W1, n, nn, (const double*)Q, n, nn,
+                     (double*)W2, n, nn, 1.0, 0.0, batch, false);
+    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, false);
+    tm.begin(MSQRT_T_UPDATE);
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, false, false, n, n, n, (const float*)Q, n, nn, (const float*)W1, n, nn,
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+    else
+      gemm_store_f64(st, false, false, n, n, n, (const double*)Q, n, nn, (const double*)W1, n, nn,
+                     (double*)W2, n, nn, 1.0, 0.0, batch, false);
+    if (it == 0)
+      gemm_set_f64<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, G, ldg, stride, batch, false);
+    else
+      gemm_update<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, G, ldg, stride, nullptr, batch,
+                     false);
+    tm.end();
+    for (int b = 0; b < batch; ++b)
+      if (!done[b]) steps[b]++;
+  }
+  // G = 2^-k G'
+  launch_scale_inplace(st, n, G, ldg, stride, f->rscale_dev(), batch);
+  MSQRT_HIP(hipStreamSynchronize(st));
+  tm.collect();
+  msqrt_status status = MSQRT_OK;
+  int max_steps = 0;
+  double max_r = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    max_steps = std::max(max_steps, steps[b]);
+    max_r = std::max(max_r, hist[b].back());
+    if (verdict[b] == Verdict::Diverged) status = MSQRT_ERR_DIVERGED;
+    else if (verdict[b] != Verdict::Converged && status == MSQRT_OK) status = MSQRT_ERR_NOT_CONVERGED;
+  }
+  if (info) {
+    info->steps = max_steps;
+    info->relres = max_r;
+    info->nhist = (int)std::min<size_t>(64, hist[0].size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[0][k];
+    info->prec_used = f->prec;
+    info->struct_used = f->structure;
+    info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+  }
+  return status;
+}
+
+msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gbar, int64_t ldgb,
+                      double* G, int64_t ldg, int64_t stride, int maxit, double tol,
+                      hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  if (f->batch > 1 && stride < std::max(std::max(ldx, ldgb), ldg) * f->n) {
+    set_last_error("msqrt_sqrtm_backward: batch stride too small");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (f->structure == MSQRT_STRUCT_HPD) {
+    if (f->prec == MSQRT_PREC_FP64)
+      return backward_hpd<double>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
+    return backward_hpd<float>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
+  }
+  set_last_error("backward for the general path is not available in this build");
+  return MSQRT_ERR_UNSUPPORTED;
+}
+
 // Computes ||A_b||_F and the scale exponents k_b = round(log4(||A_b||_F / sqrt(n)))
 // into the factor; also validates finiteness / symmetry.  Returns flags.
 int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,

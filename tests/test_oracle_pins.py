@@ -251,6 +251,16 @@ def test_adjoint_against_kronecker(n, cplx):
     assert np.abs(ga - ref).max() < 1e-12 * np.abs(ref).max()
 
 
+def test_adjoint_spd_closed_form_against_schur_route_and_kronecker():
+    n = 9
+    a, q, lam = W.spd(n, 1e3, 80)
+    g = rng(81).standard_normal((n, n))
+    x = (q * np.sqrt(lam)) @ q.T
+    ref = oracle.kron_adjoint(x, g).real
+    assert np.abs(oracle.adjoint_spd(q, lam, g) - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(oracle.adjoint(oracle.sqrtm(a), g) - ref).max() < 1e-10 * np.abs(ref).max()
+
+
 def test_adjoint_against_central_differences():
     # <Gbar, d sqrtm(A)[E]> = <G, E> with G = adjoint(X, Gbar).
     n = 7
