@@ -25,6 +25,29 @@ msqrt_status msqrt_test_sytrd(msqrt_prec prec, int64_t n, const void* A, void* d
 msqrt_status msqrt_test_stedc(msqrt_prec prec, int64_t n, const void* d, const void* e,
                               double* lam, void* Z);
 
+/* The stages of the general path (Alg. 2) work on complex matrices; their
+ * hooks take and return interleaved complex128 (double re, im pairs),
+ * column-major with ld = n, and run the stage in complex64 (FP32) or
+ * complex128 (FP64) arithmetic. */
+
+/* Householder reduction to upper Hessenberg form: A = Q H Q^*, H with exact
+ * zeros below the subdiagonal (first line of Alg. 2, the start of the Schur
+ * decomposition). */
+msqrt_status msqrt_test_gehrd(msqrt_prec prec, int64_t n, const double* A, double* H, double* Q);
+
+/* Complex Schur decomposition A = Q T Q^* (Hessenberg reduction followed by
+ * the shifted QR algorithm); T upper triangular. */
+msqrt_status msqrt_test_schur(msqrt_prec prec, int64_t n, const double* A, double* T, double* Q);
+
+/* Principal square root S of the upper triangular T (Eq. (subst), blocked);
+ * NO_PRINCIPAL if a diagonal entry lies on or next to R<=0. */
+msqrt_status msqrt_test_trsqrt(msqrt_prec prec, int64_t n, const double* T, double* S);
+
+/* Triangular Sylvester equation S Y + Y S2 = C (Eq. (triangsylv), Alg. 1):
+ * S m x m and S2 p x p upper triangular, C and Y m x p. */
+msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, const double* S,
+                              const double* S2, const double* C, double* Y);
+
 #ifdef __cplusplus
 }
 #endif

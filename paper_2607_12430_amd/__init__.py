@@ -204,6 +204,60 @@ def test_stedc(d, e, prec="fp32"):
     return lam, z
 
 
+def _cplx_f(a):
+    import numpy as np
+    return np.asfortranarray(a, dtype=np.complex128)
+
+
+def _dp(x):
+    return ctypes.cast(x.ctypes.data, ctypes.POINTER(ctypes.c_double))
+
+
+def test_gehrd(a, prec="fp32"):
+    """Test hook: (H, Q) of the on-device Hessenberg reduction, A = Q H Q^*."""
+    import numpy as np
+    a = _cplx_f(a)
+    n = a.shape[0]
+    h = np.zeros((n, n), np.complex128, order="F")
+    q = np.zeros((n, n), np.complex128, order="F")
+    check(lib().msqrt_test_gehrd(_lib.PREC_NAMES[prec], n, _dp(a), _dp(h), _dp(q)),
+          "msqrt_test_gehrd")
+    return h, q
+
+
+def test_schur(a, prec="fp32"):
+    """Test hook: (T, Q) of the on-device complex Schur decomposition."""
+    import numpy as np
+    a = _cplx_f(a)
+    n = a.shape[0]
+    t = np.zeros((n, n), np.complex128, order="F")
+    q = np.zeros((n, n), np.complex128, order="F")
+    check(lib().msqrt_test_schur(_lib.PREC_NAMES[prec], n, _dp(a), _dp(t), _dp(q)),
+          "msqrt_test_schur")
+    return t, q
+
+
+def test_trsqrt(t, prec="fp32"):
+    """Test hook: principal square root of an upper triangular matrix."""
+    import numpy as np
+    t = _cplx_f(t)
+    n = t.shape[0]
+    s = np.zeros((n, n), np.complex128, order="F")
+    check(lib().msqrt_test_trsqrt(_lib.PREC_NAMES[prec], n, _dp(t), _dp(s)), "msqrt_test_trsqrt")
+    return s
+
+
+def test_trsyl(s, s2, c, prec="fp32"):
+    """Test hook: Y with S Y + Y S2 = C (S, S2 upper triangular)."""
+    import numpy as np
+    s, s2, c = _cplx_f(s), _cplx_f(s2), _cplx_f(c)
+    m, p = c.shape
+    y = np.zeros((m, p), np.complex128, order="F")
+    check(lib().msqrt_test_trsyl(_lib.PREC_NAMES[prec], m, p, _dp(s), _dp(s2), _dp(c), _dp(y)),
+          "msqrt_test_trsyl")
+    return y
+
+
 class _SqrtmFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, a, prec, tol, maxit):

@@ -75,17 +75,28 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
 
 msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,
                           int64_t sA, hipStream_t st, PhaseTimer* tm) {
-  if (f->dtype != MSQRT_REAL64) {
-    set_last_error("complex input is not available in this build");
-    return MSQRT_ERR_UNSUPPORTED;
-  }
   if (o.prec != MSQRT_PREC_FP32 && o.prec != MSQRT_PREC_FP64 && o.prec != MSQRT_PREC_BF16SPLIT) {
     set_last_error("invalid precision");
     return MSQRT_ERR_INVALID_ARG;
   }
+  const bool cplx = f->dtype == MSQRT_COMPLEX128;
+  if (cplx && o.structure == MSQRT_STRUCT_HPD) {
+    set_last_error("complex Hermitian input runs on the general path (structure AUTO or GENERAL)");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
   if (tm) tm->begin(MSQRT_T_VALIDATE);
-  const bool want_sym_check = o.structure != MSQRT_STRUCT_GENERAL;
-  const int flags = analyse_input(f, A, lda, sA, want_sym_check, st);
+  int flags;
+  if (cplx) {
+    if (f->batch != 1) {
+      set_last_error("the general path takes one matrix per call (batch = 1)");
+      return MSQRT_ERR_UNSUPPORTED;
+    }
+    flags = analyse_input_general(f, A, lda, 1, st) | 2;
+  } else {
+    const bool want_sym_check = o.structure != MSQRT_STRUCT_GENERAL;
+    flags = analyse_input(f, A, lda, sA, want_sym_check, st);
+    if (!want_sym_check) flags |= 2;
+  }
   if (tm) tm->end();
   if (flags & 1) {
     set_last_error("input contains Inf or NaN");
@@ -97,12 +108,16 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
     set_last_error("structure HPD requested but the input is not exactly symmetric");
     return MSQRT_ERR_INVALID_ARG;
   }
-  if (sc == MSQRT_STRUCT_GENERAL) {
-    set_last_error("the general (non-symmetric) path is not available in this build");
-    return MSQRT_ERR_UNSUPPORTED;
-  }
   f->structure = sc;
   f->prec = o.prec == MSQRT_PREC_FP64 ? MSQRT_PREC_FP64 : MSQRT_PREC_FP32;
+  if (sc == MSQRT_STRUCT_GENERAL) {
+    if (f->batch != 1) {
+      set_last_error("the general path takes one matrix per call (batch = 1)");
+      return MSQRT_ERR_UNSUPPORTED;
+    }
+    if (f->prec == MSQRT_PREC_FP64) return factor_general<double>(f, A, lda, cplx ? 1 : 0, st, tm);
+    return factor_general<float>(f, A, lda, cplx ? 1 : 0, st, tm);
+  }
   std::vector<double> minlam;
   if (f->prec == MSQRT_PREC_FP64) factor_hpd<double>(f, A, lda, sA, st, tm, minlam);
   else factor_hpd<float>(f, A, lda, sA, st, tm, minlam);

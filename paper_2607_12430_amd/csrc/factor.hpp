@@ -45,6 +45,11 @@ struct DevBuf {
   }
 };
 
+// Workspace of the tile-dataflow triangular solvers.
+struct TrsylvWork {
+  DevBuf flags, ticket;
+};
+
 struct Factor {
   int64_t n = 0, batch = 1;
   msqrt_dtype dtype = MSQRT_REAL64;
@@ -62,6 +67,12 @@ struct Factor {
   DevBuf ws1, ws2, part, rnorm, active, best;
   // factorisation workspaces
   DevBuf fw1, fw2, fw3, fw4, fw5;
+  // general path: Q in the four layouts of the refinement products, the
+  // wide float64 iterate and its stacked copy, the Sylvester right-hand side,
+  // the per-plane residual scales and the tile-solver state
+  DevBuf gq, gx, gt, gsc;
+  bool gq_ready = false;
+  TrsylvWork tw;
 
   void upload_scales(hipStream_t st) {
     const int64_t b = batch;
@@ -143,6 +154,21 @@ int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool chec
 // Factorisation of the scaled input into f (Q, S, structure, prec).
 msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,
                           int64_t sA, hipStream_t st, PhaseTimer* tm);
+// General path (complex Schur, Alg. 2); A is real (cplx = 0) or interleaved
+// complex, ld in elements.
+int analyse_input_general(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st);
+template <typename T>
+msqrt_status factor_general(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st,
+                            PhaseTimer* tm);
+template <typename T>
+msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
+                            int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
+                            PhaseTimer& tm);
+template <typename T>
+msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const double* Gbar,
+                              int64_t ldgb, double* G, int64_t ldg, int maxit, double tol,
+                              hipStream_t st, msqrt_info* info, PhaseTimer& tm);
+
 // Precision choice for MSQRT_PREC_AUTO.
 msqrt_prec select_precision(const msqrt_options& o, msqrt_dtype dtype, int64_t n, const void* A,
                             int64_t lda, int64_t sA, hipStream_t st, msqrt_info* info,

@@ -67,6 +67,21 @@ int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda_,
   return s.ntiles;
 }
 
+int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
+                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+                     const double* C, int64_t ldc, int64_t sC, const double* cscale, float* Rl,
+                     double* R64, int64_t ldr, int64_t sR, double* partials, int batch) {
+  GemmShape s = make_shape(M, N, K, lda, ldb, sA, sB, false);
+  if (Rl) {
+    EpiResidual e{C, ldc, sC, cscale, Rl, ldr, sR};
+    launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
+  } else {
+    EpiResidual64 e{C, ldc, sC, cscale, R64, ldr, sR};
+    launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
+  }
+  return s.ntiles;
+}
+
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,
                    const T* B, int64_t ldb, int64_t sB, const T* s, int64_t sS, T* Y, int64_t ldy,

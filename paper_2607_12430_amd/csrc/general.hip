@@ -1,0 +1,565 @@
+// General path (Alg. 2): complex Schur factorisation A/4^k ~ Q T Q^*, the
+// triangular root S = T^{1/2}, X_0 = Q S Q^*, and the refinement
+//   R = A - X^2 (float64),  Y = rtrsyl(S, S, Q^* fl(R) Q),  X += Q Y Q^*,
+// plus the adjoint solve of the backward pass.  Real nonsymmetric input runs
+// through the same complex route and returns Re X.
+//
+// Every complex product of the refinement is one batched real MFMA GEMM with
+// an inner dimension of 2n: with the planes of Q stored in the four layouts
+//   QSa = [-Qi; Qr; Qi], QSb = [Qi; Qr; -Qi]   (3n x n, stacked)
+//   QWa = [Qi | Qr | -Qi], QWb = [-Qi | Qr | Qi] (n x 3n, wide)
+// each product's real and imaginary parts are batch entries 0 and 1, e.g.
+//   Re(R Q) = [Rr | Ri] [Qr; -Qi],  Im(R Q) = [Rr | Ri] [Qi; Qr].
+// The float64 iterate is kept wide (X = [Xr | Xi], n x 2n) and the residual
+// product X X uses XS = [Xi; Xr; -Xi].
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "factor.hpp"
+#include "kernels.hpp"
+#include "schur.hpp"
+
+namespace msqrt {
+
+namespace {
+
+constexpr int kRedBlocks = 256;
+
+// Finiteness and sum of squares of a complex (interleaved) or real matrix.
+__global__ __launch_bounds__(256) void cvalidate_kernel(int n, const double* A, int64_t lda, int cplx,
+                                                        int* flags, double* part) {
+  __shared__ double red[4];
+  const int64_t cnt = (int64_t)n * n;
+  double s = 0.0;
+  int bad = 0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < cnt;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x % n, j = x / n;
+    if (cplx) {
+      const double re = A[2 * (i + j * lda)], im = A[2 * (i + j * lda) + 1];
+      if (!isfinite(re) || !isfinite(im)) bad = 1;
+      s += re * re + im * im;
+    } else {
+      const double re = A[i + j * lda];
+      if (!isfinite(re)) bad = 1;
+      s += re * re;
+    }
+  }
+  if (bad) atomicOr(flags, 1);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// H (stacked, ld 2n) = scale * A in precision T.
+template <typename T>
+__global__ void to_stacked_kernel(int n, const double* A, int64_t lda, int cplx,
+                                  const double* scale, T* H) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)n * n) return;
+  const int64_t i = x % n, j = x / n;
+  const double s = *scale;
+  double re, im = 0.0;
+  if (cplx) { re = A[2 * (i + j * lda)]; im = A[2 * (i + j * lda) + 1]; }
+  else re = A[i + j * lda];
+  H[i + j * 2 * n] = (T)(re * s);
+  H[n + i + j * 2 * n] = (T)(im * s);
+}
+
+template <typename T>
+__global__ void q_variants_kernel(int n, const T* Q, T* QSa, T* QSb, T* QWa, T* QWb) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (x >= nn) return;
+  const int64_t i = x % n, j = x / n;
+  const T qr = Q[i + j * 2 * n], qi = Q[n + i + j * 2 * n];
+  const int64_t l3 = 3 * (int64_t)n;
+  QSa[i + j * l3] = -qi;
+  QSa[n + i + j * l3] = qr;
+  QSa[2 * n + i + j * l3] = qi;
+  QSb[i + j * l3] = qi;
+  QSb[n + i + j * l3] = qr;
+  QSb[2 * n + i + j * l3] = -qi;
+  QWa[i + j * n] = qi;
+  QWa[nn + i + j * n] = qr;
+  QWa[2 * nn + i + j * n] = -qi;
+  QWb[i + j * n] = -qi;
+  QWb[nn + i + j * n] = qr;
+  QWb[2 * nn + i + j * n] = qi;
+}
+
+// XS = [Xi; Xr; -Xi] (ld 3n) from the wide X.
+__global__ void x_stack_kernel(int n, const double* Xw, double* XS) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (x >= nn) return;
+  const int64_t i = x % n, j = x / n;
+  const double xr = Xw[i + j * n], xi = Xw[nn + i + j * n];
+  const int64_t l3 = 3 * (int64_t)n;
+  XS[i + j * l3] = xi;
+  XS[n + i + j * l3] = xr;
+  XS[2 * n + i + j * l3] = -xi;
+}
+
+// Wide float64 W = scale * op(X_user); op = identity or conjugate transpose.
+__global__ void x_in_kernel(int n, const double* X, int64_t ldx, int cplx, int ctrans,
+                            const double* scale, double* Xw) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (x >= nn) return;
+  const int64_t i = x % n, j = x / n;
+  const int64_t si = ctrans ? j : i, sj = ctrans ? i : j;
+  const double s = scale ? *scale : 1.0;
+  double re, im = 0.0;
+  if (cplx) { re = X[2 * (si + sj * ldx)]; im = X[2 * (si + sj * ldx) + 1]; }
+  else re = X[si + sj * ldx];
+  if (ctrans) im = -im;
+  Xw[i + j * n] = re * s;
+  Xw[nn + i + j * n] = im * s;
+}
+
+// X_user = scale * op(Xw) (complex: interleaved; real: the real part) and
+// partial sums of |X|^2 and |Im X|^2.
+__global__ __launch_bounds__(256) void x_out_kernel(int n, const double* Xw, int cplx, int ctrans,
+                                                    const double* scale, double* X, int64_t ldx,
+                                                    double* part) {
+  __shared__ double red[4];
+  const int64_t nn = (int64_t)n * n;
+  const double s = scale ? *scale : 1.0;
+  double a2 = 0.0, i2 = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nn;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x % n, j = x / n;
+    const int64_t di = ctrans ? j : i, dj = ctrans ? i : j;
+    const double re = Xw[i + j * n] * s;
+    double im = Xw[nn + i + j * n] * s;
+    if (ctrans) im = -im;
+    a2 += re * re + im * im;
+    i2 += im * im;
+    if (cplx) {
+      X[2 * (di + dj * ldx)] = re;
+      X[2 * (di + dj * ldx) + 1] = im;
+    } else {
+      X[di + dj * ldx] = re;
+    }
+  }
+  a2 = block_sum(a2, red);
+  i2 = block_sum(i2, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a2;
+    part[kRedBlocks + blockIdx.x] = i2;
+  }
+}
+
+inline unsigned blocks_for(int64_t cnt) { return (unsigned)std::max<int64_t>(1, ceil_div(cnt, 256)); }
+
+enum class Verdict2 { Continue, Converged, Diverged, Stagnated };
+
+// Stopping rule of Alg. 2 with the divergence / stagnation reading used by
+// the HPD loop (kept in one place for both loops of this file).
+Verdict2 judge2(const std::vector<double>& h, double tol) {
+  const double r = h.back();
+  if (!std::isfinite(r)) return Verdict2::Diverged;
+  if (r <= tol) return Verdict2::Converged;
+  if (r > 10.0 * h.front()) return Verdict2::Diverged;
+  const size_t k = h.size();
+  if (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) return Verdict2::Diverged;
+  if (k >= 3 && h[k - 1] > 0.9 * h[k - 2] && h[k - 2] > 0.9 * h[k - 3]) return Verdict2::Stagnated;
+  return Verdict2::Continue;
+}
+
+template <typename T>
+void gstore_b(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda, int64_t sA,
+              const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC) {
+  if (std::is_same<T, float>::value)
+    gemm_store_f32(st, ta, tb, n, n, K, (const float*)A, lda, sA, (const float*)B, ldb, sB,
+                   (float*)C, ldc, sC, 1.f, 0.f, 2, false);
+  else
+    gemm_store_f64(st, ta, tb, n, n, K, (const double*)A, lda, sA, (const double*)B, ldb, sB,
+                   (double*)C, ldc, sC, 1.0, 0.0, 2, false);
+}
+
+// Device views of the factor used by the refinement products.
+template <typename T>
+struct GView {
+  int n;
+  int64_t nn;
+  const T *QSa, *QSb, *QWa, *QWb, *S;
+};
+
+template <typename T>
+GView<T> prepare_view(Factor* f, hipStream_t st) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  T* qv = f->gq.ensure<T>(12 * nn);
+  if (!f->gq_ready) {
+    hipLaunchKernelGGL(q_variants_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n,
+                       (const T*)f->Q.as<T>(), qv, qv + 3 * nn, qv + 6 * nn, qv + 9 * nn);
+    MSQRT_LAUNCH_CHECK();
+    f->gq_ready = true;
+  }
+  return GView<T>{n, nn, qv, qv + 3 * nn, qv + 6 * nn, qv + 9 * nn, f->S.as<T>()};
+}
+
+// M (wide, low precision, n x 2n) -> Y = rtrsyl(S, S, Q^* M Q) (stacked, in
+// Rt) -> V = Q Y (wide, overwrites M) -> X (+)= fl64(V Q^*).
+template <typename T>
+void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* Xw, bool set,
+                TrsylvWork& tw, PhaseTimer& tm) {
+  const int n = g.n;
+  const int64_t nn = g.nn, n2 = 2 * (int64_t)n, n3 = 3 * (int64_t)n;
+  tm.begin(MSQRT_T_TRANSFORM);
+  // W = M Q (stacked): Re = [Mr | Mi][Qr; -Qi], Im = [Mr | Mi][Qi; Qr]
+  gstore_b<T>(st, false, false, n, 2 * n, M, n, 0, g.QSb + n, n3, -(int64_t)n, Wst, n2, n);
+  // Rt = Q^* W (stacked): Re = [Qr; Qi]^T W, Im = [-Qi; Qr]^T W
+  gstore_b<T>(st, true, false, n, 2 * n, g.QSa + n, n3, -(int64_t)n, Wst, n2, 0, Rt, n2, n);
+  tm.begin(MSQRT_T_SOLVE);
+  trsyl<T>(st, n, n, g.S, n2, g.S, n2, Rt, n2, tw);
+  tm.begin(MSQRT_T_UPDATE);
+  // V = Q Y (wide): Re = [Qr | -Qi][Yr; Yi], Im = [Qi | Qr][Yr; Yi]
+  gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, Rt, n2, 0, M, n, nn);
+  // X (+)= V Q^*: Re = [Vr | Vi][Qr | Qi]^T, Im = [Vr | Vi][-Qi | Qr]^T
+  if (set)
+    gemm_set_f64<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, 2, false);
+  else
+    gemm_update<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, nullptr, 2,
+                   false);
+  tm.end();
+}
+
+double sum_host(const std::vector<double>& v, int off, int cnt) {
+  double s = 0.0;
+  for (int i = 0; i < cnt; ++i) s += v[off + i];
+  return s;
+}
+
+}  // namespace
+
+// ||A||_F, finiteness and the scale exponent for complex or real input
+// without a symmetry test.  Returns the flags (bit0 = non-finite).
+int analyse_input_general(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st) {
+  const int n = (int)f->n;
+  int* flags = f->active.ensure<int>(1);
+  double* part = f->part.ensure<double>(kRedBlocks + 64);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
+  hipLaunchKernelGGL(cvalidate_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, A, lda, cplx, flags,
+                     part);
+  MSQRT_LAUNCH_CHECK();
+  std::vector<double> hp(kRedBlocks);
+  int hf = 0;
+  MSQRT_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  const double nrm = std::sqrt(sum_host(hp, 0, kRedBlocks));
+  f->kexp.assign(1, 0);
+  f->anorm.assign(1, nrm);
+  if (nrm > 0 && std::isfinite(nrm))
+    f->kexp[0] = (int)std::lround(std::log(nrm / std::sqrt((double)n)) / std::log(4.0));
+  f->upload_scales(st);
+  return hf;
+}
+
+template <typename T>
+msqrt_status factor_general(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st,
+                            PhaseTimer* tm) {
+  const int n = (int)f->n;
+  const int64_t sz = 2 * (int64_t)n * n;
+  T* Q = f->Q.ensure<T>(sz);
+  T* S = f->S.ensure<T>(sz);
+  T* H = f->fw1.ensure<T>(sz);
+  f->gq_ready = false;
+  if (tm) tm->begin(MSQRT_T_REDUCE);
+  hipLaunchKernelGGL(to_stacked_kernel<T>, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, n, A,
+                     lda, cplx, f->ascale_dev(), H);
+  MSQRT_LAUNCH_CHECK();
+  GehrdWork gw;
+  gehrd<T>(st, n, H, Q, gw);
+  if (tm) tm->begin(MSQRT_T_EIG);
+  HseqrWork hw;
+  const bool ok = hseqr<T>(st, n, H, Q, hw);
+  if (!ok) {
+    if (tm) tm->end();
+    set_last_error("complex Schur QR did not converge");
+    return MSQRT_ERR_NOT_CONVERGED;
+  }
+  if (tm) tm->begin(MSQRT_T_X0);
+  trsylv_reset(st, f->tw);
+  trsqrt<T>(st, n, H, S, f->tw, nullptr);
+  if (tm) tm->end();
+  int timed_out = 0, nonprincipal = 0;
+  trsylv_errors(st, f->tw, &timed_out, &nonprincipal);
+  if (tm) tm->collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "triangular square root: dataflow wait timed out"};
+  if (nonprincipal) {
+    set_last_error("an eigenvalue lies on or next to the closed negative real axis");
+    return MSQRT_ERR_NO_PRINCIPAL;
+  }
+  return MSQRT_OK;
+}
+
+template <typename T>
+msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
+                            int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
+                            PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  const int cplx = f->dtype == MSQRT_COMPLEX128;
+  const GView<T> g = prepare_view<T>(f, st);
+  double* Xw = f->gx.ensure<double>(7 * nn);
+  double* XS = Xw + 2 * nn;
+  double* Aw = Xw + 5 * nn;  // A in the wide layout [Ar | Ai]
+  T* M = f->ws1.ensure<T>(2 * nn);
+  T* Wst = f->ws2.ensure<T>(2 * nn);
+  T* Rt = f->gt.ensure<T>(2 * nn);
+  const int ntiles = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  double* part = f->part.ensure<double>(2 * (int64_t)ntiles + 2 * kRedBlocks + 64);
+  double* rn = f->rnorm.ensure<double>(2);
+  double* sc2 = f->gsc.ensure<double>(2);
+  {
+    const double a = std::ldexp(1.0, -2 * f->kexp[0]);
+    const double h[2] = {a, a};
+    MSQRT_HIP(hipMemcpyAsync(sc2, h, sizeof(h), hipMemcpyHostToDevice, st));
+  }
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, A, lda, cplx, 0,
+                     (const double*)nullptr, Aw);
+  MSQRT_LAUNCH_CHECK();
+  trsylv_reset(st, f->tw);
+  if (init) {
+    tm.begin(MSQRT_T_X0);
+    // V = Q S (wide), X_0 = fl64(V Q^*)
+    gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, g.S, 2 * (int64_t)n, 0, M, n, nn);
+    gemm_set_f64<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, 2, false);
+  } else {
+    tm.begin(MSQRT_T_VALIDATE);
+    hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)X,
+                       ldx, cplx, 0, f->rscale_dev(), Xw);
+    MSQRT_LAUNCH_CHECK();
+  }
+  std::vector<double> hist, hp(2 * ntiles);
+  double best_r = INFINITY;
+  double* best = nullptr;
+  Verdict2 verdict = Verdict2::Continue;
+  int steps = 0;
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    hipLaunchKernelGGL(x_stack_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)Xw,
+                       XS);
+    MSQRT_LAUNCH_CHECK();
+    // R = A - X X: Re = Ar - [Xr | Xi][Xr; -Xi], Im = Ai - [Xr | Xi][Xi; Xr]
+    const int nt = gemm_residual_ex(st, false, false, n, n, 2 * n, Xw, n, 0, XS + n, 3 * (int64_t)n,
+                                    -(int64_t)n, Aw, n, nn, sc2,
+                                    std::is_same<T, float>::value ? (float*)M : nullptr,
+                                    std::is_same<T, float>::value ? nullptr : (double*)M, n, nn,
+                                    part, 2);
+    launch_reduce_sqrt(st, part, 2 * nt, 1, rn);
+    double hrn = 0.0;
+    MSQRT_HIP(hipMemcpyAsync(&hrn, rn, sizeof(double), hipMemcpyDeviceToHost, st));
+    tm.end();
+    MSQRT_HIP(hipStreamSynchronize(st));
+    tm.collect();
+    hist.push_back(hrn / f->anorm_scaled[0]);
+    Verdict2 v = judge2(hist, tol);
+    if (v == Verdict2::Continue && it >= maxit) v = Verdict2::Stagnated;
+    if (v != Verdict2::Continue) {
+      verdict = v;
+      break;
+    }
+    if (hist.back() < best_r) {
+      best_r = hist.back();
+      if (!best) best = f->best.ensure<double>(2 * nn);
+      MSQRT_HIP(hipMemcpyAsync(best, Xw, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+    }
+    correction<T>(st, g, M, Wst, Rt, Xw, false, f->tw, tm);
+    ++steps;
+  }
+  msqrt_status status = MSQRT_OK;
+  double final_r = hist.back();
+  if (verdict != Verdict2::Converged) {
+    if (best && best_r < final_r) {
+      MSQRT_HIP(hipMemcpyAsync(Xw, best, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+      final_r = best_r;
+    }
+    status = verdict == Verdict2::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
+    set_last_error(verdict == Verdict2::Diverged ? "refinement diverged"
+                                                 : "refinement did not converge");
+  }
+  // X = 2^k X_s in the caller's layout
+  tm.begin(MSQRT_T_VALIDATE);
+  hipLaunchKernelGGL(x_out_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, (const double*)Xw, cplx, 0,
+                     f->uscale_dev(), X, ldx, part);
+  MSQRT_LAUNCH_CHECK();
+  std::vector<double> hx(2 * kRedBlocks);
+  MSQRT_HIP(hipMemcpyAsync(hx.data(), part, sizeof(double) * 2 * kRedBlocks, hipMemcpyDeviceToHost, st));
+  tm.end();
+  int timed_out = 0;
+  trsylv_errors(st, f->tw, &timed_out, nullptr);
+  tm.collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "triangular Sylvester solve: dataflow wait timed out"};
+  if (info) {
+    info->steps = steps;
+    info->relres = std::isfinite(final_r) ? final_r : INFINITY;
+    info->nhist = (int)std::min<size_t>(64, hist.size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
+  }
+  if (!cplx && status == MSQRT_OK) {
+    // a real matrix without eigenvalues on R<=0 has a real principal root
+    const double xa = std::sqrt(sum_host(hx, 0, kRedBlocks));
+    const double xi = std::sqrt(sum_host(hx, kRedBlocks, kRedBlocks));
+    if (xi > 1e-12 * xa) {
+      set_last_error("the root of the real input has a non-negligible imaginary part");
+      return MSQRT_ERR_NO_PRINCIPAL;
+    }
+  }
+  return status;
+}
+
+// Backward: X^* G + G X^* = Gbar.  Its conjugate transpose is
+// X G~ + G~ X = Gbar^* with G~ = G^*: the forward correction equation, solved
+// with the same factor (Q^* (.) Q, rtrsyl, Q (.) Q^*) and refined with
+// float64 residuals.  The factor belongs to A/4^k, whose root is
+// X_s = 2^-k X, so G = 2^-k G'.
+template <typename T>
+msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const double* Gbar,
+                              int64_t ldgb, double* G, int64_t ldg, int maxit, double tol,
+                              hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n, n3 = 3 * (int64_t)n;
+  const int cplx = f->dtype == MSQRT_COMPLEX128;
+  const GView<T> g = prepare_view<T>(f, st);
+  double* Xw = f->gx.ensure<double>(5 * nn);  // X_s (wide)
+  double* XS = Xw + 2 * nn;                   // [X_s i; X_s r; -X_s i]
+  double* Cw = f->best.ensure<double>(6 * nn);  // Gbar^* (wide), T1 (wide), G~ (wide)
+  double* T1 = Cw + 2 * nn;
+  double* Gw = Cw + 4 * nn;
+  double* GS = f->fw2.ensure<double>(3 * nn);  // [G~i; G~r; -G~i]
+  T* M = f->ws1.ensure<T>(2 * nn);
+  T* Wst = f->ws2.ensure<T>(2 * nn);
+  T* Rt = f->gt.ensure<T>(2 * nn);
+  const int ntiles = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  double* part = f->part.ensure<double>(2 * (int64_t)ntiles + 2 * kRedBlocks + 64);
+  double* rn = f->rnorm.ensure<double>(2);
+  double* one2 = f->gsc.ensure<double>(2);
+  {
+    const double h[2] = {1.0, 1.0};
+    MSQRT_HIP(hipMemcpyAsync(one2, h, sizeof(h), hipMemcpyHostToDevice, st));
+  }
+  trsylv_reset(st, f->tw);
+  tm.begin(MSQRT_T_VALIDATE);
+  int* flags = f->active.ensure<int>(1);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
+  hipLaunchKernelGGL(cvalidate_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, Gbar, ldgb, cplx,
+                     flags, part);
+  MSQRT_LAUNCH_CHECK();
+  std::vector<double> hp(kRedBlocks);
+  int hf = 0;
+  MSQRT_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, X, ldx, cplx, 0,
+                     f->rscale_dev(), Xw);
+  MSQRT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(x_stack_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)Xw, XS);
+  MSQRT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, Gbar, ldgb, cplx, 1,
+                     nullptr, Cw);
+  MSQRT_LAUNCH_CHECK();
+  tm.end();
+  MSQRT_HIP(hipStreamSynchronize(st));
+  tm.collect();
+  if (hf & 1) {
+    set_last_error("Gbar contains Inf or NaN");
+    return MSQRT_ERR_NONFINITE;
+  }
+  const double gnorm = std::sqrt(sum_host(hp, 0, kRedBlocks));
+  std::vector<double> hist;
+  Verdict2 verdict = Verdict2::Continue;
+  int steps = 0;
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    if (it == 0) {
+      // G~ = 0: the residual is Gbar^* itself
+      hist.push_back(gnorm > 0.0 ? 1.0 : 0.0);
+      if (gnorm == 0.0) {
+        verdict = Verdict2::Converged;
+        MSQRT_HIP(hipMemsetAsync(Gw, 0, sizeof(double) * 2 * nn, st));
+        break;
+      }
+      // fl(Gbar^*) in the wide low-precision layout
+      if (std::is_same<T, float>::value)
+        launch_cast_scale_f64_f32(st, n, Cw, n, nn, nullptr, (float*)M, n, nn, 2);
+      else
+        launch_cast_scale_f64_f64(st, n, Cw, n, nn, nullptr, (double*)M, n, nn, 2);
+    } else {
+      // R = Gbar^* - X_s G~ - G~ X_s
+      MSQRT_HIP(hipMemcpyAsync(T1, Cw, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(x_stack_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n,
+                         (const double*)Gw, GS);
+      MSQRT_LAUNCH_CHECK();
+      // T1 -= X_s G~: Re -= [Xr | Xi][Gr; -Gi], Im -= [Xr | Xi][Gi; Gr]
+      gemm_store_f64(st, false, false, n, n, 2 * n, Xw, n, 0, GS + n, n3, -(int64_t)n, T1, n, nn,
+                     -1.0, 1.0, 2, false);
+      // R = T1 - G~ X_s
+      const int nt = gemm_residual_ex(st, false, false, n, n, 2 * n, Gw, n, 0, XS + n, n3,
+                                      -(int64_t)n, T1, n, nn, one2,
+                                      std::is_same<T, float>::value ? (float*)M : nullptr,
+                                      std::is_same<T, float>::value ? nullptr : (double*)M, n, nn,
+                                      part, 2);
+      launch_reduce_sqrt(st, part, 2 * nt, 1, rn);
+      double hrn = 0.0;
+      MSQRT_HIP(hipMemcpyAsync(&hrn, rn, sizeof(double), hipMemcpyDeviceToHost, st));
+      tm.end();
+      MSQRT_HIP(hipStreamSynchronize(st));
+      tm.collect();
+      hist.push_back(hrn / gnorm);
+      Verdict2 v = judge2(hist, tol);
+      if (v == Verdict2::Continue && it >= maxit) v = Verdict2::Stagnated;
+      if (v != Verdict2::Continue) {
+        verdict = v;
+        break;
+      }
+    }
+    correction<T>(st, g, M, Wst, Rt, Gw, it == 0, f->tw, tm);
+    ++steps;
+  }
+  // G = 2^-k (G~)^*
+  tm.begin(MSQRT_T_VALIDATE);
+  hipLaunchKernelGGL(x_out_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, (const double*)Gw, cplx, 1,
+                     f->rscale_dev(), G, ldg, part);
+  MSQRT_LAUNCH_CHECK();
+  tm.end();
+  int timed_out = 0;
+  trsylv_errors(st, f->tw, &timed_out, nullptr);
+  tm.collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "triangular Sylvester solve: dataflow wait timed out"};
+  msqrt_status status = MSQRT_OK;
+  if (verdict == Verdict2::Diverged) status = MSQRT_ERR_DIVERGED;
+  else if (verdict != Verdict2::Converged) status = MSQRT_ERR_NOT_CONVERGED;
+  if (info) {
+    info->steps = steps;
+    info->relres = hist.back();
+    info->nhist = (int)std::min<size_t>(64, hist.size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
+    info->prec_used = f->prec;
+    info->struct_used = f->structure;
+    info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+  }
+  return status;
+}
+
+template msqrt_status factor_general<float>(Factor*, const double*, int64_t, int, hipStream_t,
+                                            PhaseTimer*);
+template msqrt_status factor_general<double>(Factor*, const double*, int64_t, int, hipStream_t,
+                                             PhaseTimer*);
+template msqrt_status refine_general<float>(Factor*, const double*, int64_t, double*, int64_t, int,
+                                            int, double, hipStream_t, msqrt_info*, PhaseTimer&);
+template msqrt_status refine_general<double>(Factor*, const double*, int64_t, double*, int64_t,
+                                             int, int, double, hipStream_t, msqrt_info*,
+                                             PhaseTimer&);
+template msqrt_status backward_general<float>(Factor*, const double*, int64_t, const double*,
+                                              int64_t, double*, int64_t, int, double, hipStream_t,
+                                              msqrt_info*, PhaseTimer&);
+template msqrt_status backward_general<double>(Factor*, const double*, int64_t, const double*,
+                                               int64_t, double*, int64_t, int, double,
+                                               hipStream_t, msqrt_info*, PhaseTimer&);
+
+}  // namespace msqrt

@@ -1,0 +1,559 @@
+// Complex Schur form of an upper Hessenberg matrix by the shifted QR
+// algorithm (the Schur decomposition of Alg. 2), GPU-resident.
+//
+//  * Blocks of at most kWin<T> rows are finished inside one workgroup: the
+//    block and the accumulated unitary U live in LDS and the single-shift
+//    QR iteration (Wilkinson shifts, exceptional shifts after 10 iterations
+//    without deflation) runs to completion (small_schur_kernel).
+//  * Larger active blocks are swept with a chain of ns single-shift bulges
+//    (shifts = eigenvalues of the trailing ns x ns block).  The chain is
+//    chased down in windows: one workgroup applies every rotation that fits
+//    in the window to the LDS copy of the window and accumulates U
+//    (chase_kernel); the rest of H and Z is then updated with U in one
+//    launch (apply_u_kernel): H(win, right) <- U^* H(win, right),
+//    H(above, win) <- H(above, win) U, Z(:, win) <- Z(:, win) U.
+//  * After every sweep subdiagonal entries below u (|h_kk| + |h_k+1,k+1|)
+//    are set to zero and the active block shrinks from the bottom.
+// Rotations: G = [c s; -conj(s) c] with real c, H <- G H G^*, U <- U G^*.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+#include "schur.hpp"
+
+namespace msqrt {
+
+namespace {
+
+template <typename T> struct Win;
+template <> struct Win<float> { static constexpr int W = 96, NS = 24; };
+template <> struct Win<double> { static constexpr int W = 64, NS = 16; };
+
+constexpr int kQrThreads = 256;
+constexpr int kMaxNs = 32;
+constexpr int kExited = 1 << 30;
+
+template <typename T>
+__device__ inline T eps_of();
+template <> __device__ inline float eps_of<float>() { return 5.9604645e-08f; }
+template <> __device__ inline double eps_of<double>() { return 1.1102230246251565e-16; }
+template <typename T>
+__device__ inline T tiny_of();
+template <> __device__ inline float tiny_of<float>() { return 1.1754944e-38f; }
+template <> __device__ inline double tiny_of<double>() { return 2.2250738585072014e-308; }
+
+template <typename T>
+__device__ inline T cabs1(cx<T> a) { return fabs(a.r) + fabs(a.i); }
+
+// Rotation with G [f; g] = [r; 0].
+template <typename T>
+__device__ inline void make_rot(cx<T> f, cx<T> g, T& c, cx<T>& s) {
+  const T ag = cabs1(g);
+  if (ag == T(0)) { c = T(1); s = {T(0), T(0)}; return; }
+  const T af = hypot(f.r, f.i);
+  const T agg = hypot(g.r, g.i);
+  if (af == T(0)) { c = T(0); s = cscale(cconj(g), T(1) / agg); return; }
+  const T nrm = hypot(af, agg);
+  c = af / nrm;
+  // s = (f / |f|) conj(g) / nrm
+  s = cscale(cmul(cscale(f, T(1) / af), cconj(g)), T(1) / nrm);
+}
+
+// [a; b] <- G [a; b]
+template <typename T>
+__device__ inline void rot_rows(T c, cx<T> s, cx<T>& a, cx<T>& b) {
+  const cx<T> na = cadd(cscale(a, c), cmul(s, b));
+  const cx<T> nb = csub(cscale(b, c), cmulc(s, a));
+  a = na;
+  b = nb;
+}
+// [a, b] <- [a, b] G^*
+template <typename T>
+__device__ inline void rot_cols(T c, cx<T> s, cx<T>& a, cx<T>& b) {
+  const cx<T> na = cadd(cscale(a, c), cmul(b, cconj(s)));
+  const cx<T> nb = csub(cscale(b, c), cmul(a, s));
+  a = na;
+  b = nb;
+}
+
+// One similarity rotation on indices (r, r+1) of the LDS matrix h (column-
+// major, stride ldh) of order m and of U (same stride, order m when u != 0):
+// rows r, r+1 for columns [c0, m), columns r, r+1 for rows [0, r1].
+template <typename T>
+__device__ void apply_rot(cx<T>* h, int ldh, cx<T>* u, int m, int r, int c0, int r1, T c,
+                          cx<T> s) {
+  const int t = threadIdx.x;
+  const int nrow = m - c0;            // row-op columns (incl. the corner)
+  const int ncol = r1 + 1;            // col-op rows (incl. the corner)
+  const int nu = u ? m : 0;
+  const int total = nrow + ncol + nu;
+  for (int x = t; x < total; x += blockDim.x) {
+    if (x < nrow) {
+      const int j = c0 + x;
+      if (j == r || j == r + 1) continue;
+      rot_rows(c, s, h[r + j * ldh], h[r + 1 + j * ldh]);
+    } else if (x < nrow + ncol) {
+      const int i = x - nrow;
+      if (i == r || i == r + 1) continue;
+      rot_cols(c, s, h[i + r * ldh], h[i + (r + 1) * ldh]);
+    } else {
+      const int i = x - nrow - ncol;
+      rot_cols(c, s, u[i + r * ldh], u[i + (r + 1) * ldh]);
+    }
+  }
+  if (__builtin_amdgcn_readfirstlane(t / kWave) == 0) {
+    // corner: rows then columns (G M G^*); wave 0 computes it redundantly
+    // (identical values) so the branch is wave-uniform
+    cx<T> a = h[r + r * ldh], b = h[r + (r + 1) * ldh];
+    cx<T> cc = h[r + 1 + r * ldh], d = h[r + 1 + (r + 1) * ldh];
+    rot_rows(c, s, a, cc);
+    rot_rows(c, s, b, d);
+    rot_cols(c, s, a, b);
+    rot_cols(c, s, cc, d);
+    h[r + r * ldh] = a;
+    h[r + (r + 1) * ldh] = b;
+    h[r + 1 + r * ldh] = cc;
+    h[r + 1 + (r + 1) * ldh] = d;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline cx<T> csqrt_any(cx<T> z) { return csqrt_principal(z); }
+
+// Eigenvalue of the 2 x 2 [[a, b], [c, d]] closer to d.
+template <typename T>
+__device__ inline cx<T> wilkinson(cx<T> a, cx<T> b, cx<T> c, cx<T> d) {
+  const cx<T> p = cscale(csub(a, d), T(0.5));
+  const cx<T> disc = csqrt_any(cadd(cmul(p, p), cmul(b, c)));
+  const cx<T> mid = cscale(cadd(a, d), T(0.5));
+  const cx<T> l1 = cadd(mid, disc), l2 = csub(mid, disc);
+  return cabs1(csub(l1, d)) <= cabs1(csub(l2, d)) ? l1 : l2;
+}
+
+// Single-shift QR on the LDS matrix h (order m) until upper triangular.
+// Returns false if the iteration limit was hit.
+template <typename T>
+__device__ bool lds_qr(cx<T>* h, int ldh, cx<T>* u, int m) {
+  __shared__ int sh_l;
+  const T ulp = eps_of<T>(), small = tiny_of<T>() * T(1e4);
+  int hi = m - 1, its = 0, total = 0;
+  const int itmax = 30 * max(10, m);
+  const bool w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave) == 0;
+  while (hi >= 1) {
+    if (w0) sh_l = 0;
+    __syncthreads();
+    for (int k = hi - threadIdx.x; k >= 1; k -= blockDim.x) {
+      const T sub = cabs1(h[k + (k - 1) * ldh]);
+      const T tst = cabs1(h[k - 1 + (k - 1) * ldh]) + cabs1(h[k + k * ldh]);
+      if (sub <= ulp * tst || sub <= small) atomicMax(&sh_l, k);
+    }
+    __syncthreads();
+    // uniform by construction; readfirstlane lets the compiler see it, so the
+    // barrier-carrying loops below are compiled as uniform control flow
+    const int l = __builtin_amdgcn_readfirstlane(sh_l);
+    __syncthreads();
+    if (l > 0 && w0) h[l + (l - 1) * ldh] = {T(0), T(0)};
+    if (l == hi) { hi -= 1; its = 0; __syncthreads(); continue; }
+    if (++total > itmax) return false;
+    ++its;
+    cx<T> sigma;
+    if (its % 10 == 0) {
+      // exceptional shift
+      const T e = T(0.75) * cabs1(h[hi + (hi - 1) * ldh]);
+      sigma = cadd(h[hi + hi * ldh], cx<T>{e, T(0)});
+    } else {
+      sigma = wilkinson(h[hi - 1 + (hi - 1) * ldh], h[hi - 1 + hi * ldh], h[hi + (hi - 1) * ldh],
+                        h[hi + hi * ldh]);
+    }
+    __syncthreads();
+    for (int k = l; k < hi; ++k) {
+      cx<T> f, g;
+      if (k == l) {
+        f = csub(h[l + l * ldh], sigma);
+        g = h[l + 1 + l * ldh];
+      } else {
+        f = h[k + (k - 1) * ldh];
+        g = h[k + 1 + (k - 1) * ldh];
+      }
+      T c;
+      cx<T> s;
+      make_rot(f, g, c, s);
+      __syncthreads();
+      const int c0 = k == l ? l : k - 1;
+      apply_rot(h, ldh, u, m, k, c0, min(k + 2, hi), c, s);
+      if (k > l && w0) h[k + 1 + (k - 1) * ldh] = {T(0), T(0)};
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
+template <typename T>
+__device__ inline cx<T> gload(const T* H, int64_t ld, int64_t i, int64_t j) {
+  return {H[i + j * ld], H[i + j * ld + ld / 2]};
+}
+template <typename T>
+__device__ inline void gstore(T* H, int64_t ld, int64_t i, int64_t j, cx<T> v) {
+  H[i + j * ld] = v.r;
+  H[i + j * ld + ld / 2] = v.i;
+}
+
+// Block [b0, b0 + m) of H: full Schur form with U (mode 0) or eigenvalues
+// only into eig (mode 1, H untouched).
+template <typename T>
+__global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, int b0, int m,
+                                                                 int mode, T* Uo, cx<T>* eig,
+                                                                 int* status) {
+  constexpr int W = Win<T>::W;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* u = h + (W + 1) * W;
+  const int ldh = W + 1;
+  const int64_t ld = 2 * (int64_t)n;
+  for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
+    const int i = x % m, j = x / m;
+    h[i + j * ldh] = (i <= j + 1) ? gload(H, ld, b0 + i, b0 + j) : cx<T>{T(0), T(0)};
+    if (mode == 0) u[i + j * ldh] = {i == j ? T(1) : T(0), T(0)};
+  }
+  __syncthreads();
+  const bool ok = lds_qr<T>(h, ldh, mode == 0 ? u : nullptr, m);
+  __syncthreads();
+  if (!ok && threadIdx.x == 0) atomicOr(status, 1);
+  if (mode == 1) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) eig[i] = h[i + i * ldh];
+    return;
+  }
+  for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
+    const int i = x % m, j = x / m;
+    gstore(H, ld, b0 + i, b0 + j, i <= j ? h[i + j * ldh] : cx<T>{T(0), T(0)});
+    Uo[i + (int64_t)j * 2 * W] = u[i + j * ldh].r;
+    Uo[i + (int64_t)j * 2 * W + W] = u[i + j * ldh].i;
+  }
+}
+
+// ---- the bulge chain schedule (shared by host and device)
+
+struct Chain {
+  int ns, nintro;
+  int pos[kMaxNs];  // bulge entry at (pos + 2, pos); kExited when gone
+};
+
+// One round over the chain inside the window [s, wend]: every bulge moves
+// one step if it stays in the window and keeps two rows to the bulge below
+// (bottom bulge first), then a new bulge is introduced at lo if there is
+// room.  op(kind, k, j): kind 0 = move bulge at k, 1 = exit move at k,
+// 2 = introduce bulge j at lo.
+template <class Op>
+__host__ __device__ inline bool chain_round(Chain& ch, int s, int wend, int lo, int hi, Op&& op) {
+  bool progress = false;
+  for (int j = 0; j < ch.nintro; ++j) {
+    const int k = ch.pos[j];
+    if (k == kExited) continue;
+    const bool exit_move = (k + 2 == hi);
+    if (k < s) continue;
+    if (exit_move ? (k + 2 > wend) : (k + 3 > wend)) continue;
+    if (j > 0 && ch.pos[j - 1] != kExited && ch.pos[j - 1] < k + 3) continue;
+    op(exit_move ? 1 : 0, k, j);
+    ch.pos[j] = exit_move ? kExited : k + 1;
+    progress = true;
+  }
+  if (ch.nintro < ch.ns && s <= lo && lo + 2 <= wend &&
+      (ch.nintro == 0 || ch.pos[ch.nintro - 1] == kExited || ch.pos[ch.nintro - 1] >= lo + 2)) {
+    op(2, lo, ch.nintro);
+    ch.pos[ch.nintro] = lo;
+    ch.nintro++;
+    progress = true;
+  }
+  return progress;
+}
+
+struct NoOp {
+  __host__ __device__ void operator()(int, int, int) const {}
+};
+
+template <typename T>
+__global__ __launch_bounds__(kQrThreads) void chase_kernel(int n, T* H, int s, int wl, int lo,
+                                                           int hi, Chain ch, const cx<T>* shifts,
+                                                           T* Uo) {
+  constexpr int W = Win<T>::W;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* u = h + (W + 1) * W;
+  const int ldh = W + 1;
+  const int64_t ld = 2 * (int64_t)n;
+  for (int x = threadIdx.x; x < wl * wl; x += blockDim.x) {
+    const int i = x % wl, j = x / wl;
+    h[i + j * ldh] = (i <= j + 2) ? gload(H, ld, s + i, s + j) : cx<T>{T(0), T(0)};
+    u[i + j * ldh] = {i == j ? T(1) : T(0), T(0)};
+  }
+  __syncthreads();
+  const int wend = s + wl - 1;
+  auto op = [&](int kind, int k, int j) {
+    const int kl = k - s;
+    cx<T> f, g;
+    if (kind == 2) {
+      f = csub(h[kl + kl * ldh], shifts[j]);
+      g = h[kl + 1 + kl * ldh];
+    } else {
+      f = h[kl + 1 + kl * ldh];
+      g = h[kl + 2 + kl * ldh];
+    }
+    T c;
+    cx<T> sr;
+    make_rot(f, g, c, sr);
+    __syncthreads();
+    if (kind == 2) {
+      apply_rot(h, ldh, u, wl, kl, kl, min(kl + 2, wl - 1), c, sr);
+    } else {
+      apply_rot(h, ldh, u, wl, kl + 1, kl, min(kl + 3, wl - 1), c, sr);
+      if (__builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave) == 0)
+        h[kl + 2 + kl * ldh] = {T(0), T(0)};
+      __syncthreads();
+    }
+  };
+  while (chain_round(ch, s, wend, lo, hi, op)) {
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < wl * wl; x += blockDim.x) {
+    const int i = x % wl, j = x / wl;
+    gstore(H, ld, s + i, s + j, h[i + j * ldh]);
+    Uo[i + (int64_t)j * 2 * W] = u[i + j * ldh].r;
+    Uo[i + (int64_t)j * 2 * W + W] = u[i + j * ldh].i;
+  }
+}
+
+// Off-window update with U (order bl, stacked, ld 2W):
+//   region R: H(b0:b0+bl, b0+bl:n) <- U^* H(...)       (column blocks of 32)
+//   region A: H(0:b0, b0:b0+bl)    <- H(...) U          (row blocks of 32)
+//   region Z: Z(0:n, b0:b0+bl)     <- Z(...) U          (row blocks of 32)
+template <typename T>
+__global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, int b0, int bl,
+                                                             const T* Uo, int gR, int gA) {
+  constexpr int W = Win<T>::W;
+  constexpr int Q = W / 8;  // outputs per thread along the window index
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* u = reinterpret_cast<cx<T>*>(smem_raw);  // (W + 1) x W
+  cx<T>* pnl = u + (W + 1) * W;                    // 32 x W panel, stride W + 1 or 33
+  const int ldu = W + 1;
+  const int64_t ld = 2 * (int64_t)n;
+  const int t = threadIdx.x;
+  for (int x = t; x < bl * bl; x += blockDim.x) {
+    const int i = x % bl, j = x / bl;
+    u[i + j * ldu] = {Uo[i + (int64_t)j * 2 * W], Uo[i + (int64_t)j * 2 * W + W]};
+  }
+  const int b = blockIdx.x;
+  if (b < gR) {
+    // columns c0 .. c0+31 of the rows b0 .. b0+bl
+    const int c0 = b0 + bl + 32 * b;
+    const int nc = min(32, n - c0);
+    for (int x = t; x < bl * 32; x += blockDim.x) {
+      const int i = x % bl, j = x / bl;
+      pnl[i + j * ldu] = j < nc ? gload(H, ld, b0 + i, c0 + j) : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    const int jj = t % 32, i0 = t / 32;
+    cx<T> acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = {T(0), T(0)};
+    for (int k = 0; k < bl; ++k) {
+      const cx<T> hv = pnl[k + jj * ldu];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int i = i0 + 8 * q;
+        if (i < bl) acc[q] = cadd(acc[q], cmulc(u[k + i * ldu], hv));
+      }
+    }
+    if (jj < nc) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int i = i0 + 8 * q;
+        if (i < bl) gstore(H, ld, b0 + i, c0 + jj, acc[q]);
+      }
+    }
+    return;
+  }
+  // row block: region A (H rows 0..b0) or Z (rows 0..n)
+  T* M;
+  int r0, nr;
+  if (b < gR + gA) {
+    M = H;
+    r0 = 32 * (b - gR);
+    nr = min(32, b0 - r0);
+  } else {
+    M = Z;
+    r0 = 32 * (b - gR - gA);
+    nr = min(32, n - r0);
+  }
+  const int ldp = 33;
+  for (int x = t; x < 32 * bl; x += blockDim.x) {
+    const int i = x % 32, j = x / 32;
+    pnl[i + j * ldp] = i < nr ? gload(M, ld, r0 + i, b0 + j) : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  const int ii = t % 32, j0 = t / 32;
+  cx<T> acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = {T(0), T(0)};
+  for (int k = 0; k < bl; ++k) {
+    const cx<T> hv = pnl[ii + k * ldp];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = j0 + 8 * q;
+      if (j < bl) acc[q] = cadd(acc[q], cmul(hv, u[k + j * ldu]));
+    }
+  }
+  if (ii < nr) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = j0 + 8 * q;
+      if (j < bl) gstore(M, ld, r0 + ii, b0 + j, acc[q]);
+    }
+  }
+}
+
+// Zero negligible subdiagonal entries in (lo, hi] and report the largest such
+// index (or lo) in out[0].
+template <typename T>
+__global__ __launch_bounds__(1024) void deflate_kernel(int n, T* H, int lo, int hi, int* out) {
+  __shared__ int best;
+  const int64_t ld = 2 * (int64_t)n;
+  if (threadIdx.x == 0) best = lo;
+  __syncthreads();
+  const T ulp = eps_of<T>(), small = tiny_of<T>() * T(1e4);
+  for (int k = lo + 1 + threadIdx.x; k <= hi; k += blockDim.x) {
+    const cx<T> sub = gload(H, ld, k, k - 1);
+    const T tst = cabs1(gload(H, ld, k - 1, k - 1)) + cabs1(gload(H, ld, k, k));
+    const T a = cabs1(sub);
+    if (a <= ulp * tst || a <= small) {
+      gstore(H, ld, k, k - 1, cx<T>{T(0), T(0)});
+      atomicMax(&best, k);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = best;
+}
+
+template <typename T>
+size_t win_lds() {
+  constexpr int W = Win<T>::W;
+  return sizeof(cx<T>) * (size_t)(W + 1) * W * 2;
+}
+
+template <typename T>
+void launch_apply(hipStream_t st, int n, T* H, T* Z, int b0, int bl, const T* U) {
+  const int gR = (int)ceil_div(n - b0 - bl, 32);
+  const int gA = (int)ceil_div(b0, 32);
+  const int gZ = (int)ceil_div(n, 32);
+  const int g = gR + gA + gZ;
+  if (g == 0) return;
+  hipLaunchKernelGGL(apply_u_kernel<T>, dim3(g), dim3(kQrThreads), win_lds<T>(), st, n, H, Z, b0,
+                     bl, U, gR, gA);
+  MSQRT_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+template <typename T>
+bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
+  constexpr int W = Win<T>::W, NS = Win<T>::NS;
+  static bool attr_set = false;
+  if (!attr_set) {
+    MSQRT_HIP(hipFuncSetAttribute((const void*)small_schur_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
+    MSQRT_HIP(hipFuncSetAttribute((const void*)chase_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
+    MSQRT_HIP(hipFuncSetAttribute((const void*)apply_u_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
+    attr_set = true;
+  }
+  if (n <= 0) return true;
+  T* U = w.U.ensure<T>((int64_t)2 * W * W);
+  cx<T>* shifts = w.shifts.ensure<cx<T>>(kMaxNs);
+  int* flag = w.flag.ensure<int>(4);
+  MSQRT_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, st));
+  int hi = n - 1;
+  int sweeps = 0, stuck = 0, last_hi = -1, last_lo = -1;
+  const int max_sweeps = 30 * std::max(10, n / NS) + 100;
+  while (hi >= 0) {
+    int lo = 0;
+    if (hi > 0) {
+      hipLaunchKernelGGL(deflate_kernel<T>, dim3(1), dim3(1024), 0, st, n, H, 0, hi, flag + 1);
+      MSQRT_LAUNCH_CHECK();
+      MSQRT_HIP(hipMemcpyAsync(&lo, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      MSQRT_HIP(hipStreamSynchronize(st));
+    }
+    const int m = hi - lo + 1;
+    if (m <= W) {
+      if (m > 1) {
+        hipLaunchKernelGGL(small_schur_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H,
+                           lo, m, 0, U, shifts, flag);
+        MSQRT_LAUNCH_CHECK();
+        launch_apply<T>(st, n, H, Z, lo, m, U);
+      }
+      hi = lo - 1;
+      continue;
+    }
+    if (++sweeps > max_sweeps) return false;
+    if (hi == last_hi && lo == last_lo) ++stuck;
+    else stuck = 0;
+    last_hi = hi;
+    last_lo = lo;
+    // shifts: eigenvalues of the trailing NS x NS block
+    const int ns = NS;
+    hipLaunchKernelGGL(small_schur_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H,
+                       hi - ns + 1, ns, 1, U, shifts, flag);
+    MSQRT_LAUNCH_CHECK();
+    if (stuck > 0 && stuck % 6 == 0) {
+      // exceptional sweep: perturb the shifts by a multiple of the coupling
+      std::vector<cx<T>> hs(ns);
+      MSQRT_HIP(hipMemcpyAsync(hs.data(), shifts, sizeof(cx<T>) * ns, hipMemcpyDeviceToHost, st));
+      T sub[2] = {0, 0};
+      MSQRT_HIP(hipMemcpyAsync(&sub[0], H + hi + (int64_t)(hi - 1) * 2 * n, sizeof(T),
+                               hipMemcpyDeviceToHost, st));
+      MSQRT_HIP(hipMemcpyAsync(&sub[1], H + n + hi + (int64_t)(hi - 1) * 2 * n, sizeof(T),
+                               hipMemcpyDeviceToHost, st));
+      MSQRT_HIP(hipStreamSynchronize(st));
+      const T e = T(0.75) * (std::fabs(sub[0]) + std::fabs(sub[1]));
+      for (int j = 0; j < ns; ++j) hs[j].r += (j % 2 ? -e : e), hs[j].i += T(0.5) * e;
+      MSQRT_HIP(hipMemcpyAsync(shifts, hs.data(), sizeof(cx<T>) * ns, hipMemcpyHostToDevice, st));
+      MSQRT_HIP(hipStreamSynchronize(st));
+    }
+    Chain ch;
+    ch.ns = ns;
+    ch.nintro = 0;
+    for (int j = 0; j < kMaxNs; ++j) ch.pos[j] = -1;
+    int s = lo;
+    for (int guard = 0;; ++guard) {
+      if (guard > 4 * n) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge schedule did not finish"};
+      const int wl = std::min(W, hi - s + 1);
+      hipLaunchKernelGGL(chase_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H, s, wl,
+                         lo, hi, ch, (const cx<T>*)shifts, U);
+      MSQRT_LAUNCH_CHECK();
+      launch_apply<T>(st, n, H, Z, s, wl, U);
+      while (chain_round(ch, s, s + wl - 1, lo, hi, NoOp{})) {
+      }
+      bool all_gone = ch.nintro == ns;
+      int top = kExited;
+      for (int j = 0; j < ch.nintro; ++j)
+        if (ch.pos[j] != kExited) {
+          all_gone = false;
+          top = std::min(top, ch.pos[j]);
+        }
+      if (all_gone) break;
+      const int ns_next = ch.nintro < ns ? lo : top;
+      if (ns_next == s) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge chain does not fit the window"};
+      s = ns_next;
+    }
+  }
+  int hflag = 0;
+  MSQRT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  return hflag == 0;
+}
+
+template bool hseqr<float>(hipStream_t, int, float*, float*, HseqrWork&);
+template bool hseqr<double>(hipStream_t, int, double*, double*, HseqrWork&);
+
+}  // namespace msqrt

@@ -56,6 +56,13 @@ int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda, 
                           const double* Xb, int64_t ldb, int64_t sXb, const double* C,
                           int64_t ldc, int64_t sC, float* Rl, double* R64, int64_t ldr, int64_t sR,
                           double* partials, int batch);
+// R_b = cscale[b] C_b - op(A_b) op(B_b) (float64, M x N, inner K); R as float
+// (Rl) or double (R64); partials[b * ntiles + tile] = sum of R^2.  Returns
+// ntiles.
+int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
+                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+                     const double* C, int64_t ldc, int64_t sC, const double* cscale, float* Rl,
+                     double* R64, int64_t ldr, int64_t sR, double* partials, int batch);
 // Y = (op(A) op(B)) ./ (s_i + s_j)
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,

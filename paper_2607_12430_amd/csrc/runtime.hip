@@ -220,7 +220,10 @@ msqrt_status refine(Factor* f, const double* A, int64_t lda, int64_t sA, double*
       return refine_hpd<double>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
     return refine_hpd<float>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
   }
-  throw Error{MSQRT_ERR_UNSUPPORTED, "general (non-HPD) refinement is not available in this build"};
+  // general path: one matrix; X is read and written at the caller's scale
+  if (f->prec == MSQRT_PREC_FP64)
+    return refine_general<double>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
+  return refine_general<float>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,8 +375,9 @@ msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gba
       return backward_hpd<double>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
     return backward_hpd<float>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
   }
-  set_last_error("backward for the general path is not available in this build");
-  return MSQRT_ERR_UNSUPPORTED;
+  if (f->prec == MSQRT_PREC_FP64)
+    return backward_general<double>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
+  return backward_general<float>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
 }
 
 // Computes ||A_b||_F and the scale exponents k_b = round(log4(||A_b||_F / sqrt(n)))
@@ -547,12 +551,23 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
   // a nearby matrix.
   {
     std::vector<int> k = f->kexp;
-    analyse_input(f, (const double*)dA, lda, strideA, false, stream);
+    if (f->structure == MSQRT_STRUCT_GENERAL)
+      analyse_input_general(f, (const double*)dA, lda, f->dtype == MSQRT_COMPLEX128, stream);
+    else
+      analyse_input(f, (const double*)dA, lda, strideA, false, stream);
     f->kexp = k;
     f->upload_scales(stream);
   }
   for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
   double* X = (double*)dX;
+  if (f->structure == MSQRT_STRUCT_GENERAL) {
+    msqrt_status s = refine(f, (const double*)dA, lda, strideA, X, ldx, strideX, init_from_factor,
+                            maxit, tol, stream, info, tm);
+    MSQRT_HIP(hipStreamSynchronize(stream));
+    tm.collect();
+    if (info) info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+    return s;
+  }
   // Refinement runs on the scaled problem A/4^k: bring X to that scale.
   launch_scale_inplace(stream, (int)f->n, X, ldx, strideX, f->rscale_dev(), (int)f->batch);
   msqrt_status s = refine(f, (const double*)dA, lda, strideA, X, ldx, strideX, init_from_factor,
@@ -616,9 +631,11 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
       for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
       st = refine(f.get(), (const double*)dA, lda, strideA, (double*)dX, ldx, strideX, 1, o.maxit,
                   o.tol, stream, info, tm);
-      tm.begin(MSQRT_T_VALIDATE);
-      launch_scale_inplace(stream, (int)n, (double*)dX, ldx, strideX, f->uscale_dev(), (int)o.batch);
-      tm.end();
+      if (f->structure == MSQRT_STRUCT_HPD) {
+        tm.begin(MSQRT_T_VALIDATE);
+        launch_scale_inplace(stream, (int)n, (double*)dX, ldx, strideX, f->uscale_dev(), (int)o.batch);
+        tm.end();
+      }
       MSQRT_HIP(hipStreamSynchronize(stream));
       tm.collect();
       if (info) { info->prec_used = prec; info->struct_used = f->structure; info->scale_exp = f->kexp[0]; }

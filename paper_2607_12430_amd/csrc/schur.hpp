@@ -1,0 +1,49 @@
+// Complex Schur decomposition and triangular solvers of the general path
+// (Alg. 2): Hessenberg reduction, shifted QR, triangular square root and the
+// triangular Sylvester solver.  All matrices are planar complex in the
+// stacked layout (real rows 0..n-1, imaginary rows n..2n-1, ld = 2n).
+#pragma once
+
+#include "complex.hpp"
+#include "factor.hpp"
+
+namespace msqrt {
+
+struct GehrdWork {
+  DevBuf V, Tall, Y, W, W2, part, VT;
+};
+
+// H (stacked, n x n) is reduced in place to upper Hessenberg form
+// H <- Q1^* H Q1 (entries below the subdiagonal are set to zero) and
+// Q1 is formed explicitly in Z (stacked, n x n).
+template <typename T>
+void gehrd(hipStream_t st, int n, T* H, T* Z, GehrdWork& w);
+
+struct HseqrWork {
+  DevBuf U, shifts, flag, scratch;
+};
+
+// Complex Schur form by the shifted QR algorithm: H (upper Hessenberg,
+// stacked) becomes upper triangular, Z <- Z U.  Returns false if the
+// iteration did not converge.
+template <typename T>
+bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w);
+
+// Error state of the tile solvers (sticky until trsylv_reset):
+// timed_out = a dataflow wait timed out, nonprincipal = a diagonal entry of T
+// on or next to R<=0.
+void trsylv_reset(hipStream_t st, TrsylvWork& w);
+void trsylv_errors(hipStream_t st, TrsylvWork& w, int* timed_out, int* nonprincipal);
+
+// S = T^{1/2} (principal) for upper triangular T (stacked, n x n); S may not
+// alias T.  Returns false if a diagonal entry of T lies on R<=0.
+template <typename T>
+void trsqrt(hipStream_t st, int n, const T* Tm, T* S, TrsylvWork& w, int* bad);
+
+// Solve S Y + Y S2 = C (S m x m, S2 p x p upper triangular; C m x p,
+// overwritten by Y); all stacked with their own leading dimensions.
+template <typename T>
+void trsyl(hipStream_t st, int m, int p, const T* S, int64_t lds, const T* S2, int64_t lds2, T* C,
+           int64_t ldc, TrsylvWork& w);
+
+}  // namespace msqrt

@@ -1,0 +1,155 @@
+// Test hooks of the general-path stages (include/msqrt_testing.h): host
+// interleaved complex128 in, stage run on the device in complex64 or
+// complex128, host interleaved complex128 out.
+#include <vector>
+
+#include "../../include/msqrt_testing.h"
+#include "kernels.hpp"
+#include "schur.hpp"
+
+using namespace msqrt;
+
+namespace {
+
+// interleaved (ld = rows) -> stacked (ld = 2 * rows) in precision T
+template <typename T>
+std::vector<T> to_stacked_host(int64_t rows, int64_t cols, const double* A) {
+  std::vector<T> s(2 * rows * cols);
+  for (int64_t j = 0; j < cols; ++j)
+    for (int64_t i = 0; i < rows; ++i) {
+      s[i + j * 2 * rows] = (T)A[2 * (i + j * rows)];
+      s[rows + i + j * 2 * rows] = (T)A[2 * (i + j * rows) + 1];
+    }
+  return s;
+}
+template <typename T>
+void from_stacked_host(int64_t rows, int64_t cols, const std::vector<T>& s, double* A) {
+  for (int64_t j = 0; j < cols; ++j)
+    for (int64_t i = 0; i < rows; ++i) {
+      A[2 * (i + j * rows)] = (double)s[i + j * 2 * rows];
+      A[2 * (i + j * rows) + 1] = (double)s[rows + i + j * 2 * rows];
+    }
+}
+template <typename T>
+T* upload(DevBuf& b, const std::vector<T>& h) {
+  T* d = b.ensure<T>((int64_t)h.size());
+  MSQRT_HIP(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return d;
+}
+template <typename T>
+std::vector<T> download(const T* d, size_t cnt) {
+  std::vector<T> h(cnt);
+  MSQRT_HIP(hipMemcpy(h.data(), d, sizeof(T) * cnt, hipMemcpyDeviceToHost));
+  return h;
+}
+
+template <typename T>
+msqrt_status gehrd_impl(int n, const double* A, double* H, double* Q, bool schur) {
+  DevBuf hb, qb;
+  T* dH = upload(hb, to_stacked_host<T>(n, n, A));
+  T* dQ = qb.ensure<T>(2 * (int64_t)n * n);
+  GehrdWork gw;
+  gehrd<T>(nullptr, n, dH, dQ, gw);
+  if (schur) {
+    HseqrWork hw;
+    if (!hseqr<T>(nullptr, n, dH, dQ, hw)) {
+      set_last_error("complex Schur QR did not converge");
+      return MSQRT_ERR_NOT_CONVERGED;
+    }
+  }
+  MSQRT_HIP(hipDeviceSynchronize());
+  from_stacked_host<T>(n, n, download(dH, 2 * (size_t)n * n), H);
+  from_stacked_host<T>(n, n, download(dQ, 2 * (size_t)n * n), Q);
+  return MSQRT_OK;
+}
+
+template <typename T>
+msqrt_status trsqrt_impl(int n, const double* Tm, double* S) {
+  DevBuf tb, sb;
+  T* dT = upload(tb, to_stacked_host<T>(n, n, Tm));
+  T* dS = sb.ensure<T>(2 * (int64_t)n * n);
+  TrsylvWork tw;
+  trsylv_reset(nullptr, tw);
+  trsqrt<T>(nullptr, n, dT, dS, tw, nullptr);
+  int to = 0, np = 0;
+  trsylv_errors(nullptr, tw, &to, &np);
+  if (to) throw Error{MSQRT_ERR_DEVICE, "dataflow wait timed out"};
+  from_stacked_host<T>(n, n, download(dS, 2 * (size_t)n * n), S);
+  if (np) {
+    set_last_error("an eigenvalue lies on or next to the closed negative real axis");
+    return MSQRT_ERR_NO_PRINCIPAL;
+  }
+  return MSQRT_OK;
+}
+
+template <typename T>
+msqrt_status trsyl_impl(int m, int p, const double* S, const double* S2, const double* C,
+                        double* Y) {
+  DevBuf sb, s2b, cb;
+  T* dS = upload(sb, to_stacked_host<T>(m, m, S));
+  T* dS2 = upload(s2b, to_stacked_host<T>(p, p, S2));
+  T* dC = upload(cb, to_stacked_host<T>(m, p, C));
+  TrsylvWork tw;
+  trsylv_reset(nullptr, tw);
+  trsyl<T>(nullptr, m, p, dS, 2 * (int64_t)m, dS2, 2 * (int64_t)p, dC, 2 * (int64_t)m, tw);
+  int to = 0;
+  trsylv_errors(nullptr, tw, &to, nullptr);
+  if (to) throw Error{MSQRT_ERR_DEVICE, "dataflow wait timed out"};
+  from_stacked_host<T>(m, p, download(dC, 2 * (size_t)m * p), Y);
+  return MSQRT_OK;
+}
+
+template <class F>
+msqrt_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return (msqrt_status)e.status;
+  } catch (...) {
+    set_last_error("unknown error");
+    return MSQRT_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" msqrt_status msqrt_test_gehrd(msqrt_prec prec, int64_t n, const double* A, double* H,
+                                         double* Q) {
+  if (n < 1 || !A || !H || !Q || n > 16384) return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    if (prec == MSQRT_PREC_FP64) return gehrd_impl<double>((int)n, A, H, Q, false);
+    if (prec == MSQRT_PREC_FP32) return gehrd_impl<float>((int)n, A, H, Q, false);
+    return MSQRT_ERR_INVALID_ARG;
+  });
+}
+
+extern "C" msqrt_status msqrt_test_schur(msqrt_prec prec, int64_t n, const double* A, double* T,
+                                         double* Q) {
+  if (n < 1 || !A || !T || !Q || n > 16384) return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    if (prec == MSQRT_PREC_FP64) return gehrd_impl<double>((int)n, A, T, Q, true);
+    if (prec == MSQRT_PREC_FP32) return gehrd_impl<float>((int)n, A, T, Q, true);
+    return MSQRT_ERR_INVALID_ARG;
+  });
+}
+
+extern "C" msqrt_status msqrt_test_trsqrt(msqrt_prec prec, int64_t n, const double* Tm, double* S) {
+  if (n < 1 || !Tm || !S || n > 16384) return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    if (prec == MSQRT_PREC_FP64) return trsqrt_impl<double>((int)n, Tm, S);
+    if (prec == MSQRT_PREC_FP32) return trsqrt_impl<float>((int)n, Tm, S);
+    return MSQRT_ERR_INVALID_ARG;
+  });
+}
+
+extern "C" msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, const double* S,
+                                         const double* S2, const double* C, double* Y) {
+  if (m < 1 || p < 1 || !S || !S2 || !C || !Y || m > 16384 || p > 16384)
+    return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    if (prec == MSQRT_PREC_FP64) return trsyl_impl<double>((int)m, (int)p, S, S2, C, Y);
+    if (prec == MSQRT_PREC_FP32) return trsyl_impl<float>((int)m, (int)p, S, S2, C, Y);
+    return MSQRT_ERR_INVALID_ARG;
+  });
+}

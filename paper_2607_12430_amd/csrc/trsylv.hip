@@ -1,0 +1,326 @@
+// Blocked triangular square root and triangular Sylvester solver on 32 x 32
+// tiles, as one persistent kernel with tile-level dataflow.
+//
+// Triangular root (Sec. 2, blocked form of Eq. (subst)): for tiles I <= J of
+// the upper triangular T,
+//   diagonal tiles:  S_II = T_II^{1/2} by the recurrence
+//                    s_ii = t_ii^{1/2},  s_ij = (t_ij - sum_{i<k<j} s_ik s_kj) / (s_ii + s_jj);
+//   off-diagonal:    S_II S_IJ + S_IJ S_JJ = T_IJ - sum_{I<K<J} S_IK S_KJ.
+// Triangular Sylvester S Y + Y S2 = C (the correction equation of Alg. 2 and
+// the solver of Alg. 1): for every tile
+//   S_II Y_IJ + Y_IJ S2_JJ = C_IJ - sum_{K>I} S_IK Y_KJ - sum_{K<J} Y_IK S2_KJ,
+// which is the order in which Alg. 1's recursion produces the blocks (rows
+// bottom-up, columns left to right).  Each tile's small Sylvester equation is
+// solved by substitution along its anti-diagonals.
+//
+// Every workgroup takes one tile from an atomic ticket in wavefront order, so
+// every tile a workgroup waits for was taken by a workgroup that is already
+// running: the dataflow cannot deadlock, whatever the dispatch order.  Finished tiles
+// are published with a release fence and a per-tile flag; waits are bounded
+// and a timed-out wait sets a sticky error flag.
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "schur.hpp"
+
+namespace msqrt {
+
+namespace {
+
+constexpr int kTb = 32;
+constexpr int kTThreads = 256;
+constexpr unsigned kSpinLimit = 1u << 22;
+
+struct TileArgs {
+  int mode;  // 0 = square root, 1 = Sylvester
+  int m, p, mt, pt, ntiles;
+  int64_t lda, ldb, ldx;
+  int* flags;
+  int* ticket;
+  int* err;  // [0] wait timed out, [1] eigenvalue on R<=0
+};
+
+template <typename T>
+__device__ inline cx<T> tload(const T* P, int64_t ld, int64_t i, int64_t j) {
+  return {P[i + j * ld], P[i + j * ld + ld / 2]};
+}
+template <typename T>
+__device__ inline void tstore(T* P, int64_t ld, int64_t i, int64_t j, cx<T> v) {
+  P[i + j * ld] = v.r;
+  P[i + j * ld + ld / 2] = v.i;
+}
+
+// Wavefront order of the tiles.
+__device__ inline void tile_of(const TileArgs& a, int tk, int& I, int& J) {
+  if (a.mode == 0) {
+    int d = 0, base = 0;
+    while (base + (a.mt - d) <= tk) { base += a.mt - d; ++d; }
+    I = tk - base;
+    J = I + d;
+    return;
+  }
+  int base = 0;
+  for (int d = 0;; ++d) {
+    const int ilo = max(0, a.mt - 1 - d), ihi = min(a.mt - 1, a.mt - 1 - d + a.pt - 1);
+    const int cnt = ihi - ilo + 1;
+    if (cnt > 0 && tk < base + cnt) {
+      I = ihi - (tk - base);
+      J = d - (a.mt - 1 - I);
+      return;
+    }
+    if (cnt > 0) base += cnt;
+  }
+}
+
+__device__ inline void wait_tile(const TileArgs& a, int I, int J) {
+  // Wave 0 spins as a whole (every lane loads the same flag; the values are
+  // made uniform with readfirstlane), so no single-lane branch sits inside
+  // the barrier-carrying loops of the caller.
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+  if (wave == 0) {
+    int* f = &a.flags[I * a.pt + J];
+    for (unsigned spins = 0;; ++spins) {
+      if (__builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+        break;
+      if (__builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(&a.err[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+        break;
+      if (spins > kSpinLimit) {
+        __hip_atomic_store(&a.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// Loads a tile (rows r0.., cols c0.., extent mr x mc, zero padded) to LDS.
+template <typename T>
+__device__ inline void load_tile(cx<T> (*dst)[kTb + 1], const T* P, int64_t ld, int r0, int c0,
+                                 int mr, int mc) {
+  for (int x = threadIdx.x; x < kTb * kTb; x += blockDim.x) {
+    const int i = x % kTb, j = x / kTb;
+    dst[j][i] = (i < mr && j < mc) ? tload(P, ld, r0 + i, c0 + j) : cx<T>{T(0), T(0)};
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A, const T* B, T* X) {
+  __shared__ cx<T> As[kTb][kTb + 1];  // [col][row]
+  __shared__ cx<T> Bs[kTb][kTb + 1];
+  __shared__ cx<T> Ys[kTb][kTb + 1];
+  __shared__ int sh_tk;
+  const int t = threadIdx.x;
+  const int ti = t % kTb, tj0 = t / kTb;  // owned entries (ti, tj0 + 8 q)
+  const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
+  {
+    // One ticket per workgroup, taken by wave 0 as a whole: lane 0 adds 1,
+    // the other lanes add 0, and lane 0's old value is broadcast.  The
+    // ticket and everything derived from it (tile, loop bounds around the
+    // barriers) are uniform, so the compiler emits only uniform branches
+    // around barriers.
+    if (wave == 0) {
+      const int old = atomicAdd(a.ticket, t == 0 ? 1 : 0);
+      sh_tk = __builtin_amdgcn_readfirstlane(old);
+    }
+    __syncthreads();
+  }
+  const int tk = __builtin_amdgcn_readfirstlane(sh_tk);
+  if (tk >= a.ntiles) return;
+  {
+    int I, J;
+    tile_of(a, tk, I, J);
+    const int mi = min(kTb, a.m - kTb * I), mj = min(kTb, a.p - kTb * J);
+    // right-hand side
+    cx<T> acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = tj0 + 8 * q;
+      acc[q] = (ti < mi && j < mj)
+                   ? tload(a.mode == 0 ? A : X, a.mode == 0 ? a.lda : a.ldx, kTb * I + ti, kTb * J + j)
+                   : cx<T>{T(0), T(0)};
+    }
+    auto subtract = [&]() {
+      __syncthreads();
+      for (int k = 0; k < kTb; ++k) {
+        const cx<T> av = As[k][ti];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = csub(acc[q], cmul(av, Bs[tj0 + 8 * q][k]));
+      }
+      __syncthreads();
+    };
+    if (a.mode == 0 && I == J) {
+      // diagonal tile: the recurrence of Eq. (subst) by superdiagonals
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ys[tj0 + 8 * q][ti] = acc[q];  // T_II into Ys
+      __syncthreads();
+      if (t < mi) {
+        const cx<T> d = Ys[t][t];
+        // on or within a few ulps of the closed negative real axis
+        const T eps = sizeof(T) == 4 ? T(5.9604645e-08) : T(1.1102230246251565e-16);
+        if (d.r <= T(0) && fabs(d.i) <= T(16) * eps * fabs(d.r)) atomicOr(&a.err[1], 1);
+        As[t][t] = csqrt_principal(d);
+      }
+      __syncthreads();
+      for (int d = 1; d < mi; ++d) {
+        if (t < mi - d) {
+          const int i = t, j = t + d;
+          cx<T> s = Ys[j][i];
+          for (int k = i + 1; k < j; ++k) s = csub(s, cmul(As[k][i], As[j][k]));
+          As[j][i] = cdiv(s, cadd(As[i][i], As[j][j]));
+        }
+        __syncthreads();
+      }
+      for (int x = t; x < kTb * kTb; x += blockDim.x) {
+        const int i = x % kTb, j = x / kTb;
+        if (i < mi && j < mj) tstore(X, a.ldx, kTb * I + i, kTb * J + j, i <= j ? As[j][i] : cx<T>{T(0), T(0)});
+      }
+    } else {
+      if (a.mode == 0) {
+        for (int K = I + 1; K < J; ++K) {
+          wait_tile(a, I, K);
+          wait_tile(a, K, J);
+          const int mk = min(kTb, a.m - kTb * K);
+          load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
+          load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
+          subtract();
+        }
+        wait_tile(a, I, I);
+        wait_tile(a, J, J);
+        load_tile(As, X, a.ldx, kTb * I, kTb * I, mi, mi);
+        load_tile(Bs, X, a.ldx, kTb * J, kTb * J, mj, mj);
+      } else {
+        for (int K = a.mt - 1; K > I; --K) {
+          wait_tile(a, K, J);
+          const int mk = min(kTb, a.m - kTb * K);
+          load_tile(As, A, a.lda, kTb * I, kTb * K, mi, mk);
+          load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
+          subtract();
+        }
+        for (int K = 0; K < J; ++K) {
+          wait_tile(a, I, K);
+          const int mk = min(kTb, a.p - kTb * K);
+          load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
+          load_tile(Bs, B, a.ldb, kTb * K, kTb * J, mk, mj);
+          subtract();
+        }
+        load_tile(As, A, a.lda, kTb * I, kTb * I, mi, mi);
+        load_tile(Bs, B, a.ldb, kTb * J, kTb * J, mj, mj);
+      }
+      __syncthreads();
+      // S_II Y + Y S2_JJ = acc by anti-diagonals e = (mi - 1 - i) + j
+      const int ne = mi + mj - 1;
+      for (int e = 0; e < ne; ++e) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = tj0 + 8 * q;
+          if (ti < mi && j < mj && (mi - 1 - ti) + j == e)
+            Ys[j][ti] = cdiv(acc[q], cadd(As[ti][ti], Bs[j][j]));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = tj0 + 8 * q;
+          if (ti < mi && j < mj && (mi - 1 - ti) + j > e) {
+            const int k = mi - 1 - e + j;  // (k, j) on wavefront e
+            if (k > ti && k < mi) acc[q] = csub(acc[q], cmul(As[k][ti], Ys[j][k]));
+            const int k2 = e - (mi - 1 - ti);  // (ti, k2) on wavefront e
+            if (k2 >= 0 && k2 < j) acc[q] = csub(acc[q], cmul(Ys[k2][ti], Bs[j][k2]));
+          }
+        }
+      }
+      __syncthreads();
+      for (int x = t; x < kTb * kTb; x += blockDim.x) {
+        const int i = x % kTb, j = x / kTb;
+        if (i < mi && j < mj) tstore(X, a.ldx, kTb * I + i, kTb * J + j, Ys[j][i]);
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      __threadfence();
+      __hip_atomic_store(&a.flags[I * a.pt + J], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <typename T>
+void launch_tiles(hipStream_t st, TileArgs a, const T* A, const T* B, T* X, TrsylvWork& w) {
+  const int nflags = a.mt * a.pt;
+  int* buf = w.flags.ensure<int>(nflags + 64);
+  a.flags = buf;
+  a.ticket = buf + nflags;
+  const bool fresh = w.ticket.p == nullptr;
+  a.err = w.ticket.ensure<int>(4);
+  if (fresh) MSQRT_HIP(hipMemsetAsync(a.err, 0, sizeof(int) * 4, st));
+  MSQRT_HIP(hipMemsetAsync(buf, 0, sizeof(int) * (nflags + 64), st));
+  // one workgroup per tile; tiles are taken in ticket (wavefront) order, so a
+  // workgroup only ever waits for tiles held by workgroups already running
+  const int grid = a.ntiles;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(tile_kernel<T>, dim3(grid), dim3(kTThreads), 0, st, a, A, B, X);
+  MSQRT_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void trsylv_reset(hipStream_t st, TrsylvWork& w) {
+  int* e = w.ticket.ensure<int>(4);
+  MSQRT_HIP(hipMemsetAsync(e, 0, sizeof(int) * 4, st));
+}
+
+// err[0]: a wait timed out; err[1]: a diagonal entry on R<=0.
+void trsylv_errors(hipStream_t st, TrsylvWork& w, int* timed_out, int* nonprincipal) {
+  int h[4] = {0, 0, 0, 0};
+  if (w.ticket.p) {
+    MSQRT_HIP(hipMemcpyAsync(h, w.ticket.p, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+    MSQRT_HIP(hipStreamSynchronize(st));
+  }
+  if (timed_out) *timed_out = h[0];
+  if (nonprincipal) *nonprincipal = h[1];
+}
+
+template <typename T>
+void trsqrt(hipStream_t st, int n, const T* Tm, T* S, TrsylvWork& w, int* bad) {
+  (void)bad;
+  if (n <= 0) return;
+  const int64_t ld = 2 * (int64_t)n;
+  MSQRT_HIP(hipMemsetAsync(S, 0, sizeof(T) * ld * n, st));
+  TileArgs a{};
+  a.mode = 0;
+  a.m = a.p = n;
+  a.mt = a.pt = (int)ceil_div(n, kTb);
+  a.ntiles = a.mt * (a.mt + 1) / 2;
+  a.lda = ld;
+  a.ldb = ld;
+  a.ldx = ld;
+  launch_tiles<T>(st, a, Tm, Tm, S, w);
+}
+
+template <typename T>
+void trsyl(hipStream_t st, int m, int p, const T* S, int64_t lds, const T* S2, int64_t lds2, T* C,
+           int64_t ldc, TrsylvWork& w) {
+  if (m <= 0 || p <= 0) return;
+  TileArgs a{};
+  a.mode = 1;
+  a.m = m;
+  a.p = p;
+  a.mt = (int)ceil_div(m, kTb);
+  a.pt = (int)ceil_div(p, kTb);
+  a.ntiles = a.mt * a.pt;
+  a.lda = lds;
+  a.ldb = lds2;
+  a.ldx = ldc;
+  launch_tiles<T>(st, a, S, S2, C, w);
+}
+
+template void trsqrt<float>(hipStream_t, int, const float*, float*, TrsylvWork&, int*);
+template void trsqrt<double>(hipStream_t, int, const double*, double*, TrsylvWork&, int*);
+template void trsyl<float>(hipStream_t, int, int, const float*, int64_t, const float*, int64_t,
+                           float*, int64_t, TrsylvWork&);
+template void trsyl<double>(hipStream_t, int, int, const double*, int64_t, const double*, int64_t,
+                            double*, int64_t, TrsylvWork&);
+
+}  // namespace msqrt
