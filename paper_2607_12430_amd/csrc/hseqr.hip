@@ -233,35 +233,40 @@ __global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, in
   }
 }
 
-// ---- the bulge chain schedule (shared by host and device)
-
+// ---- the bulge chain schedule (host)
+//
+// The schedule depends only on (lo, hi, ns, window size), not on the data,
+// so the host builds it for a whole sweep.  It proceeds in rounds: in every
+// round each bulge moves one step if it stays inside the window and keeps
+// two rows to the bulge below it (bottom bulge first), and a new bulge is
+// introduced at lo when there is room.  The rotations of one round act on
+// disjoint index pairs and none changes another's input column, so they
+// commute: the kernel computes them together, applies all row rotations,
+// then all column rotations.
 struct Chain {
   int ns, nintro;
   int pos[kMaxNs];  // bulge entry at (pos + 2, pos); kExited when gone
 };
 
-// One round over the chain inside the window [s, wend]: every bulge moves
-// one step if it stays in the window and keeps two rows to the bulge below
-// (bottom bulge first), then a new bulge is introduced at lo if there is
-// room.  op(kind, k, j): kind 0 = move bulge at k, 1 = exit move at k,
-// 2 = introduce bulge j at lo.
-template <class Op>
-__host__ __device__ inline bool chain_round(Chain& ch, int s, int wend, int lo, int hi, Op&& op) {
+// move code: kind (0 move, 1 exit move, 2 introduce) << 24 | shift << 16 | k - s
+inline int move_code(int kind, int j, int kl) { return (kind << 24) | (j << 16) | kl; }
+
+// One round inside the window [s, wend]; appends the moves to mv.
+inline bool chain_round(Chain& ch, int s, int wend, int lo, int hi, std::vector<int>& mv) {
   bool progress = false;
   for (int j = 0; j < ch.nintro; ++j) {
     const int k = ch.pos[j];
-    if (k == kExited) continue;
+    if (k == kExited || k < s) continue;
     const bool exit_move = (k + 2 == hi);
-    if (k < s) continue;
     if (exit_move ? (k + 2 > wend) : (k + 3 > wend)) continue;
     if (j > 0 && ch.pos[j - 1] != kExited && ch.pos[j - 1] < k + 3) continue;
-    op(exit_move ? 1 : 0, k, j);
+    mv.push_back(move_code(exit_move ? 1 : 0, j, k - s));
     ch.pos[j] = exit_move ? kExited : k + 1;
     progress = true;
   }
   if (ch.nintro < ch.ns && s <= lo && lo + 2 <= wend &&
       (ch.nintro == 0 || ch.pos[ch.nintro - 1] == kExited || ch.pos[ch.nintro - 1] >= lo + 2)) {
-    op(2, lo, ch.nintro);
+    mv.push_back(move_code(2, ch.nintro, lo - s));
     ch.pos[ch.nintro] = lo;
     ch.nintro++;
     progress = true;
@@ -269,54 +274,118 @@ __host__ __device__ inline bool chain_round(Chain& ch, int s, int wend, int lo, 
   return progress;
 }
 
-struct NoOp {
-  __host__ __device__ void operator()(int, int, int) const {}
+// Whole-sweep schedule: per window (s, wl, first round, rounds), per round
+// (first move, moves), and the move codes.
+struct Sweep {
+  std::vector<int> win, rnd, mv;
 };
 
+inline void build_sweep(int lo, int hi, int ns, int W, Sweep& sw) {
+  sw.win.clear();
+  sw.rnd.clear();
+  sw.mv.clear();
+  Chain ch;
+  ch.ns = ns;
+  ch.nintro = 0;
+  for (int j = 0; j < kMaxNs; ++j) ch.pos[j] = -1;
+  int s = lo;
+  for (int guard = 0;; ++guard) {
+    if (guard > 4 * (hi - lo + 2)) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge schedule did not finish"};
+    const int wl = std::min(W, hi - s + 1);
+    const int r0 = (int)sw.rnd.size() / 2;
+    for (;;) {
+      const int m0 = (int)sw.mv.size();
+      if (!chain_round(ch, s, s + wl - 1, lo, hi, sw.mv)) break;
+      sw.rnd.push_back(m0);
+      sw.rnd.push_back((int)sw.mv.size() - m0);
+    }
+    sw.win.push_back(s);
+    sw.win.push_back(wl);
+    sw.win.push_back(r0);
+    sw.win.push_back((int)sw.rnd.size() / 2 - r0);
+    bool all_gone = ch.nintro == ns;
+    int top = kExited;
+    for (int j = 0; j < ch.nintro; ++j)
+      if (ch.pos[j] != kExited) {
+        all_gone = false;
+        top = std::min(top, ch.pos[j]);
+      }
+    if (all_gone) break;
+    const int next = ch.nintro < ns ? lo : top;
+    if (next == s) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge chain does not fit the window"};
+    s = next;
+  }
+}
+
+// One window of a sweep: all rounds of rotations in LDS, U accumulated.
 template <typename T>
-__global__ __launch_bounds__(kQrThreads) void chase_kernel(int n, T* H, int s, int wl, int lo,
-                                                           int hi, Chain ch, const cx<T>* shifts,
-                                                           T* Uo) {
+__global__ __launch_bounds__(kQrThreads) void chase_kernel(int n, T* H, int s, int wl, int nrounds,
+                                                           const int* __restrict__ rnd,
+                                                           const int* __restrict__ mv,
+                                                           const cx<T>* shifts, T* Uo) {
   constexpr int W = Win<T>::W;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* u = h + (W + 1) * W;
+  __shared__ T rot_c[kMaxNs];
+  __shared__ cx<T> rot_s[kMaxNs];
+  __shared__ int rot_r[kMaxNs], rot_c0[kMaxNs], rot_r1[kMaxNs], rot_z[kMaxNs];
   const int ldh = W + 1;
   const int64_t ld = 2 * (int64_t)n;
-  for (int x = threadIdx.x; x < wl * wl; x += blockDim.x) {
+  const int t = threadIdx.x;
+  for (int x = t; x < wl * wl; x += blockDim.x) {
     const int i = x % wl, j = x / wl;
     h[i + j * ldh] = (i <= j + 2) ? gload(H, ld, s + i, s + j) : cx<T>{T(0), T(0)};
     u[i + j * ldh] = {i == j ? T(1) : T(0), T(0)};
   }
   __syncthreads();
-  const int wend = s + wl - 1;
-  auto op = [&](int kind, int k, int j) {
-    const int kl = k - s;
-    cx<T> f, g;
-    if (kind == 2) {
-      f = csub(h[kl + kl * ldh], shifts[j]);
-      g = h[kl + 1 + kl * ldh];
-    } else {
-      f = h[kl + 1 + kl * ldh];
-      g = h[kl + 2 + kl * ldh];
+  for (int ri = 0; ri < nrounds; ++ri) {
+    const int moff = rnd[2 * ri], nm = rnd[2 * ri + 1];
+    // rotations of this round (inputs from the state before the round)
+    if (t < nm) {
+      const int code = mv[moff + t];
+      const int kind = code >> 24, j = (code >> 16) & 0xff, kl = code & 0xffff;
+      cx<T> f, g;
+      int r;
+      if (kind == 2) {
+        f = csub(h[kl + kl * ldh], shifts[j]);
+        g = h[kl + 1 + kl * ldh];
+        r = kl;
+      } else {
+        f = h[kl + 1 + kl * ldh];
+        g = h[kl + 2 + kl * ldh];
+        r = kl + 1;
+      }
+      T c;
+      cx<T> sr;
+      make_rot(f, g, c, sr);
+      rot_c[t] = c;
+      rot_s[t] = sr;
+      rot_r[t] = r;
+      rot_c0[t] = kl;
+      rot_r1[t] = min(kind == 2 ? kl + 2 : kl + 3, wl - 1);
+      rot_z[t] = kind == 2 ? -1 : kl;  // column whose bulge entry becomes 0
     }
-    T c;
-    cx<T> sr;
-    make_rot(f, g, c, sr);
     __syncthreads();
-    if (kind == 2) {
-      apply_rot(h, ldh, u, wl, kl, kl, min(kl + 2, wl - 1), c, sr);
-    } else {
-      apply_rot(h, ldh, u, wl, kl + 1, kl, min(kl + 3, wl - 1), c, sr);
-      if (__builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave) == 0)
-        h[kl + 2 + kl * ldh] = {T(0), T(0)};
-      __syncthreads();
+    // all row rotations (rows r, r+1 of every move; disjoint)
+    for (int x = t; x < nm * wl; x += blockDim.x) {
+      const int m = x / wl, j = x - m * wl;
+      if (j < rot_c0[m]) continue;
+      const int r = rot_r[m];
+      rot_rows(rot_c[m], rot_s[m], h[r + j * ldh], h[r + 1 + j * ldh]);
+      if (j == rot_z[m]) h[r + 1 + j * ldh] = {T(0), T(0)};
     }
-  };
-  while (chain_round(ch, s, wend, lo, hi, op)) {
+    __syncthreads();
+    // all column rotations of H and U (columns r, r+1; disjoint)
+    for (int x = t; x < nm * wl; x += blockDim.x) {
+      const int m = x / wl, i = x - m * wl;
+      const int r = rot_r[m];
+      if (i <= rot_r1[m]) rot_cols(rot_c[m], rot_s[m], h[i + r * ldh], h[i + (r + 1) * ldh]);
+      rot_cols(rot_c[m], rot_s[m], u[i + r * ldh], u[i + (r + 1) * ldh]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int x = threadIdx.x; x < wl * wl; x += blockDim.x) {
+  for (int x = t; x < wl * wl; x += blockDim.x) {
     const int i = x % wl, j = x / wl;
     gstore(H, ld, s + i, s + j, h[i + j * ldh]);
     Uo[i + (int64_t)j * 2 * W] = u[i + j * ldh].r;
@@ -469,6 +538,7 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
     attr_set = true;
   }
   if (n <= 0) return true;
+  Sweep w_sweep;
   T* U = w.U.ensure<T>((int64_t)2 * W * W);
   cx<T>* shifts = w.shifts.ensure<cx<T>>(kMaxNs);
   int* flag = w.flag.ensure<int>(4);
@@ -520,32 +590,26 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
       MSQRT_HIP(hipMemcpyAsync(shifts, hs.data(), sizeof(cx<T>) * ns, hipMemcpyHostToDevice, st));
       MSQRT_HIP(hipStreamSynchronize(st));
     }
-    Chain ch;
-    ch.ns = ns;
-    ch.nintro = 0;
-    for (int j = 0; j < kMaxNs; ++j) ch.pos[j] = -1;
-    int s = lo;
-    for (int guard = 0;; ++guard) {
-      if (guard > 4 * n) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge schedule did not finish"};
-      const int wl = std::min(W, hi - s + 1);
-      hipLaunchKernelGGL(chase_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H, s, wl,
-                         lo, hi, ch, (const cx<T>*)shifts, U);
-      MSQRT_LAUNCH_CHECK();
-      launch_apply<T>(st, n, H, Z, s, wl, U);
-      while (chain_round(ch, s, s + wl - 1, lo, hi, NoOp{})) {
+    Sweep& sw = w_sweep;
+    build_sweep(lo, hi, ns, W, sw);
+    // upload the sweep's rounds and moves (stream-ordered, from a host
+    // staging copy that lives until the next synchronisation)
+    const int nr = (int)sw.rnd.size(), nm = (int)sw.mv.size();
+    int* dsched = w.scratch.ensure<int>(nr + nm + 64);
+    MSQRT_HIP(hipMemcpyAsync(dsched, sw.rnd.data(), sizeof(int) * nr, hipMemcpyHostToDevice, st));
+    MSQRT_HIP(hipMemcpyAsync(dsched + nr, sw.mv.data(), sizeof(int) * nm, hipMemcpyHostToDevice, st));
+    for (size_t wi = 0; wi < sw.win.size(); wi += 4) {
+      const int s = sw.win[wi], wl = sw.win[wi + 1], r0 = sw.win[wi + 2], nrw = sw.win[wi + 3];
+      if (nrw > 0) {
+        hipLaunchKernelGGL(chase_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H, s, wl,
+                           nrw, (const int*)(dsched + 2 * r0), (const int*)(dsched + nr),
+                           (const cx<T>*)shifts, U);
+        MSQRT_LAUNCH_CHECK();
+        launch_apply<T>(st, n, H, Z, s, wl, U);
       }
-      bool all_gone = ch.nintro == ns;
-      int top = kExited;
-      for (int j = 0; j < ch.nintro; ++j)
-        if (ch.pos[j] != kExited) {
-          all_gone = false;
-          top = std::min(top, ch.pos[j]);
-        }
-      if (all_gone) break;
-      const int ns_next = ch.nintro < ns ? lo : top;
-      if (ns_next == s) throw Error{MSQRT_ERR_DEVICE, "Schur QR: bulge chain does not fit the window"};
-      s = ns_next;
     }
+    // the staging vectors are reused by the next sweep: wait for the copies
+    MSQRT_HIP(hipStreamSynchronize(st));
   }
   int hflag = 0;
   MSQRT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

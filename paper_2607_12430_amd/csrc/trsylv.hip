@@ -180,7 +180,13 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
       }
     } else {
       if (a.mode == 0) {
-        for (int K = I + 1; K < J; ++K) {
+        // S_IK S_KJ is ready once tiles (I, K) and (K, J) are, i.e. at
+        // superdiagonal max(K - I, J - K): take K from the middle outwards
+        const int klo = I + 1, khi = J - 1, cnt = khi - klo + 1, mid = (I + J) / 2;
+        for (int q = 0, done = 0; done < cnt; ++q) {
+          const int K = mid + ((q & 1) ? (q + 1) / 2 : -(q / 2));
+          if (K < klo || K > khi) continue;
+          ++done;
           wait_tile(a, I, K);
           wait_tile(a, K, J);
           const int mk = min(kTb, a.m - kTb * K);
@@ -193,18 +199,27 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
         load_tile(As, X, a.ldx, kTb * I, kTb * I, mi, mi);
         load_tile(Bs, X, a.ldx, kTb * J, kTb * J, mj, mj);
       } else {
-        for (int K = a.mt - 1; K > I; --K) {
-          wait_tile(a, K, J);
-          const int mk = min(kTb, a.m - kTb * K);
-          load_tile(As, A, a.lda, kTb * I, kTb * K, mi, mk);
-          load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
-          subtract();
-        }
-        for (int K = 0; K < J; ++K) {
-          wait_tile(a, I, K);
-          const int mk = min(kTb, a.p - kTb * K);
-          load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
-          load_tile(Bs, B, a.ldb, kTb * K, kTb * J, mk, mj);
+        // the column terms S_IK Y_KJ (K > I, ready at wavefront
+        // mt-1-K+J) and the row terms Y_IK S2_KJ (K < J, ready at mt-1-I+K)
+        // are taken merged in order of readiness, so that only the last two
+        // products remain once the final dependencies arrive
+        int kc = a.mt - 1, kr = 0;
+        while (kc > I || kr < J) {
+          const int dc = kc > I ? a.mt - 1 - kc + J : 1 << 30;
+          const int dr = kr < J ? a.mt - 1 - I + kr : 1 << 30;
+          if (dc <= dr) {
+            const int K = kc--;
+            wait_tile(a, K, J);
+            const int mk = min(kTb, a.m - kTb * K);
+            load_tile(As, A, a.lda, kTb * I, kTb * K, mi, mk);
+            load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
+          } else {
+            const int K = kr++;
+            wait_tile(a, I, K);
+            const int mk = min(kTb, a.p - kTb * K);
+            load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
+            load_tile(Bs, B, a.ldb, kTb * K, kTb * J, mk, mj);
+          }
           subtract();
         }
         load_tile(As, A, a.lda, kTb * I, kTb * I, mi, mi);
