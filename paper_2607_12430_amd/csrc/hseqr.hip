@@ -200,6 +200,55 @@ __device__ inline void gstore(T* H, int64_t ld, int64_t i, int64_t j, cx<T> v) {
   H[i + j * ld + ld / 2] = v.i;
 }
 
+// Copies the m x m block at (r0, c0) of a stacked global matrix into the LDS
+// window h (stride W + 1), entries below the band-th subdiagonal as zero.
+// The index map uses the compile-time W and every thread issues all of its
+// loads before the first LDS store, so the global latencies overlap.
+template <typename T, int W, int NT>
+__device__ inline void win_load(cx<T>* h, const T* H, int64_t ld, int r0, int c0, int m,
+                                int band) {
+  constexpr int E = (W * W + NT - 1) / NT;
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = threadIdx.x + NT * e;
+    const int i = x % W, j = x / W;
+    v[e] = {T(0), T(0)};
+    if (x < W * W && i < m && j < m && i <= j + band) v[e] = gload(H, ld, r0 + i, c0 + j);
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = threadIdx.x + NT * e;
+    const int i = x % W, j = x / W;
+    if (x < W * W && i < m && j < m) h[i + j * (W + 1)] = v[e];
+  }
+}
+
+// U window as the identity (order m) in LDS.
+template <typename T, int W, int NT>
+__device__ inline void win_identity(cx<T>* u, int m) {
+  for (int x = threadIdx.x; x < W * W; x += NT) {
+    const int i = x % W, j = x / W;
+    if (i < m && j < m) u[i + j * (W + 1)] = {i == j ? T(1) : T(0), T(0)};
+  }
+}
+
+// Writes the LDS windows back: H block (lower part below the band-th
+// subdiagonal as zero) and U (stacked, ld 2W).
+template <typename T, int W, int NT>
+__device__ inline void win_store(const cx<T>* h, const cx<T>* u, T* H, int64_t ld, int r0, int m,
+                                 int band, T* Uo) {
+  for (int x = threadIdx.x; x < W * W; x += NT) {
+    const int i = x % W, j = x / W;
+    if (i >= m || j >= m) continue;
+    gstore(H, ld, r0 + i, r0 + j, i <= j + band ? h[i + j * (W + 1)] : cx<T>{T(0), T(0)});
+    if (u) {
+      Uo[i + (int64_t)j * 2 * W] = u[i + j * (W + 1)].r;
+      Uo[i + (int64_t)j * 2 * W + W] = u[i + j * (W + 1)].i;
+    }
+  }
+}
+
 // Block [b0, b0 + m) of H: full Schur form with U (mode 0) or eigenvalues
 // only into eig (mode 1, H untouched).
 template <typename T>
@@ -212,11 +261,8 @@ __global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, in
   cx<T>* u = h + (W + 1) * W;
   const int ldh = W + 1;
   const int64_t ld = 2 * (int64_t)n;
-  for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
-    const int i = x % m, j = x / m;
-    h[i + j * ldh] = (i <= j + 1) ? gload(H, ld, b0 + i, b0 + j) : cx<T>{T(0), T(0)};
-    if (mode == 0) u[i + j * ldh] = {i == j ? T(1) : T(0), T(0)};
-  }
+  win_load<T, W, kQrThreads>(h, H, ld, b0, b0, m, 1);
+  if (mode == 0) win_identity<T, W, kQrThreads>(u, m);
   __syncthreads();
   const bool ok = lds_qr<T>(h, ldh, mode == 0 ? u : nullptr, m);
   __syncthreads();
@@ -225,12 +271,7 @@ __global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, in
     for (int i = threadIdx.x; i < m; i += blockDim.x) eig[i] = h[i + i * ldh];
     return;
   }
-  for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
-    const int i = x % m, j = x / m;
-    gstore(H, ld, b0 + i, b0 + j, i <= j ? h[i + j * ldh] : cx<T>{T(0), T(0)});
-    Uo[i + (int64_t)j * 2 * W] = u[i + j * ldh].r;
-    Uo[i + (int64_t)j * 2 * W + W] = u[i + j * ldh].i;
-  }
+  win_store<T, W, kQrThreads>(h, u, H, ld, b0, m, 0, Uo);
 }
 
 // ---- the bulge chain schedule (host)
@@ -318,32 +359,41 @@ inline void build_sweep(int lo, int hi, int ns, int W, Sweep& sw) {
 }
 
 // One window of a sweep: all rounds of rotations in LDS, U accumulated.
+// The window's rounds (first move, count) and move codes are copied to LDS
+// first (at most kSchedCap ints; the host splits longer schedules).
+constexpr int kSchedCap = 3072;
+constexpr int kChaseThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(kQrThreads) void chase_kernel(int n, T* H, int s, int wl, int nrounds,
+__global__ __launch_bounds__(kChaseThreads) void chase_kernel(int n, T* H, int s, int wl, int nrounds,
                                                            const int* __restrict__ rnd,
-                                                           const int* __restrict__ mv,
-                                                           const cx<T>* shifts, T* Uo) {
+                                                           const int* __restrict__ mv, int mv0,
+                                                           int nmv, const cx<T>* shifts, T* Uo) {
   constexpr int W = Win<T>::W;
+  constexpr int G = W <= 64 ? 64 : 128;  // lanes per move in the rotation phases
+  constexpr int NG = kChaseThreads / G;  // moves handled side by side
   extern __shared__ unsigned char smem_raw[];
   cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* u = h + (W + 1) * W;
+  int* sched = reinterpret_cast<int*>(u + (W + 1) * W);  // rounds, then moves
   __shared__ T rot_c[kMaxNs];
   __shared__ cx<T> rot_s[kMaxNs];
   __shared__ int rot_r[kMaxNs], rot_c0[kMaxNs], rot_r1[kMaxNs], rot_z[kMaxNs];
   const int ldh = W + 1;
   const int64_t ld = 2 * (int64_t)n;
   const int t = threadIdx.x;
-  for (int x = t; x < wl * wl; x += blockDim.x) {
-    const int i = x % wl, j = x / wl;
-    h[i + j * ldh] = (i <= j + 2) ? gload(H, ld, s + i, s + j) : cx<T>{T(0), T(0)};
-    u[i + j * ldh] = {i == j ? T(1) : T(0), T(0)};
-  }
+  for (int x = t; x < 2 * nrounds; x += blockDim.x) sched[x] = rnd[x];
+  for (int x = t; x < nmv; x += blockDim.x) sched[2 * nrounds + x] = mv[mv0 + x];
+  win_load<T, W, kChaseThreads>(h, H, ld, s, s, wl, 2);
+  win_identity<T, W, kChaseThreads>(u, wl);
   __syncthreads();
+  const int* smv = sched + 2 * nrounds;
+  const int lane_j = t % G, grp = t / G;
   for (int ri = 0; ri < nrounds; ++ri) {
-    const int moff = rnd[2 * ri], nm = rnd[2 * ri + 1];
+    const int moff = sched[2 * ri] - mv0, nm = sched[2 * ri + 1];
     // rotations of this round (inputs from the state before the round)
     if (t < nm) {
-      const int code = mv[moff + t];
+      const int code = smv[moff + t];
       const int kind = code >> 24, j = (code >> 16) & 0xff, kl = code & 0xffff;
       cx<T> f, g;
       int r;
@@ -368,29 +418,27 @@ __global__ __launch_bounds__(kQrThreads) void chase_kernel(int n, T* H, int s, i
     }
     __syncthreads();
     // all row rotations (rows r, r+1 of every move; disjoint)
-    for (int x = t; x < nm * wl; x += blockDim.x) {
-      const int m = x / wl, j = x - m * wl;
-      if (j < rot_c0[m]) continue;
-      const int r = rot_r[m];
-      rot_rows(rot_c[m], rot_s[m], h[r + j * ldh], h[r + 1 + j * ldh]);
-      if (j == rot_z[m]) h[r + 1 + j * ldh] = {T(0), T(0)};
+    for (int m = grp; m < nm; m += NG) {
+      const int j = lane_j;
+      if (j < wl && j >= rot_c0[m]) {
+        const int r = rot_r[m];
+        rot_rows(rot_c[m], rot_s[m], h[r + j * ldh], h[r + 1 + j * ldh]);
+        if (j == rot_z[m]) h[r + 1 + j * ldh] = {T(0), T(0)};
+      }
     }
     __syncthreads();
     // all column rotations of H and U (columns r, r+1; disjoint)
-    for (int x = t; x < nm * wl; x += blockDim.x) {
-      const int m = x / wl, i = x - m * wl;
-      const int r = rot_r[m];
-      if (i <= rot_r1[m]) rot_cols(rot_c[m], rot_s[m], h[i + r * ldh], h[i + (r + 1) * ldh]);
-      rot_cols(rot_c[m], rot_s[m], u[i + r * ldh], u[i + (r + 1) * ldh]);
+    for (int m = grp; m < nm; m += NG) {
+      const int i = lane_j;
+      if (i < wl) {
+        const int r = rot_r[m];
+        if (i <= rot_r1[m]) rot_cols(rot_c[m], rot_s[m], h[i + r * ldh], h[i + (r + 1) * ldh]);
+        rot_cols(rot_c[m], rot_s[m], u[i + r * ldh], u[i + (r + 1) * ldh]);
+      }
     }
     __syncthreads();
   }
-  for (int x = t; x < wl * wl; x += blockDim.x) {
-    const int i = x % wl, j = x / wl;
-    gstore(H, ld, s + i, s + j, h[i + j * ldh]);
-    Uo[i + (int64_t)j * 2 * W] = u[i + j * ldh].r;
-    Uo[i + (int64_t)j * 2 * W + W] = u[i + j * ldh].i;
-  }
+  win_store<T, W, kChaseThreads>(h, u, H, ld, s, wl, 2, Uo);
 }
 
 // Off-window update with U (order bl, stacked, ld 2W):
@@ -408,18 +456,43 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
   const int ldu = W + 1;
   const int64_t ld = 2 * (int64_t)n;
   const int t = threadIdx.x;
-  for (int x = t; x < bl * bl; x += blockDim.x) {
-    const int i = x % bl, j = x / bl;
-    u[i + j * ldu] = {Uo[i + (int64_t)j * 2 * W], Uo[i + (int64_t)j * 2 * W + W]};
+  {
+    // the whole W x W buffer (entries beyond bl are never used), all loads
+    // in flight together
+    constexpr int E = (W * W + kQrThreads - 1) / kQrThreads;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = t + kQrThreads * e;
+      const int i = x % W, j = x / W;
+      v[e] = x < W * W ? cx<T>{Uo[i + (int64_t)j * 2 * W], Uo[i + (int64_t)j * 2 * W + W]}
+                       : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = t + kQrThreads * e;
+      if (x < W * W) u[x % W + (x / W) * ldu] = v[e];
+    }
   }
   const int b = blockIdx.x;
   if (b < gR) {
     // columns c0 .. c0+31 of the rows b0 .. b0+bl
     const int c0 = b0 + bl + 32 * b;
     const int nc = min(32, n - c0);
-    for (int x = t; x < bl * 32; x += blockDim.x) {
-      const int i = x % bl, j = x / bl;
-      pnl[i + j * ldu] = j < nc ? gload(H, ld, b0 + i, c0 + j) : cx<T>{T(0), T(0)};
+    {
+      constexpr int E = (W * 32 + kQrThreads - 1) / kQrThreads;
+      cx<T> v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int x = t + kQrThreads * e;
+        const int i = x % W, j = x / W;
+        v[e] = (i < bl && j < nc) ? gload(H, ld, b0 + i, c0 + j) : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int x = t + kQrThreads * e;
+        pnl[x % W + (x / W) * ldu] = v[e];
+      }
     }
     __syncthreads();
     const int jj = t % 32, i0 = t / 32;
@@ -456,9 +529,20 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
     nr = min(32, n - r0);
   }
   const int ldp = 33;
-  for (int x = t; x < 32 * bl; x += blockDim.x) {
-    const int i = x % 32, j = x / 32;
-    pnl[i + j * ldp] = i < nr ? gload(M, ld, r0 + i, b0 + j) : cx<T>{T(0), T(0)};
+  {
+    constexpr int E = (W * 32 + kQrThreads - 1) / kQrThreads;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = t + kQrThreads * e;
+      const int i = x % 32, j = x / 32;
+      v[e] = (i < nr && j < bl) ? gload(M, ld, r0 + i, b0 + j) : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = t + kQrThreads * e;
+      pnl[x % 32 + (x / 32) * ldp] = v[e];
+    }
   }
   __syncthreads();
   const int ii = t % 32, j0 = t / 32;
@@ -504,10 +588,21 @@ __global__ __launch_bounds__(1024) void deflate_kernel(int n, T* H, int lo, int 
   if (threadIdx.x == 0) out[0] = best;
 }
 
+// dynamic LDS of the window kernels: H and U windows (+ the schedule for
+// the chase kernel)
 template <typename T>
 size_t win_lds() {
   constexpr int W = Win<T>::W;
   return sizeof(cx<T>) * (size_t)(W + 1) * W * 2;
+}
+template <typename T>
+size_t chase_lds() {
+  return win_lds<T>() + sizeof(int) * kSchedCap;
+}
+template <typename T>
+size_t apply_lds() {
+  constexpr int W = Win<T>::W;
+  return sizeof(cx<T>) * ((size_t)(W + 1) * W + std::max<size_t>((size_t)(W + 1) * 32, 33 * (size_t)W));
 }
 
 template <typename T>
@@ -517,7 +612,7 @@ void launch_apply(hipStream_t st, int n, T* H, T* Z, int b0, int bl, const T* U)
   const int gZ = (int)ceil_div(n, 32);
   const int g = gR + gA + gZ;
   if (g == 0) return;
-  hipLaunchKernelGGL(apply_u_kernel<T>, dim3(g), dim3(kQrThreads), win_lds<T>(), st, n, H, Z, b0,
+  hipLaunchKernelGGL(apply_u_kernel<T>, dim3(g), dim3(kQrThreads), apply_lds<T>(), st, n, H, Z, b0,
                      bl, U, gR, gA);
   MSQRT_LAUNCH_CHECK();
 }
@@ -532,9 +627,9 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
     MSQRT_HIP(hipFuncSetAttribute((const void*)small_schur_kernel<T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
     MSQRT_HIP(hipFuncSetAttribute((const void*)chase_kernel<T>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)chase_lds<T>()));
     MSQRT_HIP(hipFuncSetAttribute((const void*)apply_u_kernel<T>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds<T>()));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_lds<T>()));
     attr_set = true;
   }
   if (n <= 0) return true;
@@ -600,12 +695,24 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
     MSQRT_HIP(hipMemcpyAsync(dsched + nr, sw.mv.data(), sizeof(int) * nm, hipMemcpyHostToDevice, st));
     for (size_t wi = 0; wi < sw.win.size(); wi += 4) {
       const int s = sw.win[wi], wl = sw.win[wi + 1], r0 = sw.win[wi + 2], nrw = sw.win[wi + 3];
-      if (nrw > 0) {
-        hipLaunchKernelGGL(chase_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H, s, wl,
-                           nrw, (const int*)(dsched + 2 * r0), (const int*)(dsched + nr),
-                           (const cx<T>*)shifts, U);
+      // launch the window's rounds in pieces whose schedule fits in LDS
+      for (int ra = 0; ra < nrw;) {
+        int rb = ra, used = 0;
+        while (rb < nrw) {
+          const int cnt = sw.rnd[2 * (r0 + rb) + 1];
+          if (used + 2 + cnt > kSchedCap) break;
+          used += 2 + cnt;
+          ++rb;
+        }
+        if (rb == ra) throw Error{MSQRT_ERR_DEVICE, "Schur QR: round larger than the LDS schedule"};
+        const int mv0 = sw.rnd[2 * (r0 + ra)];
+        const int mv1 = sw.rnd[2 * (r0 + rb - 1)] + sw.rnd[2 * (r0 + rb - 1) + 1];
+        hipLaunchKernelGGL(chase_kernel<T>, dim3(1), dim3(kChaseThreads), chase_lds<T>(), st, n, H, s, wl,
+                           rb - ra, (const int*)(dsched + 2 * (r0 + ra)), (const int*)(dsched + nr),
+                           mv0, mv1 - mv0, (const cx<T>*)shifts, U);
         MSQRT_LAUNCH_CHECK();
         launch_apply<T>(st, n, H, Z, s, wl, U);
+        ra = rb;
       }
     }
     // the staging vectors are reused by the next sweep: wait for the copies

@@ -16,8 +16,9 @@
 // Every workgroup takes one tile from an atomic ticket in wavefront order, so
 // every tile a workgroup waits for was taken by a workgroup that is already
 // running: the dataflow cannot deadlock, whatever the dispatch order.  Finished tiles
-// are published with a release fence and a per-tile flag; waits are bounded
-// and a timed-out wait sets a sticky error flag.
+// are exchanged with agent-scope atomic accesses and published with a
+// per-tile flag after the stores have completed; waits are bounded and a
+// timed-out wait sets a sticky error flag.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -44,10 +45,21 @@ template <typename T>
 __device__ inline cx<T> tload(const T* P, int64_t ld, int64_t i, int64_t j) {
   return {P[i + j * ld], P[i + j * ld + ld / 2]};
 }
+// Tiles produced by other workgroups are exchanged through agent-scope
+// atomic loads and stores, which are coherent across the XCDs' L2 caches
+// without writing back or invalidating the caches (the fences that would
+// otherwise be needed flush the whole L2 on every publish and wait).
 template <typename T>
-__device__ inline void tstore(T* P, int64_t ld, int64_t i, int64_t j, cx<T> v) {
-  P[i + j * ld] = v.r;
-  P[i + j * ld + ld / 2] = v.i;
+__device__ inline cx<T> tload_c(const T* P, int64_t ld, int64_t i, int64_t j) {
+  T* q = const_cast<T*>(P) + i + j * ld;
+  return {__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+          __hip_atomic_load(q + ld / 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+template <typename T>
+__device__ inline void tstore_c(T* P, int64_t ld, int64_t i, int64_t j, cx<T> v) {
+  T* q = P + i + j * ld;
+  __hip_atomic_store(q, v.r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + ld / 2, v.i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wavefront order of the tiles.
@@ -94,16 +106,18 @@ __device__ inline void wait_tile(const TileArgs& a, int I, int J) {
     }
   }
   __syncthreads();
-  __threadfence();
 }
 
-// Loads a tile (rows r0.., cols c0.., extent mr x mc, zero padded) to LDS.
+// Loads a tile (rows r0.., cols c0.., extent mr x mc, zero padded) to LDS;
+// coherent = the tile was produced by another workgroup of this launch.
 template <typename T>
 __device__ inline void load_tile(cx<T> (*dst)[kTb + 1], const T* P, int64_t ld, int r0, int c0,
-                                 int mr, int mc) {
+                                 int mr, int mc, bool coherent) {
   for (int x = threadIdx.x; x < kTb * kTb; x += blockDim.x) {
     const int i = x % kTb, j = x / kTb;
-    dst[j][i] = (i < mr && j < mc) ? tload(P, ld, r0 + i, c0 + j) : cx<T>{T(0), T(0)};
+    cx<T> v = {T(0), T(0)};
+    if (i < mr && j < mc) v = coherent ? tload_c(P, ld, r0 + i, c0 + j) : tload(P, ld, r0 + i, c0 + j);
+    dst[j][i] = v;
   }
 }
 
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
       }
       for (int x = t; x < kTb * kTb; x += blockDim.x) {
         const int i = x % kTb, j = x / kTb;
-        if (i < mi && j < mj) tstore(X, a.ldx, kTb * I + i, kTb * J + j, i <= j ? As[j][i] : cx<T>{T(0), T(0)});
+        if (i < mi && j < mj) tstore_c(X, a.ldx, kTb * I + i, kTb * J + j, i <= j ? As[j][i] : cx<T>{T(0), T(0)});
       }
     } else {
       if (a.mode == 0) {
@@ -190,14 +204,14 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
           wait_tile(a, I, K);
           wait_tile(a, K, J);
           const int mk = min(kTb, a.m - kTb * K);
-          load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
-          load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
+          load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk, true);
+          load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj, true);
           subtract();
         }
         wait_tile(a, I, I);
         wait_tile(a, J, J);
-        load_tile(As, X, a.ldx, kTb * I, kTb * I, mi, mi);
-        load_tile(Bs, X, a.ldx, kTb * J, kTb * J, mj, mj);
+        load_tile(As, X, a.ldx, kTb * I, kTb * I, mi, mi, true);
+        load_tile(Bs, X, a.ldx, kTb * J, kTb * J, mj, mj, true);
       } else {
         // the column terms S_IK Y_KJ (K > I, ready at wavefront
         // mt-1-K+J) and the row terms Y_IK S2_KJ (K < J, ready at mt-1-I+K)
@@ -211,19 +225,19 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
             const int K = kc--;
             wait_tile(a, K, J);
             const int mk = min(kTb, a.m - kTb * K);
-            load_tile(As, A, a.lda, kTb * I, kTb * K, mi, mk);
-            load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj);
+            load_tile(As, A, a.lda, kTb * I, kTb * K, mi, mk, false);
+            load_tile(Bs, X, a.ldx, kTb * K, kTb * J, mk, mj, true);
           } else {
             const int K = kr++;
             wait_tile(a, I, K);
             const int mk = min(kTb, a.p - kTb * K);
-            load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk);
-            load_tile(Bs, B, a.ldb, kTb * K, kTb * J, mk, mj);
+            load_tile(As, X, a.ldx, kTb * I, kTb * K, mi, mk, true);
+            load_tile(Bs, B, a.ldb, kTb * K, kTb * J, mk, mj, false);
           }
           subtract();
         }
-        load_tile(As, A, a.lda, kTb * I, kTb * I, mi, mi);
-        load_tile(Bs, B, a.ldb, kTb * J, kTb * J, mj, mj);
+        load_tile(As, A, a.lda, kTb * I, kTb * I, mi, mi, false);
+        load_tile(Bs, B, a.ldb, kTb * J, kTb * J, mj, mj, false);
       }
       __syncthreads();
       // S_II Y + Y S2_JJ = acc by anti-diagonals e = (mi - 1 - i) + j
@@ -250,14 +264,15 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
       __syncthreads();
       for (int x = t; x < kTb * kTb; x += blockDim.x) {
         const int i = x % kTb, j = x / kTb;
-        if (i < mi && j < mj) tstore(X, a.ldx, kTb * I + i, kTb * J + j, Ys[j][i]);
+        if (i < mi && j < mj) tstore_c(X, a.ldx, kTb * I + i, kTb * J + j, Ys[j][i]);
       }
     }
+    // every wave waits for its coherent stores to complete before the tile
+    // is published
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (wave == 0) {
-      __threadfence();
+    if (wave == 0)
       __hip_atomic_store(&a.flags[I * a.pt + J], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
   }
 }
 
