@@ -48,6 +48,14 @@ msqrt_status msqrt_test_trsqrt(msqrt_prec prec, int64_t n, const double* T, doub
 msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, const double* S,
                               const double* S2, const double* C, double* Y);
 
+/* The float GEMM of the Schur-basis transforms: C = op(A) op(B), M x N,
+ * inner dimension K, column-major float buffers (op = transpose when ta/tb is
+ * set; A is M x K or K x M, B is K x N or N x K, ld = rows as stored).
+ * split = 0: float MFMA products; split = 1: BF16-split products
+ * (hi*hi + hi*lo + lo*hi with float accumulation, the BF16SPLIT precision). */
+msqrt_status msqrt_test_gemm_f32(int split, int ta, int tb, int64_t M, int64_t N, int64_t K,
+                                 const float* A, const float* B, float* C);
+
 #ifdef __cplusplus
 }
 #endif

@@ -258,6 +258,21 @@ def test_trsyl(s, s2, c, prec="fp32"):
     return y
 
 
+def test_gemm_f32(a, b, split=False, ta=False, tb=False):
+    """Test hook: C = op(A) op(B) with the float or the BF16-split MFMA GEMM."""
+    import numpy as np
+    a = np.asfortranarray(a, dtype=np.float32)
+    b = np.asfortranarray(b, dtype=np.float32)
+    m = a.shape[1] if ta else a.shape[0]
+    k = a.shape[0] if ta else a.shape[1]
+    n = b.shape[0] if tb else b.shape[1]
+    c = np.zeros((m, n), np.float32, order="F")
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().msqrt_test_gemm_f32(1 if split else 0, 1 if ta else 0, 1 if tb else 0, m, n, k,
+                                    vp(a), vp(b), vp(c)), "msqrt_test_gemm_f32")
+    return c
+
+
 class _SqrtmFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, a, prec, tol, maxit):

@@ -32,6 +32,7 @@ EXPORTED = [
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
+    "msqrt_test_gemm_f32",
     "msqrt_profile_enable", "msqrt_profile_query", "msqrt_profile_list",
 ]
 
@@ -119,10 +120,11 @@ def lib():
     L.msqrt_test_schur.argtypes = [ci, i64, dp, dp, dp]
     L.msqrt_test_trsqrt.argtypes = [ci, i64, dp, dp]
     L.msqrt_test_trsyl.argtypes = [ci, i64, i64, dp, dp, dp, dp]
+    L.msqrt_test_gemm_f32.argtypes = [ci, ci, ci, i64, i64, i64, vp, vp, vp]
     for name in ("msqrt_factor", "msqrt_refine", "msqrt_sqrtm", "msqrt_sqrtm_backward",
                  "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
                  "msqrt_test_stedc", "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt",
-                 "msqrt_test_trsyl"):
+                 "msqrt_test_trsyl", "msqrt_test_gemm_f32"):
         getattr(L, name).restype = ci
     _lib = L
     return L

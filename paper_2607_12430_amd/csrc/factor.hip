@@ -109,7 +109,9 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
     return MSQRT_ERR_INVALID_ARG;
   }
   f->structure = sc;
-  f->prec = o.prec == MSQRT_PREC_FP64 ? MSQRT_PREC_FP64 : MSQRT_PREC_FP32;
+  // BF16SPLIT keeps the float factorisation; only the refinement's
+  // Schur-basis products differ
+  f->prec = o.prec;
   if (sc == MSQRT_STRUCT_GENERAL) {
     if (f->batch != 1) {
       set_last_error("the general path takes one matrix per call (batch = 1)");

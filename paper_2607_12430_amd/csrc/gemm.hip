@@ -6,10 +6,11 @@ namespace msqrt {
 
 void gemm_store_f32(hipStream_t st, bool ta, bool tb, int M, int N, int K, const float* A,
                     int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, float* C,
-                    int64_t ldc, int64_t sC, float alpha, float beta, int batch, bool tri) {
+                    int64_t ldc, int64_t sC, float alpha, float beta, int batch, bool tri,
+                    bool split) {
   GemmShape s = make_shape(M, N, K, lda, ldb, sA, sB, tri);
   EpiStore<float> e{C, ldc, sC, alpha, beta};
-  launch_gemm<float>(st, ta, tb, s, A, B, e, nullptr, batch);
+  launch_gemm<float>(st, ta, tb, s, A, B, e, nullptr, batch, split);
 }
 
 void gemm_store_f64(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
@@ -85,40 +86,40 @@ int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, cons
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,
                    const T* B, int64_t ldb, int64_t sB, const T* s, int64_t sS, T* Y, int64_t ldy,
-                   int64_t sY, int batch, bool tri) {
+                   int64_t sY, int batch, bool tri, bool split) {
   GemmShape sh = make_shape(n, n, n, lda, ldb, sA, sB, tri);
   EpiDiagSylv<T> e{s, sS, Y, ldy, sY};
-  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch);
+  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch, split);
 }
 
 template <typename T>
 void gemm_update(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda,
                  int64_t sA, const T* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
-                 int64_t sX, const int* active, int batch, bool tri) {
+                 int64_t sX, const int* active, int batch, bool tri, bool split) {
   GemmShape sh = make_shape(n, n, K, lda, ldb, sA, sB, tri);
   EpiUpdate<T> e{X, ldx, sX, active};
-  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch);
+  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch, split);
 }
 
 template <typename T>
 void gemm_set_f64(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda,
                   int64_t sA, const T* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
-                  int64_t sX, int batch, bool tri) {
+                  int64_t sX, int batch, bool tri, bool split) {
   GemmShape sh = make_shape(n, n, K, lda, ldb, sA, sB, tri);
   EpiSetF64<T> e{X, ldx, sX};
-  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch);
+  launch_gemm<T>(st, ta, tb, sh, A, B, e, nullptr, batch, split);
 }
 
 #define MSQRT_INST(T)                                                                          \
   template void gemm_diagsylv<T>(hipStream_t, bool, bool, int, const T*, int64_t, int64_t,     \
                                  const T*, int64_t, int64_t, const T*, int64_t, T*, int64_t,   \
-                                 int64_t, int, bool);                                          \
+                                 int64_t, int, bool, bool);                                    \
   template void gemm_update<T>(hipStream_t, bool, bool, int, int, const T*, int64_t, int64_t,  \
                                const T*, int64_t, int64_t, double*, int64_t, int64_t,          \
-                               const int*, int, bool);                                                        \
+                               const int*, int, bool, bool);                                   \
   template void gemm_set_f64<T>(hipStream_t, bool, bool, int, int, const T*, int64_t, int64_t, \
                                 const T*, int64_t, int64_t, double*, int64_t, int64_t, int,    \
-                                bool);
+                                bool, bool);
 MSQRT_INST(float)
 MSQRT_INST(double)
 #undef MSQRT_INST

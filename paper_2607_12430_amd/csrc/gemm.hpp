@@ -14,6 +14,8 @@
 // is told to mirror the element to (j, i).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "profile.hpp"
 
@@ -203,6 +205,140 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
 }
 
 // ---------------------------------------------------------------------------
+// BF16-split variant for float operands: every element x is split into
+// h = bf16(x) and l = bf16(x - h) (round to nearest even) while it is staged
+// into LDS, and the product is accumulated in float as
+//   A B ~ Ah Bh + Ah Bl + Al Bh
+// with v_mfma_f32_32x32x16_bf16 (unit roundoff about 2^-16 instead of 2^-24,
+// at the bf16 matrix rate).  Same tiling as gemm_kernel with a K-slab of 32;
+// LDS holds the hi and lo parts k-contiguous so that every lane reads its 8
+// consecutive k values with one 16-byte load.
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int SBK = 32;              // K-slab of the split kernel
+constexpr int SLD = SBK + 8;         // padded LDS row (bf16 elements)
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 2) void gemm_split_kernel(GemmShape s,
+                                                                 const float* __restrict__ A,
+                                                                 const float* __restrict__ B,
+                                                                 Epi epi,
+                                                                 double* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[GBM][SLD], Al[GBM][SLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[GBN][SLD], Bl[GBN][SLD];
+  __shared__ double red[GTHREADS / kWave];
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+
+  // Each thread stages 16 consecutive k of one row of A (m) and of one
+  // column of B (n): (row, k-half) = contiguous-m mapping (t % 128, t / 128)
+  // when m is the unit-stride index, else (t / 2, t % 2).
+  float ra[16], rb[16];
+  const int am = TA ? t / 2 : t % GBM, ak = TA ? 16 * (t % 2) : 16 * (t / GBM);
+  const int bn = TB ? t % GBN : t / 2, bk = TB ? 16 * (t / GBN) : 16 * (t % 2);
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gm = m0 + am, gk = k0 + ak + i;
+      float v = 0.f;
+      if (gm < s.M && gk < K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gn = n0 + bn, gk = k0 + bk + i;
+      float v = 0.f;
+      if (gn < s.N && gk < K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
+      rb[i] = v;
+    }
+  };
+  auto split_store = [&](const float* r, __bf16 (*hi)[SLD], __bf16 (*lo)[SLD], int row, int k) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      bf16x8_t h, l;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float x = r[8 * half + i];
+        const __bf16 xh = (__bf16)x;
+        h[i] = xh;
+        l[i] = (__bf16)(x - (float)xh);
+      }
+      *reinterpret_cast<bf16x8_t*>(&hi[row][k + 8 * half]) = h;
+      *reinterpret_cast<bf16x8_t*>(&lo[row][k + 8 * half]) = l;
+    }
+  };
+
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += SBK) {
+    __syncthreads();
+    split_store(ra, Ah, Al, am, ak);
+    split_store(rb, Bh, Bl, bn, bk);
+    __syncthreads();
+    if (k0 + SBK < K) load(k0 + SBK);
+#pragma unroll
+    for (int kk = 0; kk < SBK; kk += 16) {
+      const int fk = kk + 8 * (lane / 32), fr = lane % 32;
+      bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ah[i] = *reinterpret_cast<const bf16x8_t*>(&Ah[wm * 64 + 32 * i + fr][fk]);
+        al[i] = *reinterpret_cast<const bf16x8_t*>(&Al[wm * 64 + 32 * i + fr][fk]);
+        bh[i] = *reinterpret_cast<const bf16x8_t*>(&Bh[wn * 64 + 32 * i + fr][fk]);
+        bl[i] = *reinterpret_cast<const bf16x8_t*>(&Bl[wn * 64 + 32 * i + fr][fk]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gi = m0 + wm * 64 + i * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        const int gj = n0 + wn * 64 + j * 32 + lane % 32;
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Epilogues
 
 template <typename T>
@@ -322,12 +458,28 @@ inline GemmShape make_shape(int M, int N, int K, int64_t lda, int64_t ldb, int64
   return s;
 }
 
+// split = true selects the BF16-split kernel (float operands only).
 template <typename T, class Epi>
 void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A, const T* B,
-                 const Epi& epi, double* partials, int batch) {
+                 const Epi& epi, double* partials, int batch, bool split = false) {
   if (s.M <= 0 || s.N <= 0 || batch <= 0) return;
   dim3 grid(8 * s.per_xcd, batch), block(GTHREADS);
   const int tok = prof_begin(st);
+  if (split) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (!ta && !tb) hipLaunchKernelGGL((gemm_split_kernel<false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+      else if (ta && !tb) hipLaunchKernelGGL((gemm_split_kernel<true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+      else if (!ta && tb) hipLaunchKernelGGL((gemm_split_kernel<false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+      else hipLaunchKernelGGL((gemm_split_kernel<true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+      MSQRT_LAUNCH_CHECK();
+      if (tok >= 0) {
+        const double outs = s.tri ? 0.5 * (double)s.N * (s.N + 1) : (double)s.M * s.N;
+        const double kk = (double)s.K * (batch - 1) + s.K_last;
+        prof_end(tok, st, "gemm_bf16x3", 2.0 * outs * kk, 0.0);
+      }
+      return;
+    }
+  }
   if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
   else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);

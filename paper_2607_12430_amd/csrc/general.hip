@@ -171,10 +171,11 @@ Verdict2 judge2(const std::vector<double>& h, double tol) {
 
 template <typename T>
 void gstore_b(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda, int64_t sA,
-              const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC) {
+              const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC,
+              bool split = false) {
   if (std::is_same<T, float>::value)
     gemm_store_f32(st, ta, tb, n, n, K, (const float*)A, lda, sA, (const float*)B, ldb, sB,
-                   (float*)C, ldc, sC, 1.f, 0.f, 2, false);
+                   (float*)C, ldc, sC, 1.f, 0.f, 2, false, split);
   else
     gemm_store_f64(st, ta, tb, n, n, K, (const double*)A, lda, sA, (const double*)B, ldb, sB,
                    (double*)C, ldc, sC, 1.0, 0.0, 2, false);
@@ -206,25 +207,26 @@ GView<T> prepare_view(Factor* f, hipStream_t st) {
 // Rt) -> V = Q Y (wide, overwrites M) -> X (+)= fl64(V Q^*).
 template <typename T>
 void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* Xw, bool set,
-                TrsylvWork& tw, PhaseTimer& tm) {
+                TrsylvWork& tw, PhaseTimer& tm, bool split) {
   const int n = g.n;
   const int64_t nn = g.nn, n2 = 2 * (int64_t)n, n3 = 3 * (int64_t)n;
   tm.begin(MSQRT_T_TRANSFORM);
   // W = M Q (stacked): Re = [Mr | Mi][Qr; -Qi], Im = [Mr | Mi][Qi; Qr]
-  gstore_b<T>(st, false, false, n, 2 * n, M, n, 0, g.QSb + n, n3, -(int64_t)n, Wst, n2, n);
+  gstore_b<T>(st, false, false, n, 2 * n, M, n, 0, g.QSb + n, n3, -(int64_t)n, Wst, n2, n, split);
   // Rt = Q^* W (stacked): Re = [Qr; Qi]^T W, Im = [-Qi; Qr]^T W
-  gstore_b<T>(st, true, false, n, 2 * n, g.QSa + n, n3, -(int64_t)n, Wst, n2, 0, Rt, n2, n);
+  gstore_b<T>(st, true, false, n, 2 * n, g.QSa + n, n3, -(int64_t)n, Wst, n2, 0, Rt, n2, n, split);
   tm.begin(MSQRT_T_SOLVE);
   trsyl<T>(st, n, n, g.S, n2, g.S, n2, Rt, n2, tw);
   tm.begin(MSQRT_T_UPDATE);
   // V = Q Y (wide): Re = [Qr | -Qi][Yr; Yi], Im = [Qi | Qr][Yr; Yi]
-  gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, Rt, n2, 0, M, n, nn);
+  gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, Rt, n2, 0, M, n, nn, split);
   // X (+)= V Q^*: Re = [Vr | Vi][Qr | Qi]^T, Im = [Vr | Vi][-Qi | Qr]^T
   if (set)
-    gemm_set_f64<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, 2, false);
+    gemm_set_f64<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, 2, false,
+                    split);
   else
     gemm_update<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, nullptr, 2,
-                   false);
+                   false, split);
   tm.end();
 }
 
@@ -370,7 +372,7 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
       if (!best) best = f->best.ensure<double>(2 * nn);
       MSQRT_HIP(hipMemcpyAsync(best, Xw, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
     }
-    correction<T>(st, g, M, Wst, Rt, Xw, false, f->tw, tm);
+    correction<T>(st, g, M, Wst, Rt, Xw, false, f->tw, tm, f->prec == MSQRT_PREC_BF16SPLIT);
     ++steps;
   }
   msqrt_status status = MSQRT_OK;
@@ -518,7 +520,7 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
         break;
       }
     }
-    correction<T>(st, g, M, Wst, Rt, Gw, it == 0, f->tw, tm);
+    correction<T>(st, g, M, Wst, Rt, Gw, it == 0, f->tw, tm, f->prec == MSQRT_PREC_BF16SPLIT);
     ++steps;
   }
   // G = 2^-k (G~)^*

@@ -33,9 +33,11 @@ void launch_copy_f64(hipStream_t st, int n, const double* A, int64_t lda, int64_
 // ---- GEMMs (gemm.hip) -----------------------------------------------------
 
 // C = alpha op(A) op(B)   (+ beta C)
+// split = true: BF16-split products (hi*hi + hi*lo + lo*hi, float accumulation)
 void gemm_store_f32(hipStream_t st, bool ta, bool tb, int M, int N, int K, const float* A,
                     int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, float* C,
-                    int64_t ldc, int64_t sC, float alpha, float beta, int batch, bool tri);
+                    int64_t ldc, int64_t sC, float alpha, float beta, int batch, bool tri,
+                    bool split = false);
 void gemm_store_f64(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C,
                     int64_t ldc, int64_t sC, double alpha, double beta, int batch, bool tri);
@@ -67,16 +69,16 @@ int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, cons
 template <typename T>
 void gemm_diagsylv(hipStream_t st, bool ta, bool tb, int n, const T* A, int64_t lda, int64_t sA,
                    const T* B, int64_t ldb, int64_t sB, const T* s, int64_t sS, T* Y, int64_t ldy,
-                   int64_t sY, int batch, bool tri);
+                   int64_t sY, int batch, bool tri, bool split = false);
 // X += fl64(op(A) op(B))
 template <typename T>
 void gemm_update(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda,
                  int64_t sA, const T* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
-                 int64_t sX, const int* active, int batch, bool tri);
+                 int64_t sX, const int* active, int batch, bool tri, bool split = false);
 // X = fl64(op(A) op(B))
 template <typename T>
 void gemm_set_f64(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda,
                   int64_t sA, const T* B, int64_t ldb, int64_t sB, double* X, int64_t ldx,
-                  int64_t sX, int batch, bool tri);
+                  int64_t sX, int batch, bool tri, bool split = false);
 
 }  // namespace msqrt

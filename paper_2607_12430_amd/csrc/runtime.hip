@@ -102,6 +102,8 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
   double* rn = f->rnorm.ensure<double>(batch);
   int* active = f->active.ensure<int>(batch);
   double* best = nullptr;
+  // BF16SPLIT: float factor, Schur-basis transforms as BF16-split products
+  const bool split = f->prec == MSQRT_PREC_BF16SPLIT;
 
   if (init) {
     tm.begin(MSQRT_T_X0);
@@ -167,20 +169,21 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
     tm.begin(MSQRT_T_TRANSFORM);
     if (std::is_same<T, float>::value)
       gemm_store_f32(st, false, false, n, n, n, (const float*)W1, n, nn, (const float*)Q, n, nn,
-                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false, split);
     else
       gemm_store_f64(st, false, false, n, n, n, (const double*)W1, n, nn, (const double*)Q, n, nn,
                      (double*)W2, n, nn, 1.0, 0.0, batch, false);
-    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, true);
+    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, true, split);
     // Back-transform and working-precision update:  V = Q Y -> W2;  X += V Q^T
     tm.begin(MSQRT_T_UPDATE);
     if (std::is_same<T, float>::value)
       gemm_store_f32(st, false, false, n, n, n, (const float*)Q, n, nn, (const float*)W1, n, nn,
-                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false, split);
     else
       gemm_store_f64(st, false, false, n, n, n, (const double*)Q, n, nn, (const double*)W1, n, nn,
                      (double*)W2, n, nn, 1.0, 0.0, batch, false);
-    gemm_update<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, X, ldx, sX, active, batch, true);
+    gemm_update<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, X, ldx, sX, active, batch, true,
+                   split);
     tm.end();
     for (int b = 0; b < batch; ++b)
       if (!done[b]) steps[b]++;
@@ -250,6 +253,7 @@ static msqrt_status backward_hpd(Factor* f, const double* X, int64_t ldx, const 
   double* part = f->part.ensure<double>((int64_t)std::max(ntile, nt32 * (nt32 + 1) / 2) * batch + 64);
   double* rn = f->rnorm.ensure<double>(2 * batch);
   int* flags = f->active.ensure<int>(batch);
+  const bool split = f->prec == MSQRT_PREC_BF16SPLIT;
   // ||Gbar||_F per entry (and finiteness)
   tm.begin(MSQRT_T_VALIDATE);
   MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
@@ -317,23 +321,24 @@ static msqrt_status backward_hpd(Factor* f, const double* X, int64_t ldx, const 
     tm.begin(MSQRT_T_TRANSFORM);
     if (std::is_same<T, float>::value)
       gemm_store_f32(st, false, false, n, n, n, (const float*)W1, n, nn, (const float*)Q, n, nn,
-                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false, split);
     else
       gemm_store_f64(st, false, false, n, n, n, (const double*)W1, n, nn, (const double*)Q, n, nn,
                      (double*)W2, n, nn, 1.0, 0.0, batch, false);
-    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, false);
+    gemm_diagsylv<T>(st, true, false, n, Q, n, nn, W2, n, nn, s, n, W1, n, nn, batch, false, split);
     tm.begin(MSQRT_T_UPDATE);
     if (std::is_same<T, float>::value)
       gemm_store_f32(st, false, false, n, n, n, (const float*)Q, n, nn, (const float*)W1, n, nn,
-                     (float*)W2, n, nn, 1.f, 0.f, batch, false);
+                     (float*)W2, n, nn, 1.f, 0.f, batch, false, split);
     else
       gemm_store_f64(st, false, false, n, n, n, (const double*)Q, n, nn, (const double*)W1, n, nn,
                      (double*)W2, n, nn, 1.0, 0.0, batch, false);
     if (it == 0)
-      gemm_set_f64<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, G, ldg, stride, batch, false);
+      gemm_set_f64<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, G, ldg, stride, batch, false,
+                      split);
     else
       gemm_update<T>(st, false, true, n, n, W2, n, nn, Q, n, nn, G, ldg, stride, nullptr, batch,
-                     false);
+                     false, split);
     tm.end();
     for (int b = 0; b < batch; ++b)
       if (!done[b]) steps[b]++;

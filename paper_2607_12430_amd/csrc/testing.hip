@@ -1,6 +1,7 @@
 // Test hooks of the general-path stages (include/msqrt_testing.h): host
 // interleaved complex128 in, stage run on the device in complex64 or
 // complex128, host interleaved complex128 out.
+#include <algorithm>
 #include <vector>
 
 #include "../../include/msqrt_testing.h"
@@ -151,5 +152,26 @@ extern "C" msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, 
     if (prec == MSQRT_PREC_FP64) return trsyl_impl<double>((int)m, (int)p, S, S2, C, Y);
     if (prec == MSQRT_PREC_FP32) return trsyl_impl<float>((int)m, (int)p, S, S2, C, Y);
     return MSQRT_ERR_INVALID_ARG;
+  });
+}
+
+extern "C" msqrt_status msqrt_test_gemm_f32(int split, int ta, int tb, int64_t M, int64_t N,
+                                            int64_t K, const float* A, const float* B, float* C) {
+  if (M < 1 || N < 1 || K < 0 || !A || !B || !C || M > 65536 || N > 65536 || K > 65536)
+    return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    DevBuf ab, bb, cb;
+    const size_t na = (size_t)M * K, nb = (size_t)K * N, nc = (size_t)M * N;
+    float* dA = ab.ensure<float>((int64_t)na + 1);
+    float* dB = bb.ensure<float>((int64_t)nb + 1);
+    float* dC = cb.ensure<float>((int64_t)nc);
+    MSQRT_HIP(hipMemcpy(dA, A, sizeof(float) * na, hipMemcpyHostToDevice));
+    MSQRT_HIP(hipMemcpy(dB, B, sizeof(float) * nb, hipMemcpyHostToDevice));
+    const int64_t lda = ta ? K : M, ldb = tb ? N : K;
+    gemm_store_f32(nullptr, ta != 0, tb != 0, (int)M, (int)N, (int)K, dA, std::max<int64_t>(lda, 1),
+                   0, dB, std::max<int64_t>(ldb, 1), 0, dC, M, 0, 1.f, 0.f, 1, false, split != 0);
+    MSQRT_HIP(hipDeviceSynchronize());
+    MSQRT_HIP(hipMemcpy(C, dC, sizeof(float) * nc, hipMemcpyDeviceToHost));
+    return MSQRT_OK;
   });
 }

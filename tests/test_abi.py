@@ -11,7 +11,7 @@ def declared_symbols():
     src = "".join(open(os.path.join(ROOT, "include", h)).read()
                   for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(msqrt_[a-z_]+)\s*\(", src)
+    names = re.findall(r"\b(msqrt_[a-z0-9_]+)\s*\(", src)
     return sorted(set(names))
 
 
