@@ -136,7 +136,10 @@ msqrt_status msqrt_refine(msqrt_factor_t f, const void* dA, int64_t lda, int64_t
                           double tol, hipStream_t stream, msqrt_info* info);
 
 /* Complete solve: factor, X_0, refinement, with precision escalation when
- * opt->fallback is set.  If keep != NULL the factor is returned for reuse
+ * opt->fallback is set: a BF16SPLIT run that does not converge repeats the
+ * refinement with float transforms on the same (float) factor; a float run
+ * that fails, or a float factorisation without a principal root, is redone
+ * with an FP64 factor.  If keep != NULL the factor is returned for reuse
  * (e.g. by msqrt_sqrtm_backward); otherwise it is freed. */
 msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
                          int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,

@@ -42,6 +42,21 @@ def _dims(a: torch.Tensor):
     return n, batch, n * n
 
 
+_selector_tried = False
+
+
+def _ensure_selector():
+    """Installs the packaged selector file once (AUTO falls back to FP32
+    inside the library when none is installed)."""
+    global _selector_tried
+    if _selector_tried:
+        return
+    _selector_tried = True
+    if not lib().msqrt_selector_installed():
+        from . import selector
+        selector.install()
+
+
 def default_options(prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32, fallback=True,
                     batch=1):
     o = _lib.Options()
@@ -140,6 +155,8 @@ def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, b
     if isinstance(a, torch.Tensor) and not a.is_contiguous():
         a = a.contiguous()
     _check_matrix(a, "A")
+    if prec == "auto":
+        _ensure_selector()
     n, batch, nn = _dims(a)
     x = torch.empty_like(a) if out is None else out
     o = default_options(prec=prec, structure=structure, maxit=maxit, tol=tol, blks=blks,

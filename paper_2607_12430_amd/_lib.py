@@ -32,7 +32,9 @@ EXPORTED = [
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
-    "msqrt_test_gemm_f32",
+    "msqrt_test_gemm_f32", "msqrt_features", "msqrt_mlp_forward", "msqrt_mlp_grad",
+    "msqrt_mlp_adam", "msqrt_selector_set", "msqrt_selector_load", "msqrt_selector_clear",
+    "msqrt_selector_installed",
     "msqrt_profile_enable", "msqrt_profile_query", "msqrt_profile_list",
 ]
 
@@ -121,10 +123,23 @@ def lib():
     L.msqrt_test_trsqrt.argtypes = [ci, i64, dp, dp]
     L.msqrt_test_trsyl.argtypes = [ci, i64, i64, dp, dp, dp, dp]
     L.msqrt_test_gemm_f32.argtypes = [ci, ci, ci, i64, i64, i64, vp, vp, vp]
+    L.msqrt_features.argtypes = [ci, i64, vp, i64, vp, vp]
+    L.msqrt_mlp_forward.argtypes = [i64, vp, vp, vp, vp]
+    L.msqrt_mlp_grad.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    L.msqrt_mlp_adam.argtypes = [vp, vp, vp, vp, ci, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, vp]
+    L.msqrt_selector_set.argtypes = [vp, vp, vp, vp, ci]
+    L.msqrt_selector_load.argtypes = [ctypes.c_char_p]
+    L.msqrt_selector_clear.argtypes = []
+    L.msqrt_selector_clear.restype = None
+    L.msqrt_selector_installed.argtypes = []
+    L.msqrt_selector_installed.restype = ci
     for name in ("msqrt_factor", "msqrt_refine", "msqrt_sqrtm", "msqrt_sqrtm_backward",
                  "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
                  "msqrt_test_stedc", "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt",
-                 "msqrt_test_trsyl", "msqrt_test_gemm_f32"):
+                 "msqrt_test_trsyl", "msqrt_test_gemm_f32", "msqrt_features",
+                 "msqrt_mlp_forward", "msqrt_mlp_grad", "msqrt_mlp_adam", "msqrt_selector_set",
+                 "msqrt_selector_load"):
         getattr(L, name).restype = ci
     _lib = L
     return L

@@ -131,13 +131,6 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
   return MSQRT_OK;
 }
 
-msqrt_prec select_precision(const msqrt_options& o, msqrt_dtype dtype, int64_t n, const void* A,
-                            int64_t lda, int64_t sA, hipStream_t st, msqrt_info* info,
-                            PhaseTimer& tm) {
-  (void)o; (void)dtype; (void)n; (void)A; (void)lda; (void)sA; (void)st; (void)info; (void)tm;
-  return MSQRT_PREC_FP32;
-}
-
 }  // namespace msqrt
 
 // ---------------------------------------------------------------------------

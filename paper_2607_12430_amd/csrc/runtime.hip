@@ -626,12 +626,22 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
   if (prec == MSQRT_PREC_AUTO) prec = select_precision(o, dtype, n, dA, lda, strideA, stream, info, tm);
   msqrt_status last = MSQRT_ERR_DEVICE;
   int fallbacks = 0;
+  std::unique_ptr<Factor> reuse;  // float factor kept for the BF16SPLIT -> FP32 step
   for (;;) {
-    std::unique_ptr<Factor> f(new Factor());
-    f->n = n; f->batch = o.batch; f->dtype = dtype; f->blks = o.blks;
-    msqrt_options oo = o;
-    oo.prec = prec;
-    msqrt_status st = build_factor(f.get(), oo, (const double*)dA, lda, strideA, stream, &tm);
+    std::unique_ptr<Factor> f;
+    msqrt_status st = MSQRT_OK;
+    if (reuse) {
+      // BF16SPLIT and FP32 share the float factorisation: escalate by
+      // repeating only the refinement with float transforms
+      f = std::move(reuse);
+      f->prec = prec;
+    } else {
+      f.reset(new Factor());
+      f->n = n; f->batch = o.batch; f->dtype = dtype; f->blks = o.blks;
+      msqrt_options oo = o;
+      oo.prec = prec;
+      st = build_factor(f.get(), oo, (const double*)dA, lda, strideA, stream, &tm);
+    }
     if (st == MSQRT_OK) {
       for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
       st = refine(f.get(), (const double*)dA, lda, strideA, (double*)dX, ldx, strideX, 1, o.maxit,
@@ -652,7 +662,14 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
       if (keep && st == MSQRT_OK) *keep = reinterpret_cast<msqrt_factor_t>(f.release());
       break;
     }
-    prec = prec == MSQRT_PREC_BF16SPLIT ? MSQRT_PREC_FP32 : MSQRT_PREC_FP64;
+    if (prec == MSQRT_PREC_BF16SPLIT && st != MSQRT_ERR_NO_PRINCIPAL) {
+      // the float factor itself was usable: retry its refinement in FP32
+      prec = MSQRT_PREC_FP32;
+      reuse = std::move(f);
+    } else {
+      // a failed float factorisation fails again in FP32: go to FP64
+      prec = MSQRT_PREC_FP64;
+    }
     ++fallbacks;
   }
   if (info) info->fallbacks = fallbacks;

@@ -112,3 +112,36 @@ def hilbert(n: int, tau: float) -> np.ndarray:
 def gaussian(shape, seed: int) -> np.ndarray:
     """i.i.d. N(0, 1) array (used for upstream gradients and FD directions)."""
     return _rng(seed).standard_normal(shape)
+
+
+def nonsym_kappa(n: int, kappa: float, seed: int) -> np.ndarray:
+    """Nonsymmetric matrix whose difficulty tracks kappa: A = Q (L + N) Q^T with
+    Q Haar-orthogonal, L = diag(lam), lam log-uniform on [kappa^-1/2, kappa^1/2]
+    (endpoints pinned) and N strictly upper triangular with
+    N_ij = nu_ij sqrt(lam_i lam_j), nu_ij ~ N(0, (0.1 / sqrt(n))^2)."""
+    rng = _rng(seed)
+    q = haar_orthogonal(n, rng)
+    s = np.sqrt(kappa)
+    lam = loguniform_eigs(n, 1.0 / s, s, rng)
+    nu = rng.standard_normal((n, n)) * (0.1 / np.sqrt(n))
+    t = np.triu(nu * np.sqrt(np.outer(lam, lam)), 1) + np.diag(lam)
+    return np.asfortranarray(q @ t @ q.T)
+
+
+def selector_matrix(index: int, n_max_nonsym: int = 1024):
+    """One matrix of the selector's training / evaluation law: 50% SPD and 50%
+    nonsymmetric, n = round(exp(U(ln 64, ln 1024))) (nonsymmetric capped at
+    n_max_nonsym), kappa = 10^U(1, 8); nonsymmetric inputs are 25% of the
+    2 I + G / sqrt(n) family and 75% nonsym_kappa.  Returns (A, kind, n,
+    kappa) with kind in {"spd", "shifted", "kappa"}."""
+    rng = _rng(1_000_003 * (index + 1))
+    n = int(round(np.exp(rng.uniform(np.log(64.0), np.log(1024.0)))))
+    kappa = float(10.0 ** rng.uniform(1.0, 8.0))
+    seed = int(rng.integers(1, 2 ** 31))
+    if rng.uniform() < 0.5:
+        a, _, _ = spd(n, kappa, seed)
+        return a, "spd", n, kappa
+    n = min(n, n_max_nonsym)
+    if rng.uniform() < 0.25:
+        return nonsym_shifted(n, seed), "shifted", n, kappa
+    return nonsym_kappa(n, kappa, seed), "kappa", n, kappa
