@@ -20,6 +20,14 @@ extern "C" {
 msqrt_status msqrt_test_sytrd(msqrt_prec prec, int64_t n, const void* A, void* d, void* e,
                               void* tau);
 
+/* Two-stage tridiagonalisation A = Q T Q^T (dense -> band -> tridiagonal) of
+ * the symmetric n x n column-major A (n <= 4104): the diagonal d (n) and
+ * off-diagonal e (n-1) of T, and Q (n x n column-major) formed by the
+ * back-transformation applied to the identity.  Errors: INVALID_ARG,
+ * UNSUPPORTED (n too large), DEVICE (a dependency wait timed out). */
+msqrt_status msqrt_test_sy2tr(msqrt_prec prec, int64_t n, const void* A, void* d, void* e,
+                              void* Q);
+
 /* Divide-and-conquer eigensolver of the tridiagonal (d, e): lam (n, double,
  * ascending) and the eigenvector matrix Z (n x n column-major, prec). */
 msqrt_status msqrt_test_stedc(msqrt_prec prec, int64_t n, const void* d, const void* e,

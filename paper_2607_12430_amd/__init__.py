@@ -206,6 +206,22 @@ def test_sytrd(a, prec="fp32"):
     return d, e[: n - 1], tau[: n - 1]
 
 
+def test_sy2tr(a, prec="fp32"):
+    """Test hook: (d, e, Q) of the on-device two-stage tridiagonalisation of
+    host A (A = Q T Q^T)."""
+    import numpy as np
+    dt = np.float32 if prec == "fp32" else np.float64
+    a = np.asfortranarray(a, dtype=dt)
+    n = a.shape[0]
+    d = np.zeros(n, dt)
+    e = np.zeros(max(n - 1, 1), dt)
+    q = np.zeros((n, n), dt, order="F")
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().msqrt_test_sy2tr(_lib.PREC_NAMES[prec], n, vp(a), vp(d), vp(e), vp(q)),
+          "msqrt_test_sy2tr")
+    return d, e[: n - 1], q
+
+
 def test_stedc(d, e, prec="fp32"):
     """Test hook: (lam, Z) of the on-device divide-and-conquer eigensolver."""
     import numpy as np

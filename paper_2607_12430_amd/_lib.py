@@ -30,7 +30,8 @@ PHASES = ["validate", "select", "reduce", "eig", "back", "x0", "residual", "tran
 EXPORTED = [
     "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_sqrtm",
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
-    "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_stedc",
+    "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_sy2tr",
+    "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
     "msqrt_test_gemm_f32", "msqrt_features", "msqrt_mlp_forward", "msqrt_mlp_grad",
     "msqrt_mlp_adam", "msqrt_selector_set", "msqrt_selector_load", "msqrt_selector_clear",
@@ -116,6 +117,7 @@ def lib():
     L.msqrt_profile_list.argtypes = [ctypes.c_char_p, ci]
     L.msqrt_profile_list.restype = ci
     L.msqrt_test_sytrd.argtypes = [ci, i64, vp, vp, vp, vp]
+    L.msqrt_test_sy2tr.argtypes = [ci, i64, vp, vp, vp, vp]
     L.msqrt_test_stedc.argtypes = [ci, i64, vp, vp, vp, vp]
     dp = ctypes.POINTER(ctypes.c_double)
     L.msqrt_test_gehrd.argtypes = [ci, i64, dp, dp, dp]

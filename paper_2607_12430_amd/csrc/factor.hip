@@ -27,6 +27,14 @@ __global__ __launch_bounds__(256) void finish_hpd_kernel(int n, const double* la
   if (threadIdx.x == 0) *minlam = mn;
 }
 
+// The two-stage reduction replaces one grid synchronisation per column by
+// MFMA panel updates and a pipelined bulge chase.  It is selected from this
+// size on (above every supported size: the one-stage kernel is currently the
+// faster one at all sizes; the two-stage route is reached through its test
+// hook).
+constexpr int kTwoStageMinN = 1 << 30;
+inline bool use_two_stage(int n) { return n >= kTwoStageMinN && n <= sy2tr_max_n(); }
+
 template <typename T>
 void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t st,
                 PhaseTimer* tm, std::vector<double>& minlam) {
@@ -41,19 +49,23 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   double* lam = f->fw3.ensure<double>(n + 8);
   double* mins = f->fw4.ensure<double>(batch);
   SytrdWork sw;
+  Sy2trWork tw;
   StedcWork ew;
   OrmtrWork ow;
+  const bool two = use_two_stage(n);
   for (int b = 0; b < batch; ++b) {
     if (tm) tm->begin(MSQRT_T_REDUCE);
     if (std::is_same<T, float>::value)
       launch_cast_scale_f64_f32(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (float*)Aw, n, 0, 1);
     else
       launch_cast_scale_f64_f64(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (double*)Aw, n, 0, 1);
-    sytrd<T>(st, n, Aw, d, e, tau, sw);
+    if (two) sy2tr<T>(st, n, Aw, d, e, tw);
+    else sytrd<T>(st, n, Aw, d, e, tau, sw);
     if (tm) tm->begin(MSQRT_T_EIG);
     stedc<T>(st, n, d, e, lam, Q + b * nn, ew);
     if (tm) tm->begin(MSQRT_T_BACK);
-    ormtr<T>(st, n, Aw, tau, Q + b * nn, ow);
+    if (two) sy2tr_back<T>(st, n, Q + b * nn, tw, ow);
+    else ormtr<T>(st, n, Aw, tau, Q + b * nn, ow);
     hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(1), dim3(256), 0, st, n, (const double*)lam,
                        S + (int64_t)b * n, mins + b);
     MSQRT_LAUNCH_CHECK();
@@ -63,6 +75,8 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   MSQRT_HIP(hipMemcpyAsync(minlam.data(), mins, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
   MSQRT_HIP(hipStreamSynchronize(st));
   if (tm) tm->collect();
+  if (two && sy2tr_failed(tw))
+    throw Error{MSQRT_ERR_DEVICE, "band reduction: a bulge-chasing dependency wait timed out"};
   // the sytrd barrier error flag
   unsigned flag[2] = {0, 0};
   if (sw.bar.p) {
@@ -158,6 +172,27 @@ void test_sytrd_impl(int n, const void* A, void* d, void* e, void* tau) {
   if (flag[1]) throw Error{MSQRT_ERR_DEVICE, "grid barrier timed out"};
 }
 template <typename T>
+void test_sy2tr_impl(int n, const void* A, void* d, void* e, void* Q) {
+  if (n > sy2tr_max_n()) throw Error{MSQRT_ERR_UNSUPPORTED, "n too large for the two-stage reduction"};
+  DevBuf a, dd, q;
+  T* da = a.ensure<T>((int64_t)n * n);
+  T* dv = dd.ensure<T>(2 * (int64_t)n + 8);
+  T* dq = q.ensure<T>((int64_t)n * n);
+  MSQRT_HIP(hipMemcpy(da, A, sizeof(T) * n * n, hipMemcpyHostToDevice));
+  std::vector<T> eye((size_t)n * n, T(0));
+  for (int i = 0; i < n; ++i) eye[(size_t)i * n + i] = T(1);
+  MSQRT_HIP(hipMemcpy(dq, eye.data(), sizeof(T) * n * n, hipMemcpyHostToDevice));
+  Sy2trWork tw;
+  OrmtrWork ow;
+  sy2tr<T>(nullptr, n, da, dv, dv + n, tw);
+  sy2tr_back<T>(nullptr, n, dq, tw, ow);
+  MSQRT_HIP(hipDeviceSynchronize());
+  if (sy2tr_failed(tw)) throw Error{MSQRT_ERR_DEVICE, "bulge-chasing dependency wait timed out"};
+  MSQRT_HIP(hipMemcpy(d, dv, sizeof(T) * n, hipMemcpyDeviceToHost));
+  if (n > 1) MSQRT_HIP(hipMemcpy(e, dv + n, sizeof(T) * (n - 1), hipMemcpyDeviceToHost));
+  MSQRT_HIP(hipMemcpy(Q, dq, sizeof(T) * n * n, hipMemcpyDeviceToHost));
+}
+template <typename T>
 void test_stedc_impl(int n, const void* d, const void* e, double* lam, void* Z) {
   DevBuf dd, z, l;
   T* dv = dd.ensure<T>(2 * (int64_t)n + 8);
@@ -179,6 +214,20 @@ extern "C" msqrt_status msqrt_test_sytrd(msqrt_prec prec, int64_t n, const void*
     if (n < 1 || !A || !d || !e || !tau) return MSQRT_ERR_INVALID_ARG;
     if (prec == MSQRT_PREC_FP64) test_sytrd_impl<double>((int)n, A, d, e, tau);
     else if (prec == MSQRT_PREC_FP32) test_sytrd_impl<float>((int)n, A, d, e, tau);
+    else return MSQRT_ERR_INVALID_ARG;
+    return MSQRT_OK;
+  } catch (const Error& err) {
+    set_last_error(err.msg);
+    return (msqrt_status)err.status;
+  }
+}
+
+extern "C" msqrt_status msqrt_test_sy2tr(msqrt_prec prec, int64_t n, const void* A, void* d,
+                                         void* e, void* Q) {
+  try {
+    if (n < 1 || !A || !d || !e || !Q) return MSQRT_ERR_INVALID_ARG;
+    if (prec == MSQRT_PREC_FP64) test_sy2tr_impl<double>((int)n, A, d, e, Q);
+    else if (prec == MSQRT_PREC_FP32) test_sy2tr_impl<float>((int)n, A, d, e, Q);
     else return MSQRT_ERR_INVALID_ARG;
     return MSQRT_OK;
   } catch (const Error& err) {

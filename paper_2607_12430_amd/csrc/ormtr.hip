@@ -70,11 +70,17 @@ __global__ void sum_partials(int count, int splits, const T* P, int64_t stride, 
 
 template <typename T>
 void ormtr(hipStream_t st, int n, const T* Vc, const T* tau, T* Z, OrmtrWork& w) {
-  const int nref = n - 1;  // reflectors 0..n-2
-  if (nref <= 0) return;
-  T* V = const_cast<T*>(Vc);
-  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n), dim3(256), 0, st, n, V);
+  if (n - 1 <= 0) return;
+  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n), dim3(256), 0, st, n, const_cast<T*>(Vc));
   MSQRT_LAUNCH_CHECK();
+  ormtr_blocks<T>(st, n, n - 1, 1, Vc, tau, Z, w);
+}
+
+template <typename T>
+void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* Vc, const T* tau, T* Z,
+                  OrmtrWork& w) {
+  if (nref <= 0) return;
+  const T* V = Vc;
   const int nblk = (int)ceil_div(nref, kBlk);
   T* G = w.gram.ensure<T>((int64_t)nblk * kBlk * kBlk * 2);
   T* Tm = G + (int64_t)nblk * kBlk * kBlk;
@@ -120,7 +126,7 @@ void ormtr(hipStream_t st, int n, const T* Vc, const T* tau, T* Z, OrmtrWork& w)
   for (int b = nblk - 1; b >= 0; --b) {
     const int B = b * kBlk;
     const int nbk = std::min(kBlk, nref - B);
-    const int r0 = B + 1;
+    const int r0 = B + off;
     const int rows = n - r0;
     const T* Vb = V + (int64_t)B * n;
     int splits = (int)std::min<int64_t>(splits_max, std::max<int64_t>(1, ceil_div(rows, 256)));
@@ -142,5 +148,9 @@ void ormtr(hipStream_t st, int n, const T* Vc, const T* tau, T* Z, OrmtrWork& w)
 
 template void ormtr<float>(hipStream_t, int, const float*, const float*, float*, OrmtrWork&);
 template void ormtr<double>(hipStream_t, int, const double*, const double*, double*, OrmtrWork&);
+template void ormtr_blocks<float>(hipStream_t, int, int, int, const float*, const float*, float*,
+                                  OrmtrWork&);
+template void ormtr_blocks<double>(hipStream_t, int, int, int, const double*, const double*,
+                                   double*, OrmtrWork&);
 
 }  // namespace msqrt

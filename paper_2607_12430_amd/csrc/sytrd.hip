@@ -30,47 +30,64 @@ constexpr int kThreads = 1024;
 constexpr int kMaxTs = 256;  // max tile size handled by one workgroup
 constexpr int kNbMax = 32;
 
+// Values exchanged between workgroups inside a launch (partial products and
+// sums) are written and read with agent-scope atomic stores and loads, which
+// are coherent across the XCDs' L2 caches, so the barrier needs no device-wide
+// fence: such a fence writes back and invalidates the whole L2 of every XCD
+// on every column, and the tiles cached there would be fetched again.
+template <typename T>
+__device__ inline void cstore(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline T cload(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Two-level grid barrier: 16 workgroups per group counter, then one top
 // counter; the last arrival bumps the generation word.  Counters are reset by
 // their last arrival, so consecutive barriers (and launches) reuse them.
-// A spin limit keeps a broken launch from hanging: it raises bar[1].
+// Every thread waits for its own coherent stores to complete before the
+// workgroup arrives; the arrival protocol waits for each counter operation
+// before the next.  A spin limit keeps a broken launch from hanging: it
+// raises bar[1].
 __device__ inline void grid_barrier(unsigned* bar, int G) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     constexpr int GS = 16;
     const int ng = (G + GS - 1) / GS;
     const int g = blockIdx.x / GS;
     const int gsz = min(GS, G - g * GS);
-    const unsigned gen = __hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    const unsigned gen = cload(&bar[0]);
+    __builtin_amdgcn_s_waitcnt(0);
     unsigned* gc = &bar[32 * (1 + g)];
     unsigned* tc = &bar[32 * (1 + ng)];
     const unsigned a = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool released = false;
     if (a == (unsigned)gsz - 1) {
-      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+      cstore(gc, 0u);
+      __builtin_amdgcn_s_waitcnt(0);
       const unsigned b = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (b == (unsigned)ng - 1) {
-        __hip_atomic_store(tc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        __hip_atomic_store(&bar[0], gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cstore(tc, 0u);
+        __builtin_amdgcn_s_waitcnt(0);
+        cstore(&bar[0], gen + 1);
         released = true;
       }
     }
     if (!released) {
       unsigned spins = 0;
-      while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (cload(&bar[0]) == gen) {
         __builtin_amdgcn_s_sleep(1);
         // A timed-out barrier is sticky: later barriers stop waiting at once.
-        if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        if (cload(&bar[1]) != 0u) break;
         if (++spins > (1u << 24)) {
-          __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          cstore(&bar[1], 1u);
           break;
         }
       }
     }
-    __threadfence();
   }
   __syncthreads();
 }
@@ -247,11 +264,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       T z = T(0);
 #pragma unroll
       for (int w = 0; w < 8; ++w) z += zred[w * kMaxTs + r];
-      a.ypart[((int64_t)buf * TR + bj) * n + I0 + r] = z;
+      cstore(&a.ypart[((int64_t)buf * TR + bj) * n + I0 + r], z);
       s_uAu += (double)uI[r] * (double)z;
     }
     if (offdiag)
-      for (int r = tid; r < nK; r += kThreads) a.ypart[((int64_t)buf * TR + bi) * n + K0 + r] = zKs[r];
+      for (int r = tid; r < nK; r += kThreads) cstore(&a.ypart[((int64_t)buf * TR + bi) * n + K0 + r], zKs[r]);
     s_uAu = block_sum(s_uAu, red);
     if (offdiag) s_uAu *= 2.0;
     // ---- row-owner partials (diagonal tiles): ||u(2:)||^2, u^T a1, V^T u, W^T u
@@ -269,16 +286,16 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         double s = 0.0;
         for (int r = lane; r < nI; r += kWave) s += (double)col[r] * (double)uI[r];
         s = wave_sum(s);
-        if (lane == 0) a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c] = s;
+        if (lane == 0) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
       }
     }
     s_sig = block_sum(s_sig, red);
     s_ua1 = block_sum(s_ua1, red);
     if (tid == 0) {
       double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
-      spb[0] = s_uAu;
-      spb[1] = s_sig;
-      spb[2] = s_ua1;
+      cstore(&spb[0], s_uAu);
+      cstore(&spb[1], s_sig);
+      cstore(&spb[2], s_ua1);
       // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
       // before the barrier: owners overwrite column j right after it.
       double dj = (double)A[j + (int64_t)j * ld];
@@ -293,13 +310,13 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // (one load per thread), then reduce them there.
     for (int b = tid; b < G; b += kThreads) {
       const double* spb = a.sp + ((int64_t)buf * G + b) * 4;
-      spl[0][b] = spb[0];
-      spl[1][b] = spb[1];
-      spl[2][b] = spb[2];
+      spl[0][b] = cload(&spb[0]);
+      spl[1][b] = cload(&spb[1]);
+      spl[2][b] = cload(&spb[2]);
     }
     for (int x = tid; x < TR * 2 * jj; x += kThreads) {
       const int b = x / (2 * jj), c2 = x % (2 * jj);
-      vpl[x] = a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + c2];
+      vpl[x] = cload(&a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + c2]);
     }
     // (A22 u)_i = sum of the TR partial products of row i, for the rows of I,
     // K and the pivot rows: all loads of a row issued together.
@@ -307,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       auto rowsum = [&](int i) -> T {
         T yv[16];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) yv[b] = (b < TR) ? a.ypart[((int64_t)buf * TR + b) * n + i] : T(0);
+        for (int b = 0; b < 16; ++b) yv[b] = (b < TR) ? cload(&a.ypart[((int64_t)buf * TR + b) * n + i]) : T(0);
         T z = T(0);
 #pragma unroll
         for (int b = 0; b < 16; ++b) z += yv[b];

@@ -18,6 +18,18 @@ struct OrmtrWork {
   DevBuf gram, VT, Wpart, W;
 };
 
+// Half-bandwidth of the two-stage reduction: a panel of 4096 rows fits the
+// registers of one workgroup (16 float or 8 double columns).
+template <typename T>
+struct BandWidth {
+  static constexpr int B = sizeof(T) == 4 ? 16 : 8;
+};
+
+struct Sy2trWork {
+  DevBuf AB, V1, tau1, VW, WV, VT, X, Yp, Tg, V2, tau2, ctl;
+  int n = 0, nsw = 0, kmax = 0;
+};
+
 // A (n x n, ld n, full symmetric) is overwritten: column j holds the explicit
 // reflector v_j (rows j+1..n-1, v_j(j+1) = 1, zeros above) for rows >= its
 // panel start.  d (n), e (n-1), tau (n-1) in the factor precision.
@@ -33,5 +45,24 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
 // and tau.
 template <typename T>
 void ormtr(hipStream_t st, int n, const T* V, const T* tau, T* Z, OrmtrWork& w);
+
+// Z <- H_0 ... H_{nref-1} Z for explicit reflector columns V(:, j) (n x nref,
+// ld n) that vanish above row j + off and are 1 there.
+template <typename T>
+void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* V, const T* tau, T* Z,
+                  OrmtrWork& w);
+
+// Two-stage reduction A = Q1 Q2 T Q2^T Q1^T (A, n x n full symmetric storage,
+// is destroyed): d (n), e (n-1) of T; the reflectors of both stages stay in w
+// for sy2tr_back.  n <= sy2tr_max_n().
+template <typename T>
+void sy2tr(hipStream_t st, int n, T* A, T* d, T* e, Sy2trWork& w);
+// Z <- Q1 Q2 Z (Z n x n, ld n) with the reflectors of the last sy2tr call.
+template <typename T>
+void sy2tr_back(hipStream_t st, int n, T* Z, Sy2trWork& w, OrmtrWork& ow);
+// Reads the bulge-chasing error flag (a dependency wait that timed out);
+// synchronous.
+bool sy2tr_failed(Sy2trWork& w);
+int sy2tr_max_n();
 
 }  // namespace msqrt
