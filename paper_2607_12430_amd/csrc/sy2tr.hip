@@ -200,9 +200,7 @@ __global__ __launch_bounds__(kPT) void sb_panel_kernel(int n, int p, const T* __
 #pragma unroll
     for (int a = 0; a < B; ++a) {
       if (a >= w) break;
-      if (a < kq && i >= a) V1[r + (int64_t)(p + a) * n] = vrow[a];
       VW[r + (int64_t)a * n] = vrow[a];
-      WV[r + (int64_t)(w + a) * n] = vrow[a];
       T acc = T(0);
 #pragma unroll
       for (int b = 0; b <= a; ++b) acc += vrow[b] * Ts[b][a];
@@ -213,14 +211,28 @@ __global__ __launch_bounds__(kPT) void sb_panel_kernel(int n, int p, const T* __
   for (int j = tid; j < w; j += kPT) tau1[p + j] = Ts[j][j];
 }
 
+// out(i, c) = sum over q of P_q(i, c) (P_q m x w, ld m, stride m w), in q order.
+template <typename T>
+__global__ void sum_cols(int m, int w, int splits, const T* __restrict__ P, T* __restrict__ out,
+                         int64_t ldo) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)m * w) return;
+  const int i = (int)(x % m), c = (int)(x / m);
+  T s = T(0);
+  for (int q = 0; q < splits; ++q) s += P[(int64_t)q * m * w + x];
+  out[i + c * ldo] = s;
+}
+
 // W = X - 1/2 V M with M = T^T Y, Y = sum of the split-K partials of V^T X.
 // One thread per row; every workgroup forms M itself (fixed summation order).
+// It also copies V into [W V] and into the explicit reflector columns of V1
+// (rows on and below each unit entry; V1 is zero elsewhere).
 template <typename T, int B>
-__global__ __launch_bounds__(256) void sb_w_kernel(int n, int r0, int m, int w, int splits,
-                                                   const T* __restrict__ Yp,
+__global__ __launch_bounds__(256) void sb_w_kernel(int n, int p, int r0, int m, int w,
+                                                   int splits, const T* __restrict__ Yp,
                                                    const T* __restrict__ Tg,
                                                    const T* __restrict__ X, T* __restrict__ VW,
-                                                   T* __restrict__ WV) {
+                                                   T* __restrict__ WV, T* __restrict__ V1) {
   __shared__ T Ys[B][B + 1], Ms[B][B + 1];
   const int tid = threadIdx.x;
   for (int x = tid; x < B * B; x += blockDim.x) {
@@ -244,6 +256,12 @@ __global__ __launch_bounds__(256) void sb_w_kernel(int n, int r0, int m, int w, 
   T v[B];
 #pragma unroll
   for (int a = 0; a < B; ++a) v[a] = a < w ? VW[r + (int64_t)a * n] : T(0);
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+    if (a >= w) break;
+    WV[r + (int64_t)(w + a) * n] = v[a];
+    if (i >= a) V1[r + (int64_t)(p + a) * n] = v[a];
+  }
 #pragma unroll
   for (int c = 0; c < B; ++c) {
     if (c >= w) break;
@@ -398,46 +416,81 @@ __global__ void band_diag_kernel(int n, const T* AB, T* d, T* e) {
   if (c + 1 < n) e[c] = AB[1 + (int64_t)c * 2 * B];
 }
 
-// Z(:, c0:c0+nc) <- Q2 Z(:, c0:c0+nc), the columns held in LDS (row-major,
-// row stride nc).  One sweep per round, its reflectors in parallel.
+// Z(:, c0:c0+nc) <- Q2 Z(:, c0:c0+nc), the columns held in LDS.  One sweep
+// per round, its reflectors in parallel; the reflectors of the next sweep
+// (contiguous in V2) are loaded into registers while the current sweep is
+// applied and parked in the other LDS buffer.  LDS layouts are padded so that
+// the reflectors of one round, B rows apart, fall on different banks: row r
+// of Z at r nc + r / B, reflector k at k (B + 1).
 template <typename T, int B>
 __global__ __launch_bounds__(kPT) void apply_q2_kernel(int n, int nsw, int kmax, int nc,
                                                        const T* __restrict__ V2,
                                                        const T* __restrict__ tau2, T* Z) {
+  constexpr int kPre = 8;  // reflector values prefetched per thread (kmax B <= kPre kPT)
   extern __shared__ unsigned char smem_raw[];
   T* zs = reinterpret_cast<T*>(smem_raw);
+  const int zlen = n * nc + n / B + 1;
+  const int vpad = kmax * (B + 1);
+  T* vs = zs + zlen;           // [2][kmax (B + 1)]
+  T* ts = vs + 2 * vpad;       // [2][kmax]
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * nc, ncl = min(nc, n - c0);
+  const int vlen = kmax * B;
+  auto zi = [&](int r, int c) { return r * nc + r / B + c; };
   for (int x = tid; x < n * ncl; x += kPT) {
     const int c = x / n, r = x % n;
-    zs[r * nc + c] = Z[r + (int64_t)(c0 + c) * n];
+    zs[zi(r, c)] = Z[r + (int64_t)(c0 + c) * n];
+  }
+  if (nsw > 0) {
+    const int64_t base = (int64_t)(nsw - 1) * kmax;
+    T* vb = vs + ((nsw - 1) & 1) * vpad;
+    for (int x = tid; x < vlen; x += kPT) vb[(x / B) * (B + 1) + x % B] = V2[base * B + x];
+    for (int x = tid; x < kmax; x += kPT) ts[((nsw - 1) & 1) * kmax + x] = tau2[base + x];
   }
   __syncthreads();
   for (int s = nsw - 1; s >= 0; --s) {
+    T pv[kPre], pt = T(0);
+    if (s > 0) {
+      const int64_t base = (int64_t)(s - 1) * kmax;
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) {
+        const int x = tid + e * kPT;
+        pv[e] = x < vlen ? V2[base * B + x] : T(0);
+      }
+      if (tid < kmax) pt = tau2[base + tid];
+    }
+    const T* v = vs + (s & 1) * vpad;
+    const T* tt = ts + (s & 1) * kmax;
     const int K = (n - 1 - s + B - 1) / B;
     for (int x = tid; x < K * ncl; x += kPT) {
       const int k = x / ncl, c = x % ncl;
       const int rho = s + 1 + k * B, L = min(B, n - rho);
-      const int64_t slot = (int64_t)s * kmax + k;
-      const T tau = tau2[slot];
+      const T tau = tt[k];
       if (tau == T(0)) continue;
-      T v[B];
-#pragma unroll
-      for (int i = 0; i < B; ++i) v[i] = V2[slot * B + i];
+      const T* vk = v + k * (B + 1);
       T dot = T(0);
 #pragma unroll
       for (int i = 0; i < B; ++i)
-        if (i < L) dot += v[i] * zs[(rho + i) * nc + c];
+        if (i < L) dot += vk[i] * zs[zi(rho + i, c)];
       dot *= tau;
 #pragma unroll
       for (int i = 0; i < B; ++i)
-        if (i < L) zs[(rho + i) * nc + c] -= v[i] * dot;
+        if (i < L) zs[zi(rho + i, c)] -= vk[i] * dot;
+    }
+    if (s > 0) {
+      T* vn = vs + ((s - 1) & 1) * vpad;
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) {
+        const int x = tid + e * kPT;
+        if (x < vlen) vn[(x / B) * (B + 1) + x % B] = pv[e];
+      }
+      if (tid < kmax) ts[((s - 1) & 1) * kmax + tid] = pt;
     }
     __syncthreads();
   }
   for (int x = tid; x < n * ncl; x += kPT) {
     const int c = x / n, r = x % n;
-    Z[r + (int64_t)(c0 + c) * n] = zs[r * nc + c];
+    Z[r + (int64_t)(c0 + c) * n] = zs[zi(r, c)];
   }
 }
 
@@ -472,6 +525,8 @@ void sy2tr(hipStream_t st, int n, T* A, T* d, T* e, Sy2trWork& w) {
   constexpr int kSplitsMax = 32;
   T* Yp = w.Yp.ensure<T>((int64_t)kSplitsMax * B * B);
   T* Tg = w.Tg.ensure<T>((int64_t)B * B);
+  constexpr int kXSplits = 16;
+  T* Xp = w.Xp.ensure<T>((int64_t)kXSplits * n * B);
   MSQRT_HIP(hipMemsetAsync(V1, 0, sizeof(T) * (size_t)n * n, st));
   const int tok = prof_begin(st);
   for (int p = 0; p < n; p += B) {
@@ -481,8 +536,21 @@ void sy2tr(hipStream_t st, int n, T* A, T* d, T* e, Sy2trWork& w) {
     MSQRT_LAUNCH_CHECK();
     if (m <= 0) continue;
     T* A22 = A + r0 + (int64_t)r0 * n;
-    // X = A22 (V T)
-    gemm_t<T>(st, false, false, m, wd, m, A22, n, VT + r0, n, X + r0, n, T(1), T(0), false);
+    // X = A22 (V T): split-K partials (the output is only wd columns wide,
+    // so the K range is what gives the launch its parallelism), then a
+    // fixed-order sum.
+    {
+      const int xs = (int)std::min<int64_t>(kXSplits, std::max<int64_t>(1, ceil_div(m, 256)));
+      const int xchunk = (int)ceil_div(m, xs);
+      const int xsp = (int)ceil_div(m, xchunk);
+      const int xlast = m - (xsp - 1) * xchunk;
+      gemm_store_splitk<T>(st, false, false, m, wd, xchunk, xlast, A22, n, (int64_t)xchunk * n,
+                           VT + r0, n, xchunk, Xp, m, (int64_t)m * wd, xsp);
+      const int cnt = m * wd;
+      hipLaunchKernelGGL((sum_cols<T>), dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, m, wd,
+                         xsp, (const T*)Xp, X + r0, n);
+      MSQRT_LAUNCH_CHECK();
+    }
     // Y = V^T X (split-K partials)
     int splits = (int)std::min<int64_t>(kSplitsMax, std::max<int64_t>(1, ceil_div(m, 128)));
     const int chunk = (int)ceil_div(m, splits);
@@ -491,7 +559,7 @@ void sy2tr(hipStream_t st, int n, T* A, T* d, T* e, Sy2trWork& w) {
     gemm_store_splitk<T>(st, true, false, wd, wd, chunk, klast, VW + r0, n, chunk, X + r0, n,
                          chunk, Yp, wd, (int64_t)wd * wd, splits);
     hipLaunchKernelGGL((sb_w_kernel<T, B>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, n,
-                       r0, m, wd, splits, (const T*)Yp, (const T*)Tg, (const T*)X, VW, WV);
+                       p, r0, m, wd, splits, (const T*)Yp, (const T*)Tg, (const T*)X, VW, WV, V1);
     MSQRT_LAUNCH_CHECK();
     // A22 -= [V W] [W V]^T
     gemm_t<T>(st, false, true, m, m, 2 * wd, VW + r0, n, WV + r0, n, A22, n, T(-1), T(1), true);
@@ -541,10 +609,14 @@ template <typename T>
 void sy2tr_back(hipStream_t st, int n, T* Z, Sy2trWork& w, OrmtrWork& ow) {
   constexpr int B = BandWidth<T>::B;
   if (w.nsw > 0) {
-    const int lds_max = 128 * 1024;
-    const int nc = std::min<int64_t>(16, lds_max / ((int64_t)n * sizeof(T)));
-    if (nc < 1) throw Error{MSQRT_ERR_UNSUPPORTED, "back-transformation: n too large"};
-    const size_t lds = (size_t)n * nc * sizeof(T);
+    const int lds_max = 160 * 1024;
+    const int64_t ring = ((int64_t)2 * w.kmax * (B + 1) + 2 * w.kmax) * sizeof(T);
+    const int64_t zpad = ((int64_t)n / B + 1) * sizeof(T);
+    const int nc =
+        (int)std::min<int64_t>(16, (lds_max - ring - zpad) / ((int64_t)n * sizeof(T)));
+    if (nc < 1 || (int64_t)w.kmax * B > 8 * kPT)
+      throw Error{MSQRT_ERR_UNSUPPORTED, "back-transformation: n too large"};
+    const size_t lds = (size_t)n * nc * sizeof(T) + (size_t)(ring + zpad);
     static bool attr_set[2] = {false, false};
     if (!attr_set[sizeof(T) == 8]) {
       MSQRT_HIP(hipFuncSetAttribute((const void*)apply_q2_kernel<T, B>,

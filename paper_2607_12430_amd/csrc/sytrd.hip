@@ -44,45 +44,24 @@ __device__ inline T cload(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Two-level grid barrier: 16 workgroups per group counter, then one top
-// counter; the last arrival bumps the generation word.  Counters are reset by
-// their last arrival, so consecutive barriers (and launches) reuse them.
-// Every thread waits for its own coherent stores to complete before the
-// workgroup arrives; the arrival protocol waits for each counter operation
-// before the next.  A spin limit keeps a broken launch from hanging: it
-// raises bar[1].
-__device__ inline void grid_barrier(unsigned* bar, int G) {
+// Grid barrier on a counter that only grows within one reduction: every
+// workgroup adds 1 on arrival and waits until the counter reaches the
+// barrier's target (launch base + G (column + 1)), so an arrival costs one
+// atomic and the release is seen by the next poll, with no reset.  Every
+// thread waits for its own coherent stores to complete before the workgroup
+// arrives.  A spin limit keeps a broken launch from hanging: it raises the
+// sticky flag bar[1].
+__device__ inline void grid_barrier(unsigned* bar, unsigned target) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    constexpr int GS = 16;
-    const int ng = (G + GS - 1) / GS;
-    const int g = blockIdx.x / GS;
-    const int gsz = min(GS, G - g * GS);
-    const unsigned gen = cload(&bar[0]);
-    __builtin_amdgcn_s_waitcnt(0);
-    unsigned* gc = &bar[32 * (1 + g)];
-    unsigned* tc = &bar[32 * (1 + ng)];
-    const unsigned a = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool released = false;
-    if (a == (unsigned)gsz - 1) {
-      cstore(gc, 0u);
-      __builtin_amdgcn_s_waitcnt(0);
-      const unsigned b = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (b == (unsigned)ng - 1) {
-        cstore(tc, 0u);
-        __builtin_amdgcn_s_waitcnt(0);
-        cstore(&bar[0], gen + 1);
-        released = true;
-      }
-    }
-    if (!released) {
-      unsigned spins = 0;
-      while (cload(&bar[0]) == gen) {
-        __builtin_amdgcn_s_sleep(1);
-        // A timed-out barrier is sticky: later barriers stop waiting at once.
+    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (cload(&bar[0]) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0u) {
         if (cload(&bar[1]) != 0u) break;
-        if (++spins > (1u << 24)) {
+        if (spins > (1u << 24)) {
           cstore(&bar[1], 1u);
           break;
         }
@@ -107,6 +86,7 @@ struct PanelArgs {
   double* sp;    // [2][G][4]
   double* vp;    // [2][TR][2 kNbMax]
   unsigned* bar;
+  unsigned bar_base;  // barrier counter value when the launch starts
 };
 
 // Tile product of one lower-triangular tile (I x K, I >= K) with the current
@@ -209,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   // workgroup in the current phase is ever read.
   __shared__ T PV[kNbMax][kNbMax + 1], PW[kNbMax][kNbMax + 1], PU[kNbMax];
   __shared__ T VTv[kNbMax], WTv[kNbMax];
-  __shared__ double red[kThreads / kWave];
+  __shared__ double red3[kThreads / kWave][3];
   __shared__ double sc[8];
   __shared__ T acI[kMaxTs], acK[kMaxTs], acP[kNbMax];  // A(:, j+1) on rows I, K, pivots
   __shared__ T yzI[kMaxTs], yzK[kMaxTs], yzP[kNbMax];  // (A22 u) on rows I, K, pivots
@@ -232,6 +212,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     if (tid < nI) acv_i = A[I0 + tid + (int64_t)(j + 1) * ld];
     if (tid < nK) acv_k = A[K0 + tid + (int64_t)(j + 1) * ld];
     if (tid < nb && p + 1 + tid < n) acv_p = A[p + 1 + tid + (int64_t)(j + 1) * ld];
+    // A(j, j) for d_j (never written inside the panel)
+    const double ajj = (tid == 0) ? (double)A[j + (int64_t)j * ld] : 0.0;
     // ---- tile product; the 16 waves' row partials are folded onto 8 slots
     for (int r = tid; r < nK; r += kThreads) zKs[r] = T(0);
     __syncthreads();
@@ -269,8 +251,6 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     }
     if (offdiag)
       for (int r = tid; r < nK; r += kThreads) cstore(&a.ypart[((int64_t)buf * TR + bi) * n + K0 + r], zKs[r]);
-    s_uAu = block_sum(s_uAu, red);
-    if (offdiag) s_uAu *= 2.0;
     // ---- row-owner partials (diagonal tiles): ||u(2:)||^2, u^T a1, V^T u, W^T u
     double s_sig = 0.0, s_ua1 = 0.0;
     if (diag) {
@@ -289,22 +269,42 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         if (lane == 0) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
       }
     }
-    s_sig = block_sum(s_sig, red);
-    s_ua1 = block_sum(s_ua1, red);
-    if (tid == 0) {
-      double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
-      cstore(&spb[0], s_uAu);
-      cstore(&spb[1], s_sig);
-      cstore(&spb[2], s_ua1);
-      // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
-      // before the barrier: owners overwrite column j right after it.
-      double dj = (double)A[j + (int64_t)j * ld];
-      for (int t = 0; t < jj; ++t) dj -= 2.0 * (double)PV[jj - 1][t] * (double)PW[jj - 1][t];
-      sc[0] = dj;
-      sc[3] = (double)PU[jj];
+    // one reduction of the three scalars (wave sums, then one thread), and
+    // the pivot-row correction of d_j summed by the first wave
+    {
+      const double w0 = wave_sum(s_uAu), w1 = wave_sum(s_sig), w2 = wave_sum(s_ua1);
+      const int wv_ = tid / kWave, ln_ = tid % kWave;
+      if (ln_ == 0) {
+        red3[wv_][0] = w0;
+        red3[wv_][1] = w1;
+        red3[wv_][2] = w2;
+      }
+      double pd = 0.0;
+      if (tid < kWave) {
+        if (tid < jj) pd = (double)PV[jj - 1][tid] * (double)PW[jj - 1][tid];
+        pd = wave_sum(pd);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        for (int x = 0; x < kThreads / kWave; ++x) {
+          t0 += red3[x][0];
+          t1 += red3[x][1];
+          t2 += red3[x][2];
+        }
+        if (offdiag) t0 *= 2.0;
+        double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
+        cstore(&spb[0], t0);
+        cstore(&spb[1], t1);
+        cstore(&spb[2], t2);
+        // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
+        // before the barrier: owners overwrite column j right after it.
+        sc[0] = ajj - 2.0 * pd;
+        sc[3] = (double)PU[jj];
+      }
     }
 
-    grid_barrier(a.bar, G);
+    grid_barrier(a.bar, a.bar_base + (unsigned)G * (unsigned)(jj + 1));
 
     // ---- gather the partial sums of all workgroups into LDS in parallel
     // (one load per thread), then reduce them there.
@@ -382,12 +382,14 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       WTv[t] = (T)(c * (wtu - beta * (double)PW[jj][t]));
     }
     __syncthreads();
-    if (tid == 0) {
-      const double a11 = (double)acP[jj];
-      const double vAv = c * c * (sc[0] - 2.0 * beta * sc[2] + beta * beta * a11);
-      double vw = 0.0;
-      for (int t = 0; t < jj; ++t) vw += (double)VTv[t] * (double)WTv[t];
-      sc[7] = tau * (vAv - 2.0 * vw);  // w0^T v
+    if (tid < kWave) {
+      double vw = tid < jj ? (double)VTv[tid] * (double)WTv[tid] : 0.0;
+      vw = wave_sum(vw);
+      if (tid == 0) {
+        const double a11 = (double)acP[jj];
+        const double vAv = c * c * (sc[0] - 2.0 * beta * sc[2] + beta * beta * a11);
+        sc[7] = tau * (vAv - 2.0 * vw);  // w0^T v
+      }
     }
     __syncthreads();
     const double wv = sc[7];
@@ -515,17 +517,19 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
   double* vp = w.vp.ensure<double>((int64_t)2 * 16 * 2 * kNbMax);
   unsigned* bar = w.bar.ensure<unsigned>(32 * 40);
   MSQRT_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned) * 32 * 40, st));
+  unsigned bar_base = 0;
   for (int p = 0; p < n - 1; p += nb) {
     const int nbe = std::min(nb, n - 1 - p);
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
     const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
     const int ts = (int)ceil_div(m, TR);
-    PanelArgs<T> pa{n, p, nbe, TR, p + 1, ts, A, VW, WV, d, e, tau, ypart, sp, vp, bar};
+    PanelArgs<T> pa{n, p, nbe, TR, p + 1, ts, A, VW, WV, d, e, tau, ypart, sp, vp, bar, bar_base};
     void* args[] = {&pa};
     const int G = TR * (TR + 1) / 2;
     const int tok = prof_begin(st);
     MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G),
                                          dim3(kThreads), args, dyn_lds, st));
+    bar_base += (unsigned)G * (unsigned)nbe;
     if (tok >= 0) {
       // algorithmic traffic: one read of the symmetric trailing matrix (lower
       // triangle) per column for its product with the reflector

@@ -26,7 +26,7 @@ struct BandWidth {
 };
 
 struct Sy2trWork {
-  DevBuf AB, V1, tau1, VW, WV, VT, X, Yp, Tg, V2, tau2, ctl;
+  DevBuf AB, V1, tau1, VW, WV, VT, X, Xp, Yp, Tg, V2, tau2, ctl;
   int n = 0, nsw = 0, kmax = 0;
 };
 
