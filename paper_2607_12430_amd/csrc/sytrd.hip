@@ -100,7 +100,7 @@ template <typename T, int RPL, int NP>
 __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0,
                                     int nK, int jmin, bool offdiag, const T* uI, const T* uK,
                                     T (&zi)[NP][RPL], T* zK, int tid) {
-  constexpr int CW = sizeof(T) == 4 ? 16 : 8;            // columns per chunk
+  constexpr int CW = sizeof(T) == 4 ? 8 : 4;             // columns per chunk
   constexpr int NCH = kMaxTs / (CW * (kThreads / kWave));  // chunks per wave
   const int wave = tid / kWave, lane = tid % kWave;
 #pragma unroll
