@@ -31,6 +31,8 @@ template <> struct Win<float> { static constexpr int W = 96, NS = 24; };
 template <> struct Win<double> { static constexpr int W = 64, NS = 16; };
 
 constexpr int kQrThreads = 256;
+// off-window updates: two waves per SIMD at one workgroup per CU
+constexpr int kApplyThreads = 1024;
 constexpr int kMaxNs = 32;
 constexpr int kExited = 1 << 30;
 
@@ -446,10 +448,11 @@ __global__ __launch_bounds__(kChaseThreads) void chase_kernel(int n, T* H, int s
 //   region A: H(0:b0, b0:b0+bl)    <- H(...) U          (row blocks of 32)
 //   region Z: Z(0:n, b0:b0+bl)     <- Z(...) U          (row blocks of 32)
 template <typename T>
-__global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, int b0, int bl,
+__global__ __launch_bounds__(kApplyThreads) void apply_u_kernel(int n, T* H, T* Z, int b0, int bl,
                                                              const T* Uo, int gR, int gA) {
   constexpr int W = Win<T>::W;
-  constexpr int Q = W / 8;  // outputs per thread along the window index
+  constexpr int RS = kApplyThreads / 32;  // thread rows
+  constexpr int Q = W / RS;                // outputs per thread along the window index
   extern __shared__ unsigned char smem_raw[];
   cx<T>* u = reinterpret_cast<cx<T>*>(smem_raw);  // (W + 1) x W
   cx<T>* pnl = u + (W + 1) * W;                    // 32 x W panel, stride W + 1 or 33
@@ -459,18 +462,18 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
   {
     // the whole W x W buffer (entries beyond bl are never used), all loads
     // in flight together
-    constexpr int E = (W * W + kQrThreads - 1) / kQrThreads;
+    constexpr int E = (W * W + kApplyThreads - 1) / kApplyThreads;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int x = t + kQrThreads * e;
+      const int x = t + kApplyThreads * e;
       const int i = x % W, j = x / W;
       v[e] = x < W * W ? cx<T>{Uo[i + (int64_t)j * 2 * W], Uo[i + (int64_t)j * 2 * W + W]}
                        : cx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int x = t + kQrThreads * e;
+      const int x = t + kApplyThreads * e;
       if (x < W * W) u[x % W + (x / W) * ldu] = v[e];
     }
   }
@@ -480,17 +483,17 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
     const int c0 = b0 + bl + 32 * b;
     const int nc = min(32, n - c0);
     {
-      constexpr int E = (W * 32 + kQrThreads - 1) / kQrThreads;
+      constexpr int E = (W * 32 + kApplyThreads - 1) / kApplyThreads;
       cx<T> v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int x = t + kQrThreads * e;
+        const int x = t + kApplyThreads * e;
         const int i = x % W, j = x / W;
         v[e] = (i < bl && j < nc) ? gload(H, ld, b0 + i, c0 + j) : cx<T>{T(0), T(0)};
       }
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int x = t + kQrThreads * e;
+        const int x = t + kApplyThreads * e;
         pnl[x % W + (x / W) * ldu] = v[e];
       }
     }
@@ -503,14 +506,14 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
       const cx<T> hv = pnl[k + jj * ldu];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const int i = i0 + 8 * q;
+        const int i = i0 + RS * q;
         if (i < bl) acc[q] = cadd(acc[q], cmulc(u[k + i * ldu], hv));
       }
     }
     if (jj < nc) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const int i = i0 + 8 * q;
+        const int i = i0 + RS * q;
         if (i < bl) gstore(H, ld, b0 + i, c0 + jj, acc[q]);
       }
     }
@@ -530,17 +533,17 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
   }
   const int ldp = 33;
   {
-    constexpr int E = (W * 32 + kQrThreads - 1) / kQrThreads;
+    constexpr int E = (W * 32 + kApplyThreads - 1) / kApplyThreads;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int x = t + kQrThreads * e;
+      const int x = t + kApplyThreads * e;
       const int i = x % 32, j = x / 32;
       v[e] = (i < nr && j < bl) ? gload(M, ld, r0 + i, b0 + j) : cx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int x = t + kQrThreads * e;
+      const int x = t + kApplyThreads * e;
       pnl[x % 32 + (x / 32) * ldp] = v[e];
     }
   }
@@ -553,14 +556,14 @@ __global__ __launch_bounds__(kQrThreads) void apply_u_kernel(int n, T* H, T* Z, 
     const cx<T> hv = pnl[ii + k * ldp];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int j = j0 + 8 * q;
+      const int j = j0 + RS * q;
       if (j < bl) acc[q] = cadd(acc[q], cmul(hv, u[k + j * ldu]));
     }
   }
   if (ii < nr) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int j = j0 + 8 * q;
+      const int j = j0 + RS * q;
       if (j < bl) gstore(M, ld, r0 + ii, b0 + j, acc[q]);
     }
   }
@@ -612,7 +615,7 @@ void launch_apply(hipStream_t st, int n, T* H, T* Z, int b0, int bl, const T* U)
   const int gZ = (int)ceil_div(n, 32);
   const int g = gR + gA + gZ;
   if (g == 0) return;
-  hipLaunchKernelGGL(apply_u_kernel<T>, dim3(g), dim3(kQrThreads), apply_lds<T>(), st, n, H, Z, b0,
+  hipLaunchKernelGGL(apply_u_kernel<T>, dim3(g), dim3(kApplyThreads), apply_lds<T>(), st, n, H, Z, b0,
                      bl, U, gR, gA);
   MSQRT_LAUNCH_CHECK();
 }
