@@ -21,6 +21,7 @@
 // timed-out wait sets a sticky error flag.
 #include <algorithm>
 
+#include "gemm.hpp"
 #include "kernels.hpp"
 #include "schur.hpp"
 
@@ -30,6 +31,7 @@ namespace {
 
 constexpr int kTb = 32;
 constexpr int kTThreads = 256;
+static_assert(kTThreads == 4 * kWave, "one wave per real product of a complex tile product");
 constexpr unsigned kSpinLimit = 1u << 22;
 
 struct TileArgs {
@@ -121,10 +123,63 @@ __device__ inline void load_tile(cx<T> (*dst)[kTb + 1], const T* P, int64_t ld, 
   }
 }
 
+// The four real products of one complex 32 x 32 x 32 tile product C = A B
+// on MFMA, one per wave: P0 = Ar Br, P1 = Ai Bi, P2 = Ar Bi, P3 = Ai Br
+// (so Cr = P0 - P1, Ci = P2 + P3), stored to P[w][col][row].  A and B are
+// the LDS tiles As[k][i] = A(i, k), Bs[j][k] = B(k, j).
+template <typename T>
+__device__ inline void tile_product_mfma(const cx<T> (*As)[kTb + 1], const cx<T> (*Bs)[kTb + 1],
+                                         T (*P)[kTb][kTb + 1], int wave, int lane) {
+  // P may overlay As and Bs: every wave reads its operands before any stores
+  using M = Mfma<T>;
+  constexpr int NT = kTb / M::TM;  // MFMA tiles per dimension
+  const bool aim = wave == 1 || wave == 3, bim = wave == 1 || wave == 2;
+  typename M::acc_t acc[NT][NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = T(0);
+  const int fmn = M::frag_mn(lane);
+#pragma unroll
+  for (int k0 = 0; k0 < kTb; k0 += M::TK) {
+    const int fk = k0 + M::frag_k(lane);
+    T av[NT], bv[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const cx<T> v = As[fk][i * M::TM + fmn];
+      av[i] = aim ? v.i : v.r;
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const cx<T> v = Bs[j * M::TN + fmn][fk];
+      bv[j] = bim ? v.i : v.r;
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = M::mma(av[i], bv[j], acc[i][j]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r)
+        P[wave][j * M::TN + M::c_col(lane, r)][i * M::TM + M::c_row(lane, r)] = acc[i][j][r];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A, const T* B, T* X) {
-  __shared__ cx<T> As[kTb][kTb + 1];  // [col][row]
-  __shared__ cx<T> Bs[kTb][kTb + 1];
+  // A and B operand tiles ([col][row]) in one array: after the MFMA products
+  // have read them, the same storage holds the four real products
+  __shared__ cx<T> ABs[2][kTb][kTb + 1];
+  cx<T> (*As)[kTb + 1] = ABs[0];
+  cx<T> (*Bs)[kTb + 1] = ABs[1];
+  T (*Pp)[kTb][kTb + 1] = reinterpret_cast<T (*)[kTb][kTb + 1]>(&ABs[0][0][0]);
+  static_assert(sizeof(ABs) == 4 * kTb * (kTb + 1) * sizeof(T), "product overlay");
   __shared__ cx<T> Ys[kTb][kTb + 1];
   __shared__ int sh_tk;
   const int t = threadIdx.x;
@@ -159,10 +214,13 @@ __global__ __launch_bounds__(kTThreads) void tile_kernel(TileArgs a, const T* A,
     }
     auto subtract = [&]() {
       __syncthreads();
-      for (int k = 0; k < kTb; ++k) {
-        const cx<T> av = As[k][ti];
+      tile_product_mfma<T>(As, Bs, Pp, wave, t % kWave);
+      __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = csub(acc[q], cmul(av, Bs[tj0 + 8 * q][k]));
+      for (int q = 0; q < 4; ++q) {
+        const int j = tj0 + 8 * q;
+        acc[q].r -= Pp[0][j][ti] - Pp[1][j][ti];
+        acc[q].i -= Pp[2][j][ti] + Pp[3][j][ti];
       }
       __syncthreads();
     };
