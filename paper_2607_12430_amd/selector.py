@@ -224,7 +224,7 @@ def fit(records, epochs=400, oversample=10, seed=0, log=None):
         "val_fp32_failures": int(fail32.sum()), "val_fp32_failures_predicted": caught}
 
 
-def evaluate(path, count=64, first=50_000, n=4096, kinds=("spd",), maxit=30):
+def evaluate(path, count=64, first=50_000, n=4096, kinds=("spd",), maxit=30, device_inputs=False):
     """Selector gain on fresh matrices: total time of AUTO (selector +
     fallback) against always-BF16SPLIT / FP32 / FP64 (with fallback) and the
     per-matrix best; every AUTO answer is checked against the float64
@@ -245,11 +245,16 @@ def evaluate(path, count=64, first=50_000, n=4096, kinds=("spd",), maxit=30):
         kappa = float(10.0 ** rng.uniform(1.0, 8.0))
         kind = kinds[k % len(kinds)]
         seed = int(rng.integers(1, 2 ** 31))
-        if kind == "spd":
-            a, _, _ = W.spd(n, kappa, seed)
+        if device_inputs:
+            import workloads.device as WD
+            ad = (WD.spd(n, kappa, seed, dev) if kind == "spd"
+                  else WD.nonsym_kappa(n, kappa, seed, dev))
         else:
-            a = W.nonsym_kappa(n, kappa, seed)
-        ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            if kind == "spd":
+                a, _, _ = W.spd(n, kappa, seed)
+            else:
+                a = W.nonsym_kappa(n, kappa, seed)
+            ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         row = {"kappa": kappa, "kind": kind}
         for p in ("auto",) + PRECS:
             torch.cuda.synchronize()
@@ -281,6 +286,8 @@ def main(argv=None):
     ap.add_argument("--evaluate", action="store_true", help="measure the gain of --out instead")
     ap.add_argument("--eval-n", type=int, default=4096)
     ap.add_argument("--eval-kinds", default="spd")
+    ap.add_argument("--eval-first", type=int, default=50_000,
+                    help="first evaluation index (disjoint from the training indices)")
     ap.add_argument("--count", type=int, default=1200, help="training (or evaluation) matrices")
     ap.add_argument("--first", type=int, default=10_000, help="first dataset index")
     ap.add_argument("--n-max-nonsym", type=int, default=320)
@@ -288,11 +295,17 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_FILE)
     ap.add_argument("--records", default=None, help="write the labelled records (JSON)")
     ap.add_argument("--from-records", default=None,
-                    help="train from previously labelled records instead of labelling")
+                    help="train from previously labelled records (comma-separated files) "
+                         "instead of labelling")
+    ap.add_argument("--device-inputs", action="store_true",
+                    help="generate the matrices on the device (same laws, torch generator)")
+    ap.add_argument("--label-only", action="store_true",
+                    help="label and write --records without training")
     args = ap.parse_args(argv)
     if args.evaluate:
         res = evaluate(args.out, count=args.count, n=args.eval_n,
-                       kinds=tuple(args.eval_kinds.split(",")))
+                       kinds=tuple(args.eval_kinds.split(",")), first=args.eval_first,
+                       device_inputs=args.device_inputs)
         print(json.dumps(res), flush=True)
         return
     dev = torch.device("cuda")
@@ -300,11 +313,16 @@ def main(argv=None):
     feats = []
     t0 = time.time()
     if args.from_records:
-        with open(args.from_records) as fh:
-            records = json.load(fh)
+        for fname in args.from_records.split(","):
+            with open(fname) as fh:
+                records.extend(json.load(fh))
     for k in range(0 if args.from_records else args.count):
-        a, kind, n, kappa = W.selector_matrix(args.first + k, args.n_max_nonsym)
-        ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        if args.device_inputs:
+            import workloads.device as WD
+            ad, kind, n, kappa = WD.selector_matrix(args.first + k, args.n_max_nonsym, dev)
+        else:
+            a, kind, n, kappa = W.selector_matrix(args.first + k, args.n_max_nonsym)
+            ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         f = features(ad).cpu().numpy()
         labs = label(ad)
         records.append({"index": args.first + k, "kind": kind, "n": n, "kappa": kappa,
@@ -312,6 +330,11 @@ def main(argv=None):
         feats.append(f)
         if k % 50 == 0:
             print(f"[selector] labelled {k + 1}/{args.count} ({time.time() - t0:.0f} s)", flush=True)
+    if args.label_only:
+        with open(args.records, "w") as fh:
+            json.dump(records, fh)
+        print(json.dumps({"labelled": len(records), "records": args.records}), flush=True)
+        return
     params, mean, scale, report = fit(records, epochs=args.epochs,
                                       log=lambda s: print("[selector] " + s, flush=True))
     cost = fit_cost(records)

@@ -128,20 +128,31 @@ def nonsym_kappa(n: int, kappa: float, seed: int) -> np.ndarray:
     return np.asfortranarray(q @ t @ q.T)
 
 
-def selector_matrix(index: int, n_max_nonsym: int = 1024):
-    """One matrix of the selector's training / evaluation law: 50% SPD and 50%
-    nonsymmetric, n = round(exp(U(ln 64, ln 1024))) (nonsymmetric capped at
-    n_max_nonsym), kappa = 10^U(1, 8); nonsymmetric inputs are 25% of the
-    2 I + G / sqrt(n) family and 75% nonsym_kappa.  Returns (A, kind, n,
-    kappa) with kind in {"spd", "shifted", "kappa"}."""
+def selector_params(index: int, n_max_nonsym: int = 1024):
+    """Parameters of matrix `index` of the selector's law: (kind, n, kappa,
+    seed).  50% SPD and 50% nonsymmetric, n = round(exp(U(ln 64, ln 1024)))
+    (nonsymmetric capped at n_max_nonsym), kappa = 10^U(1, 8); nonsymmetric
+    inputs are 25% of the 2 I + G / sqrt(n) family and 75% nonsym_kappa."""
     rng = _rng(1_000_003 * (index + 1))
     n = int(round(np.exp(rng.uniform(np.log(64.0), np.log(1024.0)))))
     kappa = float(10.0 ** rng.uniform(1.0, 8.0))
     seed = int(rng.integers(1, 2 ** 31))
     if rng.uniform() < 0.5:
-        a, _, _ = spd(n, kappa, seed)
-        return a, "spd", n, kappa
+        return "spd", n, kappa, seed
     n = min(n, n_max_nonsym)
     if rng.uniform() < 0.25:
-        return nonsym_shifted(n, seed), "shifted", n, kappa
-    return nonsym_kappa(n, kappa, seed), "kappa", n, kappa
+        return "shifted", n, kappa, seed
+    return "kappa", n, kappa, seed
+
+
+def selector_matrix(index: int, n_max_nonsym: int = 1024):
+    """One matrix of the selector's training / evaluation law (see
+    selector_params).  Returns (A, kind, n, kappa) with kind in {"spd",
+    "shifted", "kappa"}."""
+    kind, n, kappa, seed = selector_params(index, n_max_nonsym)
+    if kind == "spd":
+        a, _, _ = spd(n, kappa, seed)
+        return a, kind, n, kappa
+    if kind == "shifted":
+        return nonsym_shifted(n, seed), kind, n, kappa
+    return nonsym_kappa(n, kappa, seed), kind, n, kappa
