@@ -44,6 +44,43 @@ __device__ inline T cload(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wavefront sum by DPP: butterflies inside every row of 16 lanes (two quad
+// permutations, the half-row mirror, the row mirror) leave each lane with
+// its row's sum; the four row sums are then read with readlane.  Every lane
+// gets the total (in a fixed order, so results are reproducible).  All 64
+// lanes must be active: every call site in this file is reached by whole
+// wavefronts.
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp_v(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ inline double dpp_v(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float lane_of(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_of(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename V>
+__device__ inline V wsum(V v) {
+  v += dpp_v<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_v<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_v<0x141>(v);  // row_half_mirror
+  v += dpp_v<0x140>(v);  // row_mirror
+  return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
+}
+
 // Grid barrier on a counter that only grows within one reduction: every
 // workgroup adds 1 on arrival and waits until the counter reaches the
 // barrier's target (launch base + G (column + 1)), so an arrival costs one
@@ -143,7 +180,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
           if (offdiag) zk += v[c][q] * ((r < nI) ? uI[r] : T(0));
         }
         if (offdiag) {
-          zk = wave_sum(zk);
+          zk = wsum(zk);
           if (lane == 0 && cb + c < nK) zK[cb + c] += zk;
         }
       }
@@ -265,14 +302,14 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         const T* col = c < jj ? (PVI + c * kMaxTs) : (PWI + (c - jj) * kMaxTs);
         double s = 0.0;
         for (int r = lane; r < nI; r += kWave) s += (double)col[r] * (double)uI[r];
-        s = wave_sum(s);
+        s = wsum(s);
         if (lane == 0) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
       }
     }
     // one reduction of the three scalars (wave sums, then one thread), and
     // the pivot-row correction of d_j summed by the first wave
     {
-      const double w0 = wave_sum(s_uAu), w1 = wave_sum(s_sig), w2 = wave_sum(s_ua1);
+      const double w0 = wsum(s_uAu), w1 = wsum(s_sig), w2 = wsum(s_ua1);
       const int wv_ = tid / kWave, ln_ = tid % kWave;
       if (ln_ == 0) {
         red3[wv_][0] = w0;
@@ -282,7 +319,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       double pd = 0.0;
       if (tid < kWave) {
         if (tid < jj) pd = (double)PV[jj - 1][tid] * (double)PW[jj - 1][tid];
-        pd = wave_sum(pd);
+        pd = wsum(pd);
       }
       __syncthreads();
       if (tid == 0) {
@@ -347,9 +384,9 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         sig += spl[1][b];
         ua1 += spl[2][b];
       }
-      uAu = wave_sum(uAu);
-      sig = wave_sum(sig);
-      ua1 = wave_sum(ua1);
+      uAu = wsum(uAu);
+      sig = wsum(sig);
+      ua1 = wsum(ua1);
       if (tid == 0) {
         const double alpha = sc[3];
         double beta, tau, c;
@@ -384,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     __syncthreads();
     if (tid < kWave) {
       double vw = tid < jj ? (double)VTv[tid] * (double)WTv[tid] : 0.0;
-      vw = wave_sum(vw);
+      vw = wsum(vw);
       if (tid == 0) {
         const double a11 = (double)acP[jj];
         const double vAv = c * c * (sc[0] - 2.0 * beta * sc[2] + beta * beta * a11);
