@@ -301,6 +301,9 @@ def main(argv=None):
                     help="generate the matrices on the device (same laws, torch generator)")
     ap.add_argument("--label-only", action="store_true",
                     help="label and write --records without training")
+    ap.add_argument("--refit-cost", default=None, metavar="SELECTOR",
+                    help="keep the network of this selector file and refit only its cost "
+                         "model from --count freshly timed matrices (after kernel changes)")
     args = ap.parse_args(argv)
     if args.evaluate:
         res = evaluate(args.out, count=args.count, n=args.eval_n,
@@ -330,6 +333,13 @@ def main(argv=None):
         feats.append(f)
         if k % 50 == 0:
             print(f"[selector] labelled {k + 1}/{args.count} ({time.time() - t0:.0f} s)", flush=True)
+    if args.refit_cost:
+        params, mean, scale, _ = read(args.refit_cost)
+        # the first solves of a process include one-time module loading
+        cost = fit_cost(records[20:] if len(records) > 40 else records)
+        save(args.out, params, mean, scale, cost)
+        print(json.dumps({"refit_cost_from": len(records), "out": args.out}), flush=True)
+        return
     if args.label_only:
         with open(args.records, "w") as fh:
             json.dump(records, fh)
