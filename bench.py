@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--seed", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the fixed-FP64 comparator")
-    p.add_argument("--cpu-n", type=int, default=1536)
+    p.add_argument("--cpu-n", type=int, default=2304)
     p.add_argument("--copy-probe", action="store_true",
                    help="run one 512 MiB device copy first (reference kernel for HBM counters)")
     return p.parse_args()
