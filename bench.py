@@ -26,9 +26,13 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--n", type=int, default=4096)
+    p.add_argument("--workload", default="spd", choices=["spd", "nonsym", "complex_square"],
+                   help="spd (default, the benchmark line); nonsym = real nonsymmetric "
+                        "A = 2I + G/sqrt(n) (n=2048, seed 5); complex_square = complex A = B^2 "
+                        "(seed 6): general path, mixed vs FP64 factor, no roofline")
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=None)
+    p.add_argument("--n", type=int, default=None)
     p.add_argument("--kappa", type=float, default=1e4)
     p.add_argument("--seed", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -36,7 +40,15 @@ def parse():
     p.add_argument("--cpu-n", type=int, default=2304)
     p.add_argument("--copy-probe", action="store_true",
                    help="run one 512 MiB device copy first (reference kernel for HBM counters)")
-    return p.parse_args()
+    args = p.parse_args()
+    spd = args.workload == "spd"
+    if args.steps is None:
+        args.steps = 10 if spd else 2
+    if args.warmup is None:
+        args.warmup = 3 if spd else 1
+    if args.n is None:
+        args.n = {"spd": 4096, "nonsym": 2048, "complex_square": 4096}[args.workload]
+    return args
 
 
 def time_solves(msq, torch, a, prec, steps, warmup):
@@ -100,12 +112,69 @@ def cpu_baseline(n_cpu, n, kappa, seed):
     }
 
 
+def run_general(args):
+    """General path (Alg. 2): mixed (FP32 / complex64 Schur factor) against the
+    FP64 factor on the same GPU, both refined to relres <= 1e-13."""
+    import numpy as np
+    import torch
+
+    import paper_2607_12430_amd as msq
+    import workloads as W
+
+    n = args.n
+    if args.workload == "nonsym":
+        a_h = W.nonsym_shifted(n, 5)
+        workload = f"nonsym_shifted_n{n}"
+    else:
+        a_h, _ = W.complex_square(n, 6)
+        workload = f"complex_square_n{n}"
+    a = torch.from_numpy(np.ascontiguousarray(a_h)).cuda()
+    del a_h
+    torch.cuda.synchronize()
+    dt, x, infos = time_solves(msq, torch, a, "fp32", args.steps, args.warmup)
+    rr = gpu_relres(torch, x, a)
+    res = {"solves_per_s": args.steps / dt, "ms_per_solve": 1e3 * dt / args.steps}
+    fp64 = None
+    if not args.no_fp64:
+        dt64, x64, infos64 = time_solves(msq, torch, a, "fp64", args.steps, args.warmup)
+        fp64 = {"solves_per_s": args.steps / dt64, "ms_per_solve": 1e3 * dt64 / args.steps,
+                "relres": gpu_relres(torch, x64, a), "steps": infos64[-1]["steps"],
+                "phases_ms": {k: round(v, 3) for k, v in infos64[-1]["t_ms"].items()}}
+    out = {
+        "metric": "sqrtm solves/s, general path, mixed vs FP64 Schur, relres<=1e-13",
+        "value": round(res["solves_per_s"], 5),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_solve"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex64 factor+transforms, complex128 residual+update",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "tol": 1e-13},
+        "relres": rr,
+        "refinement_steps": infos[-1]["steps"],
+        "phases_ms": {k: round(v, 3) for k, v in infos[-1]["t_ms"].items()},
+        "fp64_schur": fp64,
+        "speedup_vs_fp64": (round(res["solves_per_s"] / fp64["solves_per_s"], 4) if fp64 else None),
+        "roofline": None,
+        "dominant_phase": "eig (multishift QR: serial bulge chains, latency-bound)",
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload != "spd":
+        run_general(args)
+        return
     import numpy as np
     import torch
 
