@@ -42,10 +42,11 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   const int64_t nn = (int64_t)n * n;
   T* Q = f->Q.ensure<T>(nn * batch);
   T* S = f->S.ensure<T>((int64_t)n * batch);
-  T* Aw = f->fw1.ensure<T>(nn);
-  T* d = f->fw2.ensure<T>(3 * (int64_t)n + 8);
-  T* e = d + n;
-  T* tau = e + n;
+  // all batch entries are cast and tridiagonalised together; the
+  // eigensolver and back-transformation then run entry by entry
+  const int64_t sD = 3 * (int64_t)n + 8;
+  T* Aw = f->fw1.ensure<T>(nn * batch);
+  T* d = f->fw2.ensure<T>(sD * batch);
   double* lam = f->fw3.ensure<double>(n + 8);
   double* mins = f->fw4.ensure<double>(batch);
   SytrdWork sw;
@@ -53,36 +54,39 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   StedcWork ew;
   OrmtrWork ow;
   const bool two = use_two_stage(n);
+  if (tm) tm->begin(MSQRT_T_REDUCE);
+  if (std::is_same<T, float>::value)
+    launch_cast_scale_f64_f32(st, n, A, lda, sA, f->ascale_dev(), (float*)Aw, n, nn, batch);
+  else
+    launch_cast_scale_f64_f64(st, n, A, lda, sA, f->ascale_dev(), (double*)Aw, n, nn, batch);
+  if (!two) sytrd_batched<T>(st, n, batch, Aw, nn, d, d + n, d + 2 * n, sD, sw);
   for (int b = 0; b < batch; ++b) {
-    if (tm) tm->begin(MSQRT_T_REDUCE);
-    if (std::is_same<T, float>::value)
-      launch_cast_scale_f64_f32(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (float*)Aw, n, 0, 1);
-    else
-      launch_cast_scale_f64_f64(st, n, A + b * sA, lda, 0, f->ascale_dev() + b, (double*)Aw, n, 0, 1);
-    if (two) sy2tr<T>(st, n, Aw, d, e, tw);
-    else sytrd<T>(st, n, Aw, d, e, tau, sw);
+    T* db = d + b * sD;
+    T* eb = db + n;
+    T* taub = eb + n;
+    T* Awb = Aw + b * nn;
+    if (two) {
+      if (tm) tm->begin(MSQRT_T_REDUCE);
+      sy2tr<T>(st, n, Awb, db, eb, tw);
+    }
     if (tm) tm->begin(MSQRT_T_EIG);
-    stedc<T>(st, n, d, e, lam, Q + b * nn, ew);
+    stedc<T>(st, n, db, eb, lam, Q + b * nn, ew);
     if (tm) tm->begin(MSQRT_T_BACK);
     if (two) sy2tr_back<T>(st, n, Q + b * nn, tw, ow);
-    else ormtr<T>(st, n, Aw, tau, Q + b * nn, ow);
+    else ormtr<T>(st, n, Awb, taub, Q + b * nn, ow);
     hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(1), dim3(256), 0, st, n, (const double*)lam,
                        S + (int64_t)b * n, mins + b);
     MSQRT_LAUNCH_CHECK();
-    if (tm) tm->end();
   }
+  if (tm) tm->end();
   minlam.resize(batch);
   MSQRT_HIP(hipMemcpyAsync(minlam.data(), mins, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
   MSQRT_HIP(hipStreamSynchronize(st));
   if (tm) tm->collect();
   if (two && sy2tr_failed(tw))
     throw Error{MSQRT_ERR_DEVICE, "band reduction: a bulge-chasing dependency wait timed out"};
-  // the sytrd barrier error flag
-  unsigned flag[2] = {0, 0};
-  if (sw.bar.p) {
-    MSQRT_HIP(hipMemcpy(flag, sw.bar.p, sizeof(flag), hipMemcpyDeviceToHost));
-    if (flag[1]) throw Error{MSQRT_ERR_DEVICE, "tridiagonal reduction: grid barrier timed out"};
-  }
+  if (sytrd_failed(sw))
+    throw Error{MSQRT_ERR_DEVICE, "tridiagonal reduction: grid barrier timed out"};
 }
 
 }  // namespace
@@ -167,9 +171,7 @@ void test_sytrd_impl(int n, const void* A, void* d, void* e, void* tau) {
     MSQRT_HIP(hipMemcpy(e, dv + n, sizeof(T) * (n - 1), hipMemcpyDeviceToHost));
     MSQRT_HIP(hipMemcpy(tau, dv + 2 * n, sizeof(T) * (n - 1), hipMemcpyDeviceToHost));
   }
-  unsigned flag[2] = {0, 0};
-  if (sw.bar.p) MSQRT_HIP(hipMemcpy(flag, sw.bar.p, sizeof(flag), hipMemcpyDeviceToHost));
-  if (flag[1]) throw Error{MSQRT_ERR_DEVICE, "grid barrier timed out"};
+  if (sytrd_failed(sw)) throw Error{MSQRT_ERR_DEVICE, "grid barrier timed out"};
 }
 template <typename T>
 void test_sy2tr_impl(int n, const void* A, void* d, void* e, void* Q) {

@@ -17,6 +17,8 @@
 // each workgroup reads its tile row-wise with coalesced loads and no
 // cross-tile reduction of the product is needed beyond the TR partial vectors.
 // After the panel: A22 -= [V W] [W V]^T on the MFMA GEMM (symmetric output).
+#include <vector>
+
 #include "gemm.hpp"
 #include "kernels.hpp"
 #include "profile.hpp"
@@ -124,6 +126,9 @@ struct PanelArgs {
   double* vp;    // [2][TR][2 kNbMax]
   unsigned* bar;
   unsigned bar_base;  // barrier counter value when the launch starts
+  // batch entry b = workgroup id / G: every pointer above advances by b times
+  // its stride
+  int64_t sA, sVW, sD, sYP, sSP, sVP, sBar;
 };
 
 // Tile product of one lower-triangular tile (I x K, I >= K) with the current
@@ -192,7 +197,21 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   constexpr int RPL = sizeof(T) == 4 ? 4 : 2;
   const int n = a.n, nb = a.nb, TR = a.TR, G = TR * (TR + 1) / 2;
-  const int blk = blockIdx.x;
+  // workgroup id = batch entry * G + tile
+  {
+    const int64_t bz = blockIdx.x / G;
+    a.A += bz * a.sA;
+    a.VW += bz * a.sVW;
+    a.WV += bz * a.sVW;
+    a.d += bz * a.sD;
+    a.e += bz * a.sD;
+    a.tau += bz * a.sD;
+    a.ypart += bz * a.sYP;
+    a.sp += bz * a.sSP;
+    a.vp += bz * a.sVP;
+    a.bar += bz * a.sBar;
+  }
+  const int blk = blockIdx.x % G;
   int bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
   while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
   while (bi * (bi + 1) / 2 > blk) --bi;
@@ -519,19 +538,22 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   }
 }
 
-// Last diagonal entry after the final trailing update.
+// Last diagonal entry after the final trailing update (one block per batch
+// entry).
 template <typename T>
-__global__ void copy_last_diag(const T* A, int n, T* d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) d[n - 1] = A[(n - 1) + (int64_t)(n - 1) * n];
+__global__ void copy_last_diag(const T* A, int n, T* d, int64_t sA, int64_t sD) {
+  const int64_t b = blockIdx.x;
+  if (threadIdx.x == 0) d[b * sD + n - 1] = A[b * sA + (n - 1) + (int64_t)(n - 1) * n];
 }
 
 }  // namespace
 
 template <typename T>
-void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
-  if (n <= 0) return;
+void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* e, T* tau,
+                   int64_t sD, SytrdWork& w) {
+  if (n <= 0 || batch <= 0) return;
   if (n == 1) {
-    hipLaunchKernelGGL(copy_last_diag<T>, 1, 64, 0, st, (const T*)A, n, d);
+    hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD);
     MSQRT_LAUNCH_CHECK();
     return;
   }
@@ -542,30 +564,48 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
   const int nb = std::min(kNbMax, (int)(lds_budget / (4 * kMaxTs * (int)sizeof(T))));
   const size_t dyn_lds = (size_t)4 * nb * kMaxTs * sizeof(T);
   static bool attr_set[2] = {false, false};
+  static int resident[2] = {0, 0};  // co-resident workgroups of the panel kernel
   if (!attr_set[sizeof(T) == 8]) {
     MSQRT_HIP(hipFuncSetAttribute((const void*)sytrd_panel_kernel<T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
+    int per_cu = 0, ncu = 0, dev = 0;
+    MSQRT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, (const void*)sytrd_panel_kernel<T>, kThreads, dyn_lds));
+    MSQRT_HIP(hipGetDevice(&dev));
+    MSQRT_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    resident[sizeof(T) == 8] = std::max(1, per_cu) * std::max(1, ncu);
     attr_set[sizeof(T) == 8] = true;
   }
-  T* VW = w.VW.ensure<T>((int64_t)n * 2 * kNbMax);
-  T* WV = w.WV.ensure<T>((int64_t)n * 2 * kNbMax);
-  T* ypart = w.ypart.ensure<T>((int64_t)2 * 16 * n);
-  double* sp = w.sp.ensure<double>((int64_t)2 * 256 * 4);
-  double* vp = w.vp.ensure<double>((int64_t)2 * 16 * 2 * kNbMax);
-  unsigned* bar = w.bar.ensure<unsigned>(32 * 40);
-  MSQRT_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned) * 32 * 40, st));
+  const int64_t sVW = (int64_t)n * 2 * kNbMax, sYP = (int64_t)2 * 16 * n, sSP = (int64_t)2 * 256 * 4,
+                sVP = (int64_t)2 * 16 * 2 * kNbMax, sBar = 32 * 40;
+  T* VW = w.VW.ensure<T>(sVW * batch);
+  T* WV = w.WV.ensure<T>(sVW * batch);
+  T* ypart = w.ypart.ensure<T>(sYP * batch);
+  double* sp = w.sp.ensure<double>(sSP * batch);
+  double* vp = w.vp.ensure<double>(sVP * batch);
+  unsigned* bar = w.bar.ensure<unsigned>(sBar * batch);
+  MSQRT_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned) * (size_t)(sBar * batch), st));
+  w.nbar = batch;
   unsigned bar_base = 0;
   for (int p = 0; p < n - 1; p += nb) {
     const int nbe = std::min(nb, n - 1 - p);
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
     const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
     const int ts = (int)ceil_div(m, TR);
-    PanelArgs<T> pa{n, p, nbe, TR, p + 1, ts, A, VW, WV, d, e, tau, ypart, sp, vp, bar, bar_base};
-    void* args[] = {&pa};
     const int G = TR * (TR + 1) / 2;
+    // as many batch entries per cooperative launch as fit co-resident
+    const int chunk = std::max(1, resident[sizeof(T) == 8] / G);
     const int tok = prof_begin(st);
-    MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G),
-                                         dim3(kThreads), args, dyn_lds, st));
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+      const int nbt = std::min(chunk, batch - b0);
+      PanelArgs<T> pa{n,          p,          nbe,        TR,          p + 1,         ts,
+                      A + b0 * sA, VW + b0 * sVW, WV + b0 * sVW, d + b0 * sD, e + b0 * sD,
+                      tau + b0 * sD, ypart + b0 * sYP, sp + b0 * sSP, vp + b0 * sVP,
+                      bar + b0 * sBar, bar_base, sA, sVW, sD, sYP, sSP, sVP, sBar};
+      void* args[] = {&pa};
+      MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G * nbt),
+                                           dim3(kThreads), args, dyn_lds, st));
+    }
     bar_base += (unsigned)G * (unsigned)nbe;
     if (tok >= 0) {
       // algorithmic traffic: one read of the symmetric trailing matrix (lower
@@ -576,27 +616,45 @@ void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
         bytes += 0.5 * mj * (mj + 1.0) * sizeof(T);
       }
       prof_end(tok, st, sizeof(T) == 4 ? "sytrd_panel_f32" : "sytrd_panel_f64",
-               4.0 * 0.5 * (double)m * m * nbe, bytes);
+               4.0 * 0.5 * (double)m * m * nbe * batch, bytes * batch);
     }
-    // Trailing update A(q:n, q:n) -= [V W] [W V]^T, q = p + nbe.
+    // Trailing update A(q:n, q:n) -= [V W] [W V]^T, q = p + nbe, all entries.
     const int q = p + nbe;
     if (q < n) {
       const int mt = n - q;
       if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, true, mt, mt, 2 * nbe, (const float*)(VW + q), n, 0,
-                       (const float*)(WV + q), n, 0, (float*)(A + q + (int64_t)q * n), n, 0, -1.f,
-                       1.f, 1, true);
+        gemm_store_f32(st, false, true, mt, mt, 2 * nbe, (const float*)(VW + q), n, sVW,
+                       (const float*)(WV + q), n, sVW, (float*)(A + q + (int64_t)q * n), n, sA,
+                       -1.f, 1.f, batch, true);
       else
-        gemm_store_f64(st, false, true, mt, mt, 2 * nbe, (const double*)(VW + q), n, 0,
-                       (const double*)(WV + q), n, 0, (double*)(A + q + (int64_t)q * n), n, 0,
-                       -1.0, 1.0, 1, true);
+        gemm_store_f64(st, false, true, mt, mt, 2 * nbe, (const double*)(VW + q), n, sVW,
+                       (const double*)(WV + q), n, sVW, (double*)(A + q + (int64_t)q * n), n, sA,
+                       -1.0, 1.0, batch, true);
     }
   }
-  hipLaunchKernelGGL(copy_last_diag<T>, 1, 64, 0, st, (const T*)A, n, d);
+  hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD);
   MSQRT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w) {
+  sytrd_batched<T>(st, n, 1, A, (int64_t)n * n, d, e, tau, 0, w);
+}
+
+bool sytrd_failed(SytrdWork& w) {
+  if (!w.bar.p || w.nbar <= 0) return false;
+  std::vector<unsigned> flags((size_t)32 * 40 * w.nbar);
+  MSQRT_HIP(hipMemcpy(flags.data(), w.bar.p, sizeof(unsigned) * flags.size(), hipMemcpyDeviceToHost));
+  for (int b = 0; b < w.nbar; ++b)
+    if (flags[(size_t)b * 32 * 40 + 1]) return true;
+  return false;
 }
 
 template void sytrd<float>(hipStream_t, int, float*, float*, float*, float*, SytrdWork&);
 template void sytrd<double>(hipStream_t, int, double*, double*, double*, double*, SytrdWork&);
+template void sytrd_batched<float>(hipStream_t, int, int, float*, int64_t, float*, float*, float*,
+                                   int64_t, SytrdWork&);
+template void sytrd_batched<double>(hipStream_t, int, int, double*, int64_t, double*, double*,
+                                    double*, int64_t, SytrdWork&);
 
 }  // namespace msqrt

@@ -8,6 +8,7 @@ namespace msqrt {
 
 struct SytrdWork {
   DevBuf VW, WV, ypart, sp, vp, bar;
+  int nbar = 0;  // batch entries of the last reduction (error flags)
 };
 
 struct StedcWork {
@@ -35,6 +36,15 @@ struct Sy2trWork {
 // panel start.  d (n), e (n-1), tau (n-1) in the factor precision.
 template <typename T>
 void sytrd(hipStream_t st, int n, T* A, T* d, T* e, T* tau, SytrdWork& w);
+// The same for `batch` matrices A + b sA; entry b's d, e, tau start at
+// d + b sD, e + b sD, tau + b sD.  As many entries as fit co-resident share
+// one cooperative launch per panel (each with its own grid barrier), and
+// the trailing updates are one batched GEMM.
+template <typename T>
+void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* e, T* tau,
+                   int64_t sD, SytrdWork& w);
+// True if a grid barrier of the last reduction timed out (synchronous).
+bool sytrd_failed(SytrdWork& w);
 
 // Eigen-decomposition of the symmetric tridiagonal (d, e): lam ascending
 // (float64) and eigenvectors Z (n x n, ld n, precision T).
