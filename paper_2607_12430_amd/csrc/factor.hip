@@ -63,7 +63,6 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   for (int b = 0; b < batch; ++b) {
     T* db = d + b * sD;
     T* eb = db + n;
-    T* taub = eb + n;
     T* Awb = Aw + b * nn;
     if (two) {
       if (tm) tm->begin(MSQRT_T_REDUCE);
@@ -71,12 +70,17 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
     }
     if (tm) tm->begin(MSQRT_T_EIG);
     stedc<T>(st, n, db, eb, lam, Q + b * nn, ew);
-    if (tm) tm->begin(MSQRT_T_BACK);
-    if (two) sy2tr_back<T>(st, n, Q + b * nn, tw, ow);
-    else ormtr<T>(st, n, Awb, taub, Q + b * nn, ow);
     hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(1), dim3(256), 0, st, n, (const double*)lam,
                        S + (int64_t)b * n, mins + b);
     MSQRT_LAUNCH_CHECK();
+    if (two) {
+      if (tm) tm->begin(MSQRT_T_BACK);
+      sy2tr_back<T>(st, n, Q + b * nn, tw, ow);
+    }
+  }
+  if (!two) {
+    if (tm) tm->begin(MSQRT_T_BACK);
+    ormtr_batched<T>(st, n, batch, Aw, nn, d + 2 * n, sD, Q, nn, ow);
   }
   if (tm) tm->end();
   minlam.resize(batch);

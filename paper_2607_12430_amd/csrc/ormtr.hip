@@ -22,8 +22,9 @@ constexpr int kBlk = 128;
 // full-height products can be used; the unit entry v_j(j+1) = 1 is already
 // stored.
 template <typename T>
-__global__ void clean_reflectors(int n, T* V) {
+__global__ void clean_reflectors(int n, T* V, int64_t sV) {
   const int j = blockIdx.x;
+  V += (int64_t)blockIdx.y * sV;
   for (int i = threadIdx.x; i <= j && i < n; i += blockDim.x) V[i + (int64_t)j * n] = T(0);
 }
 
@@ -31,8 +32,12 @@ __global__ void clean_reflectors(int n, T* V) {
 // T(i,i) = tau_i,  T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i).
 template <typename T>
 __global__ __launch_bounds__(kBlk) void larft_kernel(int nb_total, const T* G, const T* tau,
-                                                     T* Tm) {
+                                                     T* Tm, int64_t sG, int64_t sTau,
+                                                     int64_t sTm) {
   const int blk = blockIdx.x;
+  G += (int64_t)blockIdx.y * sG;
+  tau += (int64_t)blockIdx.y * sTau;
+  Tm += (int64_t)blockIdx.y * sTm;
   const int B = blk * kBlk;
   const int nbk = min(kBlk, nb_total - B);
   const T* g = G + (int64_t)blk * kBlk * kBlk;
@@ -71,7 +76,8 @@ __global__ void sum_partials(int count, int splits, const T* P, int64_t stride, 
 template <typename T>
 void ormtr(hipStream_t st, int n, const T* Vc, const T* tau, T* Z, OrmtrWork& w) {
   if (n - 1 <= 0) return;
-  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n), dim3(256), 0, st, n, const_cast<T*>(Vc));
+  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n), dim3(256), 0, st, n, const_cast<T*>(Vc),
+                     (int64_t)0);
   MSQRT_LAUNCH_CHECK();
   ormtr_blocks<T>(st, n, n - 1, 1, Vc, tau, Z, w);
 }
@@ -107,7 +113,8 @@ void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* Vc, const T
     gemm(true, false, nbk, nbk, n, Vb, n, 0, Vb, n, 0, G + (int64_t)full * kBlk * kBlk, kBlk, 0,
          T(1), T(0), 1);
   }
-  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kBlk), 0, st, nref, (const T*)G, tau, Tm);
+  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kBlk), 0, st, nref, (const T*)G, tau, Tm,
+                     (int64_t)0, (int64_t)0, (int64_t)0);
   MSQRT_LAUNCH_CHECK();
   // VT_b = V_b T_b (n x nbk)
   if (full > 0)
@@ -146,8 +153,75 @@ void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* Vc, const T
   }
 }
 
+template <typename T>
+void ormtr_batched(hipStream_t st, int n, int batch, const T* Vc, int64_t sV, const T* tau,
+                   int64_t sTau, T* Z, int64_t sZ, OrmtrWork& w) {
+  if (batch == 1) {
+    ormtr<T>(st, n, Vc, tau, Z, w);
+    return;
+  }
+  const int nref = n - 1;
+  if (nref <= 0 || batch <= 0) return;
+  const int nblk = (int)ceil_div(nref, kBlk);
+  const int full = nref / kBlk;
+  const int64_t sG = (int64_t)nblk * kBlk * kBlk * 2, sVT = (int64_t)nblk * kBlk * n;
+  T* Gall = w.gram.ensure<T>(sG * batch);
+  T* VTall = w.VT.ensure<T>(sVT * batch);
+  T* Wall = w.W.ensure<T>((int64_t)kBlk * n * batch);
+  auto gemm = [&](bool ta, bool tb, int M, int N, int K, const T* A, int64_t lda, int64_t sA,
+                  const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, T alpha,
+                  T beta, int nb) {
+    if (std::is_same<T, float>::value)
+      gemm_store_f32(st, ta, tb, M, N, K, (const float*)A, lda, sA, (const float*)B, ldb, sB,
+                     (float*)C, ldc, sC, (float)alpha, (float)beta, nb, false);
+    else
+      gemm_store_f64(st, ta, tb, M, N, K, (const double*)A, lda, sA, (const double*)B, ldb, sB,
+                     (double*)C, ldc, sC, (double)alpha, (double)beta, nb, false);
+  };
+  // clean reflectors, Gram matrices, T factors and VT = V T of every entry:
+  // one launch per reflector block (batched over entries) for each product
+  T* V = const_cast<T*>(Vc);
+  const int64_t offT = (int64_t)nblk * kBlk * kBlk;  // T factors follow the Gram blocks
+  hipLaunchKernelGGL(clean_reflectors<T>, dim3(n, batch), dim3(256), 0, st, n, V, sV);
+  MSQRT_LAUNCH_CHECK();
+  MSQRT_HIP(hipMemsetAsync(Gall, 0, sizeof(T) * (size_t)(sG * batch), st));
+  for (int b = 0; b < nblk; ++b) {
+    const int nbk = std::min(kBlk, nref - b * kBlk);
+    const T* Vb = Vc + (int64_t)b * kBlk * n;
+    gemm(true, false, nbk, nbk, n, Vb, n, sV, Vb, n, sV, Gall + (int64_t)b * kBlk * kBlk, kBlk,
+         sG, T(1), T(0), batch);
+  }
+  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk, batch), dim3(kBlk), 0, st, nref, (const T*)Gall,
+                     tau, Gall + offT, sG, sTau, sG);
+  MSQRT_LAUNCH_CHECK();
+  for (int b = 0; b < nblk; ++b) {
+    const int nbk = std::min(kBlk, nref - b * kBlk);
+    gemm(false, false, n, nbk, nbk, Vc + (int64_t)b * kBlk * n, n, sV,
+         Gall + offT + (int64_t)b * kBlk * kBlk, kBlk, sG, VTall + (int64_t)b * kBlk * n, n, sVT,
+         T(1), T(0), batch);
+  }
+  // the blocks, last to first, each applied to every entry by two batched
+  // GEMMs (the batch supplies the parallelism that split-K gives one matrix)
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int B = b * kBlk;
+    const int nbk = std::min(kBlk, nref - B);
+    const int r0 = B + 1;
+    const int rows = n - r0;
+    // W_m = V_m(r0:, B:B+nbk)^T Z_m(r0:, :)
+    gemm(true, false, nbk, n, rows, Vc + (int64_t)B * n + r0, n, sV, Z + r0, n, sZ, Wall, nbk,
+         (int64_t)kBlk * n, T(1), T(0), batch);
+    // Z_m(r0:, :) -= VT_m(r0:, block) W_m
+    gemm(false, false, rows, n, nbk, VTall + (int64_t)b * kBlk * n + r0, n, sVT, Wall, nbk,
+         (int64_t)kBlk * n, Z + r0, n, sZ, T(-1), T(1), batch);
+  }
+}
+
 template void ormtr<float>(hipStream_t, int, const float*, const float*, float*, OrmtrWork&);
 template void ormtr<double>(hipStream_t, int, const double*, const double*, double*, OrmtrWork&);
+template void ormtr_batched<float>(hipStream_t, int, int, const float*, int64_t, const float*,
+                                   int64_t, float*, int64_t, OrmtrWork&);
+template void ormtr_batched<double>(hipStream_t, int, int, const double*, int64_t, const double*,
+                                    int64_t, double*, int64_t, OrmtrWork&);
 template void ormtr_blocks<float>(hipStream_t, int, int, int, const float*, const float*, float*,
                                   OrmtrWork&);
 template void ormtr_blocks<double>(hipStream_t, int, int, int, const double*, const double*,

@@ -56,6 +56,13 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
 template <typename T>
 void ormtr(hipStream_t st, int n, const T* V, const T* tau, T* Z, OrmtrWork& w);
 
+// ormtr for `batch` matrices (V + m sV, tau + m sTau, Z + m sZ); batches of
+// more than one apply every reflector block to all entries with batched
+// GEMMs.
+template <typename T>
+void ormtr_batched(hipStream_t st, int n, int batch, const T* V, int64_t sV, const T* tau,
+                   int64_t sTau, T* Z, int64_t sZ, OrmtrWork& w);
+
 // Z <- H_0 ... H_{nref-1} Z for explicit reflector columns V(:, j) (n x nref,
 // ld n) that vanish above row j + off and are 1 there.
 template <typename T>
