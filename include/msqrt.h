@@ -114,7 +114,7 @@ enum {
 /* Fills *opt with the defaults listed in msqrt_options. */
 void msqrt_default_options(msqrt_options* opt);
 
-/* Low-precision Schur factorisation of A (Alg. 2 lines 1-2, Alg. 3 lines 1-2):
+/* Low-precision Schur factorisation of A (the factorisation steps of Alg. 2 and Alg. 3):
  * HPD input -> spectral decomposition A/4^k ~ Q diag(s^2) Q^*;
  * general input -> complex Schur form A/4^k ~ Q T Q^*, S = T^{1/2}.
  * The precision is opt->prec (AUTO picks one).  On success *out owns Q, S, the

@@ -12,10 +12,14 @@ namespace msqrt {
 
 namespace {
 
-// s_i = sqrt(lam_i) in the factor precision; out[0] = min lam (float64).
+// s_i = sqrt(lam_i) in the factor precision and min lam (float64), for
+// batch entry blockIdx.x (lam, s: n per entry).
 template <typename T>
 __global__ __launch_bounds__(256) void finish_hpd_kernel(int n, const double* lam, T* s,
                                                          double* minlam) {
+  lam += (int64_t)blockIdx.x * n;
+  s += (int64_t)blockIdx.x * n;
+  minlam += blockIdx.x;
   __shared__ double red[4];
   double mn = INFINITY;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -42,12 +46,12 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
   const int64_t nn = (int64_t)n * n;
   T* Q = f->Q.ensure<T>(nn * batch);
   T* S = f->S.ensure<T>((int64_t)n * batch);
-  // all batch entries are cast and tridiagonalised together; the
-  // eigensolver and back-transformation then run entry by entry
+  // all batch entries are cast, tridiagonalised, diagonalised and
+  // back-transformed together (the two-stage route runs entry by entry)
   const int64_t sD = 3 * (int64_t)n + 8;
   T* Aw = f->fw1.ensure<T>(nn * batch);
   T* d = f->fw2.ensure<T>(sD * batch);
-  double* lam = f->fw3.ensure<double>(n + 8);
+  double* lam = f->fw3.ensure<double>((int64_t)n * batch + 8);
   double* mins = f->fw4.ensure<double>(batch);
   SytrdWork sw;
   Sy2trWork tw;
@@ -59,25 +63,24 @@ void factor_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, hipStream_t
     launch_cast_scale_f64_f32(st, n, A, lda, sA, f->ascale_dev(), (float*)Aw, n, nn, batch);
   else
     launch_cast_scale_f64_f64(st, n, A, lda, sA, f->ascale_dev(), (double*)Aw, n, nn, batch);
-  if (!two) sytrd_batched<T>(st, n, batch, Aw, nn, d, d + n, d + 2 * n, sD, sw);
-  for (int b = 0; b < batch; ++b) {
-    T* db = d + b * sD;
-    T* eb = db + n;
-    T* Awb = Aw + b * nn;
-    if (two) {
+  if (two) {
+    for (int b = 0; b < batch; ++b) {
+      T* db = d + b * sD;
       if (tm) tm->begin(MSQRT_T_REDUCE);
-      sy2tr<T>(st, n, Awb, db, eb, tw);
-    }
-    if (tm) tm->begin(MSQRT_T_EIG);
-    stedc<T>(st, n, db, eb, lam, Q + b * nn, ew);
-    hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(1), dim3(256), 0, st, n, (const double*)lam,
-                       S + (int64_t)b * n, mins + b);
-    MSQRT_LAUNCH_CHECK();
-    if (two) {
+      sy2tr<T>(st, n, Aw + b * nn, db, db + n, tw);
+      if (tm) tm->begin(MSQRT_T_EIG);
+      stedc<T>(st, n, db, db + n, lam + (int64_t)b * n, Q + b * nn, ew);
       if (tm) tm->begin(MSQRT_T_BACK);
       sy2tr_back<T>(st, n, Q + b * nn, tw, ow);
     }
+  } else {
+    sytrd_batched<T>(st, n, batch, Aw, nn, d, d + n, d + 2 * n, sD, sw);
+    if (tm) tm->begin(MSQRT_T_EIG);
+    stedc_batched<T>(st, n, batch, d, d + n, sD, lam, Q, ew);
   }
+  hipLaunchKernelGGL(finish_hpd_kernel<T>, dim3(batch), dim3(256), 0, st, n, (const double*)lam, S,
+                     mins);
+  MSQRT_LAUNCH_CHECK();
   if (!two) {
     if (tm) tm->begin(MSQRT_T_BACK);
     ormtr_batched<T>(st, n, batch, Aw, nn, d + 2 * n, sD, Q, nn, ow);

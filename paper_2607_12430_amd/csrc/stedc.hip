@@ -31,6 +31,17 @@ struct MergeDesc {
   int s, n1, m;  // start, left size, total size
 };
 
+// A batch of tridiagonal matrices of order n is solved as one matrix of
+// order batch * n whose off-diagonal vanishes at the entry boundaries: every
+// position s of the concatenated index space belongs to entry s / n, and no
+// leaf or merge straddles two entries.  The eigenvector matrices stay n x n
+// per entry (stride n * n); this is the offset of the diagonal block that
+// starts at position s.
+__host__ __device__ inline int64_t blk_off(int s, int n) {
+  const int e = s / n, sl = s - e * n;
+  return (int64_t)e * n * n + sl + (int64_t)sl * n;
+}
+
 // Per-position metadata arrays (all length n, indexed by s + local index).
 struct Meta {
   double* dl;      // non-deflated poles, ascending
@@ -142,7 +153,8 @@ __global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const i
   __syncthreads();
   if (lane < L) {
     lam[s + rank[lane]] = d[lane];
-    for (int c = 0; c < L; ++c) Z[(int64_t)(s + lane) + (int64_t)(s + rank[c]) * n] = (T)Zl[lane][c];
+    T* Zb = Z + blk_off(s, n);
+    for (int c = 0; c < L; ++c) Zb[lane + (int64_t)rank[c] * n] = (T)Zl[lane][c];
   }
 }
 
@@ -160,6 +172,7 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, co
   const double sgn = beta >= 0.0 ? 1.0 : -1.0;
   const double rho = 2.0 * fabs(beta);
   const double r2 = 0.7071067811865476;
+  const T* Zg = Z + blk_off(s, n);
   __shared__ double red[4];
   // merge-path placement of the two ascending halves
   double dmax = 0.0, zmax = 0.0;
@@ -168,14 +181,14 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, co
     int pos;
     if (i < n1) {
       di = lam[s + i];
-      zi = r2 * (double)Z[(int64_t)(s + n1 - 1) + (int64_t)(s + i) * n];
+      zi = r2 * (double)Zg[(n1 - 1) + (int64_t)i * n];
       int lo = 0, hi = n2;  // count right values < di
       while (lo < hi) { const int mid = (lo + hi) / 2; if (lam[s + n1 + mid] < di) lo = mid + 1; else hi = mid; }
       pos = i + lo;
     } else {
       const int jr = i - n1;
       di = lam[s + i];
-      zi = sgn * r2 * (double)Z[(int64_t)(s + n1) + (int64_t)(s + i) * n];
+      zi = sgn * r2 * (double)Zg[n1 + (int64_t)i * n];
       int lo = 0, hi = n1;  // count left values <= di
       while (lo < hi) { const int mid = (lo + hi) / 2; if (lam[s + mid] <= di) lo = mid + 1; else hi = mid; }
       pos = jr + lo;
@@ -285,12 +298,13 @@ __global__ void merge_rot_kernel(const MergeDesc* md, int nmerge_rows, const int
   if (b < 0) return;
   const MergeDesc g = md[b];
   const int nr = mt.kcnt[3 * b + 2];
+  T* Zr = Z + blk_off(g.s, n) + (r - g.s);  // row r of the merge block
   for (int q = 0; q < nr; ++q) {
-    const int ca = g.s + mt.rota[g.s + q], cb = g.s + mt.rotb[g.s + q];
+    const int64_t ca = (int64_t)mt.rota[g.s + q] * n, cb = (int64_t)mt.rotb[g.s + q] * n;
     const double c = mt.rotc[g.s + q], sn = mt.rots[g.s + q];
-    const double x = (double)Z[(int64_t)r + (int64_t)ca * n], y = (double)Z[(int64_t)r + (int64_t)cb * n];
-    Z[(int64_t)r + (int64_t)ca * n] = (T)(c * x + sn * y);
-    Z[(int64_t)r + (int64_t)cb * n] = (T)(c * y - sn * x);
+    const double x = (double)Zr[ca], y = (double)Zr[cb];
+    Zr[ca] = (T)(c * x + sn * y);
+    Zr[cb] = (T)(c * y - sn * x);
   }
 }
 
@@ -494,43 +508,55 @@ __global__ __launch_bounds__(64) void vectors_kernel(const MergeDesc* md, const 
   }
 }
 
+// Concatenated float64 copies of the batch's diagonals; the coupling at the
+// end of every entry is zero.
 template <typename T>
-__global__ void cast_tridiag(int n, const T* d, const T* e, double* dd, double* ee) {
+__global__ void cast_tridiag(int n, const T* d, const T* e, int64_t sD, double* dd, double* ee) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
   if (i < n) {
-    dd[i] = (double)d[i];
-    ee[i] = (i + 1 < n) ? (double)e[i] : 0.0;
+    dd[(int64_t)b * n + i] = (double)d[b * sD + i];
+    ee[(int64_t)b * n + i] = (i + 1 < n) ? (double)e[b * sD + i] : 0.0;
   }
 }
 
-// Copies the diagonal block [r0, r0+sz) of Za (and its eigenvalues) to Zb.
+// Copies the diagonal block [r0, r0+sz) of entry blockIdx.y of Za (and its
+// eigenvalues) to Zb.
 template <typename T>
 __global__ void copy_block(int n, int r0, int sz, const T* Za, T* Zb, const double* la,
                            double* lb) {
   const int c = r0 + blockIdx.x;
+  const int64_t zo = (int64_t)blockIdx.y * n * n;
   for (int i = threadIdx.x; i < sz; i += blockDim.x)
-    Zb[(int64_t)(r0 + i) + (int64_t)c * n] = Za[(int64_t)(r0 + i) + (int64_t)c * n];
-  if (threadIdx.x == 0) lb[c] = la[c];
+    Zb[zo + (int64_t)(r0 + i) + (int64_t)c * n] = Za[zo + (int64_t)(r0 + i) + (int64_t)c * n];
+  if (threadIdx.x == 0) lb[(int64_t)blockIdx.y * n + c] = la[(int64_t)blockIdx.y * n + c];
 }
 
 template <typename T>
-__global__ void copy_mat(int n, const T* a, T* b) {
+__global__ void copy_mat(int64_t cnt, const T* a, T* b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (int64_t)n * n) b[i] = a[i];
+  if (i < cnt) b[i] = a[i];
 }
 
 }  // namespace
 
 template <typename T>
-void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, StedcWork& w) {
-  if (n <= 0) return;
+void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int64_t sD,
+                   double* lam, T* Z, StedcWork& w) {
+  if (n <= 0 || batch <= 0) return;
   const int64_t nn = (int64_t)n * n;
-  double* dd = w.dd.ensure<double>(n);
-  double* ee = w.ee.ensure<double>(n);
-  hipLaunchKernelGGL(cast_tridiag<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, d, e, dd, ee);
+  const int64_t N64 = (int64_t)n * batch;
+  if (N64 > (int64_t)1 << 30 || nn * batch > ((int64_t)1 << 40))
+    throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal eigensolver: batch too large"};
+  const int N = (int)N64;
+  double* dd = w.dd.ensure<double>(N);
+  double* ee = w.ee.ensure<double>(N);
+  hipLaunchKernelGGL(cast_tridiag<T>, dim3((unsigned)ceil_div(n, 256), (unsigned)batch), dim3(256), 0,
+                     st, n, d, e, sD, dd, ee);
   MSQRT_LAUNCH_CHECK();
 
-  // Static recursion tree: halve until the pieces are at most kLeaf.
+  // Static recursion tree of one entry: halve until the pieces are at most
+  // kLeaf.  Every entry has the same tree, shifted by a multiple of n.
   std::vector<std::vector<MergeDesc>> levels;  // levels[0] = leaves' parents ... top
   std::vector<std::pair<int, int>> cur{{0, n}};
   std::vector<std::vector<std::pair<int, int>>> tree{cur};
@@ -554,7 +580,8 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
   // node of tree[L] that was split.
   const auto& leaves = tree.back();
   std::vector<int> lst, lsz, splits;
-  for (auto& pr : leaves) { lst.push_back(pr.first); lsz.push_back(pr.second); }
+  for (int b = 0; b < batch; ++b)
+    for (auto& pr : leaves) { lst.push_back(b * n + pr.first); lsz.push_back(pr.second); }
   // Nodes of a tree level that are not split are already solved leaves; they
   // are carried unchanged through that level's merge step.
   std::vector<std::vector<std::pair<int, int>>> carried;
@@ -565,7 +592,7 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
       if (pr.second > kLeaf) {
         const int h = pr.second / 2;
         lv.push_back({pr.first, h, pr.second});
-        splits.push_back(pr.first + h);
+        for (int b = 0; b < batch; ++b) splits.push_back(b * n + pr.first + h);
       } else {
         cv.push_back(pr);
       }
@@ -578,7 +605,7 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
 
   // device metadata
   const int nl = (int)lst.size();
-  int* dmeta = w.meta.ensure<int>(2 * nl + (int64_t)splits.size() + 4 * n + 8);
+  int* dmeta = w.meta.ensure<int>(2 * (int64_t)nl + (int64_t)splits.size() + 4 * N64 + 8);
   int* dlst = dmeta;
   int* dlsz = dmeta + nl;
   int* dspl = dmeta + 2 * nl;
@@ -594,26 +621,29 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
     MSQRT_LAUNCH_CHECK();
   }
   T* Za = Z;
-  T* Zb = w.Z2.ensure<T>(nn);
-  MSQRT_HIP(hipMemsetAsync(Za, 0, sizeof(T) * nn, st));
-  MSQRT_HIP(hipMemsetAsync(Zb, 0, sizeof(T) * nn, st));
+  T* Zb = w.Z2.ensure<T>(nn * batch);
+  MSQRT_HIP(hipMemsetAsync(Za, 0, sizeof(T) * nn * batch, st));
+  MSQRT_HIP(hipMemsetAsync(Zb, 0, sizeof(T) * nn * batch, st));
   double* lamA = lam;
-  double* lamB = w.lam.ensure<double>(n);
+  double* lamB = w.lam.ensure<double>(N);
   hipLaunchKernelGGL(leaf_kernel<T>, dim3(nl), dim3(64), 0, st, dlst, dlsz, dd, ee, lamA, Za, n);
   MSQRT_LAUNCH_CHECK();
   if (levels.empty()) return;
 
-  // metadata buffers
+  // metadata buffers, indexed by concatenated position (per merge: by the
+  // merge's index in its level, entry-major)
   Meta mt;
-  double* fb = w.roots.ensure<double>((int64_t)12 * n + 16);
-  int* ib = w.rot.ensure<int>((int64_t)10 * n + 16);
-  mt.dl = fb; mt.zl = fb + n; mt.defd = fb + 2 * n; mt.rotc = fb + 3 * n; mt.rots = fb + 4 * n;
-  mt.tau = fb + 5 * n; mt.lamr = fb + 6 * n; mt.zhat = fb + 7 * n; mt.tmpd = fb + 8 * n;
-  mt.tmpz = fb + 9 * n; mt.rho = fb + 10 * n;
-  mt.cl = ib; mt.defc = ib + n; mt.rota = ib + 2 * n; mt.rotb = ib + 3 * n; mt.org = ib + 4 * n;
-  mt.tmpc = ib + 5 * n; mt.kcnt = ib + 6 * n;
-  MergeDesc* dmd = (MergeDesc*)w.zhat.ensure<int>((int64_t)3 * n + 16);
-  T* M = w.M.ensure<T>(nn);
+  double* fb = w.roots.ensure<double>((int64_t)12 * N + 16);
+  int* ib = w.rot.ensure<int>((int64_t)10 * N + 16);
+  mt.dl = fb; mt.zl = fb + N; mt.defd = fb + 2 * N; mt.rotc = fb + 3 * N; mt.rots = fb + 4 * N;
+  mt.tau = fb + 5 * N; mt.lamr = fb + 6 * N; mt.zhat = fb + 7 * N; mt.tmpd = fb + 8 * N;
+  mt.tmpz = fb + 9 * N; mt.rho = fb + 10 * N;
+  mt.cl = ib; mt.defc = ib + N; mt.rota = ib + 2 * N; mt.rotb = ib + 3 * N; mt.org = ib + 4 * N;
+  mt.tmpc = ib + 5 * N; mt.kcnt = ib + 6 * N;
+  MergeDesc* dmd = (MergeDesc*)w.zhat.ensure<int>((int64_t)3 * N + 16);
+  // M: the m x m secular eigenvector block of the merge at position s sits
+  // at M + s * n (ld m)
+  T* M = w.M.ensure<T>(nn * batch);
 
   static bool prep_attr[2] = {false, false};
   if (!prep_attr[sizeof(T) == 8]) {
@@ -621,59 +651,76 @@ void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, Ste
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
     prep_attr[sizeof(T) == 8] = true;
   }
-  std::vector<int> posm(n);
+  std::vector<int> posm(N);
+  std::vector<MergeDesc> all;
   for (size_t L = 0; L < levels.size(); ++L) {
     const auto& lv = levels[L];
-    const int nm = (int)lv.size();
+    const int nm1 = (int)lv.size();
+    const int nm = nm1 * batch;
+    all.clear();
+    for (int b = 0; b < batch; ++b)
+      for (auto g : lv) { g.s += b * n; all.push_back(g); }
     std::fill(posm.begin(), posm.end(), -1);
     for (int b = 0; b < nm; ++b)
-      for (int i = 0; i < lv[b].m; ++i) posm[lv[b].s + i] = b;
-    MSQRT_HIP(hipMemcpyAsync(dmd, lv.data(), sizeof(MergeDesc) * nm, hipMemcpyHostToDevice, st));
-    MSQRT_HIP(hipMemcpyAsync(pos_merge, posm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+      for (int i = 0; i < all[b].m; ++i) posm[all[b].s + i] = b;
+    MSQRT_HIP(hipMemcpyAsync(dmd, all.data(), sizeof(MergeDesc) * nm, hipMemcpyHostToDevice, st));
+    MSQRT_HIP(hipMemcpyAsync(pos_merge, posm.data(), sizeof(int) * N, hipMemcpyHostToDevice, st));
     int mmax = 0;
     for (auto& g : lv) mmax = std::max(mmax, g.m);
     const size_t prep_lds = (size_t)mmax * (2 * sizeof(double) + sizeof(int));
     if (prep_lds > 140 * 1024) throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal eigensolver supports n <= 7000"};
     hipLaunchKernelGGL(merge_prep_kernel<T>, dim3(nm), dim3(256), prep_lds, st, dmd, ee, lamA, Za, n, mt);
     MSQRT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(merge_rot_kernel<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, dmd, n,
+    hipLaunchKernelGGL(merge_rot_kernel<T>, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, st, dmd, N,
                        pos_merge, mt, Za, n);
     MSQRT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(secular_kernel, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, n);
+    hipLaunchKernelGGL(secular_kernel, dim3(N), dim3(64), 0, st, dmd, pos_merge, mt, n);
     MSQRT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(lowner_kernel, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, n);
+    hipLaunchKernelGGL(lowner_kernel, dim3(N), dim3(64), 0, st, dmd, pos_merge, mt, n);
     MSQRT_LAUNCH_CHECK();
-    MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn, st));
-    hipLaunchKernelGGL(vectors_kernel<T>, dim3(n), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);
+    MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn * batch, st));
+    hipLaunchKernelGGL(vectors_kernel<T>, dim3(N), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);
     MSQRT_LAUNCH_CHECK();
-    for (int b = 0; b < nm; ++b) {
+    // one GEMM per merge of the level, batched over the entries
+    for (int b = 0; b < nm1; ++b) {
       const MergeDesc& g = lv[b];
-      const T* Ablk = Za + g.s + (int64_t)g.s * n;
-      T* Cblk = Zb + g.s + (int64_t)g.s * n;
+      const T* Ablk = Za + blk_off(g.s, n);
+      T* Cblk = Zb + blk_off(g.s, n);
       const T* Mb = M + (int64_t)g.s * n;
       if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, 0, (const float*)Mb,
-                       g.m, 0, (float*)Cblk, n, 0, 1.f, 0.f, 1, false);
+        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, nn, (const float*)Mb,
+                       g.m, nn, (float*)Cblk, n, nn, 1.f, 0.f, batch, false);
       else
-        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, 0, (const double*)Mb,
-                       g.m, 0, (double*)Cblk, n, 0, 1.0, 0.0, 1, false);
+        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, nn, (const double*)Mb,
+                       g.m, nn, (double*)Cblk, n, nn, 1.0, 0.0, batch, false);
     }
     for (auto& pr : carried[L]) {
-      hipLaunchKernelGGL(copy_block<T>, dim3((unsigned)pr.second), dim3(64), 0, st, n, pr.first,
-                         pr.second, (const T*)Za, Zb, (const double*)lamA, lamB);
+      hipLaunchKernelGGL(copy_block<T>, dim3((unsigned)pr.second, (unsigned)batch), dim3(64), 0, st, n,
+                         pr.first, pr.second, (const T*)Za, Zb, (const double*)lamA, lamB);
       MSQRT_LAUNCH_CHECK();
     }
     std::swap(Za, Zb);
     std::swap(lamA, lamB);
   }
   if (Za != Z) {
-    hipLaunchKernelGGL(copy_mat<T>, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, n, (const T*)Za, Z);
+    const int64_t cnt = nn * batch;
+    hipLaunchKernelGGL(copy_mat<T>, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, cnt,
+                       (const T*)Za, Z);
     MSQRT_LAUNCH_CHECK();
   }
-  if (lamA != lam) MSQRT_HIP(hipMemcpyAsync(lam, lamA, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (lamA != lam) MSQRT_HIP(hipMemcpyAsync(lam, lamA, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+}
+
+template <typename T>
+void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, StedcWork& w) {
+  stedc_batched<T>(st, n, 1, d, e, 0, lam, Z, w);
 }
 
 template void stedc<float>(hipStream_t, int, const float*, const float*, double*, float*, StedcWork&);
 template void stedc<double>(hipStream_t, int, const double*, const double*, double*, double*, StedcWork&);
+template void stedc_batched<float>(hipStream_t, int, int, const float*, const float*, int64_t, double*,
+                                   float*, StedcWork&);
+template void stedc_batched<double>(hipStream_t, int, int, const double*, const double*, int64_t,
+                                    double*, double*, StedcWork&);
 
 }  // namespace msqrt

@@ -51,6 +51,14 @@ bool sytrd_failed(SytrdWork& w);
 template <typename T>
 void stedc(hipStream_t st, int n, const T* d, const T* e, double* lam, T* Z, StedcWork& w);
 
+// stedc for `batch` tridiagonal matrices of order n (d + m sD, e + m sD),
+// solved together as one block-diagonal matrix: every launch of a recursion
+// level covers all entries.  lam is n x batch (contiguous), Z is n x n per
+// entry (stride n * n).
+template <typename T>
+void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int64_t sD,
+                   double* lam, T* Z, StedcWork& w);
+
 // Z <- H_0 H_1 ... H_{n-2} Z with the reflectors left in V (= A after sytrd)
 // and tau.
 template <typename T>

@@ -80,6 +80,27 @@ def test_batched_forward_and_backward(msq):
         assert oracle.relerr(gh[i], refs[i]) <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [1, 2, 33, 65, 100])
+def test_batched_eigensolver_tree_shapes(msq, prec, n):
+    # the batch is diagonalised as one block-diagonal tridiagonal matrix:
+    # sizes with a single leaf (1, 2, 33 -> 16 + 17), with a leaf carried
+    # through a level (65 -> 32 | 33) and with uneven halves (100)
+    import torch
+    b = 3
+    mats, truths = [], []
+    for i in range(b):
+        a, q, lam = W.spd_range(n, 1e-2, 1e2, 400 + 10 * n + i)
+        mats.append(a)
+        truths.append((q * np.sqrt(lam)) @ q.T)
+    a_d = torch.from_numpy(np.ascontiguousarray(np.stack(mats))).cuda()
+    x, info = msq.sqrtm(a_d, prec=prec, fallback=False)
+    assert info["relres"] <= 1e-13
+    xh = x.cpu().numpy()
+    for i in range(b):
+        assert oracle.relerr(xh[i], truths[i]) <= 1e-11
+
+
 def test_autograd_function(msq):
     import torch
     n = 40

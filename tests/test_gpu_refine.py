@@ -1,4 +1,4 @@
-"""GPU parity of the SPD refinement loop (Alg. 3, lines 4-13) through the
+"""GPU parity of the SPD refinement loop (the iteration of Alg. 3) through the
 C-ABI, starting from a factor imported with msqrt_factor_wrap.  The factor is
 the oracle's own single-precision spectral decomposition, so the comparison
 isolates the HIP residual / transform / update kernels."""
