@@ -29,7 +29,9 @@ namespace msqrt {
 namespace {
 
 constexpr int kThreads = 1024;
-constexpr int kMaxTs = 256;  // max tile size handled by one workgroup
+constexpr int kMaxTs = 192;  // max tile size handled by one workgroup
+constexpr int kTRMax = 22;   // max tiles per dimension: 253 workgroups, one per CU
+constexpr int kGMax = kTRMax * (kTRMax + 1) / 2;
 constexpr int kNbMax = 32;
 
 // Values exchanged between workgroups inside a launch (partial products and
@@ -83,26 +85,59 @@ __device__ inline V wsum(V v) {
   return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
 }
 
-// Grid barrier on a counter that only grows within one reduction: every
-// workgroup adds 1 on arrival and waits until the counter reaches the
-// barrier's target (launch base + G (column + 1)), so an arrival costs one
-// atomic and the release is seen by the next poll, with no reset.  Every
-// thread waits for its own coherent stores to complete before the workgroup
-// arrives.  A spin limit keeps a broken launch from hanging: it raises the
-// sticky flag bar[1].
-__device__ inline void grid_barrier(unsigned* bar, unsigned target) {
+// Grid barrier state of one batch entry (unsigned words): the top counter,
+// the sticky failure flag, the release word and 8 group counters, each on a
+// 256-byte line of its own.
+constexpr int kBarTop = 0, kBarFail = 1, kBarRel = 64, kBarSub = 128, kBarSubStride = 64;
+
+// Counter values at the start of a launch.  All counters only grow within one
+// reduction, so a barrier needs no reset: the host adds what every launch
+// contributes.
+struct BarrierBase {
+  unsigned gen;     // release word: barriers completed
+  unsigned top;     // top counter
+  unsigned sub[8];  // group counters
+};
+
+// Two-level grid barrier.  The G workgroups of a batch entry form 8 groups
+// (workgroup index mod 8, which is the XCD a workgroup is dispatched to when
+// the entry starts on a multiple of 8); a workgroup adds 1 to its group's
+// counter, the group's last arrival (known from the value its add returns)
+// adds 1 to the top counter, and the last arrival there writes the barrier's
+// generation number to the release word, which the other workgroups poll.
+// Spreading the arrivals over 8 counters halves the cost of a barrier of 253
+// workgroups against one shared counter.  Every thread waits for its own
+// coherent stores to complete before the workgroup arrives.  A spin limit
+// keeps a broken launch from hanging: it raises the sticky failure flag.
+__device__ inline void grid_barrier(unsigned* bar, const BarrierBase& base, unsigned sub_base, int blk,
+                                    int G, int k) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (cload(&bar[0]) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 255u) == 0u) {
-        if (cload(&bar[1]) != 0u) break;
-        if (spins > (1u << 24)) {
-          cstore(&bar[1], 1u);
-          break;
+    const unsigned g = (unsigned)blk & 7u;
+    const unsigned gsz = (unsigned)G / 8u + (g < ((unsigned)G & 7u) ? 1u : 0u);
+    const unsigned ng = G < 8 ? (unsigned)G : 8u;
+    const unsigned gen = base.gen + (unsigned)k;
+    const unsigned old =
+        __hip_atomic_fetch_add(&bar[kBarSub + kBarSubStride * g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool released = false;
+    if (old + 1u == sub_base + gsz * (unsigned)k) {
+      const unsigned o2 = __hip_atomic_fetch_add(&bar[kBarTop], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 + 1u == base.top + ng * (unsigned)k) {
+        cstore(&bar[kBarRel], gen);
+        released = true;
+      }
+    }
+    if (!released) {
+      unsigned spins = 0;
+      while (cload(&bar[kBarRel]) < gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255u) == 0u) {
+          if (cload(&bar[kBarFail]) != 0u) break;
+          if (spins > (1u << 24)) {
+            cstore(&bar[kBarFail], 1u);
+            break;
+          }
         }
       }
     }
@@ -125,7 +160,7 @@ struct PanelArgs {
   double* sp;    // [2][G][4]
   double* vp;    // [2][TR][2 kNbMax]
   unsigned* bar;
-  unsigned bar_base;  // barrier counter value when the launch starts
+  BarrierBase bar_base;  // barrier counters when the launch starts
   // batch entry b = workgroup id / G: every pointer above advances by b times
   // its stride
   int64_t sA, sVW, sD, sYP, sSP, sVP, sBar;
@@ -142,8 +177,9 @@ template <typename T, int RPL, int NP>
 __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0,
                                     int nK, int jmin, bool offdiag, const T* uI, const T* uK,
                                     T (&zi)[NP][RPL], T* zK, int tid) {
-  constexpr int CW = sizeof(T) == 4 ? 8 : 4;             // columns per chunk
+  constexpr int CW = sizeof(T) == 4 ? 12 : 6;            // columns per chunk
   constexpr int NCH = kMaxTs / (CW * (kThreads / kWave));  // chunks per wave
+  static_assert(NCH * CW * (kThreads / kWave) == kMaxTs, "chunks must cover the tile");
   const int wave = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int ps = 0; ps < NP; ++ps)
@@ -195,7 +231,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
-  constexpr int RPL = sizeof(T) == 4 ? 4 : 2;
+  constexpr int RPL = 3;
   const int n = a.n, nb = a.nb, TR = a.TR, G = TR * (TR + 1) / 2;
   // workgroup id = batch entry * G + tile
   {
@@ -217,6 +253,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   while (bi * (bi + 1) / 2 > blk) --bi;
   const int bj = blk - bi * (bi + 1) / 2;
   const bool diag = bi == bj, offdiag = !diag;
+  // this workgroup's group counter base (selected without dynamic indexing)
+  unsigned sub_base = 0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g)
+    if (g == (blk & 7)) sub_base = a.bar_base.sub[g];
   const int I0 = a.r0 + bi * a.ts, I1 = max(I0, min(n, I0 + a.ts));
   const int K0 = a.r0 + bj * a.ts, K1 = max(K0, min(n, K0 + a.ts));
   const int nI = I1 - I0, nK = K1 - K0;
@@ -235,11 +276,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   // zred (row partials of the tile product, before the barrier) and the
   // gathered partial sums (after it) share one buffer.
   constexpr int kZredBytes = (kThreads / kWave / 2) * kMaxTs * (int)sizeof(T);
-  constexpr int kGathBytes = (3 * 136 + 16 * 2 * kNbMax) * 8;
+  constexpr int kGathBytes = (3 * kGMax + kTRMax * 2 * kNbMax) * 8;
   __shared__ double scratch[(kZredBytes > kGathBytes ? kZredBytes : kGathBytes) / 8];
   T* zred = reinterpret_cast<T*>(scratch);
-  double (*spl)[136] = reinterpret_cast<double (*)[136]>(scratch);
-  double* vpl = scratch + 3 * 136;
+  double (*spl)[kGMax] = reinterpret_cast<double (*)[kGMax]>(scratch);
+  double* vpl = scratch + 3 * kGMax;
   // Pivot rows r = p+1+q (q < nb) of V and W and their u for the current
   // column: every workgroup keeps its own copy, so no value written by another
   // workgroup in the current phase is ever read.
@@ -275,6 +316,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     __syncthreads();
     {
       constexpr int NP = kMaxTs / (RPL * kWave);
+      static_assert(NP * RPL * kWave == kMaxTs, "row passes must cover the tile");
       T zi[NP][RPL];
       tile_product<T, RPL, NP>(A, ld, I0, nI, K0, nK, j + 1, offdiag, uI, uK, zi, zKs, tid);
       const int wave = tid / kWave, lane = tid % kWave;
@@ -360,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
 
-    grid_barrier(a.bar, a.bar_base + (unsigned)G * (unsigned)(jj + 1));
+    grid_barrier(a.bar, a.bar_base, sub_base, blk, G, jj + 1);
 
     // ---- gather the partial sums of all workgroups into LDS in parallel
     // (one load per thread), then reduce them there.
@@ -378,12 +420,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // K and the pivot rows: all loads of a row issued together.
     {
       auto rowsum = [&](int i) -> T {
-        T yv[16];
+        T yv[kTRMax];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) yv[b] = (b < TR) ? cload(&a.ypart[((int64_t)buf * TR + b) * n + i]) : T(0);
+        for (int b = 0; b < kTRMax; ++b) yv[b] = (b < TR) ? cload(&a.ypart[((int64_t)buf * TR + b) * n + i]) : T(0);
         T z = T(0);
 #pragma unroll
-        for (int b = 0; b < 16; ++b) z += yv[b];
+        for (int b = 0; b < kTRMax; ++b) z += yv[b];
         return z;
       };
       if (tid < nI) yzI[tid] = (I0 + tid >= j + 1) ? rowsum(I0 + tid) : T(0);
@@ -557,8 +599,8 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
     MSQRT_LAUNCH_CHECK();
     return;
   }
-  if (n - 1 > 16 * kMaxTs)
-    throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal reduction supports n <= 4097 in this build"};
+  if (n - 1 > kTRMax * kMaxTs)
+    throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal reduction supports n <= 4225 in this build"};
   // Panel width: the LDS cache holds 4 * nb * kMaxTs values (at most 128 KiB).
   const int lds_budget = sizeof(T) == 4 ? 128 * 1024 : 96 * 1024;
   const int nb = std::min(kNbMax, (int)(lds_budget / (4 * kMaxTs * (int)sizeof(T))));
@@ -576,8 +618,8 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
     resident[sizeof(T) == 8] = std::max(1, per_cu) * std::max(1, ncu);
     attr_set[sizeof(T) == 8] = true;
   }
-  const int64_t sVW = (int64_t)n * 2 * kNbMax, sYP = (int64_t)2 * 16 * n, sSP = (int64_t)2 * 256 * 4,
-                sVP = (int64_t)2 * 16 * 2 * kNbMax, sBar = 32 * 40;
+  const int64_t sVW = (int64_t)n * 2 * kNbMax, sYP = (int64_t)2 * kTRMax * n,
+                sSP = (int64_t)2 * kGMax * 4, sVP = (int64_t)2 * kTRMax * 2 * kNbMax, sBar = 32 * 40;
   T* VW = w.VW.ensure<T>(sVW * batch);
   T* WV = w.WV.ensure<T>(sVW * batch);
   T* ypart = w.ypart.ensure<T>(sYP * batch);
@@ -586,11 +628,11 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
   unsigned* bar = w.bar.ensure<unsigned>(sBar * batch);
   MSQRT_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned) * (size_t)(sBar * batch), st));
   w.nbar = batch;
-  unsigned bar_base = 0;
+  BarrierBase bar_base{};
   for (int p = 0; p < n - 1; p += nb) {
     const int nbe = std::min(nb, n - 1 - p);
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
-    const int TR = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
+    const int TR = (int)std::min<int64_t>(kTRMax, std::max<int64_t>(1, ceil_div(m, kMaxTs)));
     const int ts = (int)ceil_div(m, TR);
     const int G = TR * (TR + 1) / 2;
     // as many batch entries per cooperative launch as fit co-resident
@@ -606,7 +648,9 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
       MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G * nbt),
                                            dim3(kThreads), args, dyn_lds, st));
     }
-    bar_base += (unsigned)G * (unsigned)nbe;
+    bar_base.gen += (unsigned)nbe;
+    bar_base.top += (unsigned)std::min(G, 8) * (unsigned)nbe;
+    for (int g = 0; g < 8; ++g) bar_base.sub[g] += (unsigned)(G / 8 + (g < G % 8 ? 1 : 0)) * (unsigned)nbe;
     if (tok >= 0) {
       // algorithmic traffic: one read of the symmetric trailing matrix (lower
       // triangle) per column for its product with the reflector
@@ -646,7 +690,7 @@ bool sytrd_failed(SytrdWork& w) {
   std::vector<unsigned> flags((size_t)32 * 40 * w.nbar);
   MSQRT_HIP(hipMemcpy(flags.data(), w.bar.p, sizeof(unsigned) * flags.size(), hipMemcpyDeviceToHost));
   for (int b = 0; b < w.nbar; ++b)
-    if (flags[(size_t)b * 32 * 40 + 1]) return true;
+    if (flags[(size_t)b * 32 * 40 + kBarFail]) return true;
   return false;
 }
 
