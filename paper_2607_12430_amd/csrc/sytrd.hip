@@ -229,6 +229,58 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
   }
 }
 
+// Register-resident variant (float): wave w holds columns [CW w, CW w + CW)
+// of the tile, lane l rows l, l+64, l+128 (CW RPL = 36 values), loaded once
+// per launch.  The trailing matrix does not change inside a panel (its
+// updates are applied lazily through V and W), and the rows and columns that
+// the current column excludes are cancelled by the zero entries of u there,
+// so the same registers serve every column of the panel.
+template <typename T, int CW, int RPL>
+__device__ inline void tile_load(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0, int nK,
+                                 T (&v)[CW][RPL], int tid) {
+  const int wave = tid / kWave, lane = tid % kWave;
+  const int cb = wave * CW;
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const int k = cb + c;
+    const bool colok = k < nK;
+    const T* colp = A + (int64_t)(K0 + (colok ? k : 0)) * ld + I0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + q * kWave;
+      v[c][q] = (colok && r < nI) ? colp[r] : T(0);
+    }
+  }
+}
+
+template <typename T, int CW, int RPL>
+__device__ inline void tile_mul(const T (&v)[CW][RPL], int nI, int nK, bool offdiag, const T* uI,
+                                const T* uK, T (&zi)[RPL], T* zK, int tid) {
+  const int wave = tid / kWave, lane = tid % kWave;
+  const int cb = wave * CW;
+  T ui[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + q * kWave;
+    zi[q] = T(0);
+    ui[q] = (r < nI) ? uI[r] : T(0);
+  }
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const T uk = (cb + c < nK) ? uK[cb + c] : T(0);
+    T zk = T(0);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      zi[q] += v[c][q] * uk;
+      if (offdiag) zk += v[c][q] * ui[q];
+    }
+    if (offdiag) {
+      zk = wsum(zk);
+      if (lane == 0 && cb + c < nK) zK[cb + c] += zk;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   constexpr int RPL = 3;
@@ -291,7 +343,14 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   __shared__ T acI[kMaxTs], acK[kMaxTs], acP[kNbMax];  // A(:, j+1) on rows I, K, pivots
   __shared__ T yzI[kMaxTs], yzK[kMaxTs], yzP[kNbMax];  // (A22 u) on rows I, K, pivots
 
-  // ---- prologue: u for the first column of the panel
+  // ---- prologue: u for the first column of the panel (and, for float, the
+  // register copy of the tile)
+  constexpr bool kResident = sizeof(T) == 4;
+  constexpr int kRCW = kMaxTs / (kThreads / kWave);  // 12 columns per wave
+  static_assert(!kResident || (kRCW * (kThreads / kWave) == kMaxTs && RPL * kWave == kMaxTs),
+                "the register tile must cover the tile");
+  T vt[kResident ? kRCW : 1][kResident ? RPL : 1];
+  if constexpr (kResident) tile_load<T, kRCW, RPL>(A, ld, I0, nI, K0, nK, vt, tid);
   {
     const int j = p;
     for (int r = tid; r < nI; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (int64_t)j * ld] : T(0);
@@ -318,7 +377,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       constexpr int NP = kMaxTs / (RPL * kWave);
       static_assert(NP * RPL * kWave == kMaxTs, "row passes must cover the tile");
       T zi[NP][RPL];
-      tile_product<T, RPL, NP>(A, ld, I0, nI, K0, nK, j + 1, offdiag, uI, uK, zi, zKs, tid);
+      if constexpr (kResident) {
+        static_assert(!kResident || NP == 1, "one row pass");
+        tile_mul<T, kRCW, RPL>(vt, nI, nK, offdiag, uI, uK, zi[0], zKs, tid);
+      } else {
+        tile_product<T, RPL, NP>(A, ld, I0, nI, K0, nK, j + 1, offdiag, uI, uK, zi, zKs, tid);
+      }
       const int wave = tid / kWave, lane = tid % kWave;
       if (wave < 8) {
 #pragma unroll
