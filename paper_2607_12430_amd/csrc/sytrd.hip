@@ -33,6 +33,12 @@ constexpr int kMaxTs = 192;  // max tile size handled by one workgroup
 constexpr int kTRMax = 22;   // max tiles per dimension: 253 workgroups, one per CU
 constexpr int kGMax = kTRMax * (kTRMax + 1) / 2;
 constexpr int kNbMax = 32;
+// Row work of a column is spread over three thread ranges that run side by
+// side: rows of I on [0, kMaxTs), pivot rows on [kPivT, kPivT + kNbMax), rows
+// of K on [kKT, kKT + kMaxTs).
+constexpr int kPivT = 256;
+constexpr int kKT = 512;
+static_assert(kMaxTs <= kPivT && kPivT + kNbMax <= kKT && kKT + kMaxTs <= 1024, "thread ranges");
 
 // Values exchanged between workgroups inside a launch (partial products and
 // sums) are written and read with agent-scope atomic stores and loads, which
@@ -75,6 +81,15 @@ __device__ inline double lane_of(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over each row of 16 lanes, left in every lane of the row.
+template <typename V>
+__device__ inline V rsum16(V v) {
+  v += dpp_v<0xB1>(v);
+  v += dpp_v<0x4E>(v);
+  v += dpp_v<0x141>(v);
+  v += dpp_v<0x140>(v);
+  return v;
 }
 template <typename V>
 __device__ inline V wsum(V v) {
@@ -411,8 +426,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       cstore(&a.ypart[((int64_t)buf * TR + bj) * n + I0 + r], z);
       s_uAu += (double)uI[r] * (double)z;
     }
-    if (offdiag)
-      for (int r = tid; r < nK; r += kThreads) cstore(&a.ypart[((int64_t)buf * TR + bi) * n + K0 + r], zKs[r]);
+    if (offdiag && tid >= kKT && tid - kKT < nK)
+      cstore(&a.ypart[((int64_t)buf * TR + bi) * n + K0 + (tid - kKT)], zKs[tid - kKT]);
     // ---- row-owner partials (diagonal tiles): ||u(2:)||^2, u^T a1, V^T u, W^T u
     double s_sig = 0.0, s_ua1 = 0.0;
     if (diag) {
@@ -422,14 +437,17 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         if (i >= j + 2) s_sig += u * u;
         if (i >= j + 1) s_ua1 += u * (double)acI[r];
       }
-      const int wave = tid / kWave, lane = tid % kWave;
-      for (int c = wave; c < 2 * jj; c += kThreads / kWave) {
+      // one row of 16 lanes per column of [V W] (2 kNbMax rows of 16 lanes =
+      // the workgroup), each lane summing every 16th row of the tile
+      static_assert(2 * kNbMax * 16 == kThreads, "one 16-lane row per panel column");
+      const int c = tid >> 4, l16 = tid & 15;
+      double s = 0.0;
+      if (c < 2 * jj) {
         const T* col = c < jj ? (PVI + c * kMaxTs) : (PWI + (c - jj) * kMaxTs);
-        double s = 0.0;
-        for (int r = lane; r < nI; r += kWave) s += (double)col[r] * (double)uI[r];
-        s = wsum(s);
-        if (lane == 0) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
+        for (int r = l16; r < nI; r += 16) s += (double)col[r] * (double)uI[r];
       }
+      s = rsum16(s);
+      if (l16 == 0 && c < 2 * jj) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
     }
     // one reduction of the three scalars (wave sums, then one thread), and
     // the pivot-row correction of d_j summed by the first wave
@@ -493,7 +511,10 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         return z;
       };
       if (tid < nI) yzI[tid] = (I0 + tid >= j + 1) ? rowsum(I0 + tid) : T(0);
-      if (offdiag && tid < nK) yzK[tid] = (K0 + tid >= j + 1) ? rowsum(K0 + tid) : T(0);
+      if (offdiag && tid >= kKT && tid - kKT < nK) {
+        const int r = tid - kKT;
+        yzK[r] = (K0 + r >= j + 1) ? rowsum(K0 + r) : T(0);
+      }
       if (tid >= kThreads - kNbMax) {
         const int q = tid - (kThreads - kNbMax);
         const int r = p + 1 + q;
@@ -573,7 +594,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     };
 
     // Pivot rows (every workgroup): rows p+1+q >= j+1, i.e. q >= jj.
-    for (int q = jj + tid; q < nb; q += kThreads) {
+    for (int q = jj + tid - kPivT; tid >= kPivT && tid < kPivT + kNbMax && q < nb; q += kNbMax) {
       const int r = p + 1 + q;
       T vi = T(0), wi = T(0);
       if (r < n) finish(r, PU[q], yzP[q], acP[q], [&](int t) { return PV[q][t]; }, [&](int t) { return PW[q][t]; }, vi, wi);
@@ -597,8 +618,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         A[i + (int64_t)j * ld] = vi;
       }
     }
-    if (offdiag)
-      for (int r = tid; r < nK; r += kThreads) {
+    if (offdiag && tid >= kKT)
+      for (int r = tid - kKT; r < nK; r += kThreads - kKT) {
         const int i = K0 + r;
         T vi = T(0), wi = T(0);
         if (i >= j + 1)
@@ -621,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       uI[r] = u;
     }
     if (offdiag) {
-      for (int r = tid; r < nK; r += kThreads) {
+      for (int r = tid - kKT; tid >= kKT && r < nK; r += kThreads - kKT) {
         const int i = K0 + r;
         T u = T(0);
         if (i >= jn + 1) {
@@ -633,7 +654,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     } else {
       for (int r = tid; r < nK; r += kThreads) uK[r] = uI[r];  // same rows (written above by the same thread)
     }
-    for (int q = jj + 1 + tid; q < nb; q += kThreads) {
+    for (int q = jj + 1 + tid - kPivT; tid >= kPivT && tid < kPivT + kNbMax && q < nb; q += kNbMax) {
       const int r = p + 1 + q;
       if (r >= n) { PU[q] = T(0); continue; }
       T u = acP[q];
