@@ -280,19 +280,38 @@ __device__ inline void tile_mul(const T (&v)[CW][RPL], int nI, int nK, bool offd
     zi[q] = T(0);
     ui[q] = (r < nI) ? uI[r] : T(0);
   }
+  T zk[CW];
 #pragma unroll
   for (int c = 0; c < CW; ++c) {
     const T uk = (cb + c < nK) ? uK[cb + c] : T(0);
-    T zk = T(0);
+    zk[c] = T(0);
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       zi[q] += v[c][q] * uk;
-      if (offdiag) zk += v[c][q] * ui[q];
+      zk[c] += v[c][q] * ui[q];
     }
-    if (offdiag) {
-      zk = wsum(zk);
-      if (lane == 0 && cb + c < nK) zK[cb + c] += zk;
+  }
+  if (offdiag) {
+    // Column sums over the 64 lanes, 12 columns at once: halving exchanges
+    // between the wave's halves (columns c and c+6), then between the rows
+    // of 16 lanes of each half (c and c+3), then sums inside each row.  Row
+    // R of the wave ends with the sums of columns 3R .. 3R+2.
+    static_assert(CW == 12 && sizeof(T) == 4, "the exchange pattern splits 12 float columns");
+    T y[6], z[3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(zk[c]), __float_as_uint(zk[c + 6]), false,
+                                                       false);
+      y[c] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(y[c]), __float_as_uint(y[c + 3]), false,
+                                                       false);
+      z[c] = rsum16(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+    }
+    const int l16 = lane & 15, col = cb + 3 * (lane >> 4) + l16;
+    if (l16 < 3 && col < nK) zK[col] += (l16 == 0) ? z[0] : (l16 == 1 ? z[1] : z[2]);
   }
 }
 
