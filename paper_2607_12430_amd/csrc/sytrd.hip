@@ -91,6 +91,14 @@ __device__ inline V rsum16(V v) {
   v += dpp_v<0x140>(v);
   return v;
 }
+// Sum over each group of 8 lanes (half a row), left in every lane of it.
+template <typename V>
+__device__ inline V hsum8(V v) {
+  v += dpp_v<0xB1>(v);
+  v += dpp_v<0x4E>(v);
+  v += dpp_v<0x141>(v);
+  return v;
+}
 template <typename V>
 __device__ inline V wsum(V v) {
   v += dpp_v<0xB1>(v);   // quad_perm [1, 0, 3, 2]
@@ -237,7 +245,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
         }
         if (offdiag) {
           zk = wsum(zk);
-          if (lane == 0 && cb + c < nK) zK[cb + c] += zk;
+          if (lane == 0 && cb + c < nK) zK[cb + c] = zk;
         }
       }
     }
@@ -311,7 +319,7 @@ __device__ inline void tile_mul(const T (&v)[CW][RPL], int nI, int nK, bool offd
       z[c] = rsum16(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
     }
     const int l16 = lane & 15, col = cb + 3 * (lane >> 4) + l16;
-    if (l16 < 3 && col < nK) zK[col] += (l16 == 0) ? z[0] : (l16 == 1 ? z[1] : z[2]);
+    if (l16 < 3 && col < nK) zK[col] = (l16 == 0) ? z[0] : (l16 == 1 ? z[1] : z[2]);
   }
 }
 
@@ -372,6 +380,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   // workgroup in the current phase is ever read.
   __shared__ T PV[kNbMax][kNbMax + 1], PW[kNbMax][kNbMax + 1], PU[kNbMax];
   __shared__ T VTv[kNbMax], WTv[kNbMax];
+  __shared__ double vts[2 * kNbMax];  // V^T u, W^T u summed over the row tiles
   __shared__ double red3[kThreads / kWave][3];
   __shared__ double sc[8];
   __shared__ T acI[kMaxTs], acK[kMaxTs], acP[kNbMax];  // A(:, j+1) on rows I, K, pivots
@@ -404,9 +413,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     if (tid < nb && p + 1 + tid < n) acv_p = A[p + 1 + tid + (int64_t)(j + 1) * ld];
     // A(j, j) for d_j (never written inside the panel)
     const double ajj = (tid == 0) ? (double)A[j + (int64_t)j * ld] : 0.0;
-    // ---- tile product; the 16 waves' row partials are folded onto 8 slots
-    for (int r = tid; r < nK; r += kThreads) zKs[r] = T(0);
-    __syncthreads();
+    // ---- tile product; the 16 waves' row partials are folded onto 8 slots;
+    // every column sum of zKs is written once, by the wave owning the column
     {
       constexpr int NP = kMaxTs / (RPL * kWave);
       static_assert(NP * RPL * kWave == kMaxTs, "row passes must cover the tile");
@@ -471,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // one reduction of the three scalars (wave sums, then one thread), and
     // the pivot-row correction of d_j summed by the first wave
     {
-      const double w0 = wsum(s_uAu), w1 = wsum(s_sig), w2 = wsum(s_ua1);
+      const double w0 = wsum(s_uAu), w1 = diag ? wsum(s_sig) : 0.0, w2 = diag ? wsum(s_ua1) : 0.0;
       const int wv_ = tid / kWave, ln_ = tid % kWave;
       if (ln_ == 0) {
         red3[wv_][0] = w0;
@@ -484,22 +492,21 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         pd = wsum(pd);
       }
       __syncthreads();
-      if (tid == 0) {
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-        for (int x = 0; x < kThreads / kWave; ++x) {
-          t0 += red3[x][0];
-          t1 += red3[x][1];
-          t2 += red3[x][2];
-        }
+      static_assert(kThreads / kWave == 16, "one lane of the first row per wave");
+      if (tid < 16) {
+        double t0 = rsum16(red3[tid][0]);
+        const double t1 = rsum16(red3[tid][1]), t2 = rsum16(red3[tid][2]);
         if (offdiag) t0 *= 2.0;
-        double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
-        cstore(&spb[0], t0);
-        cstore(&spb[1], t1);
-        cstore(&spb[2], t2);
-        // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
-        // before the barrier: owners overwrite column j right after it.
-        sc[0] = ajj - 2.0 * pd;
-        sc[3] = (double)PU[jj];
+        if (tid == 0) {
+          double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
+          cstore(&spb[0], t0);
+          cstore(&spb[1], t1);
+          cstore(&spb[2], t2);
+          // alpha = u_{j+1} (pivot row q = jj) and d_j = updated A(j, j), read
+          // before the barrier: owners overwrite column j right after it.
+          sc[0] = ajj - 2.0 * pd;
+          sc[3] = (double)PU[jj];
+        }
       }
     }
 
@@ -541,6 +548,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
     __syncthreads();
+    // Wave 0 reduces the scalars and forms the reflector while waves 8-15 sum
+    // the row tiles' V^T u and W^T u (8 lanes per panel column).
     if (tid < kWave) {
       double uAu = 0.0, sig = 0.0, ua1 = 0.0;
       for (int b = tid; b < G; b += kWave) uAu += spl[0][b];
@@ -570,22 +579,28 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         sc[0] = uAu; sc[1] = sig; sc[2] = ua1;
         sc[4] = beta; sc[5] = tau; sc[6] = c;
       }
+    } else if (tid >= kThreads / 2) {
+      static_assert(kThreads / 2 >= 2 * kNbMax * 8, "8 lanes per panel column");
+      const int x = tid - kThreads / 2, c2 = x >> 3, l8 = x & 7;
+      double sv = 0.0;
+      if (c2 < 2 * jj)
+        for (int b = l8; b < TR; b += 8) sv += vpl[b * 2 * jj + c2];
+      sv = hsum8(sv);
+      if (l8 == 0 && c2 < 2 * jj) vts[c2] = sv;
     }
     __syncthreads();
-    const double beta = sc[4], tau = sc[5], c = sc[6];
-    // V^T v and W^T v (length jj); V(j+1, :), W(j+1, :) are pivot row jj.
-    for (int t = tid; t < jj; t += kThreads) {
-      double vtu = 0.0, wtu = 0.0;
-      for (int b = 0; b < TR; ++b) {
-        vtu += vpl[b * 2 * jj + t];
-        wtu += vpl[b * 2 * jj + jj + t];
-      }
-      VTv[t] = (T)(c * (vtu - beta * (double)PV[jj][t]));
-      WTv[t] = (T)(c * (wtu - beta * (double)PW[jj][t]));
-    }
-    __syncthreads();
+    // V^T v and W^T v (length jj; V(j+1, :), W(j+1, :) are pivot row jj) and
+    // w0^T v, in wave 0
     if (tid < kWave) {
-      double vw = tid < jj ? (double)VTv[tid] * (double)WTv[tid] : 0.0;
+      const double beta = sc[4], tau = sc[5], c = sc[6];
+      double vw = 0.0;
+      if (tid < jj) {
+        const T vt = (T)(c * (vts[tid] - beta * (double)PV[jj][tid]));
+        const T wt = (T)(c * (vts[jj + tid] - beta * (double)PW[jj][tid]));
+        VTv[tid] = vt;
+        WTv[tid] = wt;
+        vw = (double)vt * (double)wt;
+      }
       vw = wsum(vw);
       if (tid == 0) {
         const double a11 = (double)acP[jj];
@@ -594,92 +609,90 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
     __syncthreads();
+    const double beta = sc[4], tau = sc[5], c = sc[6];
     const double wv = sc[7];
     const bool zero_refl = (sc[1] == 0.0);
 
     // y_i, v_i, w_i of the current column for a row i >= j+1, given u_i,
     // (A22 u)_i, a1_i = A(i, j+1) and the row's panel coefficients.
-    auto finish = [&](int i, T ui, T yzi, T a1i, auto Vt, auto Wt, T& vi, T& wi) {
+    //
+    // The same pass over the row's panel coefficients also sums
+    // up_i = sum_{t < jj} V(i,t) W(jn,t) + W(i,t) V(jn,t) for the next column
+    // jn = j+1 (row jn's coefficients are pivot row jj, known for t < jj); the
+    // t = jj term is added once this column's pivot row is finished.
+    auto finish = [&](int i, T ui, T yzi, T a1i, auto Vt, auto Wt, T& vi, T& wi, T& up) {
+      double ys = 0.0;
+      T us = T(0);
+      for (int t = 0; t < jj; ++t) {
+        const T vt = Vt(t), wt = Wt(t);
+        ys += (double)vt * (double)WTv[t] + (double)wt * (double)VTv[t];
+        us += vt * PW[jj][t] + wt * PV[jj][t];
+      }
+      up = us;
       if (zero_refl) {
         vi = (i == j + 1) ? T(1) : T(0);
         wi = T(0);
         return;
       }
-      double y = c * ((double)yzi - beta * (double)a1i);
-      for (int t = 0; t < jj; ++t) y -= (double)Vt(t) * (double)WTv[t] + (double)Wt(t) * (double)VTv[t];
+      const double y = c * ((double)yzi - beta * (double)a1i) - ys;
       const double v = (i == j + 1) ? 1.0 : c * (double)ui;
       vi = (T)v;
       wi = (T)(tau * y - 0.5 * tau * wv * v);
     };
 
-    // Pivot rows (every workgroup): rows p+1+q >= j+1, i.e. q >= jj.
-    for (int q = jj + tid - kPivT; tid >= kPivT && tid < kPivT + kNbMax && q < nb; q += kNbMax) {
-      const int r = p + 1 + q;
-      T vi = T(0), wi = T(0);
-      if (r < n) finish(r, PU[q], yzP[q], acP[q], [&](int t) { return PV[q][t]; }, [&](int t) { return PW[q][t]; }, vi, wi);
-      PV[q][jj] = vi;
-      PW[q][jj] = wi;
+    // Each thread finishes at most one row: a pivot row (every workgroup:
+    // rows p+1+q >= j+1, i.e. q >= jj), a row of I or a row of K.  The
+    // diagonal tile's workgroup owns its rows and publishes V, W and the
+    // explicit reflector column A(:, j).
+    T vr = T(0), wr = T(0), upr = T(0);
+    const int qp = jj + tid - kPivT;  // pivot row of this thread
+    const bool pivt = tid >= kPivT && tid < kPivT + kNbMax && qp < nb;
+    if (pivt) {
+      const int r = p + 1 + qp;
+      if (r < n)
+        finish(r, PU[qp], yzP[qp], acP[qp], [&](int t) { return PV[qp][t]; }, [&](int t) { return PW[qp][t]; }, vr, wr,
+               upr);
+      PV[qp][jj] = vr;
+      PW[qp][jj] = wr;
     }
-    // Rows of I (and K); the diagonal tile's workgroup owns its rows and
-    // publishes V, W and the explicit reflector column A(:, j).
-    for (int r = tid; r < nI; r += kThreads) {
-      const int i = I0 + r;
-      T vi = T(0), wi = T(0);
+    if (tid < nI) {
+      const int r = tid, i = I0 + r;
       if (i >= j + 1)
-        finish(i, uI[r], yzI[r], acI[r], [&](int t) { return PVI[t * kMaxTs + r]; }, [&](int t) { return PWI[t * kMaxTs + r]; }, vi, wi);
-      PVI[jj * kMaxTs + r] = vi;
-      PWI[jj * kMaxTs + r] = wi;
+        finish(i, uI[r], yzI[r], acI[r], [&](int t) { return PVI[t * kMaxTs + r]; }, [&](int t) { return PWI[t * kMaxTs + r]; },
+               vr, wr, upr);
+      PVI[jj * kMaxTs + r] = vr;
+      PWI[jj * kMaxTs + r] = wr;
       if (diag) {
-        a.VW[i + (int64_t)jj * ld] = vi;
-        a.VW[i + (int64_t)(nb + jj) * ld] = wi;
-        a.WV[i + (int64_t)jj * ld] = wi;
-        a.WV[i + (int64_t)(nb + jj) * ld] = vi;
-        A[i + (int64_t)j * ld] = vi;
+        a.VW[i + (int64_t)jj * ld] = vr;
+        a.VW[i + (int64_t)(nb + jj) * ld] = wr;
+        a.WV[i + (int64_t)jj * ld] = wr;
+        a.WV[i + (int64_t)(nb + jj) * ld] = vr;
+        A[i + (int64_t)j * ld] = vr;
       }
     }
-    if (offdiag && tid >= kKT)
-      for (int r = tid - kKT; r < nK; r += kThreads - kKT) {
-        const int i = K0 + r;
-        T vi = T(0), wi = T(0);
-        if (i >= j + 1)
-          finish(i, uK[r], yzK[r], acK[r], [&](int t) { return PVK[t * kMaxTs + r]; }, [&](int t) { return PWK[t * kMaxTs + r]; }, vi, wi);
-        PVK[jj * kMaxTs + r] = vi;
-        PWK[jj * kMaxTs + r] = wi;
-      }
+    if (offdiag && tid >= kKT && tid - kKT < nK) {
+      const int r = tid - kKT, i = K0 + r;
+      if (i >= j + 1)
+        finish(i, uK[r], yzK[r], acK[r], [&](int t) { return PVK[t * kMaxTs + r]; }, [&](int t) { return PWK[t * kMaxTs + r]; },
+               vr, wr, upr);
+      PVK[jj * kMaxTs + r] = vr;
+      PWK[jj * kMaxTs + r] = wr;
+    }
     __syncthreads();
     if (jj + 1 == nb) break;
-    // ---- next column jn = j+1: u_i = A(i, jn) - sum_{t <= jj} V(i,t) W(jn,t) + W(i,t) V(jn,t)
-    // with row jn's coefficients = pivot row jj.
+    // ---- next column jn = j+1: u_i = A(i, jn) - up_i - (V(i,jj) W(jn,jj) + W(i,jj) V(jn,jj))
     const int jn = j + 1;
-    for (int r = tid; r < nI; r += kThreads) {
-      const int i = I0 + r;
-      T u = T(0);
-      if (i >= jn + 1) {
-        u = acI[r];
-        for (int t = 0; t <= jj; ++t) u -= PVI[t * kMaxTs + r] * PW[jj][t] + PWI[t * kMaxTs + r] * PV[jj][t];
-      }
-      uI[r] = u;
+    const T pwj = PW[jj][jj], pvj = PV[jj][jj];
+    if (tid < nI) {
+      const int r = tid;
+      uI[r] = (I0 + r >= jn + 1) ? acI[r] - upr - (vr * pwj + wr * pvj) : T(0);
+      if (diag && r < nK) uK[r] = uI[r];  // same rows
     }
-    if (offdiag) {
-      for (int r = tid - kKT; tid >= kKT && r < nK; r += kThreads - kKT) {
-        const int i = K0 + r;
-        T u = T(0);
-        if (i >= jn + 1) {
-          u = acK[r];
-          for (int t = 0; t <= jj; ++t) u -= PVK[t * kMaxTs + r] * PW[jj][t] + PWK[t * kMaxTs + r] * PV[jj][t];
-        }
-        uK[r] = u;
-      }
-    } else {
-      for (int r = tid; r < nK; r += kThreads) uK[r] = uI[r];  // same rows (written above by the same thread)
+    if (offdiag && tid >= kKT && tid - kKT < nK) {
+      const int r = tid - kKT;
+      uK[r] = (K0 + r >= jn + 1) ? acK[r] - upr - (vr * pwj + wr * pvj) : T(0);
     }
-    for (int q = jj + 1 + tid - kPivT; tid >= kPivT && tid < kPivT + kNbMax && q < nb; q += kNbMax) {
-      const int r = p + 1 + q;
-      if (r >= n) { PU[q] = T(0); continue; }
-      T u = acP[q];
-      for (int t = 0; t <= jj; ++t) u -= PV[q][t] * PW[jj][t] + PW[q][t] * PV[jj][t];
-      PU[q] = u;
-    }
+    if (pivt && qp >= jj + 1) PU[qp] = (p + 1 + qp < n) ? acP[qp] - upr - (vr * pwj + wr * pvj) : T(0);
     __syncthreads();
   }
 }
