@@ -205,6 +205,171 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T*
 }
 
 // ---------------------------------------------------------------------------
+// Float kernel with a deeper pipeline: K-slabs of 32 double-buffered in LDS
+// (the next slab's global loads are in flight during the current slab's
+// MFMAs and land in the other buffer, one barrier per slab), each operand
+// stored k-contiguous ([row][k], row stride 36 floats) so a lane reads four
+// k values of its row with one 128-bit LDS load.  Within a slab, lane half h
+// of a wave supplies k = 16 h + s at MFMA step s (A and B use the same
+// assignment, so every k is summed once).
+
+constexpr int FBK = 32, FLD = FBK + 4;
+constexpr size_t kGemmF32Lds = (size_t)2 * 2 * GBM * FLD * sizeof(float);
+static_assert(GBM == GBN, "square tiles");
+
+// One operand slab (128 rows x 32 k) of op(X): element (r, k) is
+// X[r + k ld] when rows are contiguous (RC), else X[k + r ld].
+template <bool RC>
+__device__ inline void f32_slab_load(const float* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                     int K, int t, float (&v)[16]) {
+  const int lane = t % kWave, wave = t / kWave;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int r, k;
+    if (RC) {
+      // 8 rows x 8 k per wave instruction: 32-byte row segments, 2-way LDS
+      // bank use on the store
+      const int id = wave * 16 + e;
+      r = (id % 16) * 8 + lane % 8;
+      k = (id / 16) * 8 + lane / 8;
+    } else {
+      const int idx = t + GTHREADS * e;
+      k = idx % FBK;
+      r = idx / FBK;
+    }
+    const int gr = r0 + r, gk = k0 + k;
+    v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.f;
+  }
+}
+
+template <bool RC>
+__device__ inline void f32_slab_store(float* Xs, int t, const float (&v)[16]) {
+  const int lane = t % kWave, wave = t / kWave;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int r, k;
+    if (RC) {
+      const int id = wave * 16 + e;
+      r = (id % 16) * 8 + lane % 8;
+      k = (id / 16) * 8 + lane / 8;
+    } else {
+      const int idx = t + GTHREADS * e;
+      k = idx % FBK;
+      r = idx / FBK;
+    }
+    Xs[r * FLD + k] = v[e];
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 2) void gemm_f32_kernel(GemmShape s, const float* __restrict__ A,
+                                                               const float* __restrict__ B, Epi epi,
+                                                               double* __restrict__ partials) {
+  using M = Mfma<float>;
+  extern __shared__ __attribute__((aligned(16))) float gemm_lds[];
+  __shared__ double red[GTHREADS / kWave];
+  // [buffer][operand][row][k]
+  auto slab = [&](int buf, int op) { return gemm_lds + (size_t)(buf * 2 + op) * GBM * FLD; };
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+  // op(A) rows are contiguous unless A is transposed; op(B)^T rows (the
+  // columns n of op(B)) are contiguous when B is transposed
+  constexpr bool ARC = !TA, BRC = TB;
+
+  typename M::acc_t acc[M::MB][M::NB];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.f;
+
+  float ra[16], rb[16];
+  if (K > 0) {
+    f32_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f32_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f32_slab_store<ARC>(slab(0, 0), t, ra);
+    f32_slab_store<BRC>(slab(0, 1), t, rb);
+  }
+  __syncthreads();
+  const int h = lane / 32, fr = lane % 32;
+  for (int k0 = 0, buf = 0; k0 < K; k0 += FBK, buf ^= 1) {
+    const bool more = k0 + FBK < K;
+    if (more) {
+      f32_slab_load<ARC>(A, s.lda, m0, s.M, k0 + FBK, K, t, ra);
+      f32_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + FBK, K, t, rb);
+    }
+    const float* As = slab(buf, 0);
+    const float* Bs = slab(buf, 1);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kc = h * 16 + s4 * 4;
+      float4 a4[M::MB], b4[M::NB];
+#pragma unroll
+      for (int i = 0; i < M::MB; ++i)
+        a4[i] = *reinterpret_cast<const float4*>(As + (wm * 64 + i * 32 + fr) * FLD + kc);
+#pragma unroll
+      for (int j = 0; j < M::NB; ++j)
+        b4[j] = *reinterpret_cast<const float4*>(Bs + (wn * 64 + j * 32 + fr) * FLD + kc);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+          for (int j = 0; j < M::NB; ++j) {
+            const float av = c == 0 ? a4[i].x : c == 1 ? a4[i].y : c == 2 ? a4[i].z : a4[i].w;
+            const float bv = c == 0 ? b4[j].x : c == 1 ? b4[j].y : c == 2 ? b4[j].z : b4[j].w;
+            acc[i][j] = M::mma(av, bv, acc[i][j]);
+          }
+    }
+    if (more) {
+      f32_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
+      f32_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+    }
+    __syncthreads();
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 64 + i * M::TM + M::c_row(lane, r);
+        const int gj = n0 + wn * 64 + j * M::TN + M::c_col(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
+template <class Kern>
+inline void gemm_f32_lds_attr(Kern k) {
+  static bool set = false;
+  if (!set) {
+    MSQRT_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmF32Lds));
+    set = true;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // BF16-split variant for float operands: every element x is split into
 // h = bf16(x) and l = bf16(x - h) (round to nearest even) while it is staged
 // into LDS, and the product is accumulated in float as
@@ -480,10 +645,21 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
       return;
     }
   }
-  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-  else hipLaunchKernelGGL((gemm_kernel<T, true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  if constexpr (std::is_same<T, float>::value) {
+    auto go = [&](auto kern) {
+      gemm_f32_lds_attr(kern);
+      hipLaunchKernelGGL(kern, grid, block, kGemmF32Lds, st, s, A, B, epi, partials);
+    };
+    if (!ta && !tb) go(gemm_f32_kernel<false, false, Epi>);
+    else if (ta && !tb) go(gemm_f32_kernel<true, false, Epi>);
+    else if (!ta && tb) go(gemm_f32_kernel<false, true, Epi>);
+    else go(gemm_f32_kernel<true, true, Epi>);
+  } else {
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+    else hipLaunchKernelGGL((gemm_kernel<T, true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+  }
   MSQRT_LAUNCH_CHECK();
   if (tok >= 0) {
     // algorithmic work: 2 M N K per entry, or the lower triangle only for
