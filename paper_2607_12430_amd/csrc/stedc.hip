@@ -215,9 +215,77 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, co
   }
   __syncthreads();
   __shared__ int counts[3];
-  if (threadIdx.x == 0) {
-    const double eps = 1.1102230246251565e-16;
-    const double tol = 8.0 * eps * fmax(dmax, zmax);
+  const double eps = 1.1102230246251565e-16;
+  const double tol = 8.0 * eps * fmax(dmax, zmax);
+  // Rotation test of the scan below for a pair of consecutive survivors
+  // (identical arithmetic, so the flags agree with it).
+  auto rot_test = [&](double dp, double zp, double dj, double zj) {
+    double sn = zp, cs = zj;
+    const double tau = hypot(cs, sn);
+    const double t = dj - dp;
+    cs /= tau;
+    sn = -sn / tau;
+    return fabs(t * cs * sn) <= tol;
+  };
+  // Parallel pass: each thread takes a contiguous chunk, survivors of the
+  // z-test and deflated entries are placed by block prefix sums, and every
+  // pair of consecutive survivors is tested with its original values.  When
+  // no pair calls for a rotation this is exactly the scan's result (kept
+  // values in order, deflated values ascending); otherwise the sequential
+  // scan below redoes the merge.
+  __shared__ int scan_k[256], scan_d[256], scan_last[256];
+  __shared__ int any_rot;
+  const int nt = blockDim.x, tid = threadIdx.x;  // nt <= 256
+  const int chunk = (m + nt - 1) / nt, c0 = min(m, tid * chunk), c1 = min(m, c0 + chunk);
+  int nk = 0, ndf = 0, last = -1;
+  for (int j = c0; j < c1; ++j) {
+    if (rho * fabs(z[j]) <= tol) ++ndf;
+    else { ++nk; last = j; }
+  }
+  scan_k[tid] = nk;
+  scan_d[tid] = ndf;
+  scan_last[tid] = last;
+  if (tid == 0) any_rot = 0;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {  // inclusive scans (sum, max)
+    const int a = tid >= off ? scan_k[tid - off] : 0, b = tid >= off ? scan_d[tid - off] : 0;
+    const int l = tid >= off ? scan_last[tid - off] : -1;
+    __syncthreads();
+    scan_k[tid] += a;
+    scan_d[tid] += b;
+    scan_last[tid] = max(scan_last[tid], l);
+    __syncthreads();
+  }
+  {
+    int kpos = scan_k[tid] - nk, dpos = scan_d[tid] - ndf;
+    int prev = tid > 0 ? scan_last[tid - 1] : -1;
+    bool rot = false;
+    for (int j = c0; j < c1; ++j) {
+      if (rho * fabs(z[j]) <= tol) {
+        mt.defd[s + dpos] = d[j];
+        mt.defc[s + dpos] = c[j];
+        ++dpos;
+      } else {
+        if (prev >= 0) rot = rot || rot_test(d[prev], z[prev], d[j], z[j]);
+        mt.dl[s + kpos] = d[j];
+        mt.zl[s + kpos] = z[j];
+        mt.cl[s + kpos] = c[j];
+        ++kpos;
+        prev = j;
+      }
+    }
+    if (rot) any_rot = 1;
+  }
+  __syncthreads();
+  const bool need_scan = any_rot != 0;
+  if (!need_scan && tid == 0) {
+    counts[0] = scan_k[nt - 1]; counts[1] = scan_d[nt - 1]; counts[2] = 0;
+    mt.kcnt[3 * blockIdx.x + 0] = scan_k[nt - 1];
+    mt.kcnt[3 * blockIdx.x + 1] = scan_d[nt - 1];
+    mt.kcnt[3 * blockIdx.x + 2] = 0;
+    mt.rho[blockIdx.x] = rho;
+  }
+  if (need_scan && tid == 0) {
     int k = 0, nd = 0, nr = 0, pj = -1;
     double dp = 0.0, zp = 0.0;
     int cp = 0;
@@ -271,8 +339,9 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(const MergeDesc* md, co
   }
   __syncthreads();
   // Deflated values in ascending order: rank sort in LDS (ties by index).
+  // Without rotations they are already in order (d ascending).
   const int nd = counts[1];
-  if (nd > 1) {
+  if (need_scan && nd > 1) {
     for (int i = threadIdx.x; i < nd; i += blockDim.x) {
       d[i] = mt.defd[s + i];
       c[i] = mt.defc[s + i];
