@@ -327,7 +327,10 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_f32_kernel(GemmShape s, cons
           for (int j = 0; j < M::NB; ++j) {
             const float av = c == 0 ? a4[i].x : c == 1 ? a4[i].y : c == 2 ? a4[i].z : a4[i].w;
             const float bv = c == 0 ? b4[j].x : c == 1 ? b4[j].y : c == 2 ? b4[j].z : b4[j].w;
-            acc[i][j] = M::mma(av, bv, acc[i][j]);
+            // B as the first operand: the accumulator holds the tile
+            // transposed, lane l on row l % 32 of C, so the epilogue's loads
+            // and stores of C are 128-byte coalesced
+            acc[i][j] = M::mma(bv, av, acc[i][j]);
           }
     }
     if (more) {
@@ -344,8 +347,8 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_f32_kernel(GemmShape s, cons
     for (int j = 0; j < M::NB; ++j)
 #pragma unroll
       for (int r = 0; r < M::NACC; ++r) {
-        const int gi = m0 + wm * 64 + i * M::TM + M::c_row(lane, r);
-        const int gj = n0 + wn * 64 + j * M::TN + M::c_col(lane, r);
+        const int gi = m0 + wm * 64 + i * M::TM + M::c_col(lane, r);
+        const int gj = n0 + wn * 64 + j * M::TN + M::c_row(lane, r);
         if (gi < s.M && gj < s.N) {
           if (s.tri && gi < gj) continue;
           part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
