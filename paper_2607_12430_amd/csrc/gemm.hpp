@@ -14,7 +14,9 @@
 // is told to mirror the element to (j, i).
 #pragma once
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "profile.hpp"
@@ -363,13 +365,289 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_f32_kernel(GemmShape s, cons
   }
 }
 
-template <class Kern>
-inline void gemm_f32_lds_attr(Kern k) {
-  static bool set = false;
-  if (!set) {
-    MSQRT_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmF32Lds));
-    set = true;
+// Double kernel of the same design: K-slabs of 16 double-buffered in LDS,
+// k-contiguous rows (stride 18 doubles), v_mfma_f64_16x16x4f64 with lane
+// quarter h supplying k = 4 h + s at step s, so a lane reads its four k
+// values of a row with two 128-bit LDS loads; B is the first MFMA operand,
+// so the epilogue's accesses to C are coalesced.
+constexpr int DBK = 16, DLD = DBK + 2;
+constexpr size_t kGemmF64Lds = (size_t)2 * 2 * GBM * DLD * sizeof(double);
+
+template <bool RC>
+__device__ inline void f64_slab_index(int t, int e, int& r, int& k) {
+  const int lane = t % kWave, wave = t / kWave;
+  if (RC) {
+    const int id = wave * 8 + e;  // 32 blocks of 8 rows x 8 k
+    r = (id % 16) * 8 + lane % 8;
+    k = (id / 16) * 8 + lane / 8;
+  } else {
+    const int idx = t + GTHREADS * e;
+    k = idx % DBK;
+    r = idx / DBK;
   }
+}
+
+template <bool RC>
+__device__ inline void f64_slab_load(const double* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                     int K, int t, double (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int r, k;
+    f64_slab_index<RC>(t, e, r, k);
+    const int gr = r0 + r, gk = k0 + k;
+    v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.0;
+  }
+}
+
+template <bool RC>
+__device__ inline void f64_slab_store(double* Xs, int t, const double (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int r, k;
+    f64_slab_index<RC>(t, e, r, k);
+    Xs[r * DLD + k] = v[e];
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 2) void gemm_f64_kernel(GemmShape s, const double* __restrict__ A,
+                                                               const double* __restrict__ B, Epi epi,
+                                                               double* __restrict__ partials) {
+  using M = Mfma<double>;
+  extern __shared__ __attribute__((aligned(16))) double gemm_lds64[];
+  __shared__ double red[GTHREADS / kWave];
+  auto slab = [&](int buf, int op) { return gemm_lds64 + (size_t)(buf * 2 + op) * GBM * DLD; };
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+  constexpr bool ARC = !TA, BRC = TB;
+
+  typename M::acc_t acc[M::MB][M::NB];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.0;
+
+  double ra[8], rb[8];
+  if (K > 0) {
+    f64_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f64_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f64_slab_store<ARC>(slab(0, 0), t, ra);
+    f64_slab_store<BRC>(slab(0, 1), t, rb);
+  }
+  __syncthreads();
+  const int h = lane / 16, fr = lane % 16;
+  for (int k0 = 0, buf = 0; k0 < K; k0 += DBK, buf ^= 1) {
+    const bool more = k0 + DBK < K;
+    if (more) {
+      f64_slab_load<ARC>(A, s.lda, m0, s.M, k0 + DBK, K, t, ra);
+      f64_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + DBK, K, t, rb);
+    }
+    const double* As = slab(buf, 0);
+    const double* Bs = slab(buf, 1);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int kc = h * 4 + half * 2;
+      double2 a2[M::MB], b2[M::NB];
+#pragma unroll
+      for (int i = 0; i < M::MB; ++i)
+        a2[i] = *reinterpret_cast<const double2*>(As + (wm * 64 + i * 16 + fr) * DLD + kc);
+#pragma unroll
+      for (int j = 0; j < M::NB; ++j)
+        b2[j] = *reinterpret_cast<const double2*>(Bs + (wn * 64 + j * 16 + fr) * DLD + kc);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+          for (int j = 0; j < M::NB; ++j)
+            acc[i][j] = M::mma(c == 0 ? b2[j].x : b2[j].y, c == 0 ? a2[i].x : a2[i].y, acc[i][j]);
+    }
+    if (more) {
+      f64_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
+      f64_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+    }
+    __syncthreads();
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 64 + i * M::TM + M::c_col(lane, r);
+        const int gj = n0 + wn * 64 + j * M::TN + M::c_row(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
+// Float kernel for launches slightly larger than two workgroups per CU
+// (a triangle of 528 tiles at n = 4096 leaves 16 tiles for a second round):
+// K-slabs of 16 double-buffered (40 KiB of LDS, at most 170 registers), so
+// three workgroups share a CU and the whole launch runs in one round.
+constexpr int HBK = 16, HLD = HBK + 4;
+constexpr size_t kGemmF32k16Lds = (size_t)2 * 2 * GBM * HLD * sizeof(float);
+
+template <bool RC>
+__device__ inline void f32h_slab_load(const float* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                      int K, int t, float (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int r, k;
+    f64_slab_index<RC>(t, e, r, k);  // same 128 x 16 slab geometry
+    const int gr = r0 + r, gk = k0 + k;
+    v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.f;
+  }
+}
+
+template <bool RC>
+__device__ inline void f32h_slab_store(float* Xs, int t, const float (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int r, k;
+    f64_slab_index<RC>(t, e, r, k);
+    Xs[r * HLD + k] = v[e];
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, const float* __restrict__ A,
+                                                                  const float* __restrict__ B, Epi epi,
+                                                                  double* __restrict__ partials) {
+  using M = Mfma<float>;
+  extern __shared__ __attribute__((aligned(16))) float gemm_lds16[];
+  __shared__ double red[GTHREADS / kWave];
+  auto slab = [&](int buf, int op) { return gemm_lds16 + (size_t)(buf * 2 + op) * GBM * HLD; };
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+  constexpr bool ARC = !TA, BRC = TB;
+
+  typename M::acc_t acc[M::MB][M::NB];
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.f;
+
+  float ra[8], rb[8];
+  if (K > 0) {
+    f32h_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f32h_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f32h_slab_store<ARC>(slab(0, 0), t, ra);
+    f32h_slab_store<BRC>(slab(0, 1), t, rb);
+  }
+  __syncthreads();
+  // lane half h supplies k = 8 h + s at step s
+  const int h = lane / 32, fr = lane % 32;
+  for (int k0 = 0, buf = 0; k0 < K; k0 += HBK, buf ^= 1) {
+    const bool more = k0 + HBK < K;
+    if (more) {
+      f32h_slab_load<ARC>(A, s.lda, m0, s.M, k0 + HBK, K, t, ra);
+      f32h_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + HBK, K, t, rb);
+    }
+    const float* As = slab(buf, 0);
+    const float* Bs = slab(buf, 1);
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+      const int kc = h * 8 + s4 * 4;
+      float4 a4[M::MB], b4[M::NB];
+#pragma unroll
+      for (int i = 0; i < M::MB; ++i)
+        a4[i] = *reinterpret_cast<const float4*>(As + (wm * 64 + i * 32 + fr) * HLD + kc);
+#pragma unroll
+      for (int j = 0; j < M::NB; ++j)
+        b4[j] = *reinterpret_cast<const float4*>(Bs + (wn * 64 + j * 32 + fr) * HLD + kc);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+          for (int j = 0; j < M::NB; ++j) {
+            const float av = c == 0 ? a4[i].x : c == 1 ? a4[i].y : c == 2 ? a4[i].z : a4[i].w;
+            const float bv = c == 0 ? b4[j].x : c == 1 ? b4[j].y : c == 2 ? b4[j].z : b4[j].w;
+            acc[i][j] = M::mma(bv, av, acc[i][j]);
+          }
+    }
+    if (more) {
+      f32h_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
+      f32h_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+    }
+    __syncthreads();
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < M::MB; ++i)
+#pragma unroll
+    for (int j = 0; j < M::NB; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 64 + i * M::TM + M::c_col(lane, r);
+        const int gj = n0 + wn * 64 + j * M::TN + M::c_row(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
+inline int gemm_cu_count() {
+  static int ncu = 0;
+  if (!ncu) {
+    int dev = 0;
+    MSQRT_HIP(hipGetDevice(&dev));
+    MSQRT_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu <= 0) ncu = 1;
+  }
+  return ncu;
+}
+
+// Raises the dynamic LDS limit of kernel k once (kernels of equal signature
+// share a function type, so they are told apart by address).
+template <class Kern>
+inline void gemm_lds_attr(Kern k, size_t bytes) {
+  static std::vector<const void*> done;
+  const void* f = (const void*)k;
+  if (std::find(done.begin(), done.end(), f) != done.end()) return;
+  MSQRT_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done.push_back(f);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,19 +927,34 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
     }
   }
   if constexpr (std::is_same<T, float>::value) {
-    auto go = [&](auto kern) {
-      gemm_f32_lds_attr(kern);
-      hipLaunchKernelGGL(kern, grid, block, kGemmF32Lds, st, s, A, B, epi, partials);
+    // more tiles than two workgroups per CU hold but no more than three:
+    // the 16-deep variant runs them in one round
+    const int64_t units = (int64_t)s.ntiles * batch, ncu = gemm_cu_count();
+    const bool three = units > 2 * ncu && units <= 3 * ncu;
+    auto go = [&](auto kern, size_t lds) {
+      gemm_lds_attr(kern, lds);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, s, A, B, epi, partials);
     };
-    if (!ta && !tb) go(gemm_f32_kernel<false, false, Epi>);
-    else if (ta && !tb) go(gemm_f32_kernel<true, false, Epi>);
-    else if (!ta && tb) go(gemm_f32_kernel<false, true, Epi>);
-    else go(gemm_f32_kernel<true, true, Epi>);
+    if (three) {
+      if (!ta && !tb) go(gemm_f32k16_kernel<false, false, Epi>, kGemmF32k16Lds);
+      else if (ta && !tb) go(gemm_f32k16_kernel<true, false, Epi>, kGemmF32k16Lds);
+      else if (!ta && tb) go(gemm_f32k16_kernel<false, true, Epi>, kGemmF32k16Lds);
+      else go(gemm_f32k16_kernel<true, true, Epi>, kGemmF32k16Lds);
+    } else {
+      if (!ta && !tb) go(gemm_f32_kernel<false, false, Epi>, kGemmF32Lds);
+      else if (ta && !tb) go(gemm_f32_kernel<true, false, Epi>, kGemmF32Lds);
+      else if (!ta && tb) go(gemm_f32_kernel<false, true, Epi>, kGemmF32Lds);
+      else go(gemm_f32_kernel<true, true, Epi>, kGemmF32Lds);
+    }
   } else {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
-    else hipLaunchKernelGGL((gemm_kernel<T, true, true, Epi>), grid, block, 0, st, s, A, B, epi, partials);
+    auto go = [&](auto kern) {
+      gemm_lds_attr(kern, kGemmF64Lds);
+      hipLaunchKernelGGL(kern, grid, block, kGemmF64Lds, st, s, A, B, epi, partials);
+    };
+    if (!ta && !tb) go(gemm_f64_kernel<false, false, Epi>);
+    else if (ta && !tb) go(gemm_f64_kernel<true, false, Epi>);
+    else if (!ta && tb) go(gemm_f64_kernel<false, true, Epi>);
+    else go(gemm_f64_kernel<true, true, Epi>);
   }
   MSQRT_LAUNCH_CHECK();
   if (tok >= 0) {
