@@ -171,6 +171,8 @@ __device__ inline void grid_barrier(unsigned* bar, const BarrierBase& base, unsi
 template <typename T>
 struct PanelArgs {
   int n, p, nb;  // matrix size, first column of the panel, panel width
+  int nbp;       // width of the previous panel whose trailing update this
+                 // launch applies itself (float; 0: none, or applied by a GEMM)
   int TR;        // tiles per dimension; G = TR (TR + 1) / 2 workgroups (lower triangle)
   int r0, ts;    // tile grid origin (p + 1) and tile size (<= kMaxTs)
   T* A;          // n x n, ld n, full symmetric storage
@@ -260,7 +262,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
 // so the same registers serve every column of the panel.
 template <typename T, int CW, int RPL>
 __device__ inline void tile_load(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0, int nK,
-                                 T (&v)[CW][RPL], int tid) {
+                                 bool diag, T (&v)[CW][RPL], int tid) {
   const int wave = tid / kWave, lane = tid % kWave;
   const int cb = wave * CW;
 #pragma unroll
@@ -271,7 +273,9 @@ __device__ inline void tile_load(const T* __restrict__ A, int64_t ld, int I0, in
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + q * kWave;
-      v[c][q] = (colok && r < nI) ? colp[r] : T(0);
+      // the upper part of a diagonal tile is read from its mirror in the
+      // lower triangle (only the lower triangle is kept up to date)
+      v[c][q] = (colok && r < nI) ? ((diag && r < k) ? A[K0 + k + (int64_t)(I0 + r) * ld] : colp[r]) : T(0);
     }
   }
 }
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   T* A = a.A;
 
   // Panel columns of this workgroup's rows: PVI[t][r] = V(I0 + r, t), etc.
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T* PVI = reinterpret_cast<T*>(smem_raw);
   T* PWI = PVI + nb * kMaxTs;
   T* PVK = PWI + nb * kMaxTs;
@@ -393,14 +397,114 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   static_assert(!kResident || (kRCW * (kThreads / kWave) == kMaxTs && RPL * kWave == kMaxTs),
                 "the register tile must cover the tile");
   T vt[kResident ? kRCW : 1][kResident ? RPL : 1];
-  if constexpr (kResident) tile_load<T, kRCW, RPL>(A, ld, I0, nI, K0, nK, vt, tid);
-  {
+  if constexpr (kResident) tile_load<T, kRCW, RPL>(A, ld, I0, nI, K0, nK, diag, vt, tid);
+  // Trailing update of the previous panel, A(p:, p:) -= [V W] [W V]^T over its
+  // 2 nbp columns (left in VW and WV), applied here instead of by a separate
+  // GEMM: the register tile is updated and written back (the lower triangle
+  // and the diagonal squares, with coherent stores), and column p, which no
+  // tile covers, is corrected where it is read.  A grid barrier then makes the
+  // written-back tiles visible; inside this launch they are read back with
+  // coherent loads (a line of another XCD's L2 may hold the old values).
+  const int nbp = kResident ? a.nbp : 0;
+  __shared__ T vwp[2 * kNbMax], wvp[2 * kNbMax];  // VW(p, :), WV(p, :)
+  __shared__ double app;                           // updated A(p, p)
+  if (nbp > 0) {
+    const int w2 = 2 * nbp;
+    T* VWs = PVI;              // [t][r]: VW(I0 + r, t), w2 x kMaxTs
+    T* WVs = PVI + w2 * kMaxTs;  // [t][k]: WV(K0 + k, t)
+    for (int x = tid; x < w2 * kMaxTs; x += kThreads) {
+      const int t = x / kMaxTs, r = x % kMaxTs;
+      VWs[x] = (r < nI) ? a.VW[I0 + r + (int64_t)t * ld] : T(0);
+      WVs[x] = (r < nK) ? a.WV[K0 + r + (int64_t)t * ld] : T(0);
+    }
+    if (tid < w2) {
+      vwp[tid] = a.VW[p + (int64_t)tid * ld];
+      wvp[tid] = a.WV[p + (int64_t)tid * ld];
+    }
+    __syncthreads();
+    if constexpr (kResident) {
+      // the products are summed apart and subtracted once, as a GEMM update
+      // would round them
+      const int wave = tid / kWave, lane = tid % kWave, cb = wave * kRCW;
+      static_assert(kRCW % 4 == 0 && kMaxTs % 4 == 0, "float4 rows of WVs");
+      T acc[kRCW][RPL];
+#pragma unroll
+      for (int c = 0; c < kRCW; ++c)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) acc[c][q] = T(0);
+      for (int t = 0; t < w2; ++t) {
+        T av[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) av[q] = VWs[t * kMaxTs + lane + q * kWave];
+        const float4* b4 = reinterpret_cast<const float4*>(WVs + t * kMaxTs + cb);
+#pragma unroll
+        for (int c4 = 0; c4 < kRCW / 4; ++c4) {
+          const float4 bq = b4[c4];
+          const T bv[4] = {bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) acc[c4 * 4 + e][q] += av[q] * bv[e];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kRCW; ++c)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) vt[c][q] -= acc[c][q];
+#pragma unroll
+      for (int c = 0; c < kRCW; ++c) {
+        const int k = cb + c;
+        if (k < nK) {
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) {
+            const int r = lane + q * kWave;
+            if (r < nI) cstore(&A[I0 + r + (int64_t)(K0 + k) * ld], vt[c][q]);
+          }
+        }
+      }
+    }
+    // column p on the rows of I and K (VW on the rows of K is WV with its
+    // halves exchanged) and on the pivot rows; A(p, p)
+    {
+      const int j = p;
+      if (tid < nI) {
+        T cr = T(0);
+        for (int t = 0; t < w2; ++t) cr += VWs[t * kMaxTs + tid] * wvp[t];
+        uI[tid] = (I0 + tid >= j + 1) ? A[I0 + tid + (int64_t)j * ld] - cr : T(0);
+      }
+      if (tid >= kKT && tid - kKT < nK) {
+        const int r = tid - kKT;
+        T cr = T(0);
+        for (int t = 0; t < w2; ++t) cr += WVs[((t + nbp) % w2) * kMaxTs + r] * wvp[t];
+        uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] - cr : T(0);
+      }
+      if (tid >= kPivT && tid < kPivT + kNbMax) {
+        const int q = tid - kPivT, r = p + 1 + q;
+        T u = T(0);
+        if (q < nb && r < n) {
+          T cr = T(0);
+          for (int t = 0; t < w2; ++t) cr += a.VW[r + (int64_t)t * ld] * wvp[t];
+          u = A[r + (int64_t)j * ld] - cr;
+        }
+        if (q < nb) PU[q] = u;
+      }
+      if (tid == 0) {
+        double s = (double)A[p + (int64_t)p * ld];
+        T corr = T(0);
+        for (int t = 0; t < w2; ++t) corr += vwp[t] * wvp[t];
+        app = s - (double)corr;
+      }
+    }
+    grid_barrier(a.bar, a.bar_base, sub_base, blk, G, 1);
+  } else {
     const int j = p;
     for (int r = tid; r < nI; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (int64_t)j * ld] : T(0);
     for (int r = tid; r < nK; r += kThreads) uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] : T(0);
     for (int q = tid; q < nb; q += kThreads) PU[q] = (p + 1 + q < n) ? A[p + 1 + q + (int64_t)j * ld] : T(0);
+    if (tid == 0) app = (double)A[p + (int64_t)p * ld];
   }
   __syncthreads();
+  const int kb0 = nbp > 0 ? 1 : 0;  // barriers before the first column's
 
   for (int jj = 0; jj < nb; ++jj) {
     const int j = p + jj;
@@ -408,11 +512,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // ---- column j+1 of A (a1 for the product, base of the next u), issued
     // together with the tile loads
     T acv_i = T(0), acv_k = T(0), acv_p = T(0);
-    if (tid < nI) acv_i = A[I0 + tid + (int64_t)(j + 1) * ld];
-    if (tid < nK) acv_k = A[K0 + tid + (int64_t)(j + 1) * ld];
-    if (tid < nb && p + 1 + tid < n) acv_p = A[p + 1 + tid + (int64_t)(j + 1) * ld];
-    // A(j, j) for d_j (never written inside the panel)
-    const double ajj = (tid == 0) ? (double)A[j + (int64_t)j * ld] : 0.0;
+    auto rd = [&](int64_t idx) -> T { return nbp > 0 ? cload(&A[idx]) : A[idx]; };
+    if (tid < nI) acv_i = rd(I0 + tid + (int64_t)(j + 1) * ld);
+    if (tid < nK) acv_k = rd(K0 + tid + (int64_t)(j + 1) * ld);
+    if (tid < nb && p + 1 + tid < n) acv_p = rd(p + 1 + tid + (int64_t)(j + 1) * ld);
+    // A(j, j) for d_j (never written inside the panel after the prologue)
+    const double ajj = (tid == 0) ? (jj == 0 ? app : (double)rd(j + (int64_t)j * ld)) : 0.0;
     // ---- tile product; the 16 waves' row partials are folded onto 8 slots;
     // every column sum of zKs is written once, by the wave owning the column
     {
@@ -510,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
 
-    grid_barrier(a.bar, a.bar_base, sub_base, blk, G, jj + 1);
+    grid_barrier(a.bar, a.bar_base, sub_base, blk, G, kb0 + jj + 1);
 
     // ---- gather the partial sums of all workgroups into LDS in parallel
     // (one load per thread), then reduce them there.
@@ -697,12 +802,19 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   }
 }
 
-// Last diagonal entry after the final trailing update (one block per batch
-// entry).
+// Last diagonal entry (one block per batch entry), with the last panel's
+// trailing update over w2 columns of VW and WV when no GEMM applied it.
 template <typename T>
-__global__ void copy_last_diag(const T* A, int n, T* d, int64_t sA, int64_t sD) {
+__global__ void copy_last_diag(const T* A, int n, T* d, int64_t sA, int64_t sD, const T* VW,
+                               const T* WV, int64_t sVW, int w2) {
   const int64_t b = blockIdx.x;
-  if (threadIdx.x == 0) d[b * sD + n - 1] = A[b * sA + (n - 1) + (int64_t)(n - 1) * n];
+  if (threadIdx.x == 0) {
+    T v = A[b * sA + (n - 1) + (int64_t)(n - 1) * n];
+    T corr = T(0);
+    for (int t = 0; t < w2; ++t)
+      corr += VW[b * sVW + (n - 1) + (int64_t)t * n] * WV[b * sVW + (n - 1) + (int64_t)t * n];
+    d[b * sD + n - 1] = v - corr;
+  }
 }
 
 }  // namespace
@@ -712,7 +824,8 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
                    int64_t sD, SytrdWork& w) {
   if (n <= 0 || batch <= 0) return;
   if (n == 1) {
-    hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD);
+    hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD,
+                       (const T*)nullptr, (const T*)nullptr, (int64_t)0, 0);
     MSQRT_LAUNCH_CHECK();
     return;
   }
@@ -746,6 +859,9 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
   MSQRT_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned) * (size_t)(sBar * batch), st));
   w.nbar = batch;
   BarrierBase bar_base{};
+  // float panels apply the previous panel's trailing update themselves
+  constexpr bool kFused = sizeof(T) == 4;
+  int nbp = 0;
   for (int p = 0; p < n - 1; p += nb) {
     const int nbe = std::min(nb, n - 1 - p);
     const int m = n - 1 - p;  // rows/cols of the tile region [p+1, n)
@@ -757,7 +873,7 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
     const int tok = prof_begin(st);
     for (int b0 = 0; b0 < batch; b0 += chunk) {
       const int nbt = std::min(chunk, batch - b0);
-      PanelArgs<T> pa{n,          p,          nbe,        TR,          p + 1,         ts,
+      PanelArgs<T> pa{n,          p,          nbe,        kFused ? nbp : 0, TR,      p + 1,         ts,
                       A + b0 * sA, VW + b0 * sVW, WV + b0 * sVW, d + b0 * sD, e + b0 * sD,
                       tau + b0 * sD, ypart + b0 * sYP, sp + b0 * sSP, vp + b0 * sVP,
                       bar + b0 * sBar, bar_base, sA, sVW, sD, sYP, sSP, sVP, sBar};
@@ -765,23 +881,32 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
       MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G * nbt),
                                            dim3(kThreads), args, dyn_lds, st));
     }
-    bar_base.gen += (unsigned)nbe;
-    bar_base.top += (unsigned)std::min(G, 8) * (unsigned)nbe;
-    for (int g = 0; g < 8; ++g) bar_base.sub[g] += (unsigned)(G / 8 + (g < G % 8 ? 1 : 0)) * (unsigned)nbe;
+    const unsigned nbar = (unsigned)nbe + ((kFused && nbp > 0) ? 1u : 0u);  // barriers of the launch
+    bar_base.gen += nbar;
+    bar_base.top += (unsigned)std::min(G, 8) * nbar;
+    for (int g = 0; g < 8; ++g) bar_base.sub[g] += (unsigned)(G / 8 + (g < G % 8 ? 1 : 0)) * nbar;
     if (tok >= 0) {
       // algorithmic traffic: one read of the symmetric trailing matrix (lower
-      // triangle) per column for its product with the reflector
-      double bytes = 0.0;
+      // triangle) per column for its product with the reflector, and, when
+      // the launch applies the previous panel's update, one read and one
+      // write of that triangle
+      double bytes = 0.0, flops = 4.0 * 0.5 * (double)m * m * nbe;
       for (int jj = 0; jj < nbe; ++jj) {
         const double mj = (double)(n - 1 - (p + jj));
         bytes += 0.5 * mj * (mj + 1.0) * sizeof(T);
       }
-      prof_end(tok, st, sizeof(T) == 4 ? "sytrd_panel_f32" : "sytrd_panel_f64",
-               4.0 * 0.5 * (double)m * m * nbe * batch, bytes * batch);
+      if (kFused && p > 0) {
+        bytes += 2.0 * 0.5 * (double)m * (m + 1.0) * sizeof(T);
+        flops += 2.0 * 0.5 * (double)m * (m + 1.0) * (2.0 * nbp);
+      }
+      prof_end(tok, st, sizeof(T) == 4 ? "sytrd_panel_f32" : "sytrd_panel_f64", flops * batch,
+               bytes * batch);
     }
-    // Trailing update A(q:n, q:n) -= [V W] [W V]^T, q = p + nbe, all entries.
+    nbp = nbe;
+    // Trailing update A(q:n, q:n) -= [V W] [W V]^T, q = p + nbe, all entries
+    // (float: applied by the next panel, or below for the last entry).
     const int q = p + nbe;
-    if (q < n) {
+    if (!kFused && q < n) {
       const int mt = n - q;
       if (std::is_same<T, float>::value)
         gemm_store_f32(st, false, true, mt, mt, 2 * nbe, (const float*)(VW + q), n, sVW,
@@ -793,7 +918,8 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
                        -1.0, 1.0, batch, true);
     }
   }
-  hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD);
+  hipLaunchKernelGGL(copy_last_diag<T>, dim3(batch), 64, 0, st, (const T*)A, n, d, sA, sD,
+                     (const T*)VW, (const T*)WV, sVW, kFused ? 2 * nbp : 0);
   MSQRT_LAUNCH_CHECK();
 }
 
