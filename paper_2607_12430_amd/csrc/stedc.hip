@@ -750,8 +750,26 @@ void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int
     MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn * batch, st));
     hipLaunchKernelGGL(vectors_kernel<T>, dim3(N), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);
     MSQRT_LAUNCH_CHECK();
-    // one GEMM per merge of the level, batched over the entries
-    for (int b = 0; b < nm1; ++b) {
+    // One GEMM per merge of the level, batched over the entries; a single
+    // entry whose merges are equal and adjacent (n a power of two times the
+    // leaf size) takes the whole level as one batch instead.
+    bool uniform = batch == 1 && nm1 > 1;
+    for (int b = 1; b < nm1 && uniform; ++b)
+      uniform = lv[b].m == lv[0].m && lv[b].n1 == lv[0].n1 && lv[b].s == lv[0].s + b * lv[0].m;
+    if (uniform) {
+      const MergeDesc& g = lv[0];
+      const int64_t sBlk = (int64_t)g.m * (n + 1), sM = (int64_t)g.m * n;
+      const T* Ablk = Za + blk_off(g.s, n);
+      T* Cblk = Zb + blk_off(g.s, n);
+      const T* Mb = M + (int64_t)g.s * n;
+      if (std::is_same<T, float>::value)
+        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, sBlk, (const float*)Mb,
+                       g.m, sM, (float*)Cblk, n, sBlk, 1.f, 0.f, nm1, false);
+      else
+        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, sBlk, (const double*)Mb,
+                       g.m, sM, (double*)Cblk, n, sBlk, 1.0, 0.0, nm1, false);
+    }
+    for (int b = 0; b < nm1 && !uniform; ++b) {
       const MergeDesc& g = lv[b];
       const T* Ablk = Za + blk_off(g.s, n);
       T* Cblk = Zb + blk_off(g.s, n);
