@@ -412,10 +412,25 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     const int w2 = 2 * nbp;
     T* VWs = PVI;              // [t][r]: VW(I0 + r, t), w2 x kMaxTs
     T* WVs = PVI + w2 * kMaxTs;  // [t][k]: WV(K0 + k, t)
-    for (int x = tid; x < w2 * kMaxTs; x += kThreads) {
-      const int t = x / kMaxTs, r = x % kMaxTs;
-      VWs[x] = (r < nI) ? a.VW[I0 + r + (int64_t)t * ld] : T(0);
-      WVs[x] = (r < nK) ? a.WV[K0 + r + (int64_t)t * ld] : T(0);
+    {
+      // every load of the staging issued before any store
+      constexpr int kSt = 2 * kNbMax * kMaxTs / kThreads;
+      static_assert(kSt * kThreads == 2 * kNbMax * kMaxTs, "staging split");
+      T va[kSt], wa[kSt];
+#pragma unroll
+      for (int e = 0; e < kSt; ++e) {
+        const int x = tid + e * kThreads, t = x / kMaxTs, r = x % kMaxTs;
+        va[e] = (t < w2 && r < nI) ? a.VW[I0 + r + (int64_t)t * ld] : T(0);
+        wa[e] = (t < w2 && r < nK) ? a.WV[K0 + r + (int64_t)t * ld] : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < kSt; ++e) {
+        const int x = tid + e * kThreads;
+        if (x < w2 * kMaxTs) {
+          VWs[x] = va[e];
+          WVs[x] = wa[e];
+        }
+      }
     }
     if (tid < w2) {
       vwp[tid] = a.VW[p + (int64_t)tid * ld];
@@ -482,8 +497,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         const int q = tid - kPivT, r = p + 1 + q;
         T u = T(0);
         if (q < nb && r < n) {
+          T vr[2 * kNbMax];  // the row's coefficients, all loads issued together
+#pragma unroll
+          for (int t = 0; t < 2 * kNbMax; ++t) vr[t] = (t < w2) ? a.VW[r + (int64_t)t * ld] : T(0);
           T cr = T(0);
-          for (int t = 0; t < w2; ++t) cr += a.VW[r + (int64_t)t * ld] * wvp[t];
+#pragma unroll
+          for (int t = 0; t < 2 * kNbMax; ++t) cr += vr[t] * ((t < w2) ? wvp[t] : T(0));
           u = A[r + (int64_t)j * ld] - cr;
         }
         if (q < nb) PU[q] = u;
