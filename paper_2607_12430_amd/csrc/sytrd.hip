@@ -595,7 +595,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       double s = 0.0;
       if (c < 2 * jj) {
         const T* col = c < jj ? (PVI + c * kMaxTs) : (PWI + (c - jj) * kMaxTs);
-        for (int r = l16; r < nI; r += 16) s += (double)col[r] * (double)uI[r];
+#pragma unroll
+        for (int i = 0; i < kMaxTs / 16; ++i) {
+          const int r = l16 + 16 * i;
+          if (r < nI) s += (double)col[r] * (double)uI[r];
+        }
       }
       s = rsum16(s);
       if (l16 == 0 && c < 2 * jj) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
@@ -638,15 +642,21 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
 
     // ---- gather the partial sums of all workgroups into LDS in parallel
     // (one load per thread), then reduce them there.
-    for (int b = tid; b < G; b += kThreads) {
-      const double* spb = a.sp + ((int64_t)buf * G + b) * 4;
-      spl[0][b] = cload(&spb[0]);
-      spl[1][b] = cload(&spb[1]);
-      spl[2][b] = cload(&spb[2]);
+    // All loads of the gather are issued before any result is stored, so
+    // they share one round trip.
+    static_assert(kGMax <= kThreads && kTRMax * 2 * kNbMax <= 2 * kThreads, "gather split");
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, gv0 = 0.0, gv1 = 0.0;
+    const int nvp = TR * 2 * jj;
+    if (tid < G) {
+      const double* spb = a.sp + ((int64_t)buf * G + tid) * 4;
+      g0 = cload(&spb[0]);
+      g1 = cload(&spb[1]);
+      g2 = cload(&spb[2]);
     }
-    for (int x = tid; x < TR * 2 * jj; x += kThreads) {
-      const int b = x / (2 * jj), c2 = x % (2 * jj);
-      vpl[x] = cload(&a.vp[((int64_t)buf * TR + b) * (2 * kNbMax) + c2]);
+    if (tid < nvp) gv0 = cload(&a.vp[((int64_t)buf * TR + tid / (2 * jj)) * (2 * kNbMax) + tid % (2 * jj)]);
+    if (tid + kThreads < nvp) {
+      const int x = tid + kThreads;
+      gv1 = cload(&a.vp[((int64_t)buf * TR + x / (2 * jj)) * (2 * kNbMax) + x % (2 * jj)]);
     }
     // (A22 u)_i = sum of the TR partial products of row i, for the rows of I,
     // K and the pivot rows: all loads of a row issued together.
@@ -671,6 +681,13 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         yzP[q] = (q < nb && r >= j + 1 && r < n) ? rowsum(r) : T(0);
       }
     }
+    if (tid < G) {
+      spl[0][tid] = g0;
+      spl[1][tid] = g1;
+      spl[2][tid] = g2;
+    }
+    if (tid < nvp) vpl[tid] = gv0;
+    if (tid + kThreads < nvp) vpl[tid + kThreads] = gv1;
     __syncthreads();
     // Wave 0 reduces the scalars and forms the reflector while waves 8-15 sum
     // the row tiles' V^T u and W^T u (8 lanes per panel column).
