@@ -1,22 +1,26 @@
 // Householder tridiagonalisation of a symmetric matrix (first step of the
 // spectral decomposition used by Alg. 3), blocked by panels of nb columns.
 //
-// Panel: one cooperative launch of G = TR x TR workgroups that walks the
-// panel's columns with ONE grid barrier per column.  For column j with
-// updated sub-column u (rows j+1..n-1) the reflector is v = (u - beta e1) c,
-// c = 1/(alpha - beta).  Because every quantity the panel needs from v is
-// linear in v, each workgroup forms its tile of the trailing product with the
-// *unnormalised* u (A22 u), plus partial sums of ||u||^2, u^T A22 u,
+// Panel: one cooperative launch of G = TR (TR + 1) / 2 workgroups, one per
+// lower-triangular tile of the trailing matrix (at most 192 x 192, up to 253
+// workgroups), that walks the panel's columns with ONE grid barrier per
+// column.  For column j with updated sub-column u (rows j+1..n-1) the
+// reflector is v = (u - beta e1) c, c = 1/(alpha - beta).  Because every
+// quantity the panel needs from v is linear in v, each workgroup forms its
+// tile's share of the trailing product with the *unnormalised* u (A22 u and,
+// off the diagonal, A22^T u), plus partial sums of ||u||^2, u^T A22 u,
 // u^T A22 e1, V^T u and W^T u, before the barrier.  After the barrier every
 // workgroup finishes the reflector scalars, y = A22 v - V (W^T v) - W (V^T v)
 // and w = tau y - (tau/2)(tau y^T v) v for the rows it needs, and prepares
 // the next column's u -- so the classic two reductions per column (norm,
 // then product) cost a single synchronisation.
 //
-// The trailing matrix is kept as a full symmetric square (both triangles), so
-// each workgroup reads its tile row-wise with coalesced loads and no
-// cross-tile reduction of the product is needed beyond the TR partial vectors.
-// After the panel: A22 -= [V W] [W V]^T on the MFMA GEMM (symmetric output).
+// After a panel, A22 -= [V W] [W V]^T.  The float kernel holds its tile in
+// registers for the whole panel and applies the previous panel's update to
+// it at launch start; it keeps only the lower triangle current (a diagonal
+// tile reads its upper half from the mirror).  The double kernel streams its
+// tile at every column and leaves the update to an MFMA GEMM with symmetric
+// output (both triangles written).
 #include <vector>
 
 #include "gemm.hpp"
