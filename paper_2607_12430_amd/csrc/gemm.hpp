@@ -1,10 +1,17 @@
 // MFMA GEMM for gfx950 with fused epilogues.
 //
 // C-tile 128 x 128 per workgroup of 256 threads (four wave64s in a 2 x 2
-// arrangement, 64 x 64 per wave), K-slab of 16 staged through LDS with the
-// next slab's global loads issued before the current slab's MFMAs.
-//   float : v_mfma_f32_32x32x2f32 (2 x 2 blocks of 32 x 32 per wave)
-//   double: v_mfma_f64_16x16x4f64 (4 x 4 blocks of 16 x 16 per wave)
+// arrangement, 64 x 64 per wave).  K-slabs are double-buffered in LDS with
+// each operand stored k-contiguous, so a lane reads several k values of its
+// row with one 128-bit LDS load, and the next slab's global loads are in
+// flight during the current slab's MFMAs (one barrier per slab):
+//   float : v_mfma_f32_32x32x2f32 (2 x 2 blocks of 32 x 32 per wave), slabs
+//           of 32 (slabs of 16 and three workgroups per CU for launches of
+//           2-3 tiles per CU)
+//   double: v_mfma_f64_16x16x4f64 (4 x 4 blocks of 16 x 16 per wave), slabs
+//           of 16
+// B is the first MFMA operand, so the accumulator holds the tile transposed
+// and the epilogue's accesses to C are coalesced.
 // Column-major operands; op(A) is M x K, op(B) is K x N; batches via strides.
 //
 // The epilogue functor receives every output element (i, j) exactly once and
@@ -62,7 +69,7 @@ struct GemmShape {
   int tiles_m, tiles_n, ntiles, per_xcd;
 };
 
-constexpr int GBM = 128, GBN = 128, GBK = 16, GTHREADS = 256;
+constexpr int GBM = 128, GBN = 128, GTHREADS = 256;
 
 // Maps the hardware workgroup id to a tile id so that each of the 8 XCDs
 // (workgroups are dispatched round-robin over XCDs) works on a contiguous
@@ -92,119 +99,6 @@ __device__ inline bool gemm_tile_coords(const GemmShape& s, int& tm, int& tn) {
   return true;
 }
 
-template <typename T, bool TA, bool TB, class Epi>
-__global__ __launch_bounds__(GTHREADS, 2) void gemm_kernel(GemmShape s, const T* __restrict__ A,
-                                                           const T* __restrict__ B, Epi epi,
-                                                           double* __restrict__ partials) {
-  using M = Mfma<T>;
-  constexpr int PAD = 1;
-  __shared__ T As[GBK][GBM + PAD];
-  __shared__ T Bs[GBK][GBN + PAD];
-  __shared__ double red[GTHREADS / kWave];
-
-  int tm, tn;
-  if (!gemm_tile_coords(s, tm, tn)) return;
-  const int batch = blockIdx.y;
-  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
-  A += (int64_t)batch * s.sA;
-  B += (int64_t)batch * s.sB;
-  const int m0 = tm * GBM, n0 = tn * GBN;
-  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
-  const int wm = wave % 2, wn = wave / 2;
-
-  constexpr int EPT = GBM * GBK / GTHREADS;  // 8 elements per thread per operand
-  T ra[EPT], rb[EPT];
-
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = t + GTHREADS * e;
-      int mm, kk;
-      if (!TA) { mm = idx % GBM; kk = idx / GBM; } else { kk = idx % GBK; mm = idx / GBK; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      T v = T(0);
-      if (gm < s.M && gk < K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
-      ra[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = t + GTHREADS * e;
-      int nn, kk;
-      if (TB) { nn = idx % GBN; kk = idx / GBN; } else { kk = idx % GBK; nn = idx / GBK; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      T v = T(0);
-      if (gn < s.N && gk < K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
-      rb[e] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = t + GTHREADS * e;
-      int mm, kk;
-      if (!TA) { mm = idx % GBM; kk = idx / GBM; } else { kk = idx % GBK; mm = idx / GBK; }
-      As[kk][mm] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int idx = t + GTHREADS * e;
-      int nn, kk;
-      if (TB) { nn = idx % GBN; kk = idx / GBN; } else { kk = idx % GBK; nn = idx / GBK; }
-      Bs[kk][nn] = rb[e];
-    }
-  };
-
-  typename M::acc_t acc[M::MB][M::NB];
-#pragma unroll
-  for (int i = 0; i < M::MB; ++i)
-#pragma unroll
-    for (int j = 0; j < M::NB; ++j)
-#pragma unroll
-      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = T(0);
-
-  if (K > 0) load(0);
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + GBK < K) load(k0 + GBK);
-#pragma unroll
-    for (int kk = 0; kk < GBK; kk += M::TK) {
-      T a[M::MB], b[M::NB];
-      const int fk = kk + M::frag_k(lane), fmn = M::frag_mn(lane);
-#pragma unroll
-      for (int i = 0; i < M::MB; ++i) a[i] = As[fk][wm * 64 + i * M::TM + fmn];
-#pragma unroll
-      for (int j = 0; j < M::NB; ++j) b[j] = Bs[fk][wn * 64 + j * M::TN + fmn];
-#pragma unroll
-      for (int i = 0; i < M::MB; ++i)
-#pragma unroll
-        for (int j = 0; j < M::NB; ++j) acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
-    }
-  }
-
-  double part = 0.0;
-#pragma unroll
-  for (int i = 0; i < M::MB; ++i)
-#pragma unroll
-    for (int j = 0; j < M::NB; ++j)
-#pragma unroll
-      for (int r = 0; r < M::NACC; ++r) {
-        const int gi = m0 + wm * 64 + i * M::TM + M::c_row(lane, r);
-        const int gj = n0 + wn * 64 + j * M::TN + M::c_col(lane, r);
-        if (gi < s.M && gj < s.N) {
-          if (s.tri && gi < gj) continue;
-          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
-        }
-      }
-  if (Epi::kReduces) {
-    part = block_sum(part, red);
-    if (t == 0) {
-      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
-      partials[(int64_t)batch * s.ntiles + id] = part;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Float kernel with a deeper pipeline: K-slabs of 32 double-buffered in LDS
