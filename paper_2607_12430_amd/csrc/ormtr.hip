@@ -108,9 +108,10 @@ void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* Vc, const T
     gemm(true, false, kBlk, kBlk, n, V, n, (int64_t)kBlk * n, V, n, (int64_t)kBlk * n, G, kBlk,
          (int64_t)kBlk * kBlk, T(1), T(0), full);
   if (full < nblk) {
-    const int nbk = nref - full * kBlk;
-    const T* Vb = V + (int64_t)full * kBlk * n;
-    gemm(true, false, nbk, nbk, n, Vb, n, 0, Vb, n, 0, G + (int64_t)full * kBlk * kBlk, kBlk, 0,
+    // rows above the block's first reflector are zero: K = n - r0
+    const int nbk = nref - full * kBlk, r0 = std::min(n - 1, full * kBlk + off);
+    const T* Vb = V + (int64_t)full * kBlk * n + r0;
+    gemm(true, false, nbk, nbk, n - r0, Vb, n, 0, Vb, n, 0, G + (int64_t)full * kBlk * kBlk, kBlk, 0,
          T(1), T(0), 1);
   }
   hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kBlk), 0, st, nref, (const T*)G, tau, Tm,
@@ -186,9 +187,10 @@ void ormtr_batched(hipStream_t st, int n, int batch, const T* Vc, int64_t sV, co
   MSQRT_LAUNCH_CHECK();
   MSQRT_HIP(hipMemsetAsync(Gall, 0, sizeof(T) * (size_t)(sG * batch), st));
   for (int b = 0; b < nblk; ++b) {
-    const int nbk = std::min(kBlk, nref - b * kBlk);
-    const T* Vb = Vc + (int64_t)b * kBlk * n;
-    gemm(true, false, nbk, nbk, n, Vb, n, sV, Vb, n, sV, Gall + (int64_t)b * kBlk * kBlk, kBlk,
+    // rows above the block's first reflector (row b kBlk + 1) are zero
+    const int nbk = std::min(kBlk, nref - b * kBlk), r0 = std::min(n - 1, b * kBlk + 1);
+    const T* Vb = Vc + (int64_t)b * kBlk * n + r0;
+    gemm(true, false, nbk, nbk, n - r0, Vb, n, sV, Vb, n, sV, Gall + (int64_t)b * kBlk * kBlk, kBlk,
          sG, T(1), T(0), batch);
   }
   hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk, batch), dim3(kBlk), 0, st, nref, (const T*)Gall,
