@@ -550,7 +550,7 @@ inline void gemm_lds_attr(Kern k, size_t bytes) {
 // into LDS, and the product is accumulated in float as
 //   A B ~ Ah Bh + Ah Bl + Al Bh
 // with v_mfma_f32_32x32x16_bf16 (unit roundoff about 2^-16 instead of 2^-24,
-// at the bf16 matrix rate).  Same tiling as gemm_kernel with a K-slab of 32;
+// at the bf16 matrix rate).  Same 128 x 128 tiling as the float kernel, K-slabs of 32;
 // LDS holds the hi and lo parts k-contiguous so that every lane reads its 8
 // consecutive k values with one 16-byte load.
 
