@@ -81,11 +81,12 @@ def test_batched_forward_and_backward(msq):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("n", [1, 2, 33, 65, 100])
+@pytest.mark.parametrize("n", [1, 2, 33, 34, 65, 100])
 def test_batched_eigensolver_tree_shapes(msq, prec, n):
     # the batch is diagonalised as one block-diagonal tridiagonal matrix:
-    # sizes with a single leaf (1, 2, 33 -> 16 + 17), with a leaf carried
-    # through a level (65 -> 32 | 33) and with uneven halves (100)
+    # sizes with a single leaf (1, 2), one merge (33 -> 16 + 17; 34 also ends
+    # the reduction with a one-column panel), a leaf carried through a level
+    # (65 -> 32 | 33) and uneven halves (100)
     import torch
     b = 3
     mats, truths = [], []

@@ -21,7 +21,7 @@ def _tri(d, e):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [2, 5, 64, 65, 129, 130, 200, 300, 1000])
+@pytest.mark.parametrize("n", [2, 5, 33, 34, 64, 65, 97, 129, 130, 200, 300, 1000, 2000])
 def test_sytrd_preserves_spectrum(msq, n, prec):
     a, _, lam = W.spd(n, 1e4, 500 + n)
     d, e, tau = msq.test_sytrd(a, prec)
