@@ -169,7 +169,7 @@ def run_general(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "spd":
