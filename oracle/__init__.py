@@ -61,6 +61,12 @@ def lib():
         _lib.orc_rtrsyl_z.argtypes = [i, i, dp, dp, dp, i]
         _lib.orc_rtrsyl_c.argtypes = [i, i, fp, fp, fp, i]
         _lib.orc_adjoint_z.argtypes = [i, dp, dp, dp]
+        _lib.orc_set_threads.argtypes = [i]
+        _lib.orc_set_threads.restype = None
+        _lib.orc_get_threads.argtypes = []
+        _lib.orc_get_threads.restype = i
+        _lib.orc_set_deferred.argtypes = [i]
+        _lib.orc_set_deferred.restype = None
         for f in ("orc_schur_z", "orc_schur_c", "orc_trsqrt_z", "orc_trsqrt_c", "orc_sqrtm_z",
                   "orc_syev_d", "orc_syev_s", "orc_adjoint_z"):
             getattr(_lib, f).restype = ctypes.c_int
@@ -71,6 +77,31 @@ def lib():
 
 class OracleError(RuntimeError):
     pass
+
+
+class execution:
+    """Context manager selecting how the C++ routines run: `threads` OpenMP
+    threads (None keeps the current count) and `deferred` (True: the QR
+    rotations outside the active block and on Q are logged and applied later
+    in parallel; False: applied at once, the plain serial order).  Every
+    setting computes the same floating-point operations per entry, so the
+    results are bitwise identical (pinned by a test)."""
+
+    def __init__(self, threads=None, deferred=True):
+        self.threads = threads
+        self.deferred = deferred
+
+    def __enter__(self):
+        self._old = lib().orc_get_threads()
+        if self.threads:
+            lib().orc_set_threads(int(self.threads))
+        lib().orc_set_deferred(1 if self.deferred else 0)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_threads(self._old)
+        lib().orc_set_deferred(1)
+        return False
 
 
 def _f(a, dtype):
@@ -289,13 +320,23 @@ def _stop_rule(hist):
     return None
 
 
-def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32):
+def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
+                  factor=None, x0=None, iterates=False):
     """Alg. 3 (SPD, structure='spd') or Alg. 2 (structure='general') with the
     low precision emulated by this module's single-precision factorisation and
     float32 arithmetic for the transforms, float64 for residual and update.
 
-    Returns dict(X, steps, hist, status).  steps counts applied corrections;
-    hist holds ||R_k||_F / ||A||_F for every residual evaluated.
+    factor: optional SPD factor {"Q": q, "s": s} used instead of the
+      emulator's own factorisation (the frozen Z = Q diag(s) Q^T of the
+      convergence theorem); it belongs to A itself (no scaling), and low
+      ("fp32" or "fp64") is the arithmetic of its transforms.
+    x0: optional start (float64) instead of X_0 = Q diag(s) Q^T; only with
+      `factor`.
+    iterates: also return the list of iterates X_0, X_1, ... (unscaled).
+
+    Returns dict(X, steps, hist, status[, iterates]).  steps counts applied
+    corrections; hist holds ||R_k||_F / ||A||_F for every residual evaluated.
+    On a failure X is the iterate with the smallest residual.
     """
     a = np.asarray(a)
     n = a.shape[0]
@@ -304,31 +345,40 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32)
         structure = "spd" if (is_real and np.array_equal(a, a.T)) else "general"
     if not np.all(np.isfinite(a)):
         return {"X": None, "steps": 0, "hist": [], "status": ST_NONFINITE}
-    k = scale_exponent(a)
+    if x0 is not None and factor is None:
+        raise ValueError("x0 needs an explicit factor")
+    lowt = np.float32 if low == "fp32" else np.float64
+    k = 0 if factor is not None else scale_exponent(a)
     asc = a / (4.0 ** k)
     na = np.linalg.norm(asc)
     if structure == "spd":
-        lam, q = syev(asc.astype(np.float32), single=True)
-        if np.any(lam <= 0):
-            return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
-        s = np.sqrt(lam).astype(np.float32)
-        x = ((q * s[None, :]) @ q.T).astype(np.float64)
-        denom = (s[:, None] + s[None, :]).astype(np.float32)
+        if factor is not None:
+            q = np.asarray(factor["Q"], dtype=lowt)
+            s = np.asarray(factor["s"], dtype=lowt)
+        else:
+            lam, q = syev(asc.astype(np.float32), single=True)
+            if np.any(lam <= 0):
+                return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
+            s = np.sqrt(lam).astype(np.float32)
+        x = ((q * s[None, :]) @ q.T).astype(np.float64) if x0 is None else np.array(x0, np.float64)
+        denom = (s[:, None] + s[None, :]).astype(lowt)
 
         def correction(r):
-            rl = r.astype(np.float32)
+            rl = r.astype(lowt)
             rt = q.T @ rl @ q
             y = rt / denom
             return (q @ y @ q.T).astype(np.float64)
     else:
+        if factor is not None:
+            raise ValueError("an explicit factor is supported for the SPD route only")
         t, q = schur(asc.astype(np.complex64), single=True)
         d = np.diag(t)
         if np.any((d.imag == 0) & (d.real <= 0)):
             return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
         s = trsqrt(t, single=True)
         qh = q.conj().T
-        x0 = (q @ s @ qh).astype(np.complex128)
-        x = x0.real.copy() if is_real else x0
+        x0c = (q @ s @ qh).astype(np.complex128)
+        x = x0c.real.copy() if is_real else x0c
 
         def correction(r):
             rl = r.astype(np.complex64)
@@ -338,26 +388,32 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32)
             return dx.real if is_real else dx
 
     hist = []
+    seq = []
     best = (np.inf, x)
     status = ST_NOT_CONVERGED
     steps = 0
-    for it in range(maxit + 1):
-        r = asc - x @ x
-        rr = float(np.linalg.norm(r) / na)
-        hist.append(rr)
-        if rr < best[0]:
-            best = (rr, x)
-        if rr <= tol:
-            status = ST_OK
-            break
-        verdict = _stop_rule(hist)
-        if verdict is not None:
-            status = verdict
-            break
-        if it == maxit:
-            break
-        x = x + correction(r)
-        steps += 1
+    with np.errstate(over="ignore", invalid="ignore"):
+        for it in range(maxit + 1):
+            if iterates:
+                seq.append(x * (2.0 ** k))
+            r = asc - x @ x
+            rr = float(np.linalg.norm(r) / na)
+            hist.append(rr)
+            if rr < best[0]:
+                best = (rr, x)
+            if rr <= tol:
+                status = ST_OK
+                break
+            verdict = _stop_rule(hist)
+            if verdict is not None:
+                status = verdict
+                break
+            if it == maxit:
+                break
+            x = x + correction(r)
+            steps += 1
     xout = (x if status == ST_OK else best[1]) * (2.0 ** k)
-    return {"X": xout, "steps": steps if status == ST_OK else steps, "hist": hist,
-            "status": status}
+    out = {"X": xout, "steps": steps, "hist": hist, "status": status}
+    if iterates:
+        out["iterates"] = seq
+    return out

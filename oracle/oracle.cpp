@@ -23,6 +23,10 @@
 //
 // All routines are templated on the real type so that the mixed-precision
 // emulator can run the *same* textbook factorisation in single precision.
+// Loops over independent entries run on OpenMP threads, and the QR sweeps
+// apply their rotations lazily where the chase does not read them (see
+// g_deferred); neither changes any entry's arithmetic, so every result is
+// bitwise that of the plain serial loops, which stay selectable.
 // Matrices are column-major: element (i,j) of an n-by-n matrix is a[i + j*n].
 
 #include <algorithm>
@@ -33,9 +37,26 @@
 #include <limits>
 #include <vector>
 
+#include <omp.h>
+
 namespace orc {
 
 template <class R> using C = std::complex<R>;
+
+// Execution mode.  Every loop that OpenMP splits below runs over independent
+// elements (rows, columns or entries of one superdiagonal), and each element
+// receives exactly the same floating-point operations in the same order as in
+// a serial run, so the results do not depend on the thread count.  With
+// g_deferred set, the plane rotations of the QR iterations are applied at
+// once only to the entries that the iteration itself reads; the others (the
+// rows of Q, and the parts of H outside the active block) are logged and
+// applied later, in log order, row block by row block.  Each entry still sees
+// the same rotations in the same order, so the result is bitwise that of the
+// immediate application (g_deferred = 0), which is kept for that comparison.
+static int g_deferred = 1;
+
+// Rows (or columns) per OpenMP work item in the blocked loops.
+constexpr int kChunk = 32;
 
 // ---------------------------------------------------------------------------
 // Principal complex square root by the half-angle formula.  For z = x + i y
@@ -76,14 +97,16 @@ bool householder(int len, const C<R>* x, C<R>* u, R* unorm2) {
 // Hessenberg reduction A <- P^H A P with Q accumulating the reflectors, so
 // that on exit A_in = Q H Q^H.
 template <class R> void hessenberg(int n, C<R>* a, C<R>* q) {
-  std::vector<C<R>> u(n), x(n);
+  std::vector<C<R>> u(n), x(n), r(n);
   for (int k = 0; k + 2 < n; ++k) {
     int len = n - k - 1;
     for (int i = 0; i < len; ++i) x[i] = a[(k + 1 + i) + (size_t)k * n];
     R un2;
     if (!householder<R>(len, x.data(), u.data(), &un2)) continue;
     R f = R(2) / un2;
-    // Left: rows k+1..n-1, all columns.  A <- (I - f u u^H) A
+    // Left: rows k+1..n-1, all columns.  A <- (I - f u u^H) A (columns are
+    // independent).
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < n; ++j) {
       C<R> s = 0;
       for (int i = 0; i < len; ++i) s += std::conj(u[i]) * a[(k + 1 + i) + (size_t)j * n];
@@ -91,11 +114,17 @@ template <class R> void hessenberg(int n, C<R>* a, C<R>* q) {
       for (int i = 0; i < len; ++i) a[(k + 1 + i) + (size_t)j * n] -= u[i] * s;
     }
     // Right: columns k+1..n-1, all rows.  A <- A (I - f u u^H), and the
-    // same for Q.  r = M u is formed column by column, then M -= f r u^H.
+    // same for Q.  r = M u is formed column by column (rows independent),
+    // then M -= f r u^H (columns independent).
     for (C<R>* m : {a, q}) {
-      std::vector<C<R>> r(n, C<R>(0, 0));
-      for (int jj = 0; jj < len; ++jj)
-        for (int i = 0; i < n; ++i) r[i] += m[i + (size_t)(k + 1 + jj) * n] * u[jj];
+#pragma omp parallel for schedule(static)
+      for (int i0 = 0; i0 < n; i0 += kChunk) {
+        const int i1 = std::min(n, i0 + kChunk);
+        for (int i = i0; i < i1; ++i) r[i] = C<R>(0, 0);
+        for (int jj = 0; jj < len; ++jj)
+          for (int i = i0; i < i1; ++i) r[i] += m[i + (size_t)(k + 1 + jj) * n] * u[jj];
+      }
+#pragma omp parallel for schedule(static)
       for (int jj = 0; jj < len; ++jj) {
         C<R> cu = f * std::conj(u[jj]);
         for (int i = 0; i < n; ++i) m[i + (size_t)(k + 1 + jj) * n] -= r[i] * cu;
@@ -116,24 +145,57 @@ template <class R> void givens(C<R> a, C<R> b, R* c, C<R>* s) {
 }
 
 // Similarity with G acting on indices (p, p+1): H <- G H G^H restricted to the
-// columns/rows that can be non-zero, Q <- Q G^H.
+// columns/rows that can be non-zero, Q <- Q G^H.  The three parts: rows p, p+1
+// of H for columns j0..j1-1; columns p, p+1 of H for rows i0..i1-1; columns p,
+// p+1 of Q for all rows.
 template <class R>
-void apply_rot(int n, C<R>* h, C<R>* q, int p, R c, C<R> s, int col_lo, int row_hi) {
-  for (int j = col_lo; j < n; ++j) {
+inline void rot_rows(int n, C<R>* h, int p, R c, C<R> s, int j0, int j1) {
+  for (int j = j0; j < j1; ++j) {
     C<R> x = h[p + (size_t)j * n], y = h[p + 1 + (size_t)j * n];
     h[p + (size_t)j * n] = c * x + s * y;
     h[p + 1 + (size_t)j * n] = -std::conj(s) * x + c * y;
   }
-  for (int i = 0; i <= row_hi; ++i) {
-    C<R> x = h[i + (size_t)p * n], y = h[i + (size_t)(p + 1) * n];
-    h[i + (size_t)p * n] = x * c + y * std::conj(s);
-    h[i + (size_t)(p + 1) * n] = -x * s + y * c;
+}
+template <class R>
+inline void rot_cols(int n, C<R>* m, int p, R c, C<R> s, int i0, int i1) {
+  for (int i = i0; i < i1; ++i) {
+    C<R> x = m[i + (size_t)p * n], y = m[i + (size_t)(p + 1) * n];
+    m[i + (size_t)p * n] = x * c + y * std::conj(s);
+    m[i + (size_t)(p + 1) * n] = -x * s + y * c;
   }
-  for (int i = 0; i < n; ++i) {
-    C<R> x = q[i + (size_t)p * n], y = q[i + (size_t)(p + 1) * n];
-    q[i + (size_t)p * n] = x * c + y * std::conj(s);
-    q[i + (size_t)(p + 1) * n] = -x * s + y * c;
+}
+
+// One logged rotation of a QR sweep on the active block [lo, hi].
+template <class R> struct RotLog {
+  int p, lo, hi;
+  R c;
+  C<R> s;
+};
+
+// Applies the logged rotations, in log order, to the entries the sweep left
+// out: rows p, p+1 of H right of the active block (columns > hi), columns p,
+// p+1 of H above it (rows < lo) and columns p, p+1 of Q (all rows).  Entries
+// are independent, so row (column) blocks run in parallel.
+template <class R>
+void flush_rotations(int n, C<R>* h, C<R>* q, std::vector<RotLog<R>>& log) {
+  if (log.empty()) return;
+  const int nl = (int)log.size();
+  const int nb = (n + kChunk - 1) / kChunk;
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < 3 * nb; ++b) {
+    const int part = b / nb;
+    const int x0 = (b % nb) * kChunk, x1 = std::min(n, x0 + kChunk);
+    if (part == 0) {  // rows x0..x1-1 of Q
+      for (int t = 0; t < nl; ++t) rot_cols<R>(n, q, log[t].p, log[t].c, log[t].s, x0, x1);
+    } else if (part == 1) {  // rows x0..x1-1 of H above the active block
+      for (int t = 0; t < nl; ++t)
+        rot_cols<R>(n, h, log[t].p, log[t].c, log[t].s, x0, std::min(x1, log[t].lo));
+    } else {  // columns x0..x1-1 of H right of the active block
+      for (int t = 0; t < nl; ++t)
+        rot_rows<R>(n, h, log[t].p, log[t].c, log[t].s, std::max(x0, log[t].hi + 1), x1);
+    }
   }
+  log.clear();
 }
 
 // Complex Schur decomposition.  On entry a holds A; on exit a holds the upper
@@ -146,7 +208,12 @@ template <class R> int schur(int n, C<R>* a, C<R>* q) {
   hessenberg<R>(n, a, q);
   const R eps = std::numeric_limits<R>::epsilon() / 2;
   auto H = [&](int i, int j) -> C<R>& { return a[i + (size_t)j * n]; };
-  int hi = n - 1, iter = 0, total = 0;
+  std::vector<RotLog<R>> log;
+  const size_t log_cap = (size_t)1 << 20;
+  std::vector<R> rc(n);
+  std::vector<C<R>> rs(n);
+  std::vector<int> next_row(n);
+  int hi = n - 1, iter = 0, total = 0, st = 0;
   while (hi > 0) {
     // Find the start of the active unreduced block by scanning for negligible
     // subdiagonal entries.
@@ -158,7 +225,7 @@ template <class R> int schur(int n, C<R>* a, C<R>* q) {
       --lo;
     }
     if (lo == hi) { --hi; iter = 0; continue; }
-    if (++total > 30 * n) return 1;
+    if (++total > 30 * n) { st = 1; break; }
     ++iter;
     // Wilkinson shift: eigenvalue of the trailing 2x2 block closest to H(hi,hi).
     C<R> mu;
@@ -172,18 +239,80 @@ template <class R> int schur(int n, C<R>* a, C<R>* q) {
       C<R> l1 = tr / R(2) + disc, l2 = tr / R(2) - disc;
       mu = (std::abs(l1 - a22) < std::abs(l2 - a22)) ? l1 : l2;
     }
-    // Implicit single-shift sweep over the active block [lo, hi].
+    // Implicit single-shift sweep over the active block [lo, hi]: each
+    // rotation acts on rows k, k+1 from column col_lo on and on columns k, k+1
+    // down to row row_hi (the only entries that can be non-zero), and on Q.
     C<R> x = H(lo, lo) - mu, y = H(lo + 1, lo);
-    for (int k = lo; k < hi; ++k) {
-      R c; C<R> s;
-      givens<R>(x, y, &c, &s);
-      int col_lo = (k > lo) ? k - 1 : lo;
-      int row_hi = std::min(k + 2, hi);
-      apply_rot<R>(n, a, q, k, c, s, col_lo, row_hi);
-      if (k > lo) H(k + 1, k - 1) = 0;
-      if (k + 1 < hi) { x = H(k + 1, k); y = H(k + 2, k); }
+    if (!g_deferred) {
+      for (int k = lo; k < hi; ++k) {
+        R c; C<R> s;
+        givens<R>(x, y, &c, &s);
+        int col_lo = (k > lo) ? k - 1 : lo;
+        int row_hi = std::min(k + 2, hi);
+        rot_rows<R>(n, a, k, c, s, col_lo, n);
+        rot_cols<R>(n, a, k, c, s, 0, row_hi + 1);
+        rot_cols<R>(n, q, k, c, s, 0, n);
+        if (k > lo) H(k + 1, k - 1) = 0;
+        if (k + 1 < hi) { x = H(k + 1, k); y = H(k + 2, k); }
+      }
+    } else {
+      // The same sweep, with every rotation applied at once only where the
+      // chase reads it next, and the rest later in an order that gives every
+      // entry the same operations in the same sequence:
+      //  * rows: column j of the block receives row rotations lo..j+1; it is
+      //    brought up to date (in rotation order, down the column) just before
+      //    a column rotation or the chase reads it, and every kLook rotations
+      //    all columns right of the bulge are brought up to date in parallel;
+      //  * columns: rotation k is applied at once to rows k-1..k+2; rows
+      //    lo..k-2 (all of whose row rotations come earlier) are rotated after
+      //    the sweep, row blocks in parallel;
+      //  * entries above the block (rows < lo), right of it (columns > hi) and
+      //    all of Q go to the log.  Within one log lo is fixed, so those two
+      //    parts never share an entry; an entry above an earlier block can lie
+      //    right of a later one, so the log is applied before lo changes.
+      if (!log.empty() && log.back().lo != lo) flush_rotations<R>(n, a, q, log);
+      for (int j = lo; j <= hi; ++j) next_row[j] = lo;
+      auto catch_up = [&](int j, int kmax) {
+        const int kend = std::min(kmax, j + 1);
+        for (int k = next_row[j]; k <= kend; ++k) {
+          C<R> u = H(k, j), v = H(k + 1, j);
+          H(k, j) = rc[k] * u + rs[k] * v;
+          H(k + 1, j) = -std::conj(rs[k]) * u + rc[k] * v;
+        }
+        if (kend + 1 > next_row[j]) next_row[j] = kend + 1;
+      };
+      constexpr int kLook = 64;
+      for (int k = lo; k < hi; ++k) {
+        R c; C<R> s;
+        givens<R>(x, y, &c, &s);
+        rc[k] = c;
+        rs[k] = s;
+        if (k > lo) catch_up(k - 1, k);
+        catch_up(k, k);
+        catch_up(k + 1, k);
+        rot_cols<R>(n, a, k, c, s, std::max(lo, k - 1), std::min(k + 2, hi) + 1);
+        log.push_back({k, lo, hi, c, s});
+        if (k > lo) H(k + 1, k - 1) = 0;
+        if (k + 1 < hi) { x = H(k + 1, k); y = H(k + 2, k); }
+        if ((k - lo) % kLook == kLook - 1) {
+#pragma omp parallel for schedule(static)
+          for (int j = k + 2; j <= hi; ++j) catch_up(j, k);
+        }
+      }
+#pragma omp parallel for schedule(static)
+      for (int j = lo; j <= hi; ++j) catch_up(j, hi - 1);
+      const int nb = (hi - lo + 1 + kChunk - 1) / kChunk;
+#pragma omp parallel for schedule(dynamic)
+      for (int b = 0; b < nb; ++b) {
+        const int i0 = lo + b * kChunk, i1 = std::min(hi + 1, i0 + kChunk);
+        for (int k = std::max(lo, i0 + 2); k < hi; ++k)
+          rot_cols<R>(n, a, k, rc[k], rs[k], i0, std::min(i1, k - 1));
+      }
     }
+    if (log.size() >= log_cap) flush_rotations<R>(n, a, q, log);
   }
+  flush_rotations<R>(n, a, q, log);
+  if (st) return st;
   for (int j = 0; j < n; ++j)
     for (int i = j + 1; i < n; ++i) a[i + (size_t)j * n] = 0;
   return 0;
@@ -200,19 +329,30 @@ template <class R> int trsqrt(int n, const C<R>* t, C<R>* s) {
     if (d.imag() == R(0) && d.real() <= R(0)) return 2;
     s[i + (size_t)i * n] = csqrt_principal<R>(d);
   }
-  for (int j = 1; j < n; ++j) {
-    for (int i = j - 1; i >= 0; --i) {
-      C<R> acc = t[i + (size_t)j * n];
-      for (int k = i + 1; k <= j - 1; ++k) acc -= s[i + (size_t)k * n] * s[k + (size_t)j * n];
-      s[i + (size_t)j * n] = acc / (s[i + (size_t)i * n] + s[j + (size_t)j * n]);
-    }
+  auto entry = [&](int i, int j) {
+    C<R> acc = t[i + (size_t)j * n];
+    for (int k = i + 1; k <= j - 1; ++k) acc -= s[i + (size_t)k * n] * s[k + (size_t)j * n];
+    s[i + (size_t)j * n] = acc / (s[i + (size_t)i * n] + s[j + (size_t)j * n]);
+  };
+  if (!g_deferred) {
+    for (int j = 1; j < n; ++j)
+      for (int i = j - 1; i >= 0; --i) entry(i, j);
+    return 0;
+  }
+  // s_ij reads only entries of lower superdiagonals (s_ik and s_kj with
+  // i < k < j), so the entries of one superdiagonal are independent.
+  for (int d = 1; d < n; ++d) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n - d; ++i) entry(i, i + d);
   }
   return 0;
 }
 
 // C = A * B (n x n, complex), plain triple loop.
+// Columns of C are independent.
 template <class R> void cgemm(int n, const C<R>* a, const C<R>* b, C<R>* c) {
   for (size_t k = 0; k < (size_t)n * n; ++k) c[k] = 0;
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < n; ++j)
     for (int k = 0; k < n; ++k) {
       C<R> bkj = b[k + (size_t)j * n];
@@ -339,14 +479,19 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
     // Two-sided update of the trailing block B = A(k+1:, k+1:) and of the
     // column/row k: A <- P A P with P = I - f u u^T.
     // p = f B u ; K = f/2 u^T p ; w = p - K u ; B <- B - u w^T - w u^T.
-    for (int i = 0; i < len; ++i) p[i] = 0;
-    for (int j = 0; j < len; ++j)
-      for (int i = 0; i < len; ++i) p[i] += A(k + 1 + i, k + 1 + j) * u[j];
+#pragma omp parallel for schedule(static)
+    for (int i0 = 0; i0 < len; i0 += kChunk) {  // rows independent
+      const int i1 = std::min(len, i0 + kChunk);
+      for (int i = i0; i < i1; ++i) p[i] = 0;
+      for (int j = 0; j < len; ++j)
+        for (int i = i0; i < i1; ++i) p[i] += A(k + 1 + i, k + 1 + j) * u[j];
+    }
     for (int i = 0; i < len; ++i) p[i] *= f;
     R K = 0;
     for (int i = 0; i < len; ++i) K += u[i] * p[i];
     K *= f / R(2);
     for (int i = 0; i < len; ++i) w[i] = p[i] - K * u[i];
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < len; ++j)
       for (int i = 0; i < len; ++i) A(k + 1 + i, k + 1 + j) -= u[i] * w[j] + w[i] * u[j];
     R newv = (x0 >= R(0) ? -nx : nx);
@@ -355,8 +500,13 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
     for (int i = 1; i < len; ++i) { A(k + 1 + i, k) = 0; A(k, k + 1 + i) = 0; }
     // Q <- Q P:  r = Q u, then Q -= f r u^T.
     std::vector<R> r(n, R(0));
-    for (int j = 0; j < len; ++j)
-      for (int i = 0; i < n; ++i) r[i] += q[i + (size_t)(k + 1 + j) * n] * u[j];
+#pragma omp parallel for schedule(static)
+    for (int i0 = 0; i0 < n; i0 += kChunk) {  // rows independent
+      const int i1 = std::min(n, i0 + kChunk);
+      for (int j = 0; j < len; ++j)
+        for (int i = i0; i < i1; ++i) r[i] += q[i + (size_t)(k + 1 + j) * n] * u[j];
+    }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < len; ++j)
       for (int i = 0; i < n; ++i) q[i + (size_t)(k + 1 + j) * n] -= f * r[i] * u[j];
   }
@@ -364,6 +514,27 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
   for (int i = 0; i < n; ++i) d[i] = A(i, i);
   for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
   const R eps = std::numeric_limits<R>::epsilon() / 2;
+  // The rotations touch d, e and two columns of Q.  Rows of Q are
+  // independent, so the rotations can be logged and applied later, in order,
+  // to blocks of rows in parallel (same operations per entry).
+  struct QRot { int k; R c, s; };
+  std::vector<QRot> qlog;
+  auto rotate_q = [&](int k, R c, R s, int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      R qa = q[i + (size_t)k * n], qb = q[i + (size_t)(k + 1) * n];
+      q[i + (size_t)k * n] = c * qa + s * qb;
+      q[i + (size_t)(k + 1) * n] = -s * qa + c * qb;
+    }
+  };
+  auto flush_q = [&]() {
+    const int nl = (int)qlog.size();
+#pragma omp parallel for schedule(static)
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      const int i1 = std::min(n, i0 + 16);
+      for (int t = 0; t < nl; ++t) rotate_q(qlog[t].k, qlog[t].c, qlog[t].s, i0, i1);
+    }
+    qlog.clear();
+  };
   int hi = n - 1, total = 0;
   while (hi > 0) {
     int lo = hi;
@@ -375,7 +546,7 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
       --lo;
     }
     if (lo == hi) { --hi; continue; }
-    if (++total > 30 * n) return 1;
+    if (++total > 30 * n) { flush_q(); return 1; }
     // Wilkinson shift from the trailing 2x2 block.
     R dd = (d[hi - 1] - d[hi]) / R(2);
     R b2 = e[hi - 1] * e[hi - 1];
@@ -398,13 +569,15 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
         z = s * e[k + 1];
         e[k + 1] = c * e[k + 1];
       }
-      for (int i = 0; i < n; ++i) {
-        R qa = q[i + (size_t)k * n], qb = q[i + (size_t)(k + 1) * n];
-        q[i + (size_t)k * n] = c * qa + s * qb;
-        q[i + (size_t)(k + 1) * n] = -s * qa + c * qb;
+      if (g_deferred) {
+        qlog.push_back({k, c, s});
+      } else {
+        rotate_q(k, c, s, 0, n);
       }
     }
+    if (qlog.size() >= ((size_t)1 << 20)) flush_q();
   }
+  flush_q();
   // Sort ascending (selection sort keeps it obviously correct).
   for (int i = 0; i < n; ++i) {
     int m = i;
@@ -424,6 +597,14 @@ template <class R> int syev(int n, const R* ain, R* lam, R* q) {
 using orc::C;
 
 extern "C" {
+
+// Number of OpenMP threads (0 keeps the runtime's default) and the rotation
+// mode (1: deferred, parallel; 0: immediate, serial order); see g_deferred.
+void orc_set_threads(int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+}
+int orc_get_threads(void) { return omp_get_max_threads(); }
+void orc_set_deferred(int on) { orc::g_deferred = on ? 1 : 0; }
 
 // Status codes shared by the oracle entry points.
 enum { ORC_OK = 0, ORC_NOCONV = 1, ORC_NO_PRINCIPAL = 2 };
