@@ -71,7 +71,10 @@ typedef enum {
 
 /* AUTO tests for exact symmetry (Hermitian symmetry for complex input) and then
  * uses Alg. 3; a non-positive low-precision eigenvalue escalates the
- * precision and, if FP64 also sees one, falls back to the general path. */
+ * precision and, if FP64 also sees one, falls back to the general path.  The
+ * symmetric route's tridiagonal reduction handles n <= 4225: a larger
+ * symmetric single input takes the general path under AUTO, and HPD (or a
+ * batch) beyond that size returns MSQRT_ERR_UNSUPPORTED. */
 typedef enum { MSQRT_STRUCT_AUTO = 0, MSQRT_STRUCT_GENERAL = 1, MSQRT_STRUCT_HPD = 2 } msqrt_struct;
 
 typedef struct {
@@ -130,7 +133,11 @@ msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n
  * first overwritten by X_0 = Q S Q^*; otherwise the caller's X is the start
  * (it may be the root of a nearby matrix).  Never escalates the precision.
  * dA/dX layout as above; A must be the matrix the factor was built from or a
- * nearby one of the same size and structure. */
+ * nearby one of the same size and structure.  With an HPD factor, A and a
+ * caller-supplied X must be exactly symmetric (the residual is formed as
+ * A - X X^T from one triangle): otherwise MSQRT_ERR_INVALID_ARG, with X
+ * untouched.  Inf or NaN in A (or in the caller-supplied X of an HPD
+ * factor): MSQRT_ERR_NONFINITE. */
 msqrt_status msqrt_refine(msqrt_factor_t f, const void* dA, int64_t lda, int64_t strideA,
                           void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
                           double tol, hipStream_t stream, msqrt_info* info);

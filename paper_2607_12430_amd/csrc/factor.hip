@@ -133,6 +133,16 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
     set_last_error("structure HPD requested but the input is not exactly symmetric");
     return MSQRT_ERR_INVALID_ARG;
   }
+  if (sc == MSQRT_STRUCT_HPD && f->n > sytrd_max_n()) {
+    // Beyond the tridiagonal reduction's size limit a symmetric input takes
+    // the general path when the caller left the structure open.
+    if (o.structure != MSQRT_STRUCT_AUTO || f->batch != 1) {
+      set_last_error("the symmetric route supports n <= " + std::to_string(sytrd_max_n()) +
+                     " (larger single inputs run on the general path with structure AUTO)");
+      return MSQRT_ERR_UNSUPPORTED;
+    }
+    sc = MSQRT_STRUCT_GENERAL;
+  }
   f->structure = sc;
   // BF16SPLIT keeps the float factorisation; only the refinement's
   // Schur-basis products differ

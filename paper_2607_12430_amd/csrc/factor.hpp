@@ -1,6 +1,7 @@
 // Factor object and the host-side pieces shared between the runtime files.
 #pragma once
 
+#include <cmath>
 #include <vector>
 
 #include "../../include/msqrt.h"
@@ -145,11 +146,33 @@ struct PhaseTimer {
   }
 };
 
+// Convergence bookkeeping of every refinement loop: the stopping rule of
+// Alg. 2 (relative residual <= tol) and the reading of the paper's remark
+// that the iteration diverges for too ill-conditioned inputs (Sec. 5.1):
+// diverged when the residual is not finite, exceeds 10x the first one or grew
+// on two consecutive sweeps; stagnated when it failed to drop below 0.9x the
+// previous one on two consecutive sweeps.  h holds every residual so far.
+enum class Verdict { Continue, Converged, Diverged, Stagnated };
+
+inline Verdict judge(const std::vector<double>& h, double tol) {
+  const double r = h.back();
+  if (!std::isfinite(r)) return Verdict::Diverged;
+  if (r <= tol) return Verdict::Converged;
+  if (r > 10.0 * h.front()) return Verdict::Diverged;
+  const size_t k = h.size();
+  if (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) return Verdict::Diverged;
+  if (k >= 3 && h[k - 1] > 0.9 * h[k - 2] && h[k - 2] > 0.9 * h[k - 3]) return Verdict::Stagnated;
+  return Verdict::Continue;
+}
+
 // Validates A (finiteness, optional exact symmetry), computes ||A_b||_F and
 // the scale exponents into f.  Returns the OR of the per-entry flags
 // (bit0 non-finite, bit1 not symmetric).
 int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
                   hipStream_t st);
+// Finiteness (bit0) and exact symmetry failures (bit1) of a batch of n x n
+// matrices with the factor's n and batch; the factor's scales are untouched.
+int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st);
 
 // Factorisation of the scaled input into f (Q, S, structure, prec).
 msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,

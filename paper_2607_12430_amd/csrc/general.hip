@@ -154,21 +154,6 @@ __global__ __launch_bounds__(256) void x_out_kernel(int n, const double* Xw, int
 
 inline unsigned blocks_for(int64_t cnt) { return (unsigned)std::max<int64_t>(1, ceil_div(cnt, 256)); }
 
-enum class Verdict2 { Continue, Converged, Diverged, Stagnated };
-
-// Stopping rule of Alg. 2 with the divergence / stagnation reading used by
-// the HPD loop (kept in one place for both loops of this file).
-Verdict2 judge2(const std::vector<double>& h, double tol) {
-  const double r = h.back();
-  if (!std::isfinite(r)) return Verdict2::Diverged;
-  if (r <= tol) return Verdict2::Converged;
-  if (r > 10.0 * h.front()) return Verdict2::Diverged;
-  const size_t k = h.size();
-  if (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) return Verdict2::Diverged;
-  if (k >= 3 && h[k - 1] > 0.9 * h[k - 2] && h[k - 2] > 0.9 * h[k - 3]) return Verdict2::Stagnated;
-  return Verdict2::Continue;
-}
-
 template <typename T>
 void gstore_b(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda, int64_t sA,
               const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC,
@@ -341,7 +326,7 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
   std::vector<double> hist, hp(2 * ntiles);
   double best_r = INFINITY;
   double* best = nullptr;
-  Verdict2 verdict = Verdict2::Continue;
+  Verdict verdict = Verdict::Continue;
   int steps = 0;
   for (int it = 0;; ++it) {
     tm.begin(MSQRT_T_RESIDUAL);
@@ -361,9 +346,9 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
     MSQRT_HIP(hipStreamSynchronize(st));
     tm.collect();
     hist.push_back(hrn / f->anorm_scaled[0]);
-    Verdict2 v = judge2(hist, tol);
-    if (v == Verdict2::Continue && it >= maxit) v = Verdict2::Stagnated;
-    if (v != Verdict2::Continue) {
+    Verdict v = judge(hist, tol);
+    if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+    if (v != Verdict::Continue) {
       verdict = v;
       break;
     }
@@ -377,13 +362,13 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
   }
   msqrt_status status = MSQRT_OK;
   double final_r = hist.back();
-  if (verdict != Verdict2::Converged) {
-    if (best && best_r < final_r) {
+  if (verdict != Verdict::Converged) {
+    if (best && !(final_r <= best_r)) {  // also when final_r is NaN
       MSQRT_HIP(hipMemcpyAsync(Xw, best, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
       final_r = best_r;
     }
-    status = verdict == Verdict2::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
-    set_last_error(verdict == Verdict2::Diverged ? "refinement diverged"
+    status = verdict == Verdict::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
+    set_last_error(verdict == Verdict::Diverged ? "refinement diverged"
                                                  : "refinement did not converge");
   }
   // X = 2^k X_s in the caller's layout
@@ -474,7 +459,7 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
   }
   const double gnorm = std::sqrt(sum_host(hp, 0, kRedBlocks));
   std::vector<double> hist;
-  Verdict2 verdict = Verdict2::Continue;
+  Verdict verdict = Verdict::Continue;
   int steps = 0;
   for (int it = 0;; ++it) {
     tm.begin(MSQRT_T_RESIDUAL);
@@ -482,7 +467,7 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
       // G~ = 0: the residual is Gbar^* itself
       hist.push_back(gnorm > 0.0 ? 1.0 : 0.0);
       if (gnorm == 0.0) {
-        verdict = Verdict2::Converged;
+        verdict = Verdict::Converged;
         MSQRT_HIP(hipMemsetAsync(Gw, 0, sizeof(double) * 2 * nn, st));
         break;
       }
@@ -513,9 +498,9 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
       MSQRT_HIP(hipStreamSynchronize(st));
       tm.collect();
       hist.push_back(hrn / gnorm);
-      Verdict2 v = judge2(hist, tol);
-      if (v == Verdict2::Continue && it >= maxit) v = Verdict2::Stagnated;
-      if (v != Verdict2::Continue) {
+      Verdict v = judge(hist, tol);
+      if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+      if (v != Verdict::Continue) {
         verdict = v;
         break;
       }
@@ -534,8 +519,8 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
   tm.collect();
   if (timed_out) throw Error{MSQRT_ERR_DEVICE, "triangular Sylvester solve: dataflow wait timed out"};
   msqrt_status status = MSQRT_OK;
-  if (verdict == Verdict2::Diverged) status = MSQRT_ERR_DIVERGED;
-  else if (verdict != Verdict2::Converged) status = MSQRT_ERR_NOT_CONVERGED;
+  if (verdict == Verdict::Diverged) status = MSQRT_ERR_DIVERGED;
+  else if (verdict != Verdict::Converged) status = MSQRT_ERR_NOT_CONVERGED;
   if (info) {
     info->steps = steps;
     info->relres = hist.back();

@@ -66,24 +66,6 @@ void pool_free(void* p, size_t bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// Convergence bookkeeping (stopping rule of Alg. 2 plus the divergence /
-// stagnation reading of the paper's remark that the iteration diverges for
-// too ill-conditioned inputs).
-
-enum class Verdict { Continue, Converged, Diverged, Stagnated };
-
-static Verdict judge(const std::vector<double>& h, double tol) {
-  const double r = h.back();
-  if (!std::isfinite(r)) return Verdict::Diverged;
-  if (r <= tol) return Verdict::Converged;
-  if (r > 10.0 * h.front()) return Verdict::Diverged;
-  const size_t k = h.size();
-  if (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) return Verdict::Diverged;
-  if (k >= 3 && h[k - 1] > 0.9 * h[k - 2] && h[k - 2] > 0.9 * h[k - 3]) return Verdict::Stagnated;
-  return Verdict::Continue;
-}
-
-// ---------------------------------------------------------------------------
 // Refinement for HPD (real SPD) factors: Alg. 3 loop.  T is the factor
 // precision (float for FP32, double for FP64).
 
@@ -197,7 +179,7 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
     max_steps = std::max(max_steps, steps[b]);
     double final_r = hist[b].back();
     if (verdict[b] != Verdict::Converged) {
-      if (best && best_r[b] < final_r) {
+      if (best && !(final_r <= best_r[b])) {  // also when final_r is NaN
         launch_copy_f64(st, n, best + b * nn, n, 0, X + b * sX, ldx, 0, 1);
         final_r = best_r[b];
       }
@@ -385,6 +367,23 @@ msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gba
   return backward_general<float>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
 }
 
+// Finiteness (bit 0) and exact symmetry failures (bit 1) of a batch of
+// matrices, without touching the factor's scales.
+int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st) {
+  const int n = (int)f->n, batch = (int)f->batch;
+  int* flags = f->active.ensure<int>(batch);
+  const int nt = (int)ceil_div(n, 32);
+  double* part = f->part.ensure<double>((int64_t)nt * (nt + 1) / 2 * batch + 64);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
+  launch_validate(st, n, M, ld, sM, batch, 1, flags, part);
+  std::vector<int> hf(batch);
+  MSQRT_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  int agg = 0;
+  for (int b = 0; b < batch; ++b) agg |= hf[b];
+  return agg;
+}
+
 // Computes ||A_b||_F and the scale exponents k_b = round(log4(||A_b||_F / sqrt(n)))
 // into the factor; also validates finiteness / symmetry.  Returns flags.
 int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
@@ -556,12 +555,27 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
   // a nearby matrix.
   {
     std::vector<int> k = f->kexp;
-    if (f->structure == MSQRT_STRUCT_GENERAL)
-      analyse_input_general(f, (const double*)dA, lda, f->dtype == MSQRT_COMPLEX128, stream);
-    else
-      analyse_input(f, (const double*)dA, lda, strideA, false, stream);
+    int flags = 0;
+    if (f->structure == MSQRT_STRUCT_GENERAL) {
+      flags = analyse_input_general(f, (const double*)dA, lda, f->dtype == MSQRT_COMPLEX128, stream) & 1;
+    } else {
+      // An HPD factor refines a symmetric A from a symmetric X: the residual
+      // is formed as A - X X^T from the lower triangle, which equals A - X^2
+      // only for exactly symmetric A and X.
+      flags = analyse_input(f, (const double*)dA, lda, strideA, true, stream);
+      if (!init_from_factor && !(flags & 3))
+        flags |= validate_flags(f, (const double*)dX, ldx, strideX, stream);
+    }
     f->kexp = k;
     f->upload_scales(stream);
+    if (flags & 1) {
+      set_last_error("msqrt_refine: A or X holds Inf or NaN");
+      return MSQRT_ERR_NONFINITE;
+    }
+    if (flags & 2) {
+      set_last_error("msqrt_refine: an HPD factor needs an exactly symmetric A and starting X");
+      return MSQRT_ERR_INVALID_ARG;
+    }
   }
   for (int64_t b = 0; b < f->batch; ++b) f->anorm_scaled[b] = f->anorm[b] * std::ldexp(1.0, -2 * f->kexp[b]);
   double* X = (double*)dX;

@@ -859,6 +859,8 @@ __global__ void copy_last_diag(const T* A, int n, T* d, int64_t sA, int64_t sD, 
 
 }  // namespace
 
+int sytrd_max_n() { return kTRMax * kMaxTs + 1; }
+
 template <typename T>
 void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* e, T* tau,
                    int64_t sD, SytrdWork& w) {
@@ -869,7 +871,7 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
     MSQRT_LAUNCH_CHECK();
     return;
   }
-  if (n - 1 > kTRMax * kMaxTs)
+  if (n > sytrd_max_n())
     throw Error{MSQRT_ERR_UNSUPPORTED, "tridiagonal reduction supports n <= 4225 in this build"};
   // Panel width: the LDS cache holds 4 * nb * kMaxTs values (at most 128 KiB).
   const int lds_budget = sizeof(T) == 4 ? 128 * 1024 : 96 * 1024;

@@ -89,5 +89,7 @@ void sy2tr_back(hipStream_t st, int n, T* Z, Sy2trWork& w, OrmtrWork& ow);
 // synchronous.
 bool sy2tr_failed(Sy2trWork& w);
 int sy2tr_max_n();
+// Largest n the one-stage tridiagonal reduction handles.
+int sytrd_max_n();
 
 }  // namespace msqrt

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
+from test_oracle_pins import FROZEN_ROOT_CASES, frozen_root_case
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +92,9 @@ def test_refine_from_caller_iterate_of_nearby_matrix(msq):
     lam32, q32 = oracle.syev(a.astype(np.float32), single=True)
     f = msq.factor_wrap(q32, np.sqrt(lam32).astype(np.float32), prec="fp32")
     ad = torch.from_numpy(np.ascontiguousarray(a2)).cuda()
-    xd = torch.from_numpy(np.ascontiguousarray(_truth(q, lam))).cuda()
+    x0 = _truth(q, lam)
+    x0 = 0.5 * (x0 + x0.T)  # an HPD factor refines from an exactly symmetric start
+    xd = torch.from_numpy(np.ascontiguousarray(x0)).cuda()
     info = msq.refine(f, ad, xd, init_from_factor=False, tol=1e-13)
     x = xd.cpu().numpy()
     assert oracle.relres(x, a2) <= 1e-13
@@ -112,3 +115,58 @@ def test_refine_maxit_zero_reports_not_converged(msq):
     assert info["steps"] == 0
     # X holds X_0 = Q S Q^T (float32 factor): relres around float32 level
     assert 1e-9 < info["relres"] < 1e-4
+
+
+def test_refine_rejects_nonsymmetric_input_for_hpd_factor(msq):
+    """An HPD factor forms the residual as A - X X^T from one triangle, so a
+    non-symmetric A or starting X is refused (X left untouched) instead of
+    being refined against the wrong equation."""
+    torch = _torch()
+    n = 96
+    a, q, lam = W.spd(n, 1e2, 12)
+    lam32, q32 = oracle.syev(a.astype(np.float32), single=True)
+    f = msq.factor_wrap(q32, np.sqrt(lam32).astype(np.float32), prec="fp32")
+    bad = a.copy()
+    bad[5, 70] += 1e-3
+    x0 = _truth(q, lam)
+    x0 = 0.5 * (x0 + x0.T)
+    for amat, xmat, init in ((bad, x0, True), (bad, x0, False), (a, x0 + np.triu(x0, 1) * 1e-9, False)):
+        ad = torch.from_numpy(np.ascontiguousarray(amat)).cuda()
+        xd = torch.from_numpy(np.ascontiguousarray(xmat)).cuda()
+        info = msq.refine(f, ad, xd, init_from_factor=init, allow_fail=True)
+        assert info["status"] == "invalid_arg"
+        assert np.array_equal(xd.cpu().numpy(), xmat)
+    # the symmetric pair still refines
+    ad = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x0)).cuda()
+    info = msq.refine(f, ad, xd, init_from_factor=False)
+    assert info["status"] == "ok" and oracle.relres(xd.cpu().numpy(), a) <= 1e-13
+
+
+@pytest.mark.parametrize("name", sorted(FROZEN_ROOT_CASES))
+def test_refine_frozen_root_statuses_match_oracle(msq, name):
+    """Every branch of the divergence / stagnation rule on the GPU: a float64
+    factor with exact Q and one deliberately wrong root (msqrt_factor_wrap),
+    started from X + delta q_0 q_0^T, against the oracle's emulation of the
+    same iteration with the same factor -- status, corrections, residual
+    history and the best iterate returned in X."""
+    torch = _torch()
+    a, q, s, x0, x_true = frozen_root_case(name)
+    x0 = 0.5 * (x0 + x0.T)
+    emu = oracle.emulate_mixed(a, low="fp64", factor={"Q": q, "s": s}, x0=x0, tol=1e-13)
+    f = msq.factor_wrap(q, s, prec="fp64")
+    ad = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x0)).cuda()
+    info = msq.refine(f, ad, xd, init_from_factor=False, tol=1e-13, allow_fail=True)
+    assert info["status"] == FROZEN_ROOT_CASES[name][2] == emu["status"]
+    assert info["steps"] == emu["steps"]
+    hist = info["relres_hist"]
+    assert len(hist) == len(emu["hist"])
+    for g, e in zip(hist, emu["hist"]):
+        if np.isfinite(e):
+            assert g == pytest.approx(e, rel=1e-9)
+        else:
+            assert not np.isfinite(g)
+    x = xd.cpu().numpy()
+    assert np.abs(x - emu["X"]).max() <= 1e-12 * np.abs(emu["X"]).max()
+    assert oracle.relres(x, a) == pytest.approx(min(emu["hist"]), rel=1e-6)
