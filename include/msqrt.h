@@ -142,6 +142,22 @@ msqrt_status msqrt_refine(msqrt_factor_t f, const void* dA, int64_t lda, int64_t
                           void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
                           double tol, hipStream_t stream, msqrt_info* info);
 
+/* msqrt_refine for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as msqrt_refine, for HPD factors
+ * (other factors: MSQRT_ERR_UNSUPPORTED).  Every device buffer the call needs
+ * beyond A, X and the factor lives in one static 64 MiB device array per GPU
+ * (held until the process ends); the call performs no hipMalloc / hipFree.
+ * It needs batch * n^2 * (2 * e + 8) bytes plus a few KiB, e = 4 (FP32 or
+ * BF16SPLIT factor) or 8 (FP64 factor): about n <= 2040 (FP32) or n <= 1670
+ * (FP64) for one matrix; larger sizes return MSQRT_ERR_INVALID_ARG before
+ * any device work.  All calls on one GPU share that array, so calls that
+ * overlap in time on one GPU (other threads, other streams) race and must
+ * not be issued.  Phase timers are not recorded (info->t_ms stays zero). */
+msqrt_status msqrt_refine_noalloc(msqrt_factor_t f, const void* dA, int64_t lda, int64_t strideA,
+                                  void* dX, int64_t ldx, int64_t strideX, int init_from_factor,
+                                  int maxit, double tol, hipStream_t stream, msqrt_info* info);
+
 /* Complete solve: factor, X_0, refinement, with precision escalation when
  * opt->fallback is set: a BF16SPLIT run that does not converge repeats the
  * refinement with float transforms on the same (float) factor; a float run

@@ -148,6 +148,25 @@ def refine(f: Factor, a: torch.Tensor, x: torch.Tensor, init_from_factor=True, m
     return d
 
 
+def refine_noalloc(f: Factor, a: torch.Tensor, x: torch.Tensor, init_from_factor=True, maxit=30,
+                   tol=1e-13, allow_fail=False):
+    """refine() through msqrt_refine_noalloc: no device allocation, static
+    scratch (HPD factors, bounded size).  Returns the info dict."""
+    _check_matrix(a, "A")
+    _check_matrix(x, "X")
+    n, batch, nn = _dims(a)
+    info = _lib.Info()
+    st = lib().msqrt_refine_noalloc(f.handle, ctypes.c_void_p(a.data_ptr()), n, nn,
+                                    ctypes.c_void_p(x.data_ptr()), n, nn,
+                                    1 if init_from_factor else 0, int(maxit), float(tol),
+                                    _stream(), ctypes.byref(info))
+    d = info.to_dict()
+    d["status"] = _lib.STATUS_NAMES.get(st, st)
+    if not allow_fail:
+        check(st, "msqrt_refine_noalloc")
+    return d
+
+
 def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32,
           fallback=True, keep_factor=False, allow_fail=False, out=None):
     """Principal square root of a (batch of) matrices.  Returns (X, info) or

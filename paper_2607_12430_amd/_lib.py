@@ -28,7 +28,7 @@ PHASES = ["validate", "select", "reduce", "eig", "back", "x0", "residual", "tran
           "update", "total", "spare"]
 
 EXPORTED = [
-    "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_sqrtm",
+    "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_refine_noalloc", "msqrt_sqrtm",
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_sy2tr",
     "msqrt_test_stedc",
@@ -97,6 +97,8 @@ def lib():
     L.msqrt_default_options.restype = None
     L.msqrt_factor.argtypes = [ctypes.POINTER(Options), ci, i64, vp, i64, i64, vp, ctypes.POINTER(vp)]
     L.msqrt_refine.argtypes = [vp, vp, i64, i64, vp, i64, i64, ci, ci, cd, vp, ctypes.POINTER(Info)]
+    L.msqrt_refine_noalloc.argtypes = [vp, vp, i64, i64, vp, i64, i64, ci, ci, cd, vp,
+                                       ctypes.POINTER(Info)]
     L.msqrt_sqrtm.argtypes = [ctypes.POINTER(Options), ci, i64, vp, i64, i64, vp, i64, i64, vp,
                               ctypes.POINTER(Info), ctypes.POINTER(vp)]
     L.msqrt_sqrtm_backward.argtypes = [vp, vp, i64, vp, i64, vp, i64, i64, ci, cd, vp,
@@ -136,7 +138,8 @@ def lib():
     L.msqrt_selector_clear.restype = None
     L.msqrt_selector_installed.argtypes = []
     L.msqrt_selector_installed.restype = ci
-    for name in ("msqrt_factor", "msqrt_refine", "msqrt_sqrtm", "msqrt_sqrtm_backward",
+    for name in ("msqrt_factor", "msqrt_refine", "msqrt_refine_noalloc", "msqrt_sqrtm",
+                 "msqrt_sqrtm_backward",
                  "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
                  "msqrt_test_stedc", "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt",
                  "msqrt_test_trsyl", "msqrt_test_gemm_f32", "msqrt_features",

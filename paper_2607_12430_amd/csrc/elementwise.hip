@@ -60,6 +60,12 @@ __global__ __launch_bounds__(kEwThreads) void validate_kernel(int n, const doubl
   if (asym) atomicOr(&flags[b], 2);
 }
 
+// p[i] = v for i < count (clears flags without a memset node).
+__global__ __launch_bounds__(kEwThreads) void fill_i32_kernel(int* p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
 __global__ __launch_bounds__(kEwThreads) void reduce_sqrt_kernel(const double* __restrict__ p,
                                                                  int count, double* out) {
   __shared__ double red[kEwThreads / kWave];
@@ -115,6 +121,13 @@ int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t
                      check_sym, flags, partials);
   MSQRT_LAUNCH_CHECK();
   return nblk;
+}
+
+void launch_fill_i32(hipStream_t st, int* p, int count, int v) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((count + kEwThreads - 1) / kEwThreads), dim3(kEwThreads),
+                     0, st, p, count, v);
+  MSQRT_LAUNCH_CHECK();
 }
 
 void launch_reduce_sqrt(hipStream_t st, const double* partials, int count, int batch, double* out) {

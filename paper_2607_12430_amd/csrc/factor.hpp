@@ -168,11 +168,27 @@ inline Verdict judge(const std::vector<double>& h, double tol) {
 // Validates A (finiteness, optional exact symmetry), computes ||A_b||_F and
 // the scale exponents into f.  Returns the OR of the per-entry flags
 // (bit0 non-finite, bit1 not symmetric).
+// Device buffers of one HPD refinement call when the caller provides them
+// (allocation-free entry point): W1, W2 hold n x n x batch values of the
+// factor precision, best n x n x batch doubles, part the per-tile partial
+// sums (max of the residual tiles and the validation blocks, times batch,
+// plus 64), rn batch doubles, flags batch ints.  nullptr everywhere else:
+// the factor's own cached buffers are used.
+struct RefineWs {
+  void* w1 = nullptr;
+  void* w2 = nullptr;
+  double* best = nullptr;
+  double* part = nullptr;
+  double* rn = nullptr;
+  int* flags = nullptr;
+};
+
 int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
-                  hipStream_t st);
+                  hipStream_t st, const RefineWs* ws = nullptr);
 // Finiteness (bit0) and exact symmetry failures (bit1) of a batch of n x n
 // matrices with the factor's n and batch; the factor's scales are untouched.
-int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st);
+int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st,
+                   const RefineWs* ws = nullptr);
 
 // Factorisation of the scaled input into f (Q, S, structure, prec).
 msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, int64_t lda,

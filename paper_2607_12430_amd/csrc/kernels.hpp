@@ -12,6 +12,8 @@ namespace msqrt {
 // symmetric; partials[b * nblk + blk] = sum of squares.  Returns nblk.
 int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, int batch,
                     int check_sym, int* flags, double* partials);
+// p[i] = v for i < count.
+void launch_fill_i32(hipStream_t st, int* p, int count, int v);
 // out[b] = sqrt(sum_{t < count} partials[b * count + t]) (fixed summation order).
 void launch_reduce_sqrt(hipStream_t st, const double* partials, int count, int batch, double* out);
 // B = scale[b] * A (double source, float or double destination).

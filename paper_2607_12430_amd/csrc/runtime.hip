@@ -69,20 +69,24 @@ void pool_free(void* p, size_t bytes) {
 // Refinement for HPD (real SPD) factors: Alg. 3 loop.  T is the factor
 // precision (float for FP32, double for FP64).
 
+// Tiles of the symmetric residual GEMM (128 x 128, lower triangle): sizes
+// the per-tile partial sums of ||R||_F.
+static int64_t residual_tiles(int n) { return ceil_div(n, 128) * (ceil_div(n, 128) + 1) / 2; }
+
 template <typename T>
 static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t sA, double* X,
                                int64_t ldx, int64_t sX, int init, int maxit, double tol,
-                               hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+                               hipStream_t st, msqrt_info* info, PhaseTimer& tm,
+                               const RefineWs* ws) {
   const int n = (int)f->n, batch = (int)f->batch;
   const int64_t nn = (int64_t)n * n;
   const T* Q = f->Q.as<T>();
   const T* s = f->S.as<T>();
-  T* W1 = f->ws1.ensure<T>(nn * batch);
-  T* W2 = f->ws2.ensure<T>(nn * batch);
-  const int ntile_est = (int)(ceil_div(n, 128) * (ceil_div(n, 128) + 1) / 2);
-  double* part = f->part.ensure<double>((int64_t)ntile_est * batch + 64);
-  double* rn = f->rnorm.ensure<double>(batch);
-  int* active = f->active.ensure<int>(batch);
+  T* W1 = ws ? (T*)ws->w1 : f->ws1.ensure<T>(nn * batch);
+  T* W2 = ws ? (T*)ws->w2 : f->ws2.ensure<T>(nn * batch);
+  double* part = ws ? ws->part : f->part.ensure<double>(residual_tiles(n) * batch + 64);
+  double* rn = ws ? ws->rn : f->rnorm.ensure<double>(batch);
+  int* active = ws ? ws->flags : f->active.ensure<int>(batch);
   double* best = nullptr;
   // BF16SPLIT: float factor, Schur-basis transforms as BF16-split products
   const bool split = f->prec == MSQRT_PREC_BF16SPLIT;
@@ -139,7 +143,7 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
         need_best = true;
       }
     if (need_best) {
-      if (!best) best = f->best.ensure<double>(nn * batch);
+      if (!best) best = ws ? ws->best : f->best.ensure<double>(nn * batch);
       for (int b = 0; b < batch; ++b)
         if (!done[b] && hist[b].back() == best_r[b])
           launch_copy_f64(st, n, X + b * sX, ldx, 0, best + b * nn, n, 0, 1);
@@ -199,12 +203,13 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
 
 msqrt_status refine(Factor* f, const double* A, int64_t lda, int64_t sA, double* X, int64_t ldx,
                     int64_t sX, int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
-                    PhaseTimer& tm) {
+                    PhaseTimer& tm, const RefineWs* ws = nullptr) {
   if (f->structure == MSQRT_STRUCT_HPD) {
     if (f->prec == MSQRT_PREC_FP64)
-      return refine_hpd<double>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
-    return refine_hpd<float>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm);
+      return refine_hpd<double>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm, ws);
+    return refine_hpd<float>(f, A, lda, sA, X, ldx, sX, init, maxit, tol, st, info, tm, ws);
   }
+  if (ws) throw Error{MSQRT_ERR_UNSUPPORTED, "caller workspace: HPD factors only"};
   // general path: one matrix; X is read and written at the caller's scale
   if (f->prec == MSQRT_PREC_FP64)
     return refine_general<double>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
@@ -369,12 +374,13 @@ msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gba
 
 // Finiteness (bit 0) and exact symmetry failures (bit 1) of a batch of
 // matrices, without touching the factor's scales.
-int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st) {
+int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream_t st,
+                   const RefineWs* ws) {
   const int n = (int)f->n, batch = (int)f->batch;
-  int* flags = f->active.ensure<int>(batch);
   const int nt = (int)ceil_div(n, 32);
-  double* part = f->part.ensure<double>((int64_t)nt * (nt + 1) / 2 * batch + 64);
-  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
+  int* flags = ws ? ws->flags : f->active.ensure<int>(batch);
+  double* part = ws ? ws->part : f->part.ensure<double>((int64_t)nt * (nt + 1) / 2 * batch + 64);
+  launch_fill_i32(st, flags, batch, 0);
   launch_validate(st, n, M, ld, sM, batch, 1, flags, part);
   std::vector<int> hf(batch);
   MSQRT_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
@@ -387,14 +393,14 @@ int validate_flags(Factor* f, const double* M, int64_t ld, int64_t sM, hipStream
 // Computes ||A_b||_F and the scale exponents k_b = round(log4(||A_b||_F / sqrt(n)))
 // into the factor; also validates finiteness / symmetry.  Returns flags.
 int analyse_input(Factor* f, const double* A, int64_t lda, int64_t sA, bool check_sym,
-                         hipStream_t st) {
+                  hipStream_t st, const RefineWs* ws) {
   const int n = (int)f->n, batch = (int)f->batch;
-  int* flags = f->active.ensure<int>(batch);
   const int nt = (int)ceil_div(n, 32);
   const int nblk = nt * (nt + 1) / 2;
-  double* part = f->part.ensure<double>((int64_t)nblk * batch + 64);
-  double* rn = f->rnorm.ensure<double>(batch);
-  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int) * batch, st));
+  int* flags = ws ? ws->flags : f->active.ensure<int>(batch);
+  double* part = ws ? ws->part : f->part.ensure<double>((int64_t)nblk * batch + 64);
+  double* rn = ws ? ws->rn : f->rnorm.ensure<double>(batch);
+  launch_fill_i32(st, flags, batch, 0);
   launch_validate(st, n, A, lda, sA, batch, check_sym ? 1 : 0, flags, part);
   launch_reduce_sqrt(st, part, nblk, batch, rn);
   std::vector<int> hf(batch);
@@ -535,11 +541,65 @@ msqrt_status msqrt_factor_export(msqrt_factor_t fh, void* Qh, void* Sh, int* sca
   MSQRT_API_END
 }
 
-msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_t strideA,
-                          void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
-                          double tol, hipStream_t stream, msqrt_info* info) {
-  MSQRT_API_BEGIN
-  Factor* f = reinterpret_cast<Factor*>(fh);
+}  // extern "C"
+
+namespace {
+
+// Static scratch of the allocation-free refinement entry point: one copy per
+// GPU, alive until the process ends.  Host code never uses the array's name
+// as an address; it takes each device's address from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;  // device -> address of its scratch
+
+// Address of the current device's scratch, looked up once per device.
+unsigned char* scratch_address() {
+  int dev = 0;
+  MSQRT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    throw Error{MSQRT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  }
+  g_scratch_addr[dev] = (unsigned char*)p;
+  return (unsigned char*)p;
+}
+
+// Carves the workspace of one HPD refinement call out of `base` (256-byte
+// aligned pieces); returns the bytes needed (base may be null to size it).
+size_t carve_refine_ws(const Factor* f, unsigned char* base, RefineWs* ws) {
+  const int64_t n = f->n, batch = f->batch, nn = n * n;
+  const size_t es = f->prec == MSQRT_PREC_FP64 ? 8 : 4;
+  const int64_t nt = ceil_div(n, 32);
+  const int64_t nparts = std::max<int64_t>(residual_tiles((int)n), nt * (nt + 1) / 2) * batch + 64;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base ? base + off : nullptr;
+    off += up(bytes);
+    return p;
+  };
+  ws->w1 = take(es * nn * batch);
+  ws->w2 = take(es * nn * batch);
+  ws->best = (double*)take(sizeof(double) * nn * batch);
+  ws->part = (double*)take(sizeof(double) * nparts);
+  ws->rn = (double*)take(sizeof(double) * batch);
+  ws->flags = (int*)take(sizeof(int) * batch);
+  return off;
+}
+
+// msqrt_refine with the factor's cached buffers (ws = null) or a caller
+// workspace.  With a workspace nothing is allocated on the device and no
+// phase timers are recorded (info->t_ms stays zero).
+msqrt_status refine_call(Factor* f, const void* dA, int64_t lda, int64_t strideA, void* dX,
+                         int64_t ldx, int64_t strideX, int init_from_factor, int maxit, double tol,
+                         hipStream_t stream, msqrt_info* info, const RefineWs* ws) {
   if (!f || !dA || !dX || lda < f->n || ldx < f->n || maxit < 0 || !(tol >= 0)) {
     set_last_error("msqrt_refine: invalid argument");
     return MSQRT_ERR_INVALID_ARG;
@@ -549,7 +609,7 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
     return MSQRT_ERR_INVALID_ARG;
   }
   if (info) { std::memset(info, 0, sizeof(*info)); info->prec_used = f->prec; info->struct_used = f->structure; }
-  PhaseTimer tm(stream, info);
+  PhaseTimer tm(stream, ws ? nullptr : info);
   // ||A||_F of the (scaled) matrix the refinement measures against.  The
   // factor's scale exponents are kept; the norm is recomputed because A may be
   // a nearby matrix.
@@ -562,9 +622,9 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
       // An HPD factor refines a symmetric A from a symmetric X: the residual
       // is formed as A - X X^T from the lower triangle, which equals A - X^2
       // only for exactly symmetric A and X.
-      flags = analyse_input(f, (const double*)dA, lda, strideA, true, stream);
+      flags = analyse_input(f, (const double*)dA, lda, strideA, true, stream, ws);
       if (!init_from_factor && !(flags & 3))
-        flags |= validate_flags(f, (const double*)dX, ldx, strideX, stream);
+        flags |= validate_flags(f, (const double*)dX, ldx, strideX, stream, ws);
     }
     f->kexp = k;
     f->upload_scales(stream);
@@ -590,12 +650,53 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
   // Refinement runs on the scaled problem A/4^k: bring X to that scale.
   launch_scale_inplace(stream, (int)f->n, X, ldx, strideX, f->rscale_dev(), (int)f->batch);
   msqrt_status s = refine(f, (const double*)dA, lda, strideA, X, ldx, strideX, init_from_factor,
-                          maxit, tol, stream, info, tm);
+                          maxit, tol, stream, info, tm, ws);
   launch_scale_inplace(stream, (int)f->n, X, ldx, strideX, f->uscale_dev(), (int)f->batch);
   MSQRT_HIP(hipStreamSynchronize(stream));
   tm.collect();
   if (info) info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
   return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_t strideA,
+                          void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
+                          double tol, hipStream_t stream, msqrt_info* info) {
+  MSQRT_API_BEGIN
+  return refine_call(reinterpret_cast<Factor*>(fh), dA, lda, strideA, dX, ldx, strideX,
+                     init_from_factor, maxit, tol, stream, info, nullptr);
+  MSQRT_API_END
+}
+
+msqrt_status msqrt_refine_noalloc(msqrt_factor_t fh, const void* dA, int64_t lda,
+                                  int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                                  int init_from_factor, int maxit, double tol, hipStream_t stream,
+                                  msqrt_info* info) {
+  MSQRT_API_BEGIN
+  Factor* f = reinterpret_cast<Factor*>(fh);
+  if (!f) {
+    set_last_error("msqrt_refine_noalloc: invalid argument");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (f->structure != MSQRT_STRUCT_HPD) {
+    set_last_error("msqrt_refine_noalloc: HPD factors only");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  RefineWs ws;
+  const size_t need = carve_refine_ws(f, nullptr, &ws);
+  if (need > kNoAllocScratchBytes) {
+    set_last_error("msqrt_refine_noalloc: n = " + std::to_string(f->n) + ", batch = " +
+                   std::to_string(f->batch) + " needs " + std::to_string(need) +
+                   " bytes of scratch; the static scratch holds " +
+                   std::to_string(kNoAllocScratchBytes) + " bytes");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  carve_refine_ws(f, scratch_address(), &ws);
+  return refine_call(f, dA, lda, strideA, dX, ldx, strideX, init_from_factor, maxit, tol, stream,
+                     info, &ws);
   MSQRT_API_END
 }
 
