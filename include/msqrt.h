@@ -71,10 +71,15 @@ typedef enum {
 
 /* AUTO tests for exact symmetry (Hermitian symmetry for complex input) and then
  * uses Alg. 3; a non-positive low-precision eigenvalue escalates the
- * precision and, if FP64 also sees one, falls back to the general path.  The
- * symmetric route's tridiagonal reduction handles n <= 4225: a larger
- * symmetric single input takes the general path under AUTO, and HPD (or a
- * batch) beyond that size returns MSQRT_ERR_UNSUPPORTED. */
+ * precision, and one that FP64 also sees means the symmetric input has no
+ * principal root (MSQRT_ERR_NO_PRINCIPAL).  Complex Hermitian input is solved
+ * through its real representation [[Re A, -Im A], [Im A, Re A]] (symmetric,
+ * positive definite exactly when A is; the representation maps sqrt(A) to
+ * the root of that matrix), so the factor of a complex HPD input is the real
+ * HPD factor of order 2n.  The symmetric route's tridiagonal reduction
+ * handles order <= 4225 (real n <= 4225, complex n <= 2112): a larger
+ * single input takes the general path under AUTO, and HPD (or a batch)
+ * beyond that size returns MSQRT_ERR_UNSUPPORTED. */
 typedef enum { MSQRT_STRUCT_AUTO = 0, MSQRT_STRUCT_GENERAL = 1, MSQRT_STRUCT_HPD = 2 } msqrt_struct;
 
 typedef struct {

@@ -110,6 +110,44 @@ __global__ __launch_bounds__(kEwThreads) void scale_inplace_kernel(int n, double
   if (i < n) X[(int64_t)b * sX + i + (int64_t)j * ldx] *= scale[b];
 }
 
+// Real representation of a complex matrix (interleaved complex, column
+// index j): E = [[Re A, -Im A], [Im A, Re A]] (2n x 2n, ld 2n).  The map is an
+// algebra homomorphism, E is symmetric exactly when A is Hermitian and
+// positive definite exactly when A is.
+__global__ __launch_bounds__(kEwThreads) void embed_complex_kernel(int n, const double* __restrict__ A,
+                                                                   int64_t lda, int64_t sA,
+                                                                   double* __restrict__ E,
+                                                                   int64_t sE) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* a = A + (int64_t)b * sA + 2 * ((int64_t)i + (int64_t)j * lda);
+  const double re = a[0], im = a[1];
+  double* e = E + (int64_t)b * sE;
+  const int64_t ld = 2 * (int64_t)n;
+  e[i + j * ld] = re;
+  e[n + i + j * ld] = im;
+  e[i + (n + j) * ld] = -im;
+  e[n + i + (n + j) * ld] = re;
+}
+
+// Complex matrix back from a real representation, averaging the two copies
+// of each part: X = (E11 + E22)/2 + i (E21 - E12)/2.
+__global__ __launch_bounds__(kEwThreads) void extract_complex_kernel(int n, const double* __restrict__ E,
+                                                                     int64_t sE, double* __restrict__ X,
+                                                                     int64_t ldx, int64_t sX) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* e = E + (int64_t)b * sE;
+  const int64_t ld = 2 * (int64_t)n;
+  double* x = X + (int64_t)b * sX + 2 * ((int64_t)i + (int64_t)j * ldx);
+  x[0] = 0.5 * (e[i + j * ld] + e[n + i + (n + j) * ld]);
+  x[1] = 0.5 * (e[n + i + j * ld] - e[i + (n + j) * ld]);
+}
+
 }  // namespace
 
 int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, int batch,
@@ -121,6 +159,22 @@ int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t
                      check_sym, flags, partials);
   MSQRT_LAUNCH_CHECK();
   return nblk;
+}
+
+void launch_embed_complex(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA,
+                          double* E, int64_t sE, int batch) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(embed_complex_kernel, dim3((unsigned)ceil_div(n, kEwThreads), n, batch), dim3(kEwThreads),
+                     0, st, n, A, lda, sA, E, sE);
+  MSQRT_LAUNCH_CHECK();
+}
+
+void launch_extract_complex(hipStream_t st, int n, const double* E, int64_t sE, double* X,
+                            int64_t ldx, int64_t sX, int batch) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(extract_complex_kernel, dim3((unsigned)ceil_div(n, kEwThreads), n, batch),
+                     dim3(kEwThreads), 0, st, n, E, sE, X, ldx, sX);
+  MSQRT_LAUNCH_CHECK();
 }
 
 void launch_fill_i32(hipStream_t st, int* p, int count, int v) {

@@ -73,6 +73,10 @@ struct Factor {
   // the per-plane residual scales and the tile-solver state
   DevBuf gq, gx, gt, gsc;
   bool gq_ready = false;
+  // Complex Hermitian input solved through its real representation
+  // [[Re A, -Im A], [Im A, Re A]]: n is 2 n_user and the factor is the HPD
+  // factor of that real matrix.
+  bool embed = false;
   TrsylvWork tw;
 
   void upload_scales(hipStream_t st) {

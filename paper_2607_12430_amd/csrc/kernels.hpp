@@ -12,6 +12,13 @@ namespace msqrt {
 // symmetric; partials[b * nblk + blk] = sum of squares.  Returns nblk.
 int launch_validate(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA, int batch,
                     int check_sym, int* flags, double* partials);
+// Real representation E = [[Re A, -Im A], [Im A, Re A]] (2n x 2n, ld 2n,
+// batch stride sE) of interleaved complex A (ld lda in complex elements).
+void launch_embed_complex(hipStream_t st, int n, const double* A, int64_t lda, int64_t sA,
+                          double* E, int64_t sE, int batch);
+// Inverse of launch_embed_complex, averaging the two copies of each part.
+void launch_extract_complex(hipStream_t st, int n, const double* E, int64_t sE, double* X,
+                            int64_t ldx, int64_t sX, int batch);
 // p[i] = v for i < count.
 void launch_fill_i32(hipStream_t st, int* p, int count, int v);
 // out[b] = sqrt(sum_{t < count} partials[b * count + t]) (fixed summation order).

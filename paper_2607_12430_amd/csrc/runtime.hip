@@ -12,6 +12,7 @@
 #include "../../include/msqrt.h"
 #include "factor.hpp"
 #include "kernels.hpp"
+#include "tridiag.hpp"
 
 namespace msqrt {
 
@@ -445,6 +446,11 @@ using namespace msqrt;
     return MSQRT_ERR_DEVICE;                                                            \
   }
 
+namespace {
+int embed_and_check(int64_t n, int64_t batch, const void* dA, int64_t lda, int64_t strideA,
+                    double* E, hipStream_t st);
+}  // namespace
+
 extern "C" {
 
 void msqrt_default_options(msqrt_options* o) {
@@ -666,8 +672,30 @@ msqrt_status msqrt_refine(msqrt_factor_t fh, const void* dA, int64_t lda, int64_
                           void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
                           double tol, hipStream_t stream, msqrt_info* info) {
   MSQRT_API_BEGIN
-  return refine_call(reinterpret_cast<Factor*>(fh), dA, lda, strideA, dX, ldx, strideX,
-                     init_from_factor, maxit, tol, stream, info, nullptr);
+  Factor* f = reinterpret_cast<Factor*>(fh);
+  if (f && f->embed) {
+    // complex Hermitian: refine the real representations of A and X
+    const int64_t n = f->n / 2, n2 = f->n, s2 = n2 * n2;
+    if (!dA || !dX || lda < n || ldx < n) {
+      set_last_error("msqrt_refine: invalid argument");
+      return MSQRT_ERR_INVALID_ARG;
+    }
+    DevBuf eb, xb;
+    double* E = eb.ensure<double>(s2 * f->batch);
+    double* XE = xb.ensure<double>(s2 * f->batch);
+    launch_embed_complex(stream, (int)n, (const double*)dA, lda, 2 * strideA, E, s2, (int)f->batch);
+    if (!init_from_factor)
+      launch_embed_complex(stream, (int)n, (const double*)dX, ldx, 2 * strideX, XE, s2, (int)f->batch);
+    const msqrt_status st = refine_call(f, E, n2, s2, XE, n2, s2, init_from_factor, maxit, tol,
+                                        stream, info, nullptr);
+    if (st == MSQRT_OK || st == MSQRT_ERR_NOT_CONVERGED || st == MSQRT_ERR_DIVERGED) {
+      launch_extract_complex(stream, (int)n, XE, s2, (double*)dX, ldx, 2 * strideX, (int)f->batch);
+      MSQRT_HIP(hipStreamSynchronize(stream));
+    }
+    return st;
+  }
+  return refine_call(f, dA, lda, strideA, dX, ldx, strideX, init_from_factor, maxit, tol, stream,
+                     info, nullptr);
   MSQRT_API_END
 }
 
@@ -681,8 +709,8 @@ msqrt_status msqrt_refine_noalloc(msqrt_factor_t fh, const void* dA, int64_t lda
     set_last_error("msqrt_refine_noalloc: invalid argument");
     return MSQRT_ERR_INVALID_ARG;
   }
-  if (f->structure != MSQRT_STRUCT_HPD) {
-    set_last_error("msqrt_refine_noalloc: HPD factors only");
+  if (f->structure != MSQRT_STRUCT_HPD || f->embed) {
+    set_last_error("msqrt_refine_noalloc: real HPD factors only");
     return MSQRT_ERR_UNSUPPORTED;
   }
   RefineWs ws;
@@ -711,6 +739,34 @@ msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n
   if (!out) return MSQRT_ERR_INVALID_ARG;
   std::unique_ptr<Factor> f(new Factor());
   f->n = n; f->batch = o.batch; f->dtype = dtype; f->blks = o.blks;
+  if (dtype == MSQRT_COMPLEX128 && o.structure != MSQRT_STRUCT_GENERAL && n > 0 &&
+      2 * n <= sytrd_max_n()) {
+    // complex Hermitian input: HPD factor of the real representation
+    const int64_t n2 = 2 * n, s2 = n2 * n2;
+    DevBuf eb;
+    double* E = eb.ensure<double>(s2 * o.batch);
+    const int flags = embed_and_check(n, o.batch, dA, lda, strideA, E, stream);
+    if (flags & 1) {
+      set_last_error("input contains Inf or NaN");
+      return MSQRT_ERR_NONFINITE;
+    }
+    if (!(flags & 2)) {
+      msqrt_options oe = o;
+      oe.structure = MSQRT_STRUCT_HPD;
+      f->n = n2;
+      f->dtype = MSQRT_REAL64;
+      msqrt_status st = build_factor(f.get(), oe, E, n2, s2, stream, nullptr);
+      if (st != MSQRT_OK) return st;
+      f->embed = true;
+      f->dtype = MSQRT_COMPLEX128;
+      *out = reinterpret_cast<msqrt_factor_t>(f.release());
+      return MSQRT_OK;
+    }
+    if (o.structure == MSQRT_STRUCT_HPD) {
+      set_last_error("structure HPD requested but the input is not exactly Hermitian");
+      return MSQRT_ERR_INVALID_ARG;
+    }
+  }
   msqrt_status st = build_factor(f.get(), o, (const double*)dA, lda, strideA, stream, nullptr);
   if (st != MSQRT_OK) return st;
   *out = reinterpret_cast<msqrt_factor_t>(f.release());
@@ -718,24 +774,16 @@ msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n
   MSQRT_API_END
 }
 
-msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
-                         int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
-                         hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep) {
-  MSQRT_API_BEGIN
-  msqrt_options o;
-  msqrt_default_options(&o);
-  if (opt) o = *opt;
-  msqrt_status cs = check_common(dtype, n, dA, lda, o.batch);
-  if (cs != MSQRT_OK) return cs;
-  if (n > 0 && (!dX || ldx < n)) return MSQRT_ERR_INVALID_ARG;
-  if (o.batch > 1 && (strideA < lda * n || strideX < ldx * n)) {
-    set_last_error("batch strides too small");
-    return MSQRT_ERR_INVALID_ARG;
-  }
-  if (info) std::memset(info, 0, sizeof(*info));
-  if (keep) *keep = nullptr;
-  if (n == 0) return MSQRT_OK;
-  PhaseTimer tm(stream, info);
+}  // extern "C"
+
+namespace {
+
+// The solve of msqrt_sqrtm after argument checks: factor, refinement and
+// precision escalation.
+msqrt_status sqrtm_impl(const msqrt_options& o, msqrt_dtype dtype, int64_t n, const void* dA,
+                        int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                        hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep,
+                        PhaseTimer& tm) {
 
   msqrt_prec prec = o.prec;
   if (prec == MSQRT_PREC_AUTO) prec = select_precision(o, dtype, n, dA, lda, strideA, stream, info, tm);
@@ -789,6 +837,113 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
   }
   if (info) info->fallbacks = fallbacks;
   return last;
+}
+
+// Real representation of a batch of interleaved complex n x n matrices into
+// E (2n x 2n per entry, ld 2n, stride 4n^2).  Returns the validation flags of
+// E (bit0 non-finite, bit1 E not exactly symmetric, i.e. A not exactly
+// Hermitian).
+int embed_and_check(int64_t n, int64_t batch, const void* dA, int64_t lda, int64_t strideA,
+                    double* E, hipStream_t st) {
+  const int64_t n2 = 2 * n, s2 = n2 * n2;
+  launch_embed_complex(st, (int)n, (const double*)dA, lda, 2 * strideA, E, s2, (int)batch);
+  DevBuf fl, pt;
+  int* flags = fl.ensure<int>(batch);
+  const int64_t nt = ceil_div(n2, 32);
+  double* part = pt.ensure<double>(nt * (nt + 1) / 2 * batch + 64);
+  launch_fill_i32(st, flags, (int)batch, 0);
+  launch_validate(st, (int)n2, E, n2, s2, (int)batch, 1, flags, part);
+  std::vector<int> hf(batch);
+  MSQRT_HIP(hipMemcpyAsync(hf.data(), flags, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipStreamSynchronize(st));
+  int agg = 0;
+  for (int v : hf) agg |= v;
+  return agg;
+}
+
+// Complex Hermitian positive definite input (Alg. 3 over C): the principal
+// root of A is read off the principal root of its real representation E,
+// which the real symmetric route computes (E is symmetric positive definite
+// exactly when A is Hermitian positive definite, and the representation is
+// an algebra homomorphism, so sqrt(E) represents sqrt(A)).  *handled is
+// false when the input is not exactly Hermitian under structure AUTO or too
+// large for the symmetric route: the caller then takes the general path.
+msqrt_status sqrtm_hermitian(const msqrt_options& o, int64_t n, const void* dA, int64_t lda,
+                             int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                             hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep,
+                             PhaseTimer& tm, bool* handled) {
+  *handled = false;
+  const int64_t n2 = 2 * n, s2 = n2 * n2;
+  if (n2 > sytrd_max_n()) {
+    if (o.structure != MSQRT_STRUCT_HPD) return MSQRT_OK;
+    *handled = true;
+    set_last_error("complex Hermitian route supports n <= " + std::to_string(sytrd_max_n() / 2));
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  DevBuf eb, xb;
+  double* E = eb.ensure<double>(s2 * o.batch);
+  double* XE = xb.ensure<double>(s2 * o.batch);
+  tm.begin(MSQRT_T_VALIDATE);
+  const int flags = embed_and_check(n, o.batch, dA, lda, strideA, E, stream);
+  tm.end();
+  if (flags & 1) {
+    *handled = true;
+    set_last_error("input contains Inf or NaN");
+    return MSQRT_ERR_NONFINITE;
+  }
+  if (flags & 2) {
+    if (o.structure != MSQRT_STRUCT_HPD) return MSQRT_OK;
+    *handled = true;
+    set_last_error("structure HPD requested but the input is not exactly Hermitian");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  *handled = true;
+  msqrt_options oe = o;
+  oe.structure = MSQRT_STRUCT_HPD;
+  msqrt_factor_t kf = nullptr;
+  const msqrt_status st = sqrtm_impl(oe, MSQRT_REAL64, n2, E, n2, s2, XE, n2, s2, stream, info,
+                                     keep ? &kf : nullptr, tm);
+  if (st == MSQRT_OK || st == MSQRT_ERR_NOT_CONVERGED || st == MSQRT_ERR_DIVERGED) {
+    launch_extract_complex(stream, (int)n, XE, s2, (double*)dX, ldx, 2 * strideX, (int)o.batch);
+    MSQRT_HIP(hipStreamSynchronize(stream));
+  }
+  if (kf) {
+    reinterpret_cast<Factor*>(kf)->embed = true;
+    reinterpret_cast<Factor*>(kf)->dtype = MSQRT_COMPLEX128;
+    *keep = kf;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n, const void* dA,
+                         int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
+                         hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep) {
+  MSQRT_API_BEGIN
+  msqrt_options o;
+  msqrt_default_options(&o);
+  if (opt) o = *opt;
+  msqrt_status cs = check_common(dtype, n, dA, lda, o.batch);
+  if (cs != MSQRT_OK) return cs;
+  if (n > 0 && (!dX || ldx < n)) return MSQRT_ERR_INVALID_ARG;
+  if (o.batch > 1 && (strideA < lda * n || strideX < ldx * n)) {
+    set_last_error("batch strides too small");
+    return MSQRT_ERR_INVALID_ARG;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (keep) *keep = nullptr;
+  if (n == 0) return MSQRT_OK;
+  PhaseTimer tm(stream, info);
+  if (dtype == MSQRT_COMPLEX128 && o.structure != MSQRT_STRUCT_GENERAL) {
+    bool handled = false;
+    msqrt_status st = sqrtm_hermitian(o, n, dA, lda, strideA, dX, ldx, strideX, stream, info, keep,
+                                      tm, &handled);
+    if (handled) return st;
+  }
+  return sqrtm_impl(o, dtype, n, dA, lda, strideA, dX, ldx, strideX, stream, info, keep, tm);
   MSQRT_API_END
 }
 
@@ -798,12 +953,31 @@ msqrt_status msqrt_sqrtm_backward(msqrt_factor_t fh, const void* dX, int64_t ldx
                                   msqrt_info* info) {
   MSQRT_API_BEGIN
   Factor* f = reinterpret_cast<Factor*>(fh);
-  if (!f || !dX || !dGbar || !dG || ldx < f->n || ldgb < f->n || ldg < f->n || maxit < 0) {
+  const int64_t nu = f ? (f->embed ? f->n / 2 : f->n) : 0;  // the caller's order
+  if (!f || !dX || !dGbar || !dG || ldx < nu || ldgb < nu || ldg < nu || maxit < 0) {
     set_last_error("msqrt_sqrtm_backward: invalid argument");
     return MSQRT_ERR_INVALID_ARG;
   }
   if (info) std::memset(info, 0, sizeof(*info));
   PhaseTimer tm(stream, info);
+  if (f->embed) {
+    // complex Hermitian X: X G + G X = Gbar holds exactly when the real
+    // representations satisfy the same equation
+    const int64_t n = f->n / 2, n2 = f->n, s2 = n2 * n2;
+    DevBuf xb, gb, ob;
+    double* XE = xb.ensure<double>(s2 * f->batch);
+    double* GB = gb.ensure<double>(s2 * f->batch);
+    double* GE = ob.ensure<double>(s2 * f->batch);
+    launch_embed_complex(stream, (int)n, (const double*)dX, ldx, 2 * stride, XE, s2, (int)f->batch);
+    launch_embed_complex(stream, (int)n, (const double*)dGbar, ldgb, 2 * stride, GB, s2,
+                         (int)f->batch);
+    const msqrt_status st = backward(f, XE, n2, GB, n2, GE, n2, s2, maxit, tol, stream, info, tm);
+    if (st == MSQRT_OK || st == MSQRT_ERR_NOT_CONVERGED || st == MSQRT_ERR_DIVERGED) {
+      launch_extract_complex(stream, (int)n, GE, s2, (double*)dG, ldg, 2 * stride, (int)f->batch);
+      MSQRT_HIP(hipStreamSynchronize(stream));
+    }
+    return st;
+  }
   return backward(f, (const double*)dX, ldx, (const double*)dGbar, ldgb, (double*)dG, ldg, stride,
                   maxit, tol, stream, info, tm);
   MSQRT_API_END

@@ -17,6 +17,8 @@ can form the known root without running any solver):
 * ``spd_range(n, lo, hi, seed)``: same with eigenvalues log-uniform in [lo, hi]
   (endpoints pinned).
 * ``nonsym_shifted(n, seed)``: A = 2 I + G / sqrt(n), G i.i.d. N(0, 1).
+* ``hpd(n, kappa, seed)``: complex Hermitian A = U diag(lam) U^H, U
+  Haar-unitary, lam as in ``spd``.
 * ``complex_square(n, seed)``: B = Q (D + N) Q^H with Q Haar-unitary, D diagonal
   uniform in the disk |z - 2| < 1.5, N strictly upper triangular complex normal
   with standard deviation 0.1/sqrt(n); A = B B.
@@ -76,6 +78,19 @@ def spd(n: int, kappa: float, seed: int):
     on [kappa^-1/2, kappa^1/2]."""
     s = np.sqrt(kappa)
     return spd_range(n, 1.0 / s, s, seed)
+
+
+def hpd(n: int, kappa: float, seed: int):
+    """Complex Hermitian positive definite A = U diag(lam) U^H with U
+    Haar-unitary and lam log-uniform on [kappa^-1/2, kappa^1/2] (endpoints
+    pinned), made exactly Hermitian as (A + A^H)/2.  Returns (A, U, lam)."""
+    rng = _rng(seed)
+    u = haar_unitary(n, rng)
+    s = np.sqrt(kappa)
+    lam = loguniform_eigs(n, 1.0 / s, s, rng)
+    a = (u * lam[None, :]) @ u.conj().T
+    a = 0.5 * (a + a.conj().T)
+    return np.asfortranarray(a), u, lam
 
 
 def nonsym_shifted(n: int, seed: int) -> np.ndarray:
