@@ -37,7 +37,8 @@ def parse():
     p.add_argument("--seed", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the fixed-FP64 comparator")
-    p.add_argument("--cpu-n", type=int, default=2304)
+    p.add_argument("--cpu-n", type=int, default=None,
+                   help="order of the CPU oracle sample (default: the benchmark's n)")
     p.add_argument("--copy-probe", action="store_true",
                    help="run one 512 MiB device copy first (reference kernel for HBM counters)")
     args = p.parse_args()
@@ -67,6 +68,21 @@ def time_solves(msq, torch, a, prec, steps, warmup):
     return (t1 - t0), x, infos
 
 
+def time_solves_opts(msq, torch, a, prec, steps, warmup):
+    """Like time_solves, with the library's precision escalation on."""
+    x = torch.empty_like(a)
+    for _ in range(warmup):
+        msq.sqrtm(a, prec=prec, tol=1e-13, out=x)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = msq.sqrtm(a, prec=prec, tol=1e-13, out=x)
+        infos.append(info)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, x, infos
+
+
 def recorded_traffic(kernel_class, workload):
     """HBM bytes per launch from a committed counter summary under profiles/,
     valid only while the kernel's source file is unchanged (sha256)."""
@@ -93,23 +109,51 @@ def gpu_relres(torch, x, a):
     return float(r)
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_cpu, n, kappa, seed):
+    """The float64 oracle (Alg. 3 route: Householder tridiagonalisation +
+    implicit QL, X = Q diag(lam^1/2) Q^T) on all host cores, one solve of the
+    benchmark's own matrix (n_cpu = n) or of a same-law matrix of order
+    n_cpu scaled by (n / n_cpu)^3."""
     import oracle
     import workloads as W
     a, _, _ = W.spd(n_cpu, kappa, seed)
+    threads = oracle.lib().orc_get_threads()
     t0 = time.perf_counter()
     oracle.sqrtm_spd(a)
     dt = time.perf_counter() - t0
     scale = (n / n_cpu) ** 3
+    what = (f"one solve of the benchmark matrix (n={n}, kappa={kappa:g}, seed {seed}), {dt:.2f} s"
+            if n_cpu == n else
+            f"one solve at n={n_cpu}, kappa={kappa:g}, {dt:.2f} s, scaled by (n/{n_cpu})^3 to n={n}")
     return {
         "value": 1.0 / (dt * scale),
         "unit": "solves/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"oracle float64 SPD route (Householder tridiagonalisation + implicit QL, "
-                   f"X = Q diag(lam^1/2) Q^T), one solve at n={n_cpu}, kappa={kappa:g}, "
-                   f"{dt:.2f} s, scaled by (n/{n_cpu})^3 to n={n}"),
+                   f"X = Q diag(lam^1/2) Q^T, OpenMP), {what}; host: {host_cpu_model()}, "
+                   f"{os.cpu_count()} logical CPUs visible"),
     }
+
+
+def spd_flops(n, sweeps):
+    """Algorithmic flops of one mixed SPD solve with `sweeps` corrections
+    (symmetry exploited): float32 factorisation 4/3 n^3 (tridiagonalisation)
+    + 4/3 n^3 (eigensolver merges, upper bound) + 2 n^3 (back-transform),
+    X_0 n^3, per correction 6 n^3 (W = R Q, Q^T W upper half, V = Q Y,
+    V Q^T upper half); float64 residuals n^3 each, sweeps + 1 of them."""
+    n3 = float(n) ** 3
+    return {"fp32": (17.0 / 3.0 + 6.0 * sweeps) * n3, "fp64": (sweeps + 1.0) * n3}
 
 
 def run_general(args):
@@ -194,18 +238,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- mixed precision (timed; kernel-class timing on)
-    _lib.profile_enable(False)
+    # ---- mixed precision: timed region without per-launch instrumentation
     for _ in range(args.warmup):
         msq.sqrtm(a, prec="fp32", tol=1e-13, fallback=False)
     torch.cuda.synchronize()
-    _lib.profile_enable(True)
     dt_mixed, x, infos = time_solves(msq, torch, a, "fp32", args.steps, 0)
-    stats = _lib.profile_stats()
-    _lib.profile_enable(False)
     rr_mixed = gpu_relres(torch, x, a)
     steps_mixed = infos[-1]["steps"]
     phases = infos[-1]["t_ms"]
+
+    # ---- the same solves again with HIP events around every kernel launch
+    # (on the launch stream): per-class time, flops and bytes
+    _lib.profile_enable(True)
+    dt_instr, _, _ = time_solves(msq, torch, a, "fp32", args.steps, 0)
+    stats = _lib.profile_stats()
+    _lib.profile_enable(False)
 
     # ---- fixed FP64 Schur method on the same GPU
     fp64 = None
@@ -215,9 +262,21 @@ def main():
                 "relres": gpu_relres(torch, x64, a), "steps": infos64[-1]["steps"],
                 "phases_ms": {k: round(v, 3) for k, v in infos64[-1]["t_ms"].items()}}
 
-    # ---- roofline of the dominant kernel class (live HIP-event timing)
-    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
-    cls, st = dom
+    # ---- learned precision selector (AUTO, fallback on)
+    dta, xa, infa = time_solves_opts(msq, torch, a, "auto", args.steps, args.warmup)
+    auto = {"solves_per_s": args.steps / dta, "ms_per_solve": 1e3 * dta / args.steps,
+            "relres": gpu_relres(torch, xa, a), "prec_used": infa[-1]["prec_used"],
+            "steps": infa[-1]["steps"], "fallbacks": infa[-1]["fallbacks"],
+            "predicted_steps": [round(v, 2) for v in infa[-1]["predicted_steps"]]}
+
+    # ---- roofline of the dominant kernel class
+    classes = {}
+    for k, v in stats.items():
+        base = k.split(":")[0]
+        c = classes.setdefault(base, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        for f in c:
+            c[f] += v[f]
+    cls, st = max(classes.items(), key=lambda kv: kv[1]["ms"])
     if cls.startswith("gemm"):
         peak, unit = PEAK[cls]
         achieved = st["flops"] / (st["ms"] * 1e-3) / 1e12
@@ -231,14 +290,31 @@ def main():
             "unit": unit, "frac": round(achieved / peak, 4),
             "traffic": recorded_traffic(cls, workload),
             "launches_per_solve": st["launches"] / args.steps,
-            "avg_launch_ms": round(st["ms"] / st["launches"], 5)}
-    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in stats.items()}
-    gemm32 = stats.get("gemm_f32")
-    gemm64 = stats.get("gemm_f64")
+            "avg_launch_ms": round(st["ms"] / st["launches"], 5),
+            "timing": "HIP events around each launch on its stream, in a repeat of the timed solves"}
+    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in classes.items()}
+    gemm_tflops = {k: {"tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2),
+                       "frac_peak": round(v["flops"] / (v["ms"] * 1e-3) / 1e12 /
+                                          PEAK[k.split(":")[0]][0], 4),
+                       "us_per_launch": round(1e3 * v["ms"] / v["launches"], 1)}
+                   for k, v in sorted(stats.items()) if k.split(":")[0] in PEAK}
+
+    # ---- whole solve against the FP32 / FP64 matrix peaks
+    fl = spd_flops(n, steps_mixed)
+    t = dt_mixed / args.steps
+    solve_rate = {
+        "fp32_tflops": round(fl["fp32"] / t / 1e12, 2),
+        "fp64_tflops": round(fl["fp64"] / t / 1e12, 2),
+        # time the algorithmic flops would take at the two matrix peaks,
+        # as a fraction of the measured time
+        "matrix_peak_frac": round((fl["fp32"] / (PEAK["gemm_f32"][0] * 1e12) +
+                                   fl["fp64"] / (PEAK["gemm_f64"][0] * 1e12)) / t, 4),
+        "flops": fl,
+    }
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.cpu_n, n, kappa, args.seed)
+        cpu = cpu_baseline(args.cpu_n or n, n, kappa, args.seed)
 
     value = args.steps / dt_mixed
     out = {
@@ -259,11 +335,13 @@ def main():
         "relres": rr_mixed,
         "refinement_steps": steps_mixed,
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "solve_rate": solve_rate,
         "kernel_ms_per_solve": kernel_ms,
+        "instrumented_ms_per_step": round(1e3 * dt_instr / args.steps, 3),
+        "gemm_tflops": gemm_tflops,
         "fp64_schur": fp64,
         "speedup_vs_fp64": (round(value / fp64["solves_per_s"], 4) if fp64 else None),
-        "gemm_f32_tflops": (round(gemm32["flops"] / (gemm32["ms"] * 1e-3) / 1e12, 2) if gemm32 else None),
-        "gemm_f64_tflops": (round(gemm64["flops"] / (gemm64["ms"] * 1e-3) / 1e12, 2) if gemm64 else None),
+        "auto": auto,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

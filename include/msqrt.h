@@ -193,6 +193,14 @@ const char* msqrt_status_string(msqrt_status s);
 /* Last error message recorded by the calling thread (static storage). */
 const char* msqrt_last_error(void);
 
+/* Frees what the library caches between calls: the pool of device
+ * allocations released by finished calls and destroyed factors, the timing
+ * events of msqrt_profile_*, and the selector's device copy.  Call it when no
+ * library call is in flight (later calls allocate again); it gives an ordered
+ * shutdown while the HIP runtime is still up (the Python binding calls it at
+ * interpreter exit).  Live factors keep their memory. */
+void msqrt_release_cached(void);
+
 /* Kernel-class timing for measurement tools.  msqrt_profile_enable(1) clears
  * the counters and starts recording a pair of hipEvents on the launch stream
  * around every launch of an instrumented kernel class ("gemm_f32",

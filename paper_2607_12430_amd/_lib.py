@@ -6,6 +6,7 @@ of any entry point raises, there is no fallback implementation.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -30,6 +31,7 @@ PHASES = ["validate", "select", "reduce", "eig", "back", "x0", "residual", "tran
 EXPORTED = [
     "msqrt_default_options", "msqrt_factor", "msqrt_refine", "msqrt_refine_noalloc", "msqrt_sqrtm",
     "msqrt_sqrtm_backward", "msqrt_factor_destroy", "msqrt_status_string", "msqrt_last_error",
+    "msqrt_release_cached",
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_sy2tr",
     "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
@@ -93,6 +95,11 @@ def lib():
             f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, ci, cd = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.msqrt_release_cached.argtypes = []
+    L.msqrt_release_cached.restype = None
+    # ordered shutdown: cached device memory and events are released while
+    # the HIP runtime is still up
+    atexit.register(L.msqrt_release_cached)
     L.msqrt_default_options.argtypes = [ctypes.POINTER(Options)]
     L.msqrt_default_options.restype = None
     L.msqrt_factor.argtypes = [ctypes.POINTER(Options), ci, i64, vp, i64, i64, vp, ctypes.POINTER(vp)]

@@ -21,6 +21,8 @@
 // is told to mirror the element to (j, i).
 #pragma once
 
+#include <string>
+
 #include <algorithm>
 #include <type_traits>
 #include <vector>
@@ -683,6 +685,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_split_kernel(GemmShape s,
 
 template <typename T>
 struct EpiStore {
+  static constexpr const char* kName = "store";
   static constexpr bool kReduces = false;
   T* C;
   int64_t ldc, sC;
@@ -700,6 +703,7 @@ struct EpiStore {
 // R = ascale * A - acc in float64; writes R_l = fl32(R) and returns R^2
 // (twice for mirrored off-diagonal elements).
 struct EpiResidual {
+  static constexpr const char* kName = "residual";
   static constexpr bool kReduces = true;
   const double* A;
   int64_t lda, sA;
@@ -718,6 +722,7 @@ struct EpiResidual {
 
 // Same residual in float64 but keeping R in float64 (fixed-FP64 path).
 struct EpiResidual64 {
+  static constexpr const char* kName = "residual";
   static constexpr bool kReduces = true;
   const double* A;
   int64_t lda, sA;
@@ -737,6 +742,7 @@ struct EpiResidual64 {
 // y_ij = acc_ij / (s_i + s_j), in the factor precision T.
 template <typename T>
 struct EpiDiagSylv {
+  static constexpr const char* kName = "diagsylv";
   static constexpr bool kReduces = false;
   const T* s;
   int64_t sS;
@@ -756,6 +762,7 @@ struct EpiDiagSylv {
 // Q Y Q^T (Alg. 2/3, last line of the loop).
 template <typename T>
 struct EpiUpdate {
+  static constexpr const char* kName = "update";
   static constexpr bool kReduces = false;
   double* X;
   int64_t ldx, sX;
@@ -773,6 +780,7 @@ struct EpiUpdate {
 // X = fl64(acc) (initial iterate X_0 = Q S Q^T).
 template <typename T>
 struct EpiSetF64 {
+  static constexpr const char* kName = "set_x0";
   static constexpr bool kReduces = false;
   double* X;
   int64_t ldx, sX;
@@ -815,7 +823,8 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
       if (tok >= 0) {
         const double outs = s.tri ? 0.5 * (double)s.N * (s.N + 1) : (double)s.M * s.N;
         const double kk = (double)s.K * (batch - 1) + s.K_last;
-        prof_end(tok, st, "gemm_bf16x3", 2.0 * outs * kk, 0.0);
+        const std::string cls = std::string("gemm_bf16x3:") + Epi::kName;
+        prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
       }
       return;
     }
@@ -856,7 +865,9 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
     // symmetric outputs
     const double outs = s.tri ? 0.5 * (double)s.N * (s.N + 1) : (double)s.M * s.N;
     const double kk = (double)s.K * (batch - 1) + s.K_last;
-    prof_end(tok, st, sizeof(T) == 4 ? "gemm_f32" : "gemm_f64", 2.0 * outs * kk, 0.0);
+    // class "gemm_f32:<epilogue>" / "gemm_f64:<epilogue>"
+    const std::string cls = std::string(sizeof(T) == 4 ? "gemm_f32:" : "gemm_f64:") + Epi::kName;
+    prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
   }
 }
 

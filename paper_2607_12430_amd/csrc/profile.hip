@@ -58,6 +58,14 @@ void resolve_locked() {
 
 bool prof_enabled() { return g_on; }
 
+void prof_release() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  resolve_locked();
+  g_open.clear();  // every recorded begin event is also in the pool now
+  for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
+  g_pool.clear();
+}
+
 int prof_begin(hipStream_t st) {
   if (!g_on) return -1;
   std::lock_guard<std::mutex> lk(g_mu);

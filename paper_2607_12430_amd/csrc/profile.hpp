@@ -9,6 +9,8 @@ namespace msqrt {
 bool prof_enabled();
 // Returns a token (>= 0) or -1 when profiling is off.
 int prof_begin(hipStream_t st);
+// Destroys the cached timing events (pending ones are resolved first).
+void prof_release();
 void prof_end(int token, hipStream_t st, const char* cls, double flops, double bytes);
 
 }  // namespace msqrt

@@ -12,6 +12,7 @@
 #include "../../include/msqrt.h"
 #include "factor.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 #include "tridiag.hpp"
 
 namespace msqrt {
@@ -57,6 +58,20 @@ void* pool_alloc(size_t bytes) {
   }
   return p;
 }
+
+// Frees every cached allocation (each on its own device).
+void pool_release() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : g_pool) {
+    if (hipSetDevice(kv.first.first) == hipSuccess) (void)hipFree(kv.second);
+  }
+  if (have) (void)hipSetDevice(cur);
+  g_pool.clear();
+}
+
+void selector_release();
 
 void pool_free(void* p, size_t bytes) {
   if (!p) return;
@@ -480,6 +495,15 @@ const char* msqrt_status_string(msqrt_status s) {
 }
 
 const char* msqrt_last_error(void) { return g_last_error.c_str(); }
+
+void msqrt_release_cached(void) {
+  try {
+    pool_release();
+    prof_release();
+    selector_release();
+  } catch (...) {
+  }
+}
 
 void msqrt_factor_destroy(msqrt_factor_t f) { delete reinterpret_cast<Factor*>(f); }
 

@@ -399,6 +399,17 @@ float* device_selector(hipStream_t st) {
 
 }  // namespace
 
+void selector_release() {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : g_sel_dev) {
+    if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second);
+  }
+  if (have) (void)hipSetDevice(cur);
+  g_sel_dev.clear();
+}
+
 void launch_features(hipStream_t st, int n, const double* A, int64_t lda, int cplx, float* F) {
   const int nt = (int)ceil_div(n, kFT);
   DevBuf work;
