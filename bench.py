@@ -26,10 +26,15 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="spd", choices=["spd", "nonsym", "complex_square"],
+    p.add_argument("--workload", default="spd",
+                   choices=["spd", "nonsym", "complex_square", "table1"],
                    help="spd (default, the benchmark line); nonsym = real nonsymmetric "
                         "A = 2I + G/sqrt(n) (n=2048, seed 5); complex_square = complex A = B^2 "
-                        "(seed 6): general path, mixed vs FP64 factor, no roofline")
+                        "(seed 6): general path, mixed vs FP64 factor, no roofline; table1 = the "
+                        "paper's test sets I-VII (Table 1): relative time of the mixed solve to "
+                        "the FP64 Schur solve, nullified-stop accuracy traces, Hilbert threshold")
+    p.add_argument("--sets", default="I,II,III,IV,V,VI,VII", help="table1: sets to run")
+    p.add_argument("--trace", type=int, default=8, help="table1: corrections traced per set")
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--n", type=int, default=None)
@@ -44,11 +49,11 @@ def parse():
     args = p.parse_args()
     spd = args.workload == "spd"
     if args.steps is None:
-        args.steps = 10 if spd else 2
+        args.steps = 10 if spd else (3 if args.workload == "table1" else 2)
     if args.warmup is None:
         args.warmup = 3 if spd else 1
     if args.n is None:
-        args.n = {"spd": 4096, "nonsym": 2048, "complex_square": 4096}[args.workload]
+        args.n = {"spd": 4096, "nonsym": 2048, "complex_square": 4096, "table1": 0}[args.workload]
     return args
 
 
@@ -210,12 +215,87 @@ def run_general(args):
     print(json.dumps(out))
 
 
+def run_table1(args):
+    """The paper's Table 1 test sets on one GPU (Sec. 5): for each set the
+    mixed-precision solve (FP32 factor) and the fixed FP64 Schur solve on the
+    same GPU (median of `steps` timed solves each, relative execution time as
+    in Sec. 5.2), and the accuracy trace of Sec. 5.1: the stopping test
+    nullified, relative residual and relative error after every correction,
+    the FP64 solve's output taken as the ground truth (as the paper does).
+    Then the Hilbert threshold: H_1024 + tau I with the FP32 factor and no
+    escalation, over a range of tau."""
+    import numpy as np
+    import torch
+
+    import paper_2607_12430_amd as msq
+    import workloads as W
+
+    def med_time(a, prec):
+        ts = []
+        x = None
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = msq.sqrtm(a, prec=prec, tol=1e-13, fallback=False)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), x, info
+
+    def rel(u, v):
+        return float(torch.linalg.matrix_norm(u - v) / torch.linalg.matrix_norm(v))
+
+    sets = []
+    for sid in [x for x in args.sets.split(",") if x]:
+        a_h, shift = W.table1(sid, 1000 + len(sets))
+        a = torch.from_numpy(np.ascontiguousarray(a_h)).cuda()
+        n = a_h.shape[0]
+        del a_h
+        t32, x32, i32 = med_time(a, "fp32")
+        t64, x64, i64 = med_time(a, "fp64")
+        # nullified-stop trace with the FP32 factor
+        f = msq.factor(a, prec="fp32")
+        x = torch.zeros_like(a)
+        info = msq.refine(f, a, x, init_from_factor=True, maxit=0, tol=-1.0)
+        trace = [{"k": 0, "relres": info["relres"], "relerr": rel(x, x64)}]
+        for k in range(1, args.trace + (8 if sid == "VII" else 0) + 1):
+            info = msq.refine(f, a, x, init_from_factor=False, maxit=1, tol=-1.0)
+            trace.append({"k": k, "relres": info["relres"], "relerr": rel(x, x64)})
+        f.close()
+        rec = {"set": sid, "n": n, "shift": round(shift, 6), "struct": i32["struct_used"],
+               "mixed_ms": round(1e3 * t32, 2), "fp64_ms": round(1e3 * t64, 2),
+               "relative_time": round(t32 / t64, 4), "speedup": round(t64 / t32, 3),
+               "mixed_steps": i32["steps"], "mixed_relres": i32["relres"],
+               "fp64_relres": i64["relres"], "mixed_relerr_vs_fp64": rel(x32, x64),
+               "mixed_phases_ms": {k: round(v, 2) for k, v in i32["t_ms"].items()},
+               "trace": trace}
+        print(json.dumps({"table1_set": rec}), flush=True)
+        sets.append(rec)
+        del a, x, x32, x64
+        torch.cuda.empty_cache()
+    hil = []
+    for tau in (1e-6, 6e-7, 4e-7, 3e-7, 2.8e-7, 2.5e-7, 2e-7, 1.5e-7, 1e-7, 1e-8):
+        a = torch.from_numpy(np.ascontiguousarray(W.hilbert(1024, tau))).cuda()
+        _, info = msq.sqrtm(a, prec="fp32", tol=1e-12, fallback=False, allow_fail=True)
+        hil.append({"tau": tau, "status": info["status"], "corrections": info["steps"],
+                    "relres": info["relres"]})
+    out = {"metric": "relative execution time mixed / FP64 Schur, Table 1 sets (Sec. 5)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+           "config": {"workload": "table1", "sets": [r["set"] for r in sets]},
+           "sets": [{k: v for k, v in r.items() if k != "trace"} for r in sets],
+           "hilbert_threshold_fp32_tol1e-12": hil}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "table1":
+        run_table1(args)
+        return
     if args.workload != "spd":
         run_general(args)
         return

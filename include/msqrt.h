@@ -86,7 +86,8 @@ typedef struct {
   msqrt_prec prec;        /* default MSQRT_PREC_FP32 */
   msqrt_struct structure; /* default MSQRT_STRUCT_AUTO */
   int maxit;              /* maximum number of corrections, default 30 */
-  double tol;             /* stop when ||A - X^2||_F <= tol ||A||_F, default 1e-13 */
+  double tol;             /* stop when ||A - X^2||_F <= tol ||A||_F, default 1e-13;
+                             tol < 0 nullifies the stopping test (see msqrt_refine) */
   int blks;               /* minimal block size of the triangular solvers, default 32 */
   int fallback;           /* 1: escalate BF16SPLIT -> FP32 -> FP64 on failure (default) */
   int64_t batch;          /* number of matrices, default 1 */
@@ -142,7 +143,11 @@ msqrt_status msqrt_factor(const msqrt_options* opt, msqrt_dtype dtype, int64_t n
  * caller-supplied X must be exactly symmetric (the residual is formed as
  * A - X X^T from one triangle): otherwise MSQRT_ERR_INVALID_ARG, with X
  * untouched.  Inf or NaN in A (or in the caller-supplied X of an HPD
- * factor): MSQRT_ERR_NONFINITE. */
+ * factor): MSQRT_ERR_NONFINITE.  tol < 0 nullifies the stopping test, as in
+ * the paper's accuracy experiments (Sec. 5.1): exactly maxit corrections are
+ * applied, every residual is recorded in info, X is the last iterate and the
+ * status is MSQRT_OK (a non-finite residual still ends the loop as
+ * MSQRT_ERR_DIVERGED).  tol = NaN: MSQRT_ERR_INVALID_ARG. */
 msqrt_status msqrt_refine(msqrt_factor_t f, const void* dA, int64_t lda, int64_t strideA,
                           void* dX, int64_t ldx, int64_t strideX, int init_from_factor, int maxit,
                           double tol, hipStream_t stream, msqrt_info* info);

@@ -333,6 +333,8 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
     x0: optional start (float64) instead of X_0 = Q diag(s) Q^T; only with
       `factor`.
     iterates: also return the list of iterates X_0, X_1, ... (unscaled).
+    tol < 0 nullifies the stopping test (the accuracy experiments of Sec. 5.1):
+      exactly maxit corrections, status ok, X the last iterate.
 
     Returns dict(X, steps, hist, status[, iterates]).  steps counts applied
     corrections; hist holds ||R_k||_F / ||A||_F for every residual evaluated.
@@ -401,15 +403,25 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
             hist.append(rr)
             if rr < best[0]:
                 best = (rr, x)
-            if rr <= tol:
-                status = ST_OK
-                break
-            verdict = _stop_rule(hist)
-            if verdict is not None:
-                status = verdict
-                break
-            if it == maxit:
-                break
+            if tol < 0:
+                # nullified stopping test (Sec. 5.1 accuracy experiments):
+                # exactly maxit corrections, the last iterate is kept
+                if not np.isfinite(rr):
+                    status = ST_DIVERGED
+                    break
+                if it == maxit:
+                    status = ST_OK
+                    break
+            else:
+                if rr <= tol:
+                    status = ST_OK
+                    break
+                verdict = _stop_rule(hist)
+                if verdict is not None:
+                    status = verdict
+                    break
+                if it == maxit:
+                    break
             x = x + correction(r)
             steps += 1
     xout = (x if status == ST_OK else best[1]) * (2.0 ** k)

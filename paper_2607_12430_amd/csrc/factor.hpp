@@ -169,6 +169,20 @@ inline Verdict judge(const std::vector<double>& h, double tol) {
   return Verdict::Continue;
 }
 
+// Verdict after residual number it (it = corrections applied so far).  A
+// negative tol nullifies the stopping test, as the paper's accuracy
+// experiments do (Sec. 5.1): exactly maxit corrections are applied and the
+// last iterate is kept (a non-finite residual still stops the loop).
+inline Verdict judge_step(const std::vector<double>& h, double tol, int it, int maxit) {
+  if (tol < 0) {
+    if (!std::isfinite(h.back())) return Verdict::Diverged;
+    return it >= maxit ? Verdict::Converged : Verdict::Continue;
+  }
+  Verdict v = judge(h, tol);
+  if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+  return v;
+}
+
 // Validates A (finiteness, optional exact symmetry), computes ||A_b||_F and
 // the scale exponents into f.  Returns the OR of the per-entry flags
 // (bit0 non-finite, bit1 not symmetric).

@@ -264,7 +264,8 @@ msqrt_status factor_general(Factor* f, const double* A, int64_t lda, int cplx, h
   gehrd<T>(st, n, H, Q, gw);
   if (tm) tm->begin(MSQRT_T_EIG);
   HseqrWork hw;
-  const bool ok = hseqr<T>(st, n, H, Q, hw);
+  // ||H||_F = ||A||_F / 4^k (unitary similarity)
+  const bool ok = hseqr<T>(st, n, H, Q, hw, (T)f->anorm_scaled[0]);
   if (!ok) {
     if (tm) tm->end();
     set_last_error("complex Schur QR did not converge");
@@ -346,8 +347,7 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
     MSQRT_HIP(hipStreamSynchronize(st));
     tm.collect();
     hist.push_back(hrn / f->anorm_scaled[0]);
-    Verdict v = judge(hist, tol);
-    if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+    Verdict v = judge_step(hist, tol, it, maxit);
     if (v != Verdict::Continue) {
       verdict = v;
       break;
@@ -389,8 +389,9 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
     info->nhist = (int)std::min<size_t>(64, hist.size());
     for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
   }
-  if (!cplx && status == MSQRT_OK) {
+  if (!cplx && status == MSQRT_OK && tol >= 0) {
     // a real matrix without eigenvalues on R<=0 has a real principal root
+    // (not asserted for the intermediate iterates of a nullified-stop run)
     const double xa = std::sqrt(sum_host(hx, 0, kRedBlocks));
     const double xi = std::sqrt(sum_host(hx, kRedBlocks, kRedBlocks));
     if (xi > 1e-12 * xa) {
@@ -498,8 +499,7 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
       MSQRT_HIP(hipStreamSynchronize(st));
       tm.collect();
       hist.push_back(hrn / gnorm);
-      Verdict v = judge(hist, tol);
-      if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+      Verdict v = judge_step(hist, tol, it, maxit);
       if (v != Verdict::Continue) {
         verdict = v;
         break;

@@ -48,18 +48,25 @@ template <> __device__ inline double tiny_of<double>() { return 2.22507385850720
 template <typename T>
 __device__ inline T cabs1(cx<T> a) { return fabs(a.r) + fabs(a.i); }
 
-// Rotation with G [f; g] = [r; 0].
+// Rotation with G [f; g] = [r; 0].  c and s do not change when f and g are
+// scaled together, so both are first divided by max(|f|_1, |g|_1): no
+// reciprocal of a tiny |f| or norm is ever formed (a bulge that has decayed
+// to subnormal size, as at the top of a block that is about to deflate,
+// otherwise overflows 1/|f| in float32 and turns the whole window into NaN).
 template <typename T>
 __device__ inline void make_rot(cx<T> f, cx<T> g, T& c, cx<T>& s) {
   const T ag = cabs1(g);
   if (ag == T(0)) { c = T(1); s = {T(0), T(0)}; return; }
-  const T af = hypot(f.r, f.i);
-  const T agg = hypot(g.r, g.i);
-  if (af == T(0)) { c = T(0); s = cscale(cconj(g), T(1) / agg); return; }
+  const T sc = fmax(cabs1(f), ag);
+  const cx<T> fs = {f.r / sc, f.i / sc}, gs = {g.r / sc, g.i / sc};
+  const T af = hypot(fs.r, fs.i);
+  const T agg = hypot(gs.r, gs.i);
+  if (af == T(0)) { c = T(0); s = {gs.r / agg, -gs.i / agg}; return; }
   const T nrm = hypot(af, agg);
   c = af / nrm;
   // s = (f / |f|) conj(g) / nrm
-  s = cscale(cmul(cscale(f, T(1) / af), cconj(g)), T(1) / nrm);
+  const cx<T> p = cmul(cx<T>{fs.r / af, fs.i / af}, cconj(gs));
+  s = {p.r / nrm, p.i / nrm};
 }
 
 // [a; b] <- G [a; b]
@@ -137,9 +144,9 @@ __device__ inline cx<T> wilkinson(cx<T> a, cx<T> b, cx<T> c, cx<T> d) {
 // Single-shift QR on the LDS matrix h (order m) until upper triangular.
 // Returns false if the iteration limit was hit.
 template <typename T>
-__device__ bool lds_qr(cx<T>* h, int ldh, cx<T>* u, int m) {
+__device__ bool lds_qr(cx<T>* h, int ldh, cx<T>* u, int m, T hnorm) {
   __shared__ int sh_l;
-  const T ulp = eps_of<T>(), small = tiny_of<T>() * T(1e4);
+  const T ulp = eps_of<T>(), small = max(tiny_of<T>() * T(1e4), ulp * hnorm);
   int hi = m - 1, its = 0, total = 0;
   const int itmax = 30 * max(10, m);
   const bool w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave) == 0;
@@ -256,7 +263,7 @@ __device__ inline void win_store(const cx<T>* h, const cx<T>* u, T* H, int64_t l
 template <typename T>
 __global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, int b0, int m,
                                                                  int mode, T* Uo, cx<T>* eig,
-                                                                 int* status) {
+                                                                 int* status, T hnorm) {
   constexpr int W = Win<T>::W;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(kQrThreads) void small_schur_kernel(int n, T* H, in
   win_load<T, W, kQrThreads>(h, H, ld, b0, b0, m, 1);
   if (mode == 0) win_identity<T, W, kQrThreads>(u, m);
   __syncthreads();
-  const bool ok = lds_qr<T>(h, ldh, mode == 0 ? u : nullptr, m);
+  const bool ok = lds_qr<T>(h, ldh, mode == 0 ? u : nullptr, m, hnorm);
   __syncthreads();
   if (!ok && threadIdx.x == 0) atomicOr(status, 1);
   if (mode == 1) {
@@ -570,14 +577,20 @@ __global__ __launch_bounds__(kApplyThreads) void apply_u_kernel(int n, T* H, T* 
 }
 
 // Zero negligible subdiagonal entries in (lo, hi] and report the largest such
-// index (or lo) in out[0].
+// index (or lo) in out[0].  Negligible: below ulp times the two adjacent
+// diagonal entries, or below ulp ||H||_F -- a perturbation of that size is
+// within the backward error the factorisation has anyway, and without the
+// norm-wise floor subdiagonals next to eigenvalues much smaller than ||H||
+// can stall above the local threshold in float32 (seen with one large
+// outlier eigenvalue, e.g. a uniform(0, 1) matrix plus shift).
 template <typename T>
-__global__ __launch_bounds__(1024) void deflate_kernel(int n, T* H, int lo, int hi, int* out) {
+__global__ __launch_bounds__(1024) void deflate_kernel(int n, T* H, int lo, int hi, int* out,
+                                                      T hnorm) {
   __shared__ int best;
   const int64_t ld = 2 * (int64_t)n;
   if (threadIdx.x == 0) best = lo;
   __syncthreads();
-  const T ulp = eps_of<T>(), small = tiny_of<T>() * T(1e4);
+  const T ulp = eps_of<T>(), small = max(tiny_of<T>() * T(1e4), ulp * hnorm);
   for (int k = lo + 1 + threadIdx.x; k <= hi; k += blockDim.x) {
     const cx<T> sub = gload(H, ld, k, k - 1);
     const T tst = cabs1(gload(H, ld, k - 1, k - 1)) + cabs1(gload(H, ld, k, k));
@@ -623,7 +636,7 @@ void launch_apply(hipStream_t st, int n, T* H, T* Z, int b0, int bl, const T* U)
 }  // namespace
 
 template <typename T>
-bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
+bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm) {
   constexpr int W = Win<T>::W, NS = Win<T>::NS;
   static bool attr_set = false;
   if (!attr_set) {
@@ -647,7 +660,7 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
   while (hi >= 0) {
     int lo = 0;
     if (hi > 0) {
-      hipLaunchKernelGGL(deflate_kernel<T>, dim3(1), dim3(1024), 0, st, n, H, 0, hi, flag + 1);
+      hipLaunchKernelGGL(deflate_kernel<T>, dim3(1), dim3(1024), 0, st, n, H, 0, hi, flag + 1, hnorm);
       MSQRT_LAUNCH_CHECK();
       MSQRT_HIP(hipMemcpyAsync(&lo, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
       MSQRT_HIP(hipStreamSynchronize(st));
@@ -656,7 +669,7 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
     if (m <= W) {
       if (m > 1) {
         hipLaunchKernelGGL(small_schur_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H,
-                           lo, m, 0, U, shifts, flag);
+                           lo, m, 0, U, shifts, flag, hnorm);
         MSQRT_LAUNCH_CHECK();
         launch_apply<T>(st, n, H, Z, lo, m, U);
       }
@@ -666,12 +679,13 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
     if (++sweeps > max_sweeps) return false;
     if (hi == last_hi && lo == last_lo) ++stuck;
     else stuck = 0;
+    if (stuck > 300) return false;  // no deflation for 300 sweeps: give up early
     last_hi = hi;
     last_lo = lo;
     // shifts: eigenvalues of the trailing NS x NS block
     const int ns = NS;
     hipLaunchKernelGGL(small_schur_kernel<T>, dim3(1), dim3(kQrThreads), win_lds<T>(), st, n, H,
-                       hi - ns + 1, ns, 1, U, shifts, flag);
+                       hi - ns + 1, ns, 1, U, shifts, flag, hnorm);
     MSQRT_LAUNCH_CHECK();
     if (stuck > 0 && stuck % 6 == 0) {
       // exceptional sweep: perturb the shifts by a multiple of the coupling
@@ -727,7 +741,7 @@ bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w) {
   return hflag == 0;
 }
 
-template bool hseqr<float>(hipStream_t, int, float*, float*, HseqrWork&);
-template bool hseqr<double>(hipStream_t, int, double*, double*, HseqrWork&);
+template bool hseqr<float>(hipStream_t, int, float*, float*, HseqrWork&, float);
+template bool hseqr<double>(hipStream_t, int, double*, double*, HseqrWork&, double);
 
 }  // namespace msqrt

@@ -140,8 +140,7 @@ static msqrt_status refine_hpd(Factor* f, const double* A, int64_t lda, int64_t 
       if (done[b]) continue;
       const double r = host_rn[b] / f->anorm_scaled[b];
       hist[b].push_back(r);
-      Verdict v = judge(hist[b], tol);
-      if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+      Verdict v = judge_step(hist[b], tol, it, maxit);
       if (v != Verdict::Continue) {
         done[b] = 1;
         verdict[b] = v;
@@ -312,8 +311,7 @@ static msqrt_status backward_hpd(Factor* f, const double* X, int64_t ldx, const 
       for (int b = 0; b < batch; ++b) {
         if (done[b]) continue;
         hist[b].push_back(host_rn[b] / gnorm[b]);
-        Verdict v = judge(hist[b], tol);
-        if (v == Verdict::Continue && it >= maxit) v = Verdict::Stagnated;
+        Verdict v = judge_step(hist[b], tol, it, maxit);
         if (v != Verdict::Continue) { done[b] = 1; verdict[b] = v; }
       }
     }
@@ -630,7 +628,7 @@ size_t carve_refine_ws(const Factor* f, unsigned char* base, RefineWs* ws) {
 msqrt_status refine_call(Factor* f, const void* dA, int64_t lda, int64_t strideA, void* dX,
                          int64_t ldx, int64_t strideX, int init_from_factor, int maxit, double tol,
                          hipStream_t stream, msqrt_info* info, const RefineWs* ws) {
-  if (!f || !dA || !dX || lda < f->n || ldx < f->n || maxit < 0 || !(tol >= 0)) {
+  if (!f || !dA || !dX || lda < f->n || ldx < f->n || maxit < 0 || std::isnan(tol)) {
     set_last_error("msqrt_refine: invalid argument");
     return MSQRT_ERR_INVALID_ARG;
   }

@@ -24,10 +24,11 @@ struct HseqrWork {
 };
 
 // Complex Schur form by the shifted QR algorithm: H (upper Hessenberg,
-// stacked) becomes upper triangular, Z <- Z U.  Returns false if the
-// iteration did not converge.
+// stacked) becomes upper triangular, Z <- Z U.  hnorm = ||H||_F (sets the
+// norm-wise deflation floor).  Returns false if the iteration did not
+// converge.
 template <typename T>
-bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w);
+bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm);
 
 // Error state of the tile solvers (sticky until trsylv_reset):
 // timed_out = a dataflow wait timed out, nonprincipal = a diagonal entry of T

@@ -1,6 +1,7 @@
 // Test hooks of the general-path stages (include/msqrt_testing.h): host
 // interleaved complex128 in, stage run on the device in complex64 or
 // complex128, host interleaved complex128 out.
+#include <cmath>
 #include <algorithm>
 #include <vector>
 
@@ -53,7 +54,9 @@ msqrt_status gehrd_impl(int n, const double* A, double* H, double* Q, bool schur
   gehrd<T>(nullptr, n, dH, dQ, gw);
   if (schur) {
     HseqrWork hw;
-    if (!hseqr<T>(nullptr, n, dH, dQ, hw)) {
+    double fro = 0.0;
+    for (size_t k = 0; k < 2 * (size_t)n * n; ++k) fro += A[k] * A[k];
+    if (!hseqr<T>(nullptr, n, dH, dQ, hw, (T)std::sqrt(fro))) {
       set_last_error("complex Schur QR did not converge");
       return MSQRT_ERR_NOT_CONVERGED;
     }

@@ -530,3 +530,18 @@ def test_parallel_oracle_bitwise_equals_serial():
             got = run()
         for u, v in zip(ref, got):
             assert np.array_equal(u, v)
+
+
+def test_table1_families_structure_and_shift():
+    """Table 1 generators: symmetric sets are exactly symmetric, the shift
+    reading puts the whole spectrum in the open right half-plane, set VII is
+    the Hilbert matrix plus 1e-6 I."""
+    for sid in ("I", "II", "V", "VI"):
+        a, shift = W.table1(sid, 5, n=160)
+        sigma = np.sqrt(1 / 12.0) if sid in ("I", "V") else 1.0
+        sym = sid in ("V", "VI")
+        assert np.array_equal(a, a.T) == sym
+        assert shift == pytest.approx((2.2 if sym else 1.1) * sigma * np.sqrt(160) + 1.0)
+        assert np.linalg.eigvals(a).real.min() > 0
+    h, tau = W.table1("VII", 0, n=12)
+    assert tau == 1e-6 and h[2, 4] == pytest.approx(1.0 / 7.0) and h[0, 0] == 1.0 + 1e-6

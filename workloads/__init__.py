@@ -23,6 +23,8 @@ can form the known root without running any solver):
   uniform in the disk |z - 2| < 1.5, N strictly upper triangular complex normal
   with standard deviation 0.1/sqrt(n); A = B B.
 * ``hilbert(n, tau)``: H_n + tau I with (H_n)_ij = 1/(i + j - 1), 1-based.
+* ``table1(set_id, seed)``: the test sets I-VII of the paper's Table 1 (the
+  unspecified shift is stated at ``TABLE1``).
 """
 
 from __future__ import annotations
@@ -122,6 +124,41 @@ def hilbert(n: int, tau: float) -> np.ndarray:
     i = np.arange(1, n + 1, dtype=np.float64)
     h = 1.0 / (i[:, None] + i[None, :] - 1.0)
     return np.asfortranarray(h + tau * np.eye(n))
+
+
+# The test sets of the paper's Table 1: (kind, entry law, n).  "Plus shift"
+# is unspecified there; the shift used here is 1.1 times the asymptotic
+# radius of the centred bulk (sigma sqrt(n) for i.i.d. nonsymmetric entries,
+# 2 sigma sqrt(n) for symmetric ones) plus 1, so the bulk lies in Re z > 1.
+TABLE1 = {
+    "I": ("nonsym", "uniform", 2048),
+    "II": ("nonsym", "normal", 2048),
+    "III": ("nonsym", "uniform", 4096),
+    "IV": ("nonsym", "normal", 4096),
+    "V": ("sym", "uniform", 4096),
+    "VI": ("sym", "normal", 4096),
+    "VII": ("hilbert", None, 1024),
+}
+
+
+def table1(set_id: str, seed: int, n: int = None):
+    """Matrix of test set `set_id` (Table 1).  Returns (A, shift).
+    I-IV: A_ij i.i.d. U(0,1) or N(0,1) plus shift; V-VI: A_ij i.i.d. for
+    i >= j, mirrored, plus shift; VII: H_n + 1e-6 I (shift 1e-6)."""
+    kind, law, n0 = TABLE1[set_id]
+    n = n0 if n is None else n
+    if kind == "hilbert":
+        return hilbert(n, 1e-6), 1e-6
+    rng = _rng(seed)
+    g = rng.uniform(size=(n, n)) if law == "uniform" else rng.standard_normal((n, n))
+    sigma = np.sqrt(1.0 / 12.0) if law == "uniform" else 1.0
+    if kind == "sym":
+        low = np.tril(g)
+        g = low + np.tril(low, -1).T
+        shift = 2.2 * sigma * np.sqrt(n) + 1.0
+    else:
+        shift = 1.1 * sigma * np.sqrt(n) + 1.0
+    return np.asfortranarray(g + shift * np.eye(n)), float(shift)
 
 
 def gaussian(shape, seed: int) -> np.ndarray:
