@@ -23,6 +23,10 @@ What it computes (each function cites the passage of the paper it follows):
   update in double precision, with the stopping rule of Alg. 2 and the
   divergence / stagnation rules stated below.  Used for step counts and the
   failure paths without a GPU.
+* ``rootm3``, ``trroot3``, ``trsyl3`` / ``rtrsyl3``, ``emulate_mixed_root3``:
+  the matrix cube root of Sec. 4 (Schur method, the generalized triangular
+  Sylvester equation S^2 Y + S Y St + Y St^2 = C by substitution and by the
+  block recursion, and the mixed-precision framework for p = 3).
 * ``mlp_*``: float64 forward/backward of the small precision-selector network.
 """
 
@@ -61,6 +65,16 @@ def lib():
         _lib.orc_rtrsyl_z.argtypes = [i, i, dp, dp, dp, i]
         _lib.orc_rtrsyl_c.argtypes = [i, i, fp, fp, fp, i]
         _lib.orc_adjoint_z.argtypes = [i, dp, dp, dp]
+        _lib.orc_trroot3_z.argtypes = [i, dp, dp]
+        _lib.orc_trroot3_c.argtypes = [i, fp, fp]
+        _lib.orc_trsyl3_z.argtypes = [i, i, dp, dp, dp, dp]
+        _lib.orc_rtrsyl3_z.argtypes = [i, i, dp, dp, dp, i]
+        _lib.orc_rtrsyl3_c.argtypes = [i, i, fp, fp, fp, i]
+        _lib.orc_rootm3_z.argtypes = [i, dp, dp, dp, dp, dp]
+        for f in ("orc_trroot3_z", "orc_trroot3_c", "orc_rootm3_z"):
+            getattr(_lib, f).restype = ctypes.c_int
+        for f in ("orc_trsyl3_z", "orc_rtrsyl3_z", "orc_rtrsyl3_c"):
+            getattr(_lib, f).restype = None
         _lib.orc_set_threads.argtypes = [i]
         _lib.orc_set_threads.restype = None
         _lib.orc_get_threads.argtypes = []
@@ -196,6 +210,159 @@ def sqrtm_spd(a):
         raise OracleError("sqrtm_spd: matrix is not positive definite")
     x = (q * np.sqrt(lam)[None, :]) @ q.T
     return np.asfortranarray(0.5 * (x + x.T))
+
+
+# ---------------------------------------------------------------------------
+# Matrix cube roots (Sec. 4, p = 3)
+
+
+def trroot3(t, single=False):
+    """U = T^{1/3} for upper triangular T: principal cube roots on the
+    diagonal and the Schur-method recurrence for p = 3 (see oracle.cpp)."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    t = _f(t, dt)
+    n = t.shape[0]
+    u = np.zeros((n, n), dtype=dt, order="F")
+    fn = lib().orc_trroot3_c if single else lib().orc_trroot3_z
+    _check(fn(n, _ptr(t, ct), _ptr(u, ct)), "trroot3")
+    return u
+
+
+def rootm3(a, return_factors=False, imag_tol=1e-12):
+    """Principal cube root (Sec. 4 definition: X^3 = A, eigenvalues in
+    |arg z| < pi/3) by the float64 Schur method: A = Q T Q^H, U = T^{1/3},
+    X = Q U Q^H.  Real input returns the real part after asserting that the
+    imaginary part is at rounding level."""
+    a = np.asarray(a)
+    is_real = not np.iscomplexobj(a)
+    az = _f(a, np.complex128)
+    n = az.shape[0]
+    if not np.all(np.isfinite(az)):
+        raise OracleError("rootm3: non-finite input")
+    x = np.zeros((n, n), dtype=np.complex128, order="F")
+    q, t, u = np.zeros_like(x), np.zeros_like(x), np.zeros_like(x)
+    dp = ctypes.c_double
+    _check(lib().orc_rootm3_z(n, _ptr(az, dp), _ptr(x, dp), _ptr(q, dp), _ptr(t, dp), _ptr(u, dp)),
+           "rootm3")
+    if is_real:
+        nx, ni = np.linalg.norm(x), np.linalg.norm(x.imag)
+        if nx > 0 and ni > imag_tol * nx:
+            raise OracleError(f"rootm3: real input gave imaginary part {ni / nx:.2e}")
+        x = np.asfortranarray(x.real)
+    return (x, {"Q": q, "T": t, "U": u}) if return_factors else x
+
+
+def trsyl3(s, st, c):
+    """S^2 Y + S Y St + Y St^2 = C (S, St upper triangular), unblocked
+    substitution (complex128)."""
+    s, st, c = _f(s, np.complex128), _f(st, np.complex128), _f(c, np.complex128)
+    m, n = c.shape
+    y = np.zeros((m, n), dtype=np.complex128, order="F")
+    dp = ctypes.c_double
+    lib().orc_trsyl3_z(m, n, _ptr(s, dp), _ptr(st, dp), _ptr(c, dp), _ptr(y, dp))
+    return y
+
+
+def rtrsyl3(s, st, c, blks=32, single=False):
+    """The p = 3 block recursion of Sec. 4 for S^2 Y + S Y St + Y St^2 = C."""
+    dt = np.complex64 if single else np.complex128
+    ct = ctypes.c_float if single else ctypes.c_double
+    s, st = _f(s, dt), _f(st, dt)
+    y = _f(c, dt).copy(order="F")
+    m, n = y.shape
+    fn = lib().orc_rtrsyl3_c if single else lib().orc_rtrsyl3_z
+    fn(m, n, _ptr(s, ct), _ptr(st, ct), _ptr(y, ct), int(blks))
+    return y
+
+
+def kron_sylvester3(s, st, c):
+    """Brute force: (I kron S^2 + St^T kron S + (St^2)^T kron I) vec(Y) = vec(C),
+    the vec form of the p = 3 correction operator (Sec. 4 with Sec. 3.1)."""
+    s = np.asarray(s, dtype=np.complex128)
+    st = np.asarray(st, dtype=np.complex128)
+    c = np.asarray(c, dtype=np.complex128)
+    m, n = c.shape
+    big = (np.kron(np.eye(n), s @ s) + np.kron(st.T, s) + np.kron((st @ st).T, np.eye(m)))
+    y = np.linalg.solve(big, c.reshape(-1, order="F"))
+    return y.reshape((m, n), order="F")
+
+
+def scale_exponent3(a):
+    """k with A/8^k of Frobenius norm near sqrt(n): exact scaling for the
+    cube root (X is scaled by 2^-k)."""
+    n = a.shape[0]
+    nrm = np.linalg.norm(a)
+    if nrm == 0 or n == 0:
+        return 0
+    return int(np.round(np.log(nrm / np.sqrt(n)) / np.log(8.0)))
+
+
+def emulate_mixed_root3(a, maxit=30, tol=1e-13, blks=32, iterates=False):
+    """The Sec. 4 framework for p = 3: X_0 from the single-precision Schur
+    cube root, residual R = A - X^3 in double precision, correction from
+    S^2 Y + S Y S + Y S^2 = Q^H fl_l(R) Q in single precision (the p = 3
+    block recursion), X += Q Y Q^H in double precision; stopping and
+    divergence rules as in emulate_mixed (tol < 0 nullifies the stop)."""
+    a = np.asarray(a)
+    is_real = not np.iscomplexobj(a)
+    if not np.all(np.isfinite(a)):
+        return {"X": None, "steps": 0, "hist": [], "status": ST_NONFINITE}
+    k = scale_exponent3(a)
+    asc = a / (8.0 ** k)
+    na = np.linalg.norm(asc)
+    t, q = schur(asc.astype(np.complex64), single=True)
+    d = np.diag(t)
+    if np.any((d.imag == 0) & (d.real <= 0)):
+        return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
+    u = trroot3(t, single=True)
+    qh = q.conj().T
+    x0 = (q @ u @ qh).astype(np.complex128)
+    x = x0.real.copy() if is_real else x0
+
+    def correction(r):
+        rl = r.astype(np.complex64)
+        y = rtrsyl3(u, u, qh @ rl @ q, blks=blks, single=True)
+        dx = (q @ y @ qh).astype(np.complex128)
+        return dx.real if is_real else dx
+
+    hist, seq = [], []
+    best = (np.inf, x)
+    status = ST_NOT_CONVERGED
+    steps = 0
+    with np.errstate(over="ignore", invalid="ignore"):
+        for it in range(maxit + 1):
+            if iterates:
+                seq.append(x * (2.0 ** k))
+            r = asc - x @ x @ x
+            rr = float(np.linalg.norm(r) / na)
+            hist.append(rr)
+            if rr < best[0]:
+                best = (rr, x)
+            if tol < 0:
+                if not np.isfinite(rr):
+                    status = ST_DIVERGED
+                    break
+                if it == maxit:
+                    status = ST_OK
+                    break
+            else:
+                if rr <= tol:
+                    status = ST_OK
+                    break
+                verdict = _stop_rule(hist)
+                if verdict is not None:
+                    status = verdict
+                    break
+                if it == maxit:
+                    break
+            x = x + correction(r)
+            steps += 1
+    xout = (x if status == ST_OK else best[1]) * (2.0 ** k)
+    out = {"X": xout, "steps": steps, "hist": hist, "status": status}
+    if iterates:
+        out["iterates"] = seq
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -452,6 +452,217 @@ void rtrsyl(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, C<R>*
 }
 
 // ---------------------------------------------------------------------------
+// Matrix cube roots (Sec. 4, p = 3).
+
+// Principal cube root of z (z not on the closed negative real axis):
+// |z|^{1/3} e^{i arg(z)/3} with arg in (-pi, pi).
+template <class R> C<R> ccbrt_principal(C<R> z) {
+  if (z.real() == R(0) && z.imag() == R(0)) return C<R>(0, 0);
+  const R r = std::cbrt(std::abs(z));
+  const R th = std::atan2(z.imag(), z.real()) / R(3);
+  return C<R>(r * std::cos(th), r * std::sin(th));
+}
+
+// Cube root of an upper triangular matrix: U with U^3 = T, principal cube
+// roots on the diagonal.  With V = U^2, entry (i, j), i < j, of U^3 = U V
+// and of V = U U give
+//   v_ij = (u_ii + u_jj) u_ij + a_ij,            a_ij = sum_{i<k<j} u_ik u_kj,
+//   (u_ii^2 + u_ii u_jj + u_jj^2) u_ij = t_ij - u_ii a_ij - b_ij,
+//                                                 b_ij = sum_{i<k<j} u_ik v_kj,
+// solved column by column (j ascending, i descending), the Schur method for
+// p-th roots specialised to p = 3.  Returns 2 if a diagonal entry of T lies
+// on the closed negative real axis.
+template <class R> int trroot3(int n, const C<R>* t, C<R>* u) {
+  std::vector<C<R>> v((size_t)n * n, C<R>(0, 0));
+  for (size_t k = 0; k < (size_t)n * n; ++k) u[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    C<R> d = t[i + (size_t)i * n];
+    if (d.imag() == R(0) && d.real() <= R(0)) return 2;
+    u[i + (size_t)i * n] = ccbrt_principal<R>(d);
+    v[i + (size_t)i * n] = u[i + (size_t)i * n] * u[i + (size_t)i * n];
+  }
+  for (int j = 1; j < n; ++j) {
+    for (int i = j - 1; i >= 0; --i) {
+      C<R> a = 0, b = 0;
+      for (int k = i + 1; k <= j - 1; ++k) {
+        a += u[i + (size_t)k * n] * u[k + (size_t)j * n];
+        b += u[i + (size_t)k * n] * v[k + (size_t)j * n];
+      }
+      const C<R> ui = u[i + (size_t)i * n], uj = u[j + (size_t)j * n];
+      const C<R> x = (t[i + (size_t)j * n] - ui * a - b) / (ui * ui + ui * uj + uj * uj);
+      u[i + (size_t)j * n] = x;
+      v[i + (size_t)j * n] = (ui + uj) * x + a;
+    }
+  }
+  return 0;
+}
+
+// Cm(mxn) -= A(mxk) * B(kxn) * Cr(nxp)... helpers for the generalized
+// equation use plain products into temporaries.
+template <class R>
+void mat_mul(int m, int n, int k, const C<R>* A, int lda, const C<R>* B, int ldb, C<R>* D,
+             int ldd) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) D[i + (size_t)j * ldd] = 0;
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < k; ++l) {
+      const C<R> b = B[l + (size_t)j * ldb];
+      for (int i = 0; i < m; ++i) D[i + (size_t)j * ldd] += A[i + (size_t)l * lda] * b;
+    }
+}
+
+// Base case of the p = 3 equation S^2 Y + S Y St + Y St^2 = Cm (S m x m, St
+// n x n upper triangular): Bartels-Stewart-type substitution, columns left
+// to right and rows bottom to top.  The coefficient of y_ij is
+// s_ii^2 + s_ii st_jj + st_jj^2; every other term involves entries of Y
+// already known, with U = Y St accumulated column by column.
+template <class R>
+void trsyl3(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, const C<R>* Cm, int ldC,
+            C<R>* Y, int ldY) {
+  std::vector<C<R>> S2((size_t)m * m), T2((size_t)n * n), U((size_t)m * n, C<R>(0, 0));
+  mat_mul<R>(m, m, m, S, ldS, S, ldS, S2.data(), m);
+  mat_mul<R>(n, n, n, St, ldT, St, ldT, T2.data(), n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = m - 1; i >= 0; --i) {
+      C<R> acc = Cm[i + (size_t)j * ldC];
+      // (S^2 Y)_ij without the diagonal term
+      for (int k = i + 1; k < m; ++k) acc -= S2[i + (size_t)k * m] * Y[k + (size_t)j * ldY];
+      // (S Y St)_ij = sum_{k >= i} s_ik (Y St)_kj: rows k > i are complete in U
+      for (int k = i + 1; k < m; ++k) acc -= S[i + (size_t)k * ldS] * U[k + (size_t)j * m];
+      //   k = i: s_ii sum_{l < j} y_il st_lj (the l = j term is on the left)
+      C<R> yst = 0;
+      for (int l = 0; l < j; ++l) yst += Y[i + (size_t)l * ldY] * St[l + (size_t)j * ldT];
+      acc -= S[i + (size_t)i * ldS] * yst;
+      // (Y St^2)_ij without the diagonal term
+      for (int l = 0; l < j; ++l) acc -= Y[i + (size_t)l * ldY] * T2[l + (size_t)j * n];
+      const C<R> si = S[i + (size_t)i * ldS], tj = St[j + (size_t)j * ldT];
+      const C<R> y = acc / (si * si + si * tj + tj * tj);
+      Y[i + (size_t)j * ldY] = y;
+      U[i + (size_t)j * m] = yst + y * tj;
+    }
+  }
+}
+
+// Cm(mxn) -= A(mxk) B(kxn).
+template <class R>
+void sub_prod(int m, int n, int k, const C<R>* A, int lda, const C<R>* B, int ldb, C<R>* Cm,
+              int ldc) {
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < k; ++l) {
+      const C<R> b = B[l + (size_t)j * ldb];
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldc] -= A[i + (size_t)l * lda] * b;
+    }
+}
+
+// Cm(mxn) -= A(mxk) B(kxl) D(lxn) (B, D may be rectangular blocks).
+template <class R>
+void sub_prod3(int m, int n, int k, int l, const C<R>* A, int lda, const C<R>* B, int ldb,
+               const C<R>* D, int ldd, C<R>* Cm, int ldc) {
+  std::vector<C<R>> tmp((size_t)k * n);
+  mat_mul<R>(k, n, l, B, ldb, D, ldd, tmp.data(), k);
+  sub_prod<R>(m, n, k, A, lda, tmp.data(), k, Cm, ldc);
+}
+
+// (X Y + Z W) for blocks: D = A11 A12 + A12 A22 with A = [A11 A12; 0 A22],
+// the (1,2) block of A^2 (A11 is m1 x m1, A22 m2 x m2).
+template <class R>
+std::vector<C<R>> square_12(int m1, int m2, const C<R>* A, int lda) {
+  std::vector<C<R>> d((size_t)m1 * m2), t((size_t)m1 * m2);
+  const C<R>* A11 = A;
+  const C<R>* A12 = A + (size_t)m1 * lda;
+  const C<R>* A22 = A + m1 + (size_t)m1 * lda;
+  mat_mul<R>(m1, m2, m1, A11, lda, A12, lda, d.data(), m1);
+  mat_mul<R>(m1, m2, m2, A12, lda, A22, lda, t.data(), m1);
+  for (size_t x = 0; x < d.size(); ++x) d[x] += t[x];
+  return d;
+}
+
+// Block recursion for S^2 Y + S Y St + Y St^2 = Cm (Sec. 4, p = 3), the
+// analogue of Alg. 1: the diagonal blocks are split at floor(m/2) (floor(n/2))
+// and the four block equations of Sec. 4 are solved in the order
+// Y21, Y11, Y22, Y12; when only one side is large, only that side is split
+// (the same block algebra with one block row or column).  Cm is overwritten
+// by Y.
+template <class R>
+void rtrsyl3(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, C<R>* Cm, int ldC,
+             int blks) {
+  if (m <= 0 || n <= 0) return;
+  if (m <= blks && n <= blks) {
+    std::vector<C<R>> y((size_t)m * n, C<R>(0, 0));
+    trsyl3<R>(m, n, S, ldS, St, ldT, Cm, ldC, y.data(), m);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldC] = y[i + (size_t)j * m];
+    return;
+  }
+  if (2 * n <= m) {
+    // rows only: S = [S11 S12; 0 S22], Y = [Y1; Y2]
+    const int m1 = m / 2, m2 = m - m1;
+    const C<R>* S11 = S;
+    const C<R>* S12 = S + (size_t)m1 * ldS;
+    const C<R>* S22 = S + m1 + (size_t)m1 * ldS;
+    C<R>* C1 = Cm;
+    C<R>* C2 = Cm + m1;
+    rtrsyl3<R>(m2, n, S22, ldS, St, ldT, C2, ldC, blks);                  // Y2
+    std::vector<C<R>> s2_12 = square_12<R>(m1, m2, S, ldS);
+    sub_prod<R>(m1, n, m2, s2_12.data(), m1, C2, ldC, C1, ldC);           // -(S^2)_12 Y2
+    sub_prod3<R>(m1, n, m2, n, S12, ldS, C2, ldC, St, ldT, C1, ldC);      // -S12 Y2 St
+    rtrsyl3<R>(m1, n, S11, ldS, St, ldT, C1, ldC, blks);                  // Y1
+    return;
+  }
+  if (2 * m <= n) {
+    // columns only: St = [T11 T12; 0 T22], Y = [Y1 Y2]
+    const int n1 = n / 2, n2 = n - n1;
+    const C<R>* T11 = St;
+    const C<R>* T12 = St + (size_t)n1 * ldT;
+    const C<R>* T22 = St + n1 + (size_t)n1 * ldT;
+    C<R>* C1 = Cm;
+    C<R>* C2 = Cm + (size_t)n1 * ldC;
+    rtrsyl3<R>(m, n1, S, ldS, T11, ldT, C1, ldC, blks);                   // Y1
+    sub_prod3<R>(m, n2, m, n1, S, ldS, C1, ldC, T12, ldT, C2, ldC);       // -S Y1 T12
+    std::vector<C<R>> t2_12 = square_12<R>(n1, n2, St, ldT);
+    sub_prod<R>(m, n2, n1, C1, ldC, t2_12.data(), n1, C2, ldC);           // -Y1 (St^2)_12
+    rtrsyl3<R>(m, n2, S, ldS, T22, ldT, C2, ldC, blks);                   // Y2
+    return;
+  }
+  const int m1 = m / 2, m2 = m - m1, n1 = n / 2, n2 = n - n1;
+  const C<R>* S11 = S;
+  const C<R>* S12 = S + (size_t)m1 * ldS;
+  const C<R>* S22 = S + m1 + (size_t)m1 * ldS;
+  const C<R>* T11 = St;
+  const C<R>* T12 = St + (size_t)n1 * ldT;
+  const C<R>* T22 = St + n1 + (size_t)n1 * ldT;
+  C<R>* C11 = Cm;
+  C<R>* C21 = Cm + m1;
+  C<R>* C12 = Cm + (size_t)n1 * ldC;
+  C<R>* C22 = Cm + m1 + (size_t)n1 * ldC;
+  const std::vector<C<R>> s2_12 = square_12<R>(m1, m2, S, ldS);   // S11 S12 + S12 S22
+  const std::vector<C<R>> t2_12 = square_12<R>(n1, n2, St, ldT);  // T11 T12 + T12 T22
+  // Y21: S22^2 Y21 + S22 Y21 T11 + Y21 T11^2 = C21
+  rtrsyl3<R>(m2, n1, S22, ldS, T11, ldT, C21, ldC, blks);
+  // Y11: ... = C11 - (S11 S12 + S12 S22) Y21 - S12 Y21 T11
+  sub_prod<R>(m1, n1, m2, s2_12.data(), m1, C21, ldC, C11, ldC);
+  sub_prod3<R>(m1, n1, m2, n1, S12, ldS, C21, ldC, T11, ldT, C11, ldC);
+  rtrsyl3<R>(m1, n1, S11, ldS, T11, ldT, C11, ldC, blks);
+  // Y22: ... = C22 - Y21 (T11 T12 + T12 T22) - S22 Y21 T12
+  sub_prod<R>(m2, n2, n1, C21, ldC, t2_12.data(), n1, C22, ldC);
+  sub_prod3<R>(m2, n2, m2, n1, S22, ldS, C21, ldC, T12, ldT, C22, ldC);
+  rtrsyl3<R>(m2, n2, S22, ldS, T22, ldT, C22, ldC, blks);
+  // Y12: ... = C12 - (S11 S12 + S12 S22) Y22 - S12 Y22 T22
+  //            - Y11 (T11 T12 + T12 T22) - (S11 Y11 + S12 Y21) T12
+  sub_prod<R>(m1, n2, m2, s2_12.data(), m1, C22, ldC, C12, ldC);
+  sub_prod3<R>(m1, n2, m2, n2, S12, ldS, C22, ldC, T22, ldT, C12, ldC);
+  sub_prod<R>(m1, n2, n1, C11, ldC, t2_12.data(), n1, C12, ldC);
+  {
+    std::vector<C<R>> w((size_t)m1 * n1), t((size_t)m1 * n1);
+    mat_mul<R>(m1, n1, m1, S11, ldS, C11, ldC, w.data(), m1);
+    mat_mul<R>(m1, n1, m2, S12, ldS, C21, ldC, t.data(), m1);
+    for (size_t x = 0; x < w.size(); ++x) w[x] += t[x];
+    sub_prod<R>(m1, n2, n1, w.data(), m1, T12, ldT, C12, ldC);
+  }
+  rtrsyl3<R>(m1, n2, S11, ldS, T22, ldT, C12, ldC, blks);
+}
+
+// ---------------------------------------------------------------------------
 // Real symmetric eigendecomposition A = Q diag(lam) Q^T: Householder
 // tridiagonalisation with explicit accumulation of Q, then the implicit
 // symmetric QR iteration with Wilkinson shifts (Golub & Van Loan, Sec. 8.3),
@@ -645,6 +856,57 @@ int orc_sqrtm_z(int n, const double* a_in, double* x_out, double* q_out, double*
   if (q_out) std::memcpy(q_out, q.data(), sizeof(Z) * (size_t)n * n);
   if (t_out) std::memcpy(t_out, a.data(), sizeof(Z) * (size_t)n * n);
   if (s_out) std::memcpy(s_out, s.data(), sizeof(Z) * (size_t)n * n);
+  return 0;
+}
+
+// Triangular cube root (complex128 / complex64).
+int orc_trroot3_z(int n, const double* t, double* u) {
+  return orc::trroot3<double>(n, reinterpret_cast<const C<double>*>(t), reinterpret_cast<C<double>*>(u));
+}
+int orc_trroot3_c(int n, const float* t, float* u) {
+  return orc::trroot3<float>(n, reinterpret_cast<const C<float>*>(t), reinterpret_cast<C<float>*>(u));
+}
+
+// p = 3 generalized triangular Sylvester equation: unblocked substitution
+// (y = solution) and the block recursion (cm overwritten by Y).
+void orc_trsyl3_z(int m, int n, const double* s, const double* st, const double* cm, double* y) {
+  using Z = C<double>;
+  std::vector<Z> yy((size_t)m * n, Z(0, 0));
+  orc::trsyl3<double>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                      reinterpret_cast<const Z*>(cm), m, yy.data(), m);
+  std::memcpy(y, yy.data(), sizeof(Z) * (size_t)m * n);
+}
+void orc_rtrsyl3_z(int m, int n, const double* s, const double* st, double* cm, int blks) {
+  using Z = C<double>;
+  orc::rtrsyl3<double>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                       reinterpret_cast<Z*>(cm), m, blks);
+}
+void orc_rtrsyl3_c(int m, int n, const float* s, const float* st, float* cm, int blks) {
+  using Z = C<float>;
+  orc::rtrsyl3<float>(m, n, reinterpret_cast<const Z*>(s), m, reinterpret_cast<const Z*>(st), n,
+                      reinterpret_cast<Z*>(cm), m, blks);
+}
+
+// Principal cube root by the Schur method: A = Q T Q^H, U = T^{1/3},
+// X = Q U Q^H (complex128).  Optionally returns Q, T, U.
+int orc_rootm3_z(int n, const double* a_in, double* x_out, double* q_out, double* t_out,
+                 double* u_out) {
+  using Z = C<double>;
+  std::vector<Z> a(reinterpret_cast<const Z*>(a_in), reinterpret_cast<const Z*>(a_in) + (size_t)n * n);
+  std::vector<Z> q((size_t)n * n), u((size_t)n * n), tmp((size_t)n * n), x((size_t)n * n),
+      qh((size_t)n * n);
+  int st = orc::schur<double>(n, a.data(), q.data());
+  if (st) return st;
+  st = orc::trroot3<double>(n, a.data(), u.data());
+  if (st) return st;
+  orc::cgemm<double>(n, q.data(), u.data(), tmp.data());
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) qh[i + (size_t)j * n] = std::conj(q[j + (size_t)i * n]);
+  orc::cgemm<double>(n, tmp.data(), qh.data(), x.data());
+  std::memcpy(x_out, x.data(), sizeof(Z) * (size_t)n * n);
+  if (q_out) std::memcpy(q_out, q.data(), sizeof(Z) * (size_t)n * n);
+  if (t_out) std::memcpy(t_out, a.data(), sizeof(Z) * (size_t)n * n);
+  if (u_out) std::memcpy(u_out, u.data(), sizeof(Z) * (size_t)n * n);
   return 0;
 }
 

@@ -545,3 +545,99 @@ def test_table1_families_structure_and_shift():
         assert np.linalg.eigvals(a).real.min() > 0
     h, tau = W.table1("VII", 0, n=12)
     assert tau == 1e-6 and h[2, 4] == pytest.approx(1.0 / 7.0) and h[0, 0] == 1.0 + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Matrix cube roots (Sec. 4, p = 3)
+
+
+def _cube_root_pair(n, seed, cplx=True):
+    """A = B^3 with B = Q (D + N) Q^H, D uniform in |z - 2| < 1 (so
+    |arg| < 30 degrees and B is the principal cube root of A)."""
+    r = rng(seed)
+    z = r.standard_normal((n, n)) + (1j * r.standard_normal((n, n)) if cplx else 0)
+    q, _ = np.linalg.qr(z)
+    rad = np.sqrt(r.uniform(size=n))
+    ang = 2 * np.pi * r.uniform(size=n)
+    d = 2.0 + rad * np.exp(1j * ang)
+    if not cplx:
+        d = 2.0 + rad * np.cos(ang)
+    nn = np.triu(r.standard_normal((n, n)), 1) * (0.1 / np.sqrt(n))
+    b = q @ (np.diag(d) + nn) @ q.conj().T
+    return b @ b @ b, b
+
+
+def test_cube_root_diagonal_and_2x2_closed_forms():
+    d = np.array([8.0, 0.125, 2.0 + 1j, -3.0 + 1e-3j, -3.0 - 1e-3j, 1j, 1e-9])
+    x = oracle.rootm3(np.diag(d))
+    expect = d.astype(np.complex128) ** (1.0 / 3.0)  # numpy's principal branch
+    assert np.allclose(np.diag(x), expect, rtol=1e-14, atol=0)
+    assert np.all(np.abs(np.angle(np.diag(x))) < np.pi / 3)
+    # [[a, b], [0, c]]^(1/3) = [[a^1/3, b / (a^2/3 + a^1/3 c^1/3 + c^2/3)], [0, c^1/3]]
+    a, b, c = 2.0 + 1j, -0.5 + 3j, 0.3 - 0.1j
+    u = oracle.trroot3(np.array([[a, b], [0, c]]))
+    ra, rc = a ** (1 / 3), c ** (1 / 3)
+    assert np.abs(u - np.array([[ra, b / (ra * ra + ra * rc + rc * rc)], [0, rc]])).max() <= 1e-15 * 8
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_cube_root_known_root_library_and_invariants(cplx):
+    import scipy.linalg as sl
+    a, b = _cube_root_pair(60, 31 + cplx, cplx)
+    if not cplx:
+        a, b = a.real, b.real
+    x = oracle.rootm3(a)
+    assert np.iscomplexobj(x) == cplx
+    assert oracle.relerr(x, b) <= 1e-12
+    assert np.linalg.norm(x @ x @ x - a) / np.linalg.norm(a) <= 1e-13
+    assert np.linalg.norm(x @ a - a @ x) / (np.linalg.norm(x) * np.linalg.norm(a)) <= 1e-14
+    assert np.all(np.abs(np.angle(np.linalg.eigvals(x))) < np.pi / 3)
+    xs = sl.fractional_matrix_power(a, 1.0 / 3.0)  # Schur-Pade, an independent method
+    assert oracle.relerr(x, xs) <= 1e-11
+
+
+@pytest.mark.parametrize("m,n,blks", [(9, 7, 64), (9, 7, 2), (40, 6, 4), (5, 37, 4), (33, 29, 8)])
+def test_rtrsyl3_every_branch_against_kronecker(m, n, blks):
+    r = rng(100 + m + n)
+    s = np.triu(r.standard_normal((m, m)) + 1j * r.standard_normal((m, m))) * 0.3 + 2 * np.eye(m)
+    st = np.triu(r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))) * 0.3 + 2 * np.eye(n)
+    c = r.standard_normal((m, n)) + 1j * r.standard_normal((m, n))
+    ref = oracle.kron_sylvester3(s, st, c)
+    for y in (oracle.trsyl3(s, st, c), oracle.rtrsyl3(s, st, c, blks=blks)):
+        assert oracle.relerr(y, ref) <= 1e-13
+
+
+def test_rtrsyl3_block_equations_of_one_level():
+    """The four block equations of Sec. 4 hold for the blocks of the
+    recursion's solution (one level, split at floor(m/2), floor(n/2))."""
+    r = rng(7)
+    m = n = 24
+    s = np.triu(r.standard_normal((m, m)) + 1j * r.standard_normal((m, m))) * 0.3 + 2 * np.eye(m)
+    st = np.triu(r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))) * 0.3 + 2 * np.eye(n)
+    c = r.standard_normal((m, n)) + 1j * r.standard_normal((m, n))
+    y = oracle.rtrsyl3(s, st, c, blks=4)
+    h, g = m // 2, n // 2
+    S11, S12, S22 = s[:h, :h], s[:h, h:], s[h:, h:]
+    T11, T12, T22 = st[:g, :g], st[:g, g:], st[g:, g:]
+    Y11, Y12, Y21, Y22 = y[:h, :g], y[:h, g:], y[h:, :g], y[h:, g:]
+    C11, C12, C21, C22 = c[:h, :g], c[:h, g:], c[h:, :g], c[h:, g:]
+
+    def op(sa, yy, tb):
+        return sa @ sa @ yy + sa @ yy @ tb + yy @ tb @ tb
+
+    s2_12 = S11 @ S12 + S12 @ S22
+    t2_12 = T11 @ T12 + T12 @ T22
+    tol = 1e-12 * np.linalg.norm(c)
+    assert np.linalg.norm(op(S22, Y21, T11) - C21) <= tol
+    assert np.linalg.norm(op(S11, Y11, T11) - (C11 - s2_12 @ Y21 - S12 @ Y21 @ T11)) <= tol
+    assert np.linalg.norm(op(S22, Y22, T22) - (C22 - Y21 @ t2_12 - S22 @ Y21 @ T12)) <= tol
+    rhs12 = (C12 - s2_12 @ Y22 - S12 @ Y22 @ T22 - Y11 @ t2_12 - (S11 @ Y11 + S12 @ Y21) @ T12)
+    assert np.linalg.norm(op(S11, Y12, T22) - rhs12) <= tol
+
+
+def test_emulator_cube_root_converges_to_the_known_root():
+    a, b = _cube_root_pair(80, 41)
+    res = oracle.emulate_mixed_root3(a, tol=1e-13)
+    assert res["status"] == "ok" and 1 <= res["steps"] <= 3
+    assert oracle.relerr(res["X"], b) <= 1e-12
+    assert oracle.relerr(res["X"], oracle.rootm3(a)) <= 1e-12
