@@ -178,6 +178,22 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
                          int64_t lda, int64_t strideA, void* dX, int64_t ldx, int64_t strideX,
                          hipStream_t stream, msqrt_info* info, msqrt_factor_t* keep);
 
+/* Principal matrix p-th root (Sec. 4): the unique X with X^p = A whose
+ * eigenvalues lie in |arg z| < pi/p, for A with no eigenvalue on R<=0.
+ * p = 2 is msqrt_sqrtm for one matrix.  p = 3 runs the Sec. 4 framework on
+ * the general path: low-precision complex Schur form of A/8^k, U = T^{1/3}
+ * (the Schur method for p-th roots), X_0 = Q U Q^*, then corrections from
+ * S^2 Y + S Y S + Y S^2 = Q^* fl_l(A - X^3) Q (S = U) with the residual and
+ * update in working precision, X <- 2^k X on exit; real input returns the
+ * real root.  opt->prec FP64 selects a float64 factor, anything else float32
+ * (escalated to FP64 when opt->fallback is set and the float run fails);
+ * opt->batch must be 1; maxit, tol (tol < 0: nullified stop) as for
+ * msqrt_sqrtm.  Other p: MSQRT_ERR_UNSUPPORTED.  Buffers, streams and errors
+ * as above (ld in elements). */
+msqrt_status msqrt_rootm(const msqrt_options* opt, int p, msqrt_dtype dtype, int64_t n,
+                         const void* dA, int64_t lda, void* dX, int64_t ldx, hipStream_t stream,
+                         msqrt_info* info);
+
 /* Reverse-mode derivative of X = sqrtm(A): given Gbar = dL/dX, returns
  * G = dL/dA, the solution of X^* G + G X^* = Gbar (adjoint of the Frechet
  * derivative; for HPD input X G + G X = Gbar).  Solved in the factor's Schur

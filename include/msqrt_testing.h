@@ -51,6 +51,11 @@ msqrt_status msqrt_test_schur(msqrt_prec prec, int64_t n, const double* A, doubl
  * NO_PRINCIPAL if a diagonal entry lies on or next to R<=0. */
 msqrt_status msqrt_test_trsqrt(msqrt_prec prec, int64_t n, const double* T, double* S);
 
+/* Principal cube root U of the upper triangular T (U^3 = T, Sec. 4 with
+ * p = 3), interleaved complex host buffers, computed on the device in the
+ * precision `prec`; NO_PRINCIPAL if a diagonal entry lies on R<=0. */
+msqrt_status msqrt_test_trcbrt(msqrt_prec prec, int64_t n, const double* T, double* U);
+
 /* Triangular Sylvester equation S Y + Y S2 = C (Eq. (triangsylv), Alg. 1):
  * S m x m and S2 p x p upper triangular, C and Y m x p. */
 msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, const double* S,

@@ -195,6 +195,30 @@ def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, b
     return x, d
 
 
+def rootm(a: torch.Tensor, p=3, prec="fp32", maxit=30, tol=1e-13, blks=32, fallback=True,
+          allow_fail=False, out=None):
+    """Principal p-th root (p = 2 or 3) of one matrix through msqrt_rootm.
+    Returns (X, info)."""
+    if isinstance(a, torch.Tensor) and not a.is_contiguous():
+        a = a.contiguous()
+    _check_matrix(a, "A")
+    if a.dim() != 2:
+        raise ValueError("rootm takes one matrix")
+    n = a.shape[-1]
+    x = torch.empty_like(a) if out is None else out
+    o = default_options(prec=prec, structure="general" if p == 3 else "auto", maxit=maxit, tol=tol,
+                        blks=blks, fallback=fallback, batch=1)
+    info = _lib.Info()
+    dt = _lib.COMPLEX128 if a.is_complex() else _lib.REAL64
+    st = lib().msqrt_rootm(ctypes.byref(o), int(p), dt, n, ctypes.c_void_p(a.data_ptr()), n,
+                           ctypes.c_void_p(x.data_ptr()), n, _stream(), ctypes.byref(info))
+    d = info.to_dict()
+    d["status"] = _lib.STATUS_NAMES.get(st, st)
+    if not allow_fail:
+        check(st, "msqrt_rootm")
+    return x, d
+
+
 def sqrtm_backward(f: Factor, x: torch.Tensor, gbar: torch.Tensor, maxit=30, tol=1e-13):
     _check_matrix(x, "X")
     gbar = gbar.contiguous()
@@ -297,6 +321,16 @@ def test_trsqrt(t, prec="fp32"):
     s = np.zeros((n, n), np.complex128, order="F")
     check(lib().msqrt_test_trsqrt(_lib.PREC_NAMES[prec], n, _dp(t), _dp(s)), "msqrt_test_trsqrt")
     return s
+
+
+def test_trcbrt(t, prec="fp32"):
+    """Test hook: principal cube root of an upper triangular matrix."""
+    import numpy as np
+    t = _cplx_f(t)
+    n = t.shape[0]
+    u = np.zeros((n, n), np.complex128, order="F")
+    check(lib().msqrt_test_trcbrt(_lib.PREC_NAMES[prec], n, _dp(t), _dp(u)), "msqrt_test_trcbrt")
+    return u
 
 
 def test_trsyl(s, s2, c, prec="fp32"):

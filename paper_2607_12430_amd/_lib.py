@@ -35,6 +35,7 @@ EXPORTED = [
     "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd", "msqrt_test_sy2tr",
     "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
+    "msqrt_test_trcbrt", "msqrt_rootm",
     "msqrt_test_gemm_f32", "msqrt_features", "msqrt_mlp_forward", "msqrt_mlp_grad",
     "msqrt_mlp_adam", "msqrt_selector_set", "msqrt_selector_load", "msqrt_selector_clear",
     "msqrt_selector_installed",
@@ -132,6 +133,9 @@ def lib():
     L.msqrt_test_gehrd.argtypes = [ci, i64, dp, dp, dp]
     L.msqrt_test_schur.argtypes = [ci, i64, dp, dp, dp]
     L.msqrt_test_trsqrt.argtypes = [ci, i64, dp, dp]
+    L.msqrt_test_trcbrt.argtypes = [ci, i64, dp, dp]
+    L.msqrt_rootm.argtypes = [ctypes.POINTER(Options), ci, ci, i64, vp, i64, vp, i64, vp,
+                              ctypes.POINTER(Info)]
     L.msqrt_test_trsyl.argtypes = [ci, i64, i64, dp, dp, dp, dp]
     L.msqrt_test_gemm_f32.argtypes = [ci, ci, ci, i64, i64, i64, vp, vp, vp]
     L.msqrt_features.argtypes = [ci, i64, vp, i64, vp, vp]
@@ -149,6 +153,7 @@ def lib():
                  "msqrt_sqrtm_backward",
                  "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
                  "msqrt_test_stedc", "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt",
+                 "msqrt_test_trcbrt", "msqrt_rootm",
                  "msqrt_test_trsyl", "msqrt_test_gemm_f32", "msqrt_features",
                  "msqrt_mlp_forward", "msqrt_mlp_grad", "msqrt_mlp_adam", "msqrt_selector_set",
                  "msqrt_selector_load"):

@@ -77,6 +77,9 @@ struct Factor {
   // [[Re A, -Im A], [Im A, Re A]]: n is 2 n_user and the factor is the HPD
   // factor of that real matrix.
   bool embed = false;
+  // Root order p of the factor (2: square root; 3: cube root, Sec. 4): the
+  // input is scaled by 2^(-p k), the root by 2^-k.
+  int root = 2;
   TrsylvWork tw;
 
   void upload_scales(hipStream_t st) {
@@ -85,7 +88,7 @@ struct Factor {
     anorm_scaled.assign(b, 0.0);
     for (int64_t i = 0; i < b; ++i) {
       const int k = kexp.empty() ? 0 : kexp[i];
-      h[i] = std::ldexp(1.0, -2 * k);
+      h[i] = std::ldexp(1.0, -root * k);
       h[b + i] = std::ldexp(1.0, -k);
       h[2 * b + i] = std::ldexp(1.0, k);
       if ((int64_t)anorm.size() > i) anorm_scaled[i] = anorm[i] * h[i];
@@ -217,6 +220,15 @@ int analyse_input_general(Factor* f, const double* A, int64_t lda, int cplx, hip
 template <typename T>
 msqrt_status factor_general(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st,
                             PhaseTimer* tm);
+// Cube root (Sec. 4, p = 3) on the general path: complex Schur form of the
+// scaled input, U = T^{1/3}, and the refinement with residual A - X^3.
+template <typename T>
+msqrt_status factor_root3(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st,
+                          PhaseTimer* tm);
+template <typename T>
+msqrt_status refine_root3(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
+                          int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
+                          PhaseTimer& tm);
 template <typename T>
 msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
                             int init, int maxit, double tol, hipStream_t st, msqrt_info* info,

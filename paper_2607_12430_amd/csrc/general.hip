@@ -154,6 +154,78 @@ __global__ __launch_bounds__(256) void x_out_kernel(int n, const double* Xw, int
 
 inline unsigned blocks_for(int64_t cnt) { return (unsigned)std::max<int64_t>(1, ceil_div(cnt, 256)); }
 
+// ---- triangular cube root U = T^{1/3} (stacked, ld 2n), by superdiagonals.
+// With V = U^2, entry (i, j), i < j, of U^3 = U V and V = U U give
+//   (u_ii^2 + u_ii u_jj + u_jj^2) u_ij = t_ij - u_ii a_ij - b_ij,
+//   v_ij = (u_ii + u_jj) u_ij + a_ij,
+// a_ij = sum_{i<k<j} u_ik u_kj, b_ij = sum_{i<k<j} u_ik v_kj: every entry of
+// superdiagonal d needs only superdiagonals < d, so a launch per superdiagonal
+// computes all its entries at once (one wave per entry; UT = U^T holds the
+// rows of U as contiguous columns).
+
+template <typename T>
+__device__ inline cx<T> sload(const T* M, int n, int i, int j) {
+  const int64_t ld = 2 * (int64_t)n;
+  return {M[i + j * ld], M[n + i + j * ld]};
+}
+template <typename T>
+__device__ inline void sstore(T* M, int n, int i, int j, cx<T> v) {
+  const int64_t ld = 2 * (int64_t)n;
+  M[i + j * ld] = v.r;
+  M[n + i + j * ld] = v.i;
+}
+
+template <typename T>
+__global__ void trcbrt_diag_kernel(int n, const T* Tm, T* U, T* UT, T* V, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const cx<T> t = sload(Tm, n, i, i);
+  if (t.i == T(0) && t.r <= T(0)) atomicOr(bad, 1);
+  // principal cube root |t|^{1/3} e^{i arg(t) / 3}
+  const T r = cbrt(hypot(t.r, t.i));
+  const T th = atan2(t.i, t.r) / T(3);
+  const cx<T> u = {r * cos(th), r * sin(th)};
+  sstore(U, n, i, i, u);
+  sstore(UT, n, i, i, u);
+  sstore(V, n, i, i, cmul(u, u));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trcbrt_band_kernel(int n, int d, const T* Tm, T* U, T* UT,
+                                                          T* V) {
+  const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int j = i + d;
+  if (j >= n) return;  // uniform over the wave
+  cx<T> a = {T(0), T(0)}, b = {T(0), T(0)};
+  for (int k = i + 1 + lane; k < j; k += kWave) {
+    const cx<T> uik = sload(UT, n, k, i);
+    a = cadd(a, cmul(uik, sload(U, n, k, j)));
+    b = cadd(b, cmul(uik, sload(V, n, k, j)));
+  }
+  a.r = wave_sum(a.r);
+  a.i = wave_sum(a.i);
+  b.r = wave_sum(b.r);
+  b.i = wave_sum(b.i);
+  if (lane == 0) {
+    const cx<T> ui = sload(U, n, i, i), uj = sload(U, n, j, j);
+    const cx<T> den = cadd(cadd(cmul(ui, ui), cmul(ui, uj)), cmul(uj, uj));
+    const cx<T> x = cdiv(csub(csub(sload(Tm, n, i, j), cmul(ui, a)), b), den);
+    sstore(U, n, i, j, x);
+    sstore(UT, n, j, i, x);
+    sstore(V, n, i, j, cadd(cmul(cadd(ui, uj), x), a));
+  }
+}
+
+// S2 = c S for the complex scalar c (stacked, n x n).
+template <typename T>
+__global__ void cscale_stacked_kernel(int n, const T* S, T cr, T ci, T* S2) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)n * n) return;
+  const int i = (int)(x % n), j = (int)(x / n);
+  sstore(S2, n, i, j, cmul(sload(S, n, i, j), cx<T>{cr, ci}));
+}
+
 template <typename T>
 void gstore_b(hipStream_t st, bool ta, bool tb, int n, int K, const T* A, int64_t lda, int64_t sA,
               const T* B, int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC,
@@ -190,9 +262,15 @@ GView<T> prepare_view(Factor* f, hipStream_t st) {
 
 // M (wide, low precision, n x 2n) -> Y = rtrsyl(S, S, Q^* M Q) (stacked, in
 // Rt) -> V = Q Y (wide, overwrites M) -> X (+)= fl64(V Q^*).
+// With S2a = -w S and S2b = -w^2 S (w = e^{2 pi i / 3}) the p = 3 equation
+// S^2 Y + S Y S + Y S^2 = C is solved instead: its operator is
+// L^2 + L R + R^2 with the commuting L(Y) = S Y, R(Y) = Y S, and
+// a^2 + ab + b^2 = (a - w b)(a - w^2 b), so Y follows from the two triangular
+// Sylvester equations S Z + Z S2a = C and S Y + Y S2b = Z.
 template <typename T>
 void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* Xw, bool set,
-                TrsylvWork& tw, PhaseTimer& tm, bool split) {
+                TrsylvWork& tw, PhaseTimer& tm, bool split, const T* S2a = nullptr,
+                const T* S2b = nullptr) {
   const int n = g.n;
   const int64_t nn = g.nn, n2 = 2 * (int64_t)n, n3 = 3 * (int64_t)n;
   tm.begin(MSQRT_T_TRANSFORM);
@@ -201,7 +279,12 @@ void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* 
   // Rt = Q^* W (stacked): Re = [Qr; Qi]^T W, Im = [-Qi; Qr]^T W
   gstore_b<T>(st, true, false, n, 2 * n, g.QSa + n, n3, -(int64_t)n, Wst, n2, 0, Rt, n2, n, split);
   tm.begin(MSQRT_T_SOLVE);
-  trsyl<T>(st, n, n, g.S, n2, g.S, n2, Rt, n2, tw);
+  if (S2a) {
+    trsyl<T>(st, n, n, g.S, n2, S2a, n2, Rt, n2, tw);
+    trsyl<T>(st, n, n, g.S, n2, S2b, n2, Rt, n2, tw);
+  } else {
+    trsyl<T>(st, n, n, g.S, n2, g.S, n2, Rt, n2, tw);
+  }
   tm.begin(MSQRT_T_UPDATE);
   // V = Q Y (wide): Re = [Qr | -Qi][Yr; Yi], Im = [Qi | Qr][Yr; Yi]
   gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, Rt, n2, 0, M, n, nn, split);
@@ -242,7 +325,8 @@ int analyse_input_general(Factor* f, const double* A, int64_t lda, int cplx, hip
   f->kexp.assign(1, 0);
   f->anorm.assign(1, nrm);
   if (nrm > 0 && std::isfinite(nrm))
-    f->kexp[0] = (int)std::lround(std::log(nrm / std::sqrt((double)n)) / std::log(4.0));
+    f->kexp[0] = (int)std::lround(std::log(nrm / std::sqrt((double)n)) /
+                                  std::log(std::ldexp(1.0, f->root)));
   f->upload_scales(st);
   return hf;
 }
@@ -402,6 +486,200 @@ msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, 
   return status;
 }
 
+template <typename T>
+void trcbrt(hipStream_t st, int n, const T* Tm, T* U, T* UT, T* V, int* bad) {
+  const int64_t sz = 2 * (int64_t)n * n;
+  MSQRT_HIP(hipMemsetAsync(U, 0, sizeof(T) * sz, st));
+  MSQRT_HIP(hipMemsetAsync(UT, 0, sizeof(T) * sz, st));
+  MSQRT_HIP(hipMemsetAsync(V, 0, sizeof(T) * sz, st));
+  MSQRT_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+  if (n <= 0) return;
+  hipLaunchKernelGGL(trcbrt_diag_kernel<T>, dim3(blocks_for(n)), dim3(256), 0, st, n, Tm, U, UT, V,
+                     bad);
+  MSQRT_LAUNCH_CHECK();
+  for (int d = 1; d < n; ++d) {
+    const int waves = n - d;
+    hipLaunchKernelGGL(trcbrt_band_kernel<T>, dim3((unsigned)ceil_div(waves, 256 / kWave)),
+                       dim3(256), 0, st, n, d, Tm, U, UT, V);
+    MSQRT_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+msqrt_status factor_root3(Factor* f, const double* A, int64_t lda, int cplx, hipStream_t st,
+                          PhaseTimer* tm) {
+  const int n = (int)f->n;
+  const int64_t sz = 2 * (int64_t)n * n;
+  T* Q = f->Q.ensure<T>(sz);
+  T* U = f->S.ensure<T>(sz);
+  T* H = f->fw1.ensure<T>(sz);
+  T* UT = f->fw2.ensure<T>(sz);
+  T* V = f->fw3.ensure<T>(sz);
+  T* S2a = f->fw4.ensure<T>(sz);
+  T* S2b = f->fw5.ensure<T>(sz);
+  int* bad = f->active.ensure<int>(1);
+  f->gq_ready = false;
+  if (tm) tm->begin(MSQRT_T_REDUCE);
+  hipLaunchKernelGGL(to_stacked_kernel<T>, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, n, A,
+                     lda, cplx, f->ascale_dev(), H);
+  MSQRT_LAUNCH_CHECK();
+  GehrdWork gw;
+  gehrd<T>(st, n, H, Q, gw);
+  if (tm) tm->begin(MSQRT_T_EIG);
+  HseqrWork hw;
+  const bool ok = hseqr<T>(st, n, H, Q, hw, (T)f->anorm_scaled[0]);
+  if (!ok) {
+    if (tm) tm->end();
+    set_last_error("complex Schur QR did not converge");
+    return MSQRT_ERR_NOT_CONVERGED;
+  }
+  if (tm) tm->begin(MSQRT_T_X0);
+  trcbrt<T>(st, n, H, U, UT, V, bad);
+  // -w U and -w^2 U, w = e^{2 pi i / 3}: -w = (1/2, -sqrt(3)/2), -w^2 = (1/2, sqrt(3)/2)
+  const T h3 = (T)0.86602540378443864676;
+  hipLaunchKernelGGL(cscale_stacked_kernel<T>, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, n,
+                     (const T*)U, T(0.5), -h3, S2a);
+  MSQRT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cscale_stacked_kernel<T>, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, n,
+                     (const T*)U, T(0.5), h3, S2b);
+  MSQRT_LAUNCH_CHECK();
+  int hbad = 0;
+  MSQRT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (tm) tm->end();
+  MSQRT_HIP(hipStreamSynchronize(st));
+  if (tm) tm->collect();
+  if (hbad) {
+    set_last_error("an eigenvalue lies on or next to the closed negative real axis");
+    return MSQRT_ERR_NO_PRINCIPAL;
+  }
+  return MSQRT_OK;
+}
+
+template <typename T>
+msqrt_status refine_root3(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
+                            int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
+                            PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  const int cplx = f->dtype == MSQRT_COMPLEX128;
+  const GView<T> g = prepare_view<T>(f, st);
+  double* Xw = f->gx.ensure<double>(12 * nn);
+  double* XS = Xw + 2 * nn;
+  double* Aw = Xw + 5 * nn;  // A in the wide layout [Ar | Ai]
+  double* Pw = Xw + 7 * nn;  // X^2, wide
+  double* PS = Xw + 9 * nn;  // X^2, stacked variant
+  T* M = f->ws1.ensure<T>(2 * nn);
+  T* Wst = f->ws2.ensure<T>(2 * nn);
+  T* Rt = f->gt.ensure<T>(2 * nn);
+  const int ntiles = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  double* part = f->part.ensure<double>(2 * (int64_t)ntiles + 2 * kRedBlocks + 64);
+  double* rn = f->rnorm.ensure<double>(2);
+  double* sc2 = f->gsc.ensure<double>(2);
+  {
+    const double a = std::ldexp(1.0, -3 * f->kexp[0]);
+    const double h[2] = {a, a};
+    MSQRT_HIP(hipMemcpyAsync(sc2, h, sizeof(h), hipMemcpyHostToDevice, st));
+  }
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, A, lda, cplx, 0,
+                     (const double*)nullptr, Aw);
+  MSQRT_LAUNCH_CHECK();
+  trsylv_reset(st, f->tw);
+  if (init) {
+    tm.begin(MSQRT_T_X0);
+    // V = Q S (wide), X_0 = fl64(V Q^*)
+    gstore_b<T>(st, false, false, n, 2 * n, g.QWa + nn, n, -nn, g.S, 2 * (int64_t)n, 0, M, n, nn);
+    gemm_set_f64<T>(st, false, true, n, 2 * n, M, n, 0, g.QWb + nn, n, -nn, Xw, n, nn, 2, false);
+  } else {
+    tm.begin(MSQRT_T_VALIDATE);
+    hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)X,
+                       ldx, cplx, 0, f->rscale_dev(), Xw);
+    MSQRT_LAUNCH_CHECK();
+  }
+  std::vector<double> hist, hp(2 * ntiles);
+  double best_r = INFINITY;
+  double* best = nullptr;
+  Verdict verdict = Verdict::Continue;
+  int steps = 0;
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    hipLaunchKernelGGL(x_stack_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)Xw,
+                       XS);
+    MSQRT_LAUNCH_CHECK();
+    // P = X X (float64, wide), then R = A - X P: the same planar products
+    // as for the square root, Re = [Xr | Xi][Pr; -Pi], Im = [Xr | Xi][Pi; Pr]
+    gemm_store_f64(st, false, false, n, n, 2 * n, Xw, n, 0, XS + n, 3 * (int64_t)n, -(int64_t)n,
+                   Pw, n, nn, 1.0, 0.0, 2, false);
+    hipLaunchKernelGGL(x_stack_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)Pw,
+                       PS);
+    MSQRT_LAUNCH_CHECK();
+    const int nt = gemm_residual_ex(st, false, false, n, n, 2 * n, Xw, n, 0, PS + n, 3 * (int64_t)n,
+                                    -(int64_t)n, Aw, n, nn, sc2,
+                                    std::is_same<T, float>::value ? (float*)M : nullptr,
+                                    std::is_same<T, float>::value ? nullptr : (double*)M, n, nn,
+                                    part, 2);
+    launch_reduce_sqrt(st, part, 2 * nt, 1, rn);
+    double hrn = 0.0;
+    MSQRT_HIP(hipMemcpyAsync(&hrn, rn, sizeof(double), hipMemcpyDeviceToHost, st));
+    tm.end();
+    MSQRT_HIP(hipStreamSynchronize(st));
+    tm.collect();
+    hist.push_back(hrn / f->anorm_scaled[0]);
+    Verdict v = judge_step(hist, tol, it, maxit);
+    if (v != Verdict::Continue) {
+      verdict = v;
+      break;
+    }
+    if (hist.back() < best_r) {
+      best_r = hist.back();
+      if (!best) best = f->best.ensure<double>(2 * nn);
+      MSQRT_HIP(hipMemcpyAsync(best, Xw, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+    }
+    correction<T>(st, g, M, Wst, Rt, Xw, false, f->tw, tm, false, f->fw4.as<T>(),
+                  f->fw5.as<T>());
+    ++steps;
+  }
+  msqrt_status status = MSQRT_OK;
+  double final_r = hist.back();
+  if (verdict != Verdict::Converged) {
+    if (best && !(final_r <= best_r)) {  // also when final_r is NaN
+      MSQRT_HIP(hipMemcpyAsync(Xw, best, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+      final_r = best_r;
+    }
+    status = verdict == Verdict::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
+    set_last_error(verdict == Verdict::Diverged ? "refinement diverged"
+                                                 : "refinement did not converge");
+  }
+  // X = 2^k X_s in the caller's layout
+  tm.begin(MSQRT_T_VALIDATE);
+  hipLaunchKernelGGL(x_out_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, (const double*)Xw, cplx, 0,
+                     f->uscale_dev(), X, ldx, part);
+  MSQRT_LAUNCH_CHECK();
+  std::vector<double> hx(2 * kRedBlocks);
+  MSQRT_HIP(hipMemcpyAsync(hx.data(), part, sizeof(double) * 2 * kRedBlocks, hipMemcpyDeviceToHost, st));
+  tm.end();
+  int timed_out = 0;
+  trsylv_errors(st, f->tw, &timed_out, nullptr);
+  tm.collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "triangular Sylvester solve: dataflow wait timed out"};
+  if (info) {
+    info->steps = steps;
+    info->relres = std::isfinite(final_r) ? final_r : INFINITY;
+    info->nhist = (int)std::min<size_t>(64, hist.size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
+  }
+  if (!cplx && status == MSQRT_OK && tol >= 0) {
+    // a real matrix without eigenvalues on R<=0 has a real principal root
+    // (not asserted for the intermediate iterates of a nullified-stop run)
+    const double xa = std::sqrt(sum_host(hx, 0, kRedBlocks));
+    const double xi = std::sqrt(sum_host(hx, kRedBlocks, kRedBlocks));
+    if (xi > 1e-12 * xa) {
+      set_last_error("the cube root of the real input has a non-negligible imaginary part");
+      return MSQRT_ERR_NO_PRINCIPAL;
+    }
+  }
+  return status;
+}
+
 // Backward: X^* G + G X^* = Gbar.  Its conjugate transpose is
 // X G~ + G~ X = Gbar^* with G~ = G^*: the forward correction equation, solved
 // with the same factor (Q^* (.) Q, rtrsyl, Q (.) Q^*) and refined with
@@ -542,6 +820,16 @@ template msqrt_status refine_general<float>(Factor*, const double*, int64_t, dou
 template msqrt_status refine_general<double>(Factor*, const double*, int64_t, double*, int64_t,
                                              int, int, double, hipStream_t, msqrt_info*,
                                              PhaseTimer&);
+template void trcbrt<float>(hipStream_t, int, const float*, float*, float*, float*, int*);
+template void trcbrt<double>(hipStream_t, int, const double*, double*, double*, double*, int*);
+template msqrt_status factor_root3<float>(Factor*, const double*, int64_t, int, hipStream_t,
+                                          PhaseTimer*);
+template msqrt_status factor_root3<double>(Factor*, const double*, int64_t, int, hipStream_t,
+                                           PhaseTimer*);
+template msqrt_status refine_root3<float>(Factor*, const double*, int64_t, double*, int64_t, int,
+                                          int, double, hipStream_t, msqrt_info*, PhaseTimer&);
+template msqrt_status refine_root3<double>(Factor*, const double*, int64_t, double*, int64_t, int,
+                                           int, double, hipStream_t, msqrt_info*, PhaseTimer&);
 template msqrt_status backward_general<float>(Factor*, const double*, int64_t, const double*,
                                               int64_t, double*, int64_t, int, double, hipStream_t,
                                               msqrt_info*, PhaseTimer&);

@@ -969,6 +969,75 @@ msqrt_status msqrt_sqrtm(const msqrt_options* opt, msqrt_dtype dtype, int64_t n,
   MSQRT_API_END
 }
 
+msqrt_status msqrt_rootm(const msqrt_options* opt, int p, msqrt_dtype dtype, int64_t n,
+                         const void* dA, int64_t lda, void* dX, int64_t ldx, hipStream_t stream,
+                         msqrt_info* info) {
+  MSQRT_API_BEGIN
+  msqrt_options o;
+  msqrt_default_options(&o);
+  if (opt) o = *opt;
+  if (p == 2) {
+    o.batch = 1;
+    return msqrt_sqrtm(&o, dtype, n, dA, lda, lda * n, dX, ldx, ldx * n, stream, info, nullptr);
+  }
+  if (p != 3) {
+    set_last_error("msqrt_rootm: p must be 2 or 3");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  msqrt_status cs = check_common(dtype, n, dA, lda, 1);
+  if (cs != MSQRT_OK) return cs;
+  if (n > 0 && (!dX || ldx < n)) return MSQRT_ERR_INVALID_ARG;
+  if (o.batch != 1) {
+    set_last_error("msqrt_rootm: one matrix per call");
+    return MSQRT_ERR_UNSUPPORTED;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return MSQRT_OK;
+  PhaseTimer tm(stream, info);
+  const int cplx = dtype == MSQRT_COMPLEX128;
+  msqrt_prec prec = o.prec == MSQRT_PREC_FP64 ? MSQRT_PREC_FP64 : MSQRT_PREC_FP32;
+  msqrt_status last = MSQRT_ERR_DEVICE;
+  int fallbacks = 0;
+  for (;;) {
+    Factor f;
+    f.n = n; f.batch = 1; f.dtype = dtype; f.blks = o.blks; f.root = 3;
+    f.structure = MSQRT_STRUCT_GENERAL;
+    f.prec = prec;
+    tm.begin(MSQRT_T_VALIDATE);
+    const int flags = analyse_input_general(&f, (const double*)dA, lda, cplx, stream);
+    tm.end();
+    if (flags & 1) {
+      set_last_error("input contains Inf or NaN");
+      return MSQRT_ERR_NONFINITE;
+    }
+    msqrt_status st = prec == MSQRT_PREC_FP64
+                          ? factor_root3<double>(&f, (const double*)dA, lda, cplx, stream, &tm)
+                          : factor_root3<float>(&f, (const double*)dA, lda, cplx, stream, &tm);
+    if (st == MSQRT_OK)
+      st = prec == MSQRT_PREC_FP64
+               ? refine_root3<double>(&f, (const double*)dA, lda, (double*)dX, ldx, 1, o.maxit,
+                                      o.tol, stream, info, tm)
+               : refine_root3<float>(&f, (const double*)dA, lda, (double*)dX, ldx, 1, o.maxit,
+                                     o.tol, stream, info, tm);
+    MSQRT_HIP(hipStreamSynchronize(stream));
+    tm.collect();
+    if (info) {
+      info->prec_used = prec;
+      info->struct_used = MSQRT_STRUCT_GENERAL;
+      info->scale_exp = f.kexp.empty() ? 0 : f.kexp[0];
+    }
+    last = st;
+    const bool retryable = st == MSQRT_ERR_DIVERGED || st == MSQRT_ERR_NOT_CONVERGED ||
+                           st == MSQRT_ERR_NO_PRINCIPAL;
+    if (st == MSQRT_OK || !o.fallback || !retryable || prec == MSQRT_PREC_FP64) break;
+    prec = MSQRT_PREC_FP64;
+    ++fallbacks;
+  }
+  if (info) info->fallbacks = fallbacks;
+  return last;
+  MSQRT_API_END
+}
+
 msqrt_status msqrt_sqrtm_backward(msqrt_factor_t fh, const void* dX, int64_t ldx,
                                   const void* dGbar, int64_t ldgb, void* dG, int64_t ldg,
                                   int64_t stride, int maxit, double tol, hipStream_t stream,

@@ -41,6 +41,12 @@ void trsylv_errors(hipStream_t st, TrsylvWork& w, int* timed_out, int* nonprinci
 template <typename T>
 void trsqrt(hipStream_t st, int n, const T* Tm, T* S, TrsylvWork& w, int* bad);
 
+// U = T^{1/3} (principal) for upper triangular T (stacked, n x n), with
+// workspaces UT (U^T) and V (U^2) of the same shape; *bad (device) becomes
+// nonzero if a diagonal entry of T lies on R<=0.  U may not alias T.
+template <typename T>
+void trcbrt(hipStream_t st, int n, const T* Tm, T* U, T* UT, T* V, int* bad);
+
 // Solve S Y + Y S2 = C (S m x m, S2 p x p upper triangular; C m x p,
 // overwritten by Y); all stacked with their own leading dimensions.
 template <typename T>

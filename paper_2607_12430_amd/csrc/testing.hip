@@ -68,6 +68,26 @@ msqrt_status gehrd_impl(int n, const double* A, double* H, double* Q, bool schur
 }
 
 template <typename T>
+msqrt_status trcbrt_impl(int n, const double* Tm, double* U) {
+  DevBuf tb, ub, utb, vb, fb;
+  T* dT = upload(tb, to_stacked_host<T>(n, n, Tm));
+  T* dU = ub.ensure<T>(2 * (int64_t)n * n);
+  T* dUT = utb.ensure<T>(2 * (int64_t)n * n);
+  T* dV = vb.ensure<T>(2 * (int64_t)n * n);
+  int* bad = fb.ensure<int>(1);
+  trcbrt<T>(nullptr, n, dT, dU, dUT, dV, bad);
+  MSQRT_HIP(hipDeviceSynchronize());
+  int hbad = 0;
+  MSQRT_HIP(hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost));
+  if (hbad) {
+    set_last_error("a diagonal entry lies on the closed negative real axis");
+    return MSQRT_ERR_NO_PRINCIPAL;
+  }
+  from_stacked_host<T>(n, n, download(dU, 2 * (size_t)n * n), U);
+  return MSQRT_OK;
+}
+
+template <typename T>
 msqrt_status trsqrt_impl(int n, const double* Tm, double* S) {
   DevBuf tb, sb;
   T* dT = upload(tb, to_stacked_host<T>(n, n, Tm));
@@ -143,6 +163,15 @@ extern "C" msqrt_status msqrt_test_trsqrt(msqrt_prec prec, int64_t n, const doub
   return guarded([&] {
     if (prec == MSQRT_PREC_FP64) return trsqrt_impl<double>((int)n, Tm, S);
     if (prec == MSQRT_PREC_FP32) return trsqrt_impl<float>((int)n, Tm, S);
+    return MSQRT_ERR_INVALID_ARG;
+  });
+}
+
+extern "C" msqrt_status msqrt_test_trcbrt(msqrt_prec prec, int64_t n, const double* Tm, double* U) {
+  if (n < 1 || !Tm || !U || n > 16384) return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    if (prec == MSQRT_PREC_FP64) return trcbrt_impl<double>((int)n, Tm, U);
+    if (prec == MSQRT_PREC_FP32) return trcbrt_impl<float>((int)n, Tm, U);
     return MSQRT_ERR_INVALID_ARG;
   });
 }
