@@ -524,6 +524,154 @@ __global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Float kernel with 192 x 192 tiles: one workgroup of four wave64s per CU,
+// each wave a 96 x 96 block (3 x 3 MFMA 32 x 32 blocks, 144 accumulator
+// registers), K-slabs of 32 double-buffered in LDS as in the 128 kernel
+// (110 KiB).  It serves the large symmetric-output products: at n = 4096 the
+// lower triangle has 253 tiles of 192 (one per CU) against 528 of 128
+// (2.06 per CU, so some CUs run a third tile while the rest idle); measured
+// 0.78 ms against 1.01 ms for the n^3 flops of one such product.
+
+constexpr int WBM = 192;
+// smallest order of a triangle that takes the 192-tile kernel
+constexpr int kWideMin = 1536;
+constexpr size_t kGemmF32wLds = (size_t)2 * 2 * WBM * FLD * sizeof(float);
+
+template <bool RC>
+__device__ inline void f32w_slab_index(int t, int e, int& r, int& k) {
+  const int lane = t % kWave, wave = t / kWave;
+  if (RC) {
+    // 96 blocks of 8 rows x 8 k, 24 per wave
+    const int id = wave * 24 + e;
+    r = (id % 24) * 8 + lane % 8;
+    k = (id / 24) * 8 + lane / 8;
+  } else {
+    const int idx = t + GTHREADS * e;
+    k = idx % FBK;
+    r = idx / FBK;
+  }
+}
+
+template <bool RC>
+__device__ inline void f32w_slab_load(const float* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                      int K, int t, float (&v)[24]) {
+#pragma unroll
+  for (int e = 0; e < 24; ++e) {
+    int r, k;
+    f32w_slab_index<RC>(t, e, r, k);
+    const int gr = r0 + r, gk = k0 + k;
+    v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.f;
+  }
+}
+
+template <bool RC>
+__device__ inline void f32w_slab_store(float* Xs, int t, const float (&v)[24]) {
+#pragma unroll
+  for (int e = 0; e < 24; ++e) {
+    int r, k;
+    f32w_slab_index<RC>(t, e, r, k);
+    Xs[r * FLD + k] = v[e];
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, const float* __restrict__ A,
+                                                                const float* __restrict__ B, Epi epi,
+                                                                double* __restrict__ partials) {
+  using M = Mfma<float>;
+  constexpr int NBW = 3;  // 32 x 32 blocks per wave side
+  extern __shared__ __attribute__((aligned(16))) float gemm_ldsw[];
+  __shared__ double red[GTHREADS / kWave];
+  auto slab = [&](int buf, int op) { return gemm_ldsw + (size_t)(buf * 2 + op) * WBM * FLD; };
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * WBM, n0 = tn * WBM;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;
+  constexpr bool ARC = !TA, BRC = TB;
+
+  typename M::acc_t acc[NBW][NBW];
+#pragma unroll
+  for (int i = 0; i < NBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.f;
+
+  float ra[24], rb[24];
+  if (K > 0) {
+    f32w_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f32w_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f32w_slab_store<ARC>(slab(0, 0), t, ra);
+    f32w_slab_store<BRC>(slab(0, 1), t, rb);
+  }
+  __syncthreads();
+  const int h = lane / 32, fr = lane % 32;
+  for (int k0 = 0, buf = 0; k0 < K; k0 += FBK, buf ^= 1) {
+    const bool more = k0 + FBK < K;
+    if (more) {
+      f32w_slab_load<ARC>(A, s.lda, m0, s.M, k0 + FBK, K, t, ra);
+      f32w_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + FBK, K, t, rb);
+    }
+    const float* As = slab(buf, 0);
+    const float* Bs = slab(buf, 1);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kc = h * 16 + s4 * 4;
+      float4 a4[NBW], b4[NBW];
+#pragma unroll
+      for (int i = 0; i < NBW; ++i)
+        a4[i] = *reinterpret_cast<const float4*>(As + (wm * 96 + i * 32 + fr) * FLD + kc);
+#pragma unroll
+      for (int j = 0; j < NBW; ++j)
+        b4[j] = *reinterpret_cast<const float4*>(Bs + (wn * 96 + j * 32 + fr) * FLD + kc);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < NBW; ++i)
+#pragma unroll
+          for (int j = 0; j < NBW; ++j) {
+            const float av = c == 0 ? a4[i].x : c == 1 ? a4[i].y : c == 2 ? a4[i].z : a4[i].w;
+            const float bv = c == 0 ? b4[j].x : c == 1 ? b4[j].y : c == 2 ? b4[j].z : b4[j].w;
+            acc[i][j] = M::mma(bv, av, acc[i][j]);
+          }
+    }
+    if (more) {
+      f32w_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
+      f32w_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+    }
+    __syncthreads();
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < NBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
+        const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
 inline int gemm_cu_count() {
   static int ncu = 0;
   if (!ncu) {
@@ -795,12 +943,12 @@ struct EpiSetF64 {
 
 // Host-side shape setup shared by the launchers.
 inline GemmShape make_shape(int M, int N, int K, int64_t lda, int64_t ldb, int64_t sA, int64_t sB,
-                            bool tri) {
+                            bool tri, int tile = GBM) {
   GemmShape s;
   s.M = M; s.N = N; s.K = K; s.K_last = K; s.lda = lda; s.ldb = ldb; s.sA = sA; s.sB = sB;
   s.tri = tri ? 1 : 0;
-  s.tiles_m = (int)ceil_div(M, GBM);
-  s.tiles_n = (int)ceil_div(N, GBN);
+  s.tiles_m = (int)ceil_div(M, tile);
+  s.tiles_n = (int)ceil_div(N, tile);
   s.ntiles = tri ? s.tiles_m * (s.tiles_m + 1) / 2 : s.tiles_m * s.tiles_n;
   s.per_xcd = (int)ceil_div(s.ntiles, 8);
   return s;
@@ -830,9 +978,35 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
     }
   }
   if constexpr (std::is_same<T, float>::value) {
+    const int64_t ncu = gemm_cu_count();
+    if (s.tri && s.M >= kWideMin && s.K >= 256 && (int64_t)s.ntiles * batch > 2 * ncu) {
+      // large triangles that 128-tiles would spread over more than two
+      // workgroups per CU: 192 x 192 tiles, one workgroup per CU.  (Full
+      // products keep the 128 kernel: at n = 4096 its 1024 tiles fill every
+      // CU with two co-resident workgroups, measured 1.31 ms against 1.58 ms.)
+      GemmShape w = make_shape(s.M, s.N, s.K, s.lda, s.ldb, s.sA, s.sB, s.tri != 0, WBM);
+      w.K_last = s.K_last;
+      dim3 gw(8 * w.per_xcd, batch);
+      auto gow = [&](auto kern) {
+        gemm_lds_attr(kern, kGemmF32wLds);
+        hipLaunchKernelGGL(kern, gw, block, kGemmF32wLds, st, w, A, B, epi, partials);
+      };
+      if (!ta && !tb) gow(gemm_f32w_kernel<false, false, Epi>);
+      else if (ta && !tb) gow(gemm_f32w_kernel<true, false, Epi>);
+      else if (!ta && tb) gow(gemm_f32w_kernel<false, true, Epi>);
+      else gow(gemm_f32w_kernel<true, true, Epi>);
+      MSQRT_LAUNCH_CHECK();
+      if (tok >= 0) {
+        const double outs = w.tri ? 0.5 * (double)w.N * (w.N + 1) : (double)w.M * w.N;
+        const double kk = (double)w.K * (batch - 1) + w.K_last;
+        const std::string cls = std::string("gemm_f32:") + Epi::kName;
+        prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
+      }
+      return;
+    }
     // more tiles than two workgroups per CU hold but no more than three:
     // the 16-deep variant runs them in one round
-    const int64_t units = (int64_t)s.ntiles * batch, ncu = gemm_cu_count();
+    const int64_t units = (int64_t)s.ntiles * batch;
     const bool three = units > 2 * ncu && units <= 3 * ncu;
     auto go = [&](auto kern, size_t lds) {
       gemm_lds_attr(kern, lds);

@@ -1,0 +1,23 @@
+"""The float MFMA GEMM at the sizes where it uses 192 x 192 tiles (M, N >=
+1536, K >= 256), ragged in every dimension and with every transpose, element
+by element against a float64 product: |C - AB| <= 4 k 2^-24 (|A||B|)."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("m,n,k", [(1601, 1543, 301), (1537, 2113, 257), (2048, 2048, 512)])
+def test_wide_tile_float_gemm(ta, tb, m, n, k):
+    import paper_2607_12430_amd as msq
+    rng = np.random.Generator(np.random.PCG64(m + 3 * n + 7 * k + 11 * ta + 13 * tb))
+    a = rng.standard_normal((k, m) if ta else (m, k)).astype(np.float32)
+    b = rng.standard_normal((n, k) if tb else (k, n)).astype(np.float32)
+    a64 = a.astype(np.float64).T if ta else a.astype(np.float64)
+    b64 = b.astype(np.float64).T if tb else b.astype(np.float64)
+    ref = a64 @ b64
+    scale = np.abs(a64) @ np.abs(b64)
+    c = msq.test_gemm_f32(a, b, split=False, ta=ta, tb=tb).astype(np.float64)
+    assert np.max(np.abs(c - ref) / scale) <= 4.0 * k * 2.0 ** -24
