@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import gzip
 import json
 import os
 import struct
@@ -224,59 +225,101 @@ def fit(records, epochs=400, oversample=10, seed=0, log=None):
         "val_fp32_failures": int(fail32.sum()), "val_fp32_failures_predicted": caught}
 
 
-def evaluate(path, count=64, first=50_000, n=4096, kinds=("spd",), maxit=30, device_inputs=False):
-    """Selector gain on fresh matrices: total time of AUTO (selector +
-    fallback) against always-BF16SPLIT / FP32 / FP64 (with fallback) and the
-    per-matrix best; every AUTO answer is checked against the float64
-    residual bound."""
+def boundary_params(index: int):
+    """Extra labelling law near the float factor's failure boundary at the
+    evaluation sizes: (kind, n, kappa, seed).  Two thirds SPD with n
+    log-uniform in [2048, 4096] and kappa = 10^U(6, 9); one third
+    nonsymmetric (Q (L + N) Q^T) with n log-uniform in [512, 1024] and
+    kappa = 10^U(3, 9)."""
+    rng = np.random.Generator(np.random.PCG64(7_000_003 * (index + 1)))
+    seed = int(rng.integers(1, 2 ** 31))
+    if rng.uniform() < 2.0 / 3.0:
+        n = int(round(np.exp(rng.uniform(np.log(2048.0), np.log(4096.0)))))
+        return "spd", n, float(10.0 ** rng.uniform(6.0, 9.0)), seed
+    n = int(round(np.exp(rng.uniform(np.log(512.0), np.log(1024.0)))))
+    return "kappa", n, float(10.0 ** rng.uniform(3.0, 9.0)), seed
+
+
+def evaluate(path, count=64, first=50_000, n=4096, kinds=("spd", "nonsym"), maxit=30,
+             device_inputs=False, n_nonsym=None, log=True):
+    """Selector gain on fresh matrices of the selector law (kind, kappa and
+    seed of matrix `first + k`; SPD at order n, nonsymmetric at n_nonsym,
+    default n; with kinds = ("spd",) every matrix is SPD): time of AUTO
+    (selector + fallback) against always-BF16SPLIT / FP32 / FP64 (with
+    fallback) and the per-matrix best; every AUTO answer is checked against
+    the float64 residual bound."""
     import workloads as W
     from . import sqrtm
     install(path)
     dev = torch.device("cuda")
     # warm every code path once (allocations, first launches) before timing
-    a0, _, _ = W.spd(n, 1e3, 7)
-    a0d = torch.from_numpy(np.ascontiguousarray(a0)).to(dev)
+    if device_inputs:
+        import workloads.device as WD
+        a0d = WD.spd(n, 1e3, 7, dev)
+        a1d = WD.nonsym_shifted(n_nonsym or n, 7, dev)
+    else:
+        a0, _, _ = W.spd(n, 1e3, 7)
+        a0d = torch.from_numpy(np.ascontiguousarray(a0)).to(dev)
+        a1d = torch.from_numpy(np.ascontiguousarray(W.nonsym_shifted(n_nonsym or n, 7))).to(dev)
     for p in ("auto",) + PRECS:
         sqrtm(a0d, prec=p, fallback=True, allow_fail=True, maxit=maxit)
+    if "nonsym" in kinds:
+        for p in ("auto",) + PRECS:
+            sqrtm(a1d, prec=p, fallback=True, allow_fail=True, maxit=maxit)
     torch.cuda.synchronize()
     rows = []
     for k in range(count):
-        rng = np.random.Generator(np.random.PCG64(first + k))
-        kappa = float(10.0 ** rng.uniform(1.0, 8.0))
-        kind = kinds[k % len(kinds)]
-        seed = int(rng.integers(1, 2 ** 31))
+        kind, _, kappa, seed = W.selector_params(first + k)
+        if kind != "spd" and "nonsym" not in kinds:
+            kind = "spd"
+        elif kind == "spd" and "spd" not in kinds:
+            kind = "kappa"
+        nk = n if kind == "spd" or not n_nonsym else n_nonsym
         if device_inputs:
             import workloads.device as WD
-            ad = (WD.spd(n, kappa, seed, dev) if kind == "spd"
-                  else WD.nonsym_kappa(n, kappa, seed, dev))
+            ad = {"spd": lambda: WD.spd(nk, kappa, seed, dev),
+                  "shifted": lambda: WD.nonsym_shifted(nk, seed, dev),
+                  "kappa": lambda: WD.nonsym_kappa(nk, kappa, seed, dev)}[kind]()
         else:
             if kind == "spd":
-                a, _, _ = W.spd(n, kappa, seed)
+                a, _, _ = W.spd(nk, kappa, seed)
+            elif kind == "shifted":
+                a = W.nonsym_shifted(nk, seed)
             else:
-                a = W.nonsym_kappa(n, kappa, seed)
+                a = W.nonsym_kappa(nk, kappa, seed)
             ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-        row = {"kappa": kappa, "kind": kind}
+        row = {"kappa": kappa, "kind": kind, "n": nk}
         for p in ("auto",) + PRECS:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, info = sqrtm(ad, prec=p, fallback=True, allow_fail=True, maxit=maxit)
             torch.cuda.synchronize()
             row[p] = 1e3 * (time.perf_counter() - t0)
+            row[p + "_escalations"] = info["fallbacks"]
             if p == "auto":
                 rr = float(torch.linalg.matrix_norm(x @ x - ad) / torch.linalg.matrix_norm(ad))
                 row["auto_ok"] = info["status"] == "ok" and rr <= 1e-13
                 row["auto_prec"] = info["prec_used"]
-                row["auto_fallbacks"] = info["fallbacks"]
                 row["predicted"] = info["predicted_steps"]
         rows.append(row)
-        print(f"[selector-eval] {k + 1}/{count} kappa={kappa:.1e} auto={row['auto_prec']} "
-              f"t_auto={row['auto']:.1f} t_fp32={row['fp32']:.1f} t_fp64={row['fp64']:.1f}",
-              flush=True)
-    tot = {p: sum(r[p] for r in rows) for p in ("auto",) + PRECS}
-    best = sum(min(r[p] for p in PRECS) for r in rows)
-    return {"count": count, "n": n, "kinds": list(kinds), "total_ms": tot, "per_matrix_best_ms": best,
-            "auto_all_ok": all(r["auto_ok"] for r in rows),
-            "auto_choices": {p: sum(r["auto_prec"] == p for r in rows) for p in PRECS}}
+        if log:
+            print(f"[selector-eval] {k + 1}/{count} {kind} n={nk} kappa={kappa:.1e} "
+                  f"auto={row['auto_prec']} t_auto={row['auto']:.1f} t_fp32={row['fp32']:.1f} "
+                  f"t_fp64={row['fp64']:.1f}", flush=True)
+    out = {"count": count, "n": n, "n_nonsym": n_nonsym, "kinds": list(kinds),
+           "auto_all_ok": all(r["auto_ok"] for r in rows), "rows": rows}
+    groups = {"spd": ("spd",), "nonsym": ("shifted", "kappa"), "all": ("spd", "shifted", "kappa")}
+    for g, members in groups.items():
+        rs = [r for r in rows if r["kind"] in members]
+        if not rs:
+            continue
+        out[g] = {
+            "count": len(rs),
+            "total_ms": {p: sum(r[p] for r in rs) for p in ("auto",) + PRECS},
+            "per_matrix_best_ms": sum(min(r[p] for p in PRECS) for r in rs),
+            "auto_choices": {p: sum(r["auto_prec"] == p for r in rs) for p in PRECS},
+            "escalations": {p: sum(r[p + "_escalations"] for r in rs) for p in ("auto",) + PRECS}}
+    return out
 
 
 def main(argv=None):
@@ -285,7 +328,12 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--evaluate", action="store_true", help="measure the gain of --out instead")
     ap.add_argument("--eval-n", type=int, default=4096)
-    ap.add_argument("--eval-kinds", default="spd")
+    ap.add_argument("--eval-kinds", default="spd,nonsym")
+    ap.add_argument("--eval-n-nonsym", type=int, default=None,
+                    help="order of the nonsymmetric evaluation matrices (default: --eval-n)")
+    ap.add_argument("--boundary", action="store_true",
+                    help="label matrices of the boundary law (boundary_params) instead of the "
+                         "selector law")
     ap.add_argument("--eval-first", type=int, default=50_000,
                     help="first evaluation index (disjoint from the training indices)")
     ap.add_argument("--count", type=int, default=1200, help="training (or evaluation) matrices")
@@ -308,8 +356,11 @@ def main(argv=None):
     if args.evaluate:
         res = evaluate(args.out, count=args.count, n=args.eval_n,
                        kinds=tuple(args.eval_kinds.split(",")), first=args.eval_first,
-                       device_inputs=args.device_inputs)
-        print(json.dumps(res), flush=True)
+                       device_inputs=args.device_inputs, n_nonsym=args.eval_n_nonsym)
+        if args.records:
+            with open(args.records, "w") as fh:
+                json.dump(res, fh)
+        print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
         return
     dev = torch.device("cuda")
     records = []
@@ -317,10 +368,15 @@ def main(argv=None):
     t0 = time.time()
     if args.from_records:
         for fname in args.from_records.split(","):
-            with open(fname) as fh:
+            with (gzip.open(fname, "rt") if fname.endswith(".gz") else open(fname)) as fh:
                 records.extend(json.load(fh))
     for k in range(0 if args.from_records else args.count):
-        if args.device_inputs:
+        if args.boundary:
+            import workloads.device as WD
+            kind, n, kappa, seed = boundary_params(args.first + k)
+            ad = (WD.spd(n, kappa, seed, dev) if kind == "spd"
+                  else WD.nonsym_kappa(n, kappa, seed, dev))
+        elif args.device_inputs:
             import workloads.device as WD
             ad, kind, n, kappa = WD.selector_matrix(args.first + k, args.n_max_nonsym, dev)
         else:
@@ -341,7 +397,8 @@ def main(argv=None):
         print(json.dumps({"refit_cost_from": len(records), "out": args.out}), flush=True)
         return
     if args.label_only:
-        with open(args.records, "w") as fh:
+        with (gzip.open(args.records, "wt") if args.records.endswith(".gz")
+              else open(args.records, "w")) as fh:
             json.dump(records, fh)
         print(json.dumps({"labelled": len(records), "records": args.records}), flush=True)
         return
