@@ -27,6 +27,9 @@ What it computes (each function cites the passage of the paper it follows):
   the matrix cube root of Sec. 4 (Schur method, the generalized triangular
   Sylvester equation S^2 Y + S Y St + Y St^2 = C by substitution and by the
   block recursion, and the mixed-precision framework for p = 3).
+* ``real_schur``, ``trsqrt_quasi``, ``trsyl_quasi`` / ``rtrsyl_quasi``,
+  ``sqrtm_real``: the real route of the remark in Sec. 2.2.1 (real Schur form,
+  quasi-triangular root and Sylvester solves, no 2x2 block cut by a split).
 * ``mlp_*``: float64 forward/backward of the small precision-selector network.
 """
 
@@ -74,6 +77,16 @@ def lib():
         for f in ("orc_trroot3_z", "orc_trroot3_c", "orc_rootm3_z"):
             getattr(_lib, f).restype = ctypes.c_int
         for f in ("orc_trsyl3_z", "orc_rtrsyl3_z", "orc_rtrsyl3_c"):
+            getattr(_lib, f).restype = None
+        _lib.orc_trsqrt_quasi_d.argtypes = [i, dp, dp]
+        _lib.orc_trsqrt_quasi_s.argtypes = [i, fp, fp]
+        _lib.orc_trsyl_quasi_d.argtypes = [i, i, dp, dp, dp, dp]
+        _lib.orc_rtrsyl_quasi_d.argtypes = [i, i, dp, dp, dp, i]
+        _lib.orc_rtrsyl_quasi_s.argtypes = [i, i, fp, fp, fp, i]
+        _lib.orc_sqrt_2x2_d.argtypes = [dp, dp]
+        for f in ("orc_trsqrt_quasi_d", "orc_trsqrt_quasi_s", "orc_sqrt_2x2_d"):
+            getattr(_lib, f).restype = ctypes.c_int
+        for f in ("orc_trsyl_quasi_d", "orc_rtrsyl_quasi_d", "orc_rtrsyl_quasi_s"):
             getattr(_lib, f).restype = None
         _lib.orc_set_threads.argtypes = [i]
         _lib.orc_set_threads.restype = None
@@ -393,6 +406,81 @@ def rtrsyl(s, st, c, blks=32, single=False):
     return y
 
 
+def real_schur(a, single=False):
+    """Real Schur form A = Q T Q^T (remark in Sec. 2.2.1): T quasi-upper-
+    triangular with 1x1 blocks and standardised 2x2 blocks (equal diagonal
+    entries, off-diagonal entries of opposite sign) for complex conjugate
+    eigenvalue pairs.  The decomposition is the LAPACK routine behind
+    scipy.linalg.schur (a library step; float32 input stays in single
+    precision).  Returns (T, Q)."""
+    import scipy.linalg
+    dt = np.float32 if single else np.float64
+    t, q = scipy.linalg.schur(np.asarray(a, dtype=dt), output="real")
+    return np.asfortranarray(t), np.asfortranarray(q)
+
+
+def sqrt_2x2(b):
+    """Principal square root of a real 2x2 block by the Cayley-Hamilton
+    closed form X = (B + d I) / t, d = det(B)^1/2, t = (tr B + 2 d)^1/2."""
+    b = _f(b, np.float64)
+    x = np.zeros((2, 2), order="F")
+    _check(lib().orc_sqrt_2x2_d(_ptr(b, ctypes.c_double), _ptr(x, ctypes.c_double)), "sqrt_2x2")
+    return x
+
+
+def trsqrt_quasi(t, single=False):
+    """Square root of a quasi-upper-triangular T by blocks (Eq. (subst) with
+    1x1 / 2x2 diagonal blocks as units)."""
+    dt = np.float32 if single else np.float64
+    ct = ctypes.c_float if single else ctypes.c_double
+    t = _f(t, dt)
+    n = t.shape[0]
+    u = np.zeros((n, n), dtype=dt, order="F")
+    fn = lib().orc_trsqrt_quasi_s if single else lib().orc_trsqrt_quasi_d
+    _check(fn(n, _ptr(t, ct), _ptr(u, ct)), "trsqrt_quasi")
+    return u
+
+
+def trsyl_quasi(s, st, c):
+    """S Y + Y St = C with quasi-upper-triangular S, St (float64), block
+    back-substitution."""
+    s, st, c = _f(s, np.float64), _f(st, np.float64), _f(c, np.float64)
+    m, n = c.shape
+    y = np.zeros((m, n), order="F")
+    dp = ctypes.c_double
+    lib().orc_trsyl_quasi_d(m, n, _ptr(s, dp), _ptr(st, dp), _ptr(c, dp), _ptr(y, dp))
+    return y
+
+
+def rtrsyl_quasi(s, st, c, blks=32, single=False):
+    """Alg. 1 for quasi-upper-triangular S, St: splits never cut a 2x2 block."""
+    dt = np.float32 if single else np.float64
+    ct = ctypes.c_float if single else ctypes.c_double
+    s, st = _f(s, dt), _f(st, dt)
+    y = _f(c, dt).copy(order="F")
+    m, n = y.shape
+    fn = lib().orc_rtrsyl_quasi_s if single else lib().orc_rtrsyl_quasi_d
+    fn(m, n, _ptr(s, ct), _ptr(st, ct), _ptr(y, ct), int(blks))
+    return y
+
+
+def sqrtm_real(a, return_factors=False):
+    """Principal square root of a real matrix by the real Schur route in
+    float64: A = Q T Q^T, U = T^{1/2} (quasi-triangular), X = Q U Q^T."""
+    a = _f(a, np.float64)
+    if a.shape[0] == 0:
+        x = np.zeros((0, 0))
+        return (x, None) if return_factors else x
+    if not np.all(np.isfinite(a)):
+        raise OracleError("sqrtm_real: non-finite input")
+    t, q = real_schur(a)
+    u = trsqrt_quasi(t)
+    x = np.asfortranarray(q @ u @ q.T)
+    if return_factors:
+        return x, {"Q": q, "T": t, "U": u}
+    return x
+
+
 def kron_sylvester(s, st, c):
     """Brute force: (I kron S + St^T kron I) vec(Y) = vec(C) (Sec. 3.1 vec form)."""
     s = np.asarray(s, dtype=np.complex128)
@@ -488,7 +576,7 @@ def _stop_rule(hist):
 
 
 def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
-                  factor=None, x0=None, iterates=False):
+                  factor=None, x0=None, iterates=False, schur_form="complex"):
     """Alg. 3 (SPD, structure='spd') or Alg. 2 (structure='general') with the
     low precision emulated by this module's single-precision factorisation and
     float32 arithmetic for the transforms, float64 for residual and update.
@@ -500,6 +588,9 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
     x0: optional start (float64) instead of X_0 = Q diag(s) Q^T; only with
       `factor`.
     iterates: also return the list of iterates X_0, X_1, ... (unscaled).
+    schur_form: "complex" (Alg. 2 as printed) or "real" (real input only: the
+      real Schur form and the quasi-triangular solves of the remark in
+      Sec. 2.2.1).
     tol < 0 nullifies the stopping test (the accuracy experiments of Sec. 5.1):
       exactly maxit corrections, status ok, X the last iterate.
 
@@ -536,6 +627,22 @@ def emulate_mixed(a, structure="auto", low="fp32", maxit=30, tol=1e-13, blks=32,
             rl = r.astype(lowt)
             rt = q.T @ rl @ q
             y = rt / denom
+            return (q @ y @ q.T).astype(np.float64)
+    elif schur_form == "real":
+        if factor is not None or not is_real:
+            raise ValueError("the real Schur route takes real input and its own factor")
+        single = low == "fp32"
+        t, q = real_schur(asc, single=single)
+        try:
+            u = trsqrt_quasi(t, single=single)
+        except OracleError:
+            return {"X": None, "steps": 0, "hist": [], "status": ST_NO_PRINCIPAL}
+        x = (q @ u @ q.T).astype(np.float64)
+
+        def correction(r):
+            rl = r.astype(lowt)
+            rt = q.T @ rl @ q
+            y = rtrsyl_quasi(u, u, rt, blks=blks, single=single)
             return (q @ y @ q.T).astype(np.float64)
     else:
         if factor is not None:

@@ -452,6 +452,234 @@ void rtrsyl(int m, int n, const C<R>* S, int ldS, const C<R>* St, int ldT, C<R>*
 }
 
 // ---------------------------------------------------------------------------
+// Real quasi-triangular route (remark after the blocked square root in
+// Sec. 2.2.1): for real A the real Schur form A = Q T Q^T is used, T
+// quasi-upper-triangular with 1x1 and 2x2 diagonal blocks, and a block
+// partition never separates the two rows of a 2x2 block.  The square root and
+// the Sylvester solves below are the block forms of Eq. (subst) and of the
+// back-substitution, with 1x1 / 2x2 blocks in place of scalars.
+
+// Diagonal block structure of an m x m quasi-upper-triangular matrix: the
+// block starts, followed by m.  A 2x2 block starts at i when t(i+1, i) != 0.
+template <class R> std::vector<int> qt_blocks(int m, const R* t, int ld) {
+  std::vector<int> st;
+  for (int i = 0; i < m;) {
+    st.push_back(i);
+    i += (i + 1 < m && t[i + 1 + (size_t)i * ld] != R(0)) ? 2 : 1;
+  }
+  st.push_back(m);
+  return st;
+}
+
+// A Y + Y B = Cm for a p x p block A and a q x q block B (p, q <= 2): the
+// Kronecker form (I_q kron A + B^T kron I_p) vec(Y) = vec(Cm) (Sec. 3.1's
+// vec form, at block size) by Gaussian elimination with partial pivoting.
+template <class R>
+void sylv_small(int p, int q, const R* A, int lda, const R* B, int ldb, const R* Cm, int ldc, R* Y,
+                int ldy) {
+  const int N = p * q;
+  R M[4][5];
+  for (int c = 0; c < q; ++c)
+    for (int r = 0; r < p; ++r) {
+      const int row = r + p * c;
+      for (int l = 0; l < q; ++l)
+        for (int k = 0; k < p; ++k) {
+          R v = 0;
+          if (l == c) v += A[r + (size_t)k * lda];
+          if (k == r) v += B[l + (size_t)c * ldb];
+          M[row][k + p * l] = v;
+        }
+      M[row][N] = Cm[r + (size_t)c * ldc];
+    }
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < N; ++i)
+      if (std::abs(M[i][k]) > std::abs(M[piv][k])) piv = i;
+    if (piv != k)
+      for (int j = 0; j <= N; ++j) std::swap(M[k][j], M[piv][j]);
+    for (int i = k + 1; i < N; ++i) {
+      const R f = M[i][k] / M[k][k];
+      for (int j = k; j <= N; ++j) M[i][j] -= f * M[k][j];
+    }
+  }
+  R x[4];
+  for (int i = N - 1; i >= 0; --i) {
+    R acc = M[i][N];
+    for (int j = i + 1; j < N; ++j) acc -= M[i][j] * x[j];
+    x[i] = acc / M[i][i];
+  }
+  for (int c = 0; c < q; ++c)
+    for (int r = 0; r < p; ++r) Y[r + (size_t)c * ldy] = x[r + p * c];
+}
+
+// Principal square root of a 2x2 real block B without eigenvalues on R<=0.
+// For X = B^{1/2}, Cayley-Hamilton gives X^2 - tr(X) X + det(X) I = 0, i.e.
+// B + det(X) I = tr(X) X; det(X)^2 = det B and, taking traces,
+// tr(X)^2 = tr B + 2 det(X).  The principal root has both eigenvalues in the
+// open right half-plane, so det(X) and tr(X) are the positive roots:
+//   X = (B + d I) / t,  d = sqrt(det B),  t = sqrt(tr B + 2 d).
+// Returns false when det B <= 0 or tr B + 2 d <= 0 (no real principal root).
+template <class R> bool sqrt_2x2(const R* b, int ldb, R* x, int ldx) {
+  const R a11 = b[0], a21 = b[1], a12 = b[ldb], a22 = b[1 + ldb];
+  const R det = a11 * a22 - a12 * a21;
+  if (!(det > R(0))) return false;
+  const R d = std::sqrt(det);
+  const R t2 = a11 + a22 + R(2) * d;
+  if (!(t2 > R(0))) return false;
+  const R t = std::sqrt(t2);
+  x[0] = (a11 + d) / t;
+  x[1] = a21 / t;
+  x[ldx] = a12 / t;
+  x[1 + ldx] = (a22 + d) / t;
+  return true;
+}
+
+// Square root U of a quasi-upper-triangular T by blocks (Eq. (subst) with
+// the diagonal blocks as units): U_ii = T_ii^{1/2} (scalar root, or the 2x2
+// closed form above), and for i < j
+//   U_ii U_ij + U_ij U_jj = T_ij - sum_{i<k<j} U_ik U_kj.
+// Returns 2 when a diagonal block has an eigenvalue on R<=0.
+template <class R> int trsqrt_quasi(int n, const R* t, R* u) {
+  for (size_t k = 0; k < (size_t)n * n; ++k) u[k] = 0;
+  const std::vector<int> bs = qt_blocks<R>(n, t, n);
+  const int nb = (int)bs.size() - 1;
+  for (int b = 0; b < nb; ++b) {
+    const int i = bs[b], p = bs[b + 1] - i;
+    if (p == 1) {
+      const R d = t[i + (size_t)i * n];
+      if (!(d > R(0))) return 2;
+      u[i + (size_t)i * n] = std::sqrt(d);
+    } else if (!sqrt_2x2<R>(t + i + (size_t)i * n, n, u + i + (size_t)i * n, n)) {
+      return 2;
+    }
+  }
+  auto block = [&](int bi, int bj) {
+    const int i0 = bs[bi], p = bs[bi + 1] - i0, j0 = bs[bj], q = bs[bj + 1] - j0;
+    R rhs[4];
+    for (int c = 0; c < q; ++c)
+      for (int r = 0; r < p; ++r) {
+        R acc = t[i0 + r + (size_t)(j0 + c) * n];
+        for (int k = bs[bi + 1]; k < j0; ++k)
+          acc -= u[i0 + r + (size_t)k * n] * u[k + (size_t)(j0 + c) * n];
+        rhs[r + p * c] = acc;
+      }
+    sylv_small<R>(p, q, u + i0 + (size_t)i0 * n, n, u + j0 + (size_t)j0 * n, n, rhs, p,
+                  u + i0 + (size_t)j0 * n, n);
+  };
+  // block (bi, bj) reads only blocks of lower block superdiagonals
+  for (int d = 1; d < nb; ++d) {
+#pragma omp parallel for schedule(static) if (g_deferred)
+    for (int bi = 0; bi < nb - d; ++bi) block(bi, bi + d);
+  }
+  return 0;
+}
+
+// S Y + Y St = Cm with S (m x m) and St (n x n) quasi-upper-triangular, by
+// block back-substitution: block columns left to right, block rows bottom to
+// top,
+//   S_ii Y_ij + Y_ij St_jj = C_ij - sum_{k>i} S_ik Y_kj - sum_{l<j} Y_il St_lj.
+template <class R>
+void trsyl_quasi(int m, int n, const R* S, int ldS, const R* St, int ldT, const R* Cm, int ldC,
+                 R* Y, int ldY) {
+  const std::vector<int> rb = qt_blocks<R>(m, S, ldS), cb = qt_blocks<R>(n, St, ldT);
+  const int nrb = (int)rb.size() - 1, ncb = (int)cb.size() - 1;
+  for (int bj = 0; bj < ncb; ++bj) {
+    const int j0 = cb[bj], q = cb[bj + 1] - j0;
+    for (int bi = nrb - 1; bi >= 0; --bi) {
+      const int i0 = rb[bi], p = rb[bi + 1] - i0;
+      R rhs[4];
+      for (int c = 0; c < q; ++c)
+        for (int r = 0; r < p; ++r) {
+          const int i = i0 + r, j = j0 + c;
+          R acc = Cm[i + (size_t)j * ldC];
+          for (int k = rb[bi + 1]; k < m; ++k) acc -= S[i + (size_t)k * ldS] * Y[k + (size_t)j * ldY];
+          for (int k = 0; k < j0; ++k) acc -= Y[i + (size_t)k * ldY] * St[k + (size_t)j * ldT];
+          rhs[r + p * c] = acc;
+        }
+      sylv_small<R>(p, q, S + i0 + (size_t)i0 * ldS, ldS, St + j0 + (size_t)j0 * ldT, ldT, rhs, p,
+                    Y + i0 + (size_t)j0 * ldY, ldY);
+    }
+  }
+}
+
+// Cm(mxn) -= A(mxk) * B(kxn), real sub-blocks with leading dimensions.
+template <class R>
+void sub_gemm_real(int m, int n, int k, const R* A, int lda, const R* B, int ldb, R* Cm, int ldc) {
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < k; ++l) {
+      const R b = B[l + (size_t)j * ldb];
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldc] -= A[i + (size_t)l * lda] * b;
+    }
+}
+
+// Split point of a quasi-triangular dimension m for Alg. 1: floor(m/2),
+// moved one index down when it would separate the two rows of a 2x2 diagonal
+// block (s(h, h-1) != 0), so that no 2x2 block is cut.  Returns m when no
+// split is possible (a single 2x2 block).
+template <class R> int qsplit(int m, const R* S, int ld) {
+  int h = m / 2;
+  if (h > 0 && h < m && S[h + (size_t)(h - 1) * ld] != R(0)) ++h;
+  return h;
+}
+
+// Alg. 1 for quasi-upper-triangular S and St: the recursion of rtrsyl above
+// with the split points of qsplit; Cm is overwritten with Y.
+template <class R>
+void rtrsyl_quasi(int m, int n, const R* S, int ldS, const R* St, int ldT, R* Cm, int ldC,
+                  int blks) {
+  if (m <= 0 || n <= 0) return;
+  const int m1 = qsplit<R>(m, S, ldS), n1 = qsplit<R>(n, St, ldT);
+  const bool base = (m <= blks && n <= blks);
+  const bool rows = !base && 2 * n <= m && m1 < m;
+  const bool cols = !base && !rows && 2 * m <= n && n1 < n;
+  const bool both = !base && !rows && !cols && 2 * n > m && 2 * m > n && m1 < m && n1 < n;
+  if (!rows && !cols && !both) {
+    std::vector<R> y((size_t)m * n);
+    trsyl_quasi<R>(m, n, S, ldS, St, ldT, Cm, ldC, y.data(), m);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < m; ++i) Cm[i + (size_t)j * ldC] = y[i + (size_t)j * m];
+    return;
+  }
+  if (rows) {
+    const int m2 = m - m1;
+    const R* S12 = S + (size_t)m1 * ldS;
+    const R* S22 = S + m1 + (size_t)m1 * ldS;
+    R* C2 = Cm + m1;
+    rtrsyl_quasi<R>(m2, n, S22, ldS, St, ldT, C2, ldC, blks);
+    sub_gemm_real<R>(m1, n, m2, S12, ldS, C2, ldC, Cm, ldC);
+    rtrsyl_quasi<R>(m1, n, S, ldS, St, ldT, Cm, ldC, blks);
+    return;
+  }
+  if (cols) {
+    const int n2 = n - n1;
+    const R* T12 = St + (size_t)n1 * ldT;
+    const R* T22 = St + n1 + (size_t)n1 * ldT;
+    R* C2 = Cm + (size_t)n1 * ldC;
+    rtrsyl_quasi<R>(m, n1, S, ldS, St, ldT, Cm, ldC, blks);
+    sub_gemm_real<R>(m, n2, n1, Cm, ldC, T12, ldT, C2, ldC);
+    rtrsyl_quasi<R>(m, n2, S, ldS, T22, ldT, C2, ldC, blks);
+    return;
+  }
+  const int m2 = m - m1, n2 = n - n1;
+  const R* S12 = S + (size_t)m1 * ldS;
+  const R* S22 = S + m1 + (size_t)m1 * ldS;
+  const R* T12 = St + (size_t)n1 * ldT;
+  const R* T22 = St + n1 + (size_t)n1 * ldT;
+  R* C11 = Cm;
+  R* C21 = Cm + m1;
+  R* C12 = Cm + (size_t)n1 * ldC;
+  R* C22 = Cm + m1 + (size_t)n1 * ldC;
+  rtrsyl_quasi<R>(m2, n1, S22, ldS, St, ldT, C21, ldC, blks);   // Y21
+  sub_gemm_real<R>(m1, n1, m2, S12, ldS, C21, ldC, C11, ldC);    // C11 -= S12 Y21
+  sub_gemm_real<R>(m2, n2, n1, C21, ldC, T12, ldT, C22, ldC);    // C22 -= Y21 St12
+  rtrsyl_quasi<R>(m1, n1, S, ldS, St, ldT, C11, ldC, blks);     // Y11
+  rtrsyl_quasi<R>(m2, n2, S22, ldS, T22, ldT, C22, ldC, blks);  // Y22
+  sub_gemm_real<R>(m1, n2, m2, S12, ldS, C22, ldC, C12, ldC);    // C12 -= S12 Y22
+  sub_gemm_real<R>(m1, n2, n1, C11, ldC, T12, ldT, C12, ldC);    // C12 -= Y11 St12
+  rtrsyl_quasi<R>(m1, n2, S, ldS, T22, ldT, C12, ldC, blks);    // Y12
+}
+
+// ---------------------------------------------------------------------------
 // Matrix cube roots (Sec. 4, p = 3).
 
 // Principal cube root of z (z not on the closed negative real axis):
@@ -819,6 +1047,21 @@ void orc_set_deferred(int on) { orc::g_deferred = on ? 1 : 0; }
 
 // Status codes shared by the oracle entry points.
 enum { ORC_OK = 0, ORC_NOCONV = 1, ORC_NO_PRINCIPAL = 2 };
+
+// Real quasi-triangular route: square root of a quasi-upper-triangular T,
+// the block back-substitution and Alg. 1 with the no-cut split rule.
+int orc_trsqrt_quasi_d(int n, const double* t, double* u) { return orc::trsqrt_quasi<double>(n, t, u); }
+int orc_trsqrt_quasi_s(int n, const float* t, float* u) { return orc::trsqrt_quasi<float>(n, t, u); }
+void orc_trsyl_quasi_d(int m, int n, const double* s, const double* st, const double* cm, double* y) {
+  orc::trsyl_quasi<double>(m, n, s, m, st, n, cm, m, y, m);
+}
+void orc_rtrsyl_quasi_d(int m, int n, const double* s, const double* st, double* cm, int blks) {
+  orc::rtrsyl_quasi<double>(m, n, s, m, st, n, cm, m, blks);
+}
+void orc_rtrsyl_quasi_s(int m, int n, const float* s, const float* st, float* cm, int blks) {
+  orc::rtrsyl_quasi<float>(m, n, s, m, st, n, cm, m, blks);
+}
+int orc_sqrt_2x2_d(const double* b, double* x) { return orc::sqrt_2x2<double>(b, 2, x, 2) ? 0 : 2; }
 
 // Complex Schur decomposition A = Q T Q^H (complex128).  a: in A, out T.
 int orc_schur_z(int n, double* a, double* q) {
