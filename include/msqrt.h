@@ -91,6 +91,10 @@ typedef struct {
   int blks;               /* minimal block size of the triangular solvers, default 32 */
   int fallback;           /* 1: escalate BF16SPLIT -> FP32 -> FP64 on failure (default) */
   int64_t batch;          /* number of matrices, default 1 */
+  int real_schur;         /* real input on the general path: 1 = real Schur form
+                             A = Q T Q^T with quasi-triangular T (1x1 and 2x2 diagonal
+                             blocks, remark on real input in Sec. 2.2.1), default;
+                             0 = complex Schur form (Alg. 2 as printed) */
 } msqrt_options;
 
 typedef struct {
@@ -125,7 +129,11 @@ void msqrt_default_options(msqrt_options* opt);
 
 /* Low-precision Schur factorisation of A (the factorisation steps of Alg. 2 and Alg. 3):
  * HPD input -> spectral decomposition A/4^k ~ Q diag(s^2) Q^*;
- * general input -> complex Schur form A/4^k ~ Q T Q^*, S = T^{1/2}.
+ * general input -> complex Schur form A/4^k ~ Q T Q^*, S = T^{1/2}; real general input
+ * with opt->real_schur (default) -> real Schur form A/4^k ~ Q T Q^T, T quasi-upper-
+ * triangular with standardised 2x2 blocks for complex conjugate pairs, S = T^{1/2}
+ * quasi-upper-triangular (remark on real input in Sec. 2.2.1), and the refinement's
+ * Sylvester solves run on tiles that never cut a 2x2 block.
  * The precision is opt->prec (AUTO picks one).  On success *out owns Q, S, the
  * scale exponent k and workspaces; release it with msqrt_factor_destroy.
  * Errors: INVALID_ARG (n < 0, ld < n, NULL pointer with n > 0), NONFINITE,
@@ -245,8 +253,9 @@ msqrt_status msqrt_factor_wrap(msqrt_prec prec, msqrt_struct structure, msqrt_dt
                                msqrt_factor_t* out);
 
 /* Test hook: reads the factor's Q and S back to host buffers in the factor's
- * own precision (layout as in msqrt_factor_wrap); the scale exponent goes to
- * *scale_exp.  Either pointer may be NULL. */
+ * own precision (layout as in msqrt_factor_wrap; for a real-Schur general
+ * factor Q and S are both real n x n, column-major); the scale exponent goes
+ * to *scale_exp.  Either pointer may be NULL. */
 msqrt_status msqrt_factor_export(msqrt_factor_t f, void* Q, void* S, int* scale_exp);
 
 #ifdef __cplusplus

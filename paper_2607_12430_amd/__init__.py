@@ -58,7 +58,7 @@ def _ensure_selector():
 
 
 def default_options(prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32, fallback=True,
-                    batch=1):
+                    batch=1, real_schur=True):
     o = _lib.Options()
     lib().msqrt_default_options(ctypes.byref(o))
     o.prec = _lib.PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
@@ -68,6 +68,7 @@ def default_options(prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32,
     o.blks = int(blks)
     o.fallback = 1 if fallback else 0
     o.batch = int(batch)
+    o.real_schur = 1 if real_schur else 0
     return o
 
 
@@ -105,10 +106,11 @@ class Factor:
         return np.ascontiguousarray(np.swapaxes(q, 1, 2)), s, k.value
 
 
-def factor(a: torch.Tensor, prec="fp32", structure="auto", blks=32) -> Factor:
+def factor(a: torch.Tensor, prec="fp32", structure="auto", blks=32, real_schur=True) -> Factor:
     _check_matrix(a, "A")
     n, batch, nn = _dims(a)
-    o = default_options(prec=prec, structure=structure, blks=blks, batch=batch)
+    o = default_options(prec=prec, structure=structure, blks=blks, batch=batch,
+                        real_schur=real_schur)
     h = ctypes.c_void_p(0)
     dt = _lib.COMPLEX128 if a.is_complex() else _lib.REAL64
     check(lib().msqrt_factor(ctypes.byref(o), dt, n, ctypes.c_void_p(a.data_ptr()), n, nn,
@@ -168,9 +170,10 @@ def refine_noalloc(f: Factor, a: torch.Tensor, x: torch.Tensor, init_from_factor
 
 
 def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, blks=32,
-          fallback=True, keep_factor=False, allow_fail=False, out=None):
+          fallback=True, keep_factor=False, allow_fail=False, out=None, real_schur=True):
     """Principal square root of a (batch of) matrices.  Returns (X, info) or
-    (X, info, factor) when keep_factor is set."""
+    (X, info, factor) when keep_factor is set.  real_schur selects the real
+    Schur form (default) or the complex one for real nonsymmetric input."""
     if isinstance(a, torch.Tensor) and not a.is_contiguous():
         a = a.contiguous()
     _check_matrix(a, "A")
@@ -179,7 +182,7 @@ def sqrtm(a: torch.Tensor, prec="fp32", structure="auto", maxit=30, tol=1e-13, b
     n, batch, nn = _dims(a)
     x = torch.empty_like(a) if out is None else out
     o = default_options(prec=prec, structure=structure, maxit=maxit, tol=tol, blks=blks,
-                        fallback=fallback, batch=batch)
+                        fallback=fallback, batch=batch, real_schur=real_schur)
     info = _lib.Info()
     h = ctypes.c_void_p(0)
     dt = _lib.COMPLEX128 if a.is_complex() else _lib.REAL64

@@ -52,6 +52,7 @@ class Options(ctypes.Structure):
         ("blks", ctypes.c_int),
         ("fallback", ctypes.c_int),
         ("batch", ctypes.c_int64),
+        ("real_schur", ctypes.c_int),
     ]
 
 

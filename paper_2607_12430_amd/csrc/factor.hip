@@ -105,6 +105,7 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
     return MSQRT_ERR_INVALID_ARG;
   }
   const bool cplx = f->dtype == MSQRT_COMPLEX128;
+  f->real_schur = false;
   if (cplx && o.structure == MSQRT_STRUCT_HPD) {
     set_last_error("complex Hermitian input runs on the general path (structure AUTO or GENERAL)");
     return MSQRT_ERR_UNSUPPORTED;
@@ -152,6 +153,11 @@ msqrt_status build_factor(Factor* f, const msqrt_options& o, const double* A, in
       set_last_error("the general path takes one matrix per call (batch = 1)");
       return MSQRT_ERR_UNSUPPORTED;
     }
+    if (!cplx && o.real_schur) {
+      if (f->prec == MSQRT_PREC_FP64) return factor_real<double>(f, A, lda, st, tm);
+      return factor_real<float>(f, A, lda, st, tm);
+    }
+    f->real_schur = false;
     if (f->prec == MSQRT_PREC_FP64) return factor_general<double>(f, A, lda, cplx ? 1 : 0, st, tm);
     return factor_general<float>(f, A, lda, cplx ? 1 : 0, st, tm);
   }

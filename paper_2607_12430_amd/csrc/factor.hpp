@@ -80,6 +80,14 @@ struct Factor {
   // Root order p of the factor (2: square root; 3: cube root, Sec. 4): the
   // input is scaled by 2^(-p k), the root by 2^-k.
   int root = 2;
+  // Real input on the general path with the real Schur form (remark on real
+  // input in Sec. 2.2.1): Q real n x n, S = T^{1/2} real quasi-upper-
+  // triangular n x n (both in the factor precision), qpart the device tile
+  // partition of S (qnt tiles) that keeps every 2x2 block inside one tile.
+  bool real_schur = false;
+  DevBuf qpart;
+  std::vector<int> qpart_h;
+  int qnt = 0;
   TrsylvWork tw;
 
   void upload_scales(hipStream_t st) {
@@ -233,6 +241,17 @@ template <typename T>
 msqrt_status refine_general(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx,
                             int init, int maxit, double tol, hipStream_t st, msqrt_info* info,
                             PhaseTimer& tm);
+// Real route of the general path (real Schur form, quasi-triangular root and
+// Sylvester solves).
+template <typename T>
+msqrt_status factor_real(Factor* f, const double* A, int64_t lda, hipStream_t st, PhaseTimer* tm);
+template <typename T>
+msqrt_status refine_real(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx, int init,
+                         int maxit, double tol, hipStream_t st, msqrt_info* info, PhaseTimer& tm);
+template <typename T>
+msqrt_status backward_real(Factor* f, const double* X, int64_t ldx, const double* Gbar,
+                           int64_t ldgb, double* G, int64_t ldg, int maxit, double tol,
+                           hipStream_t st, msqrt_info* info, PhaseTimer& tm);
 template <typename T>
 msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const double* Gbar,
                               int64_t ldgb, double* G, int64_t ldg, int maxit, double tol,

@@ -298,6 +298,63 @@ void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* 
   tm.end();
 }
 
+// ---- real route helpers
+
+// H (n x n, ld n) = real plane of the stacked Hs (ld 2n).
+template <typename T>
+__global__ void real_plane_kernel(int n, const T* Hs, T* H) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)n * n) return;
+  const int64_t i = x % n, j = x / n;
+  H[i + j * n] = Hs[i + j * 2 * n];
+}
+
+// sub[i] = 1 where t(i+1, i) != 0 (2x2 diagonal blocks of a quasi-
+// triangular T); 2 where that entry is not finite.
+template <typename T>
+__global__ void quasi_sub_kernel(int n, const T* Tm, unsigned char* sub) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const T v = Tm[(i + 1) + (int64_t)i * n];
+  sub[i] = !isfinite(v) ? 2 : (v != T(0) ? 1 : 0);
+}
+
+// C = op(A) op(B), all n x n real in precision T (batch 1).
+template <typename T>
+void gstore1(hipStream_t st, bool ta, bool tb, int n, const T* A, const T* B, T* C,
+             bool split = false) {
+  if (std::is_same<T, float>::value)
+    gemm_store_f32(st, ta, tb, n, n, n, (const float*)A, n, 0, (const float*)B, n, 0, (float*)C,
+                   n, 0, 1.f, 0.f, 1, false, split);
+  else
+    gemm_store_f64(st, ta, tb, n, n, n, (const double*)A, n, 0, (const double*)B, n, 0,
+                   (double*)C, n, 0, 1.0, 0.0, 1, false);
+}
+
+// M (low precision, n x n) -> Y = rtrsyl(U, U, Q^T M Q) (in Rt) -> V = Q Y (in
+// M) -> X (+)= fl64(V Q^T), with the quasi-triangular U and its partition.
+template <typename T>
+void correction_real(hipStream_t st, Factor* f, T* M, T* Wm, T* Rt, double* Xw, bool set,
+                     PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const T* Q = f->Q.as<T>();
+  const T* U = f->S.as<T>();
+  const bool split = f->prec == MSQRT_PREC_BF16SPLIT;
+  tm.begin(MSQRT_T_TRANSFORM);
+  gstore1<T>(st, false, false, n, M, Q, Wm, split);
+  gstore1<T>(st, true, false, n, Q, Wm, Rt, split);
+  tm.begin(MSQRT_T_SOLVE);
+  const int* dp = f->qpart.as<int>();
+  trsyl_quasi<T>(st, n, n, U, n, dp, f->qnt, U, n, dp, f->qnt, Rt, n, f->tw);
+  tm.begin(MSQRT_T_UPDATE);
+  gstore1<T>(st, false, false, n, Q, Rt, M, split);
+  if (set)
+    gemm_set_f64<T>(st, false, true, n, n, M, n, 0, Q, n, 0, Xw, n, 0, 1, false, split);
+  else
+    gemm_update<T>(st, false, true, n, n, M, n, 0, Q, n, 0, Xw, n, 0, nullptr, 1, false, split);
+  tm.end();
+}
+
 double sum_host(const std::vector<double>& v, int off, int cnt) {
   double s = 0.0;
   for (int i = 0; i < cnt; ++i) s += v[off + i];
@@ -810,6 +867,296 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
   }
   return status;
 }
+
+// ---------------------------------------------------------------------------
+// Real route: real input on the general path with the real Schur form
+// A/4^k ~ Q T Q^T (remark on real input in Sec. 2.2.1).  The Hessenberg
+// reduction runs in the complex kernels on the real data (its reflectors
+// and both factors stay real), then the real double-shift QR, the tile
+// partition that keeps 2x2 blocks whole, and U = T^{1/2} on it.
+
+template <typename T>
+msqrt_status factor_real(Factor* f, const double* A, int64_t lda, hipStream_t st, PhaseTimer* tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  T* Q = f->Q.ensure<T>(nn);
+  T* U = f->S.ensure<T>(nn);
+  T* Hs = f->fw1.ensure<T>(2 * nn);
+  T* Qs = f->fw2.ensure<T>(2 * nn);
+  T* H = f->fw3.ensure<T>(nn);
+  unsigned char* dsub = f->fw4.ensure<unsigned char>(n + 64);
+  f->gq_ready = false;
+  f->real_schur = true;
+  if (tm) tm->begin(MSQRT_T_REDUCE);
+  hipLaunchKernelGGL(to_stacked_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n, A, lda, 0,
+                     f->ascale_dev(), Hs);
+  MSQRT_LAUNCH_CHECK();
+  GehrdWork gw;
+  gehrd<T>(st, n, Hs, Qs, gw);
+  hipLaunchKernelGGL(real_plane_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n,
+                     (const T*)Hs, H);
+  MSQRT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(real_plane_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n,
+                     (const T*)Qs, Q);
+  MSQRT_LAUNCH_CHECK();
+  if (tm) tm->begin(MSQRT_T_EIG);
+  HseqrWork hw;
+  const bool ok = rhseqr<T>(st, n, H, Q, hw, (T)f->anorm_scaled[0]);
+  if (!ok) {
+    if (tm) tm->end();
+    set_last_error("real Schur QR did not converge");
+    return MSQRT_ERR_NOT_CONVERGED;
+  }
+  if (tm) tm->begin(MSQRT_T_X0);
+  std::vector<unsigned char> sub(std::max(n, 1), 0);
+  if (n > 1) {
+    hipLaunchKernelGGL(quasi_sub_kernel<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n,
+                       (const T*)H, dsub);
+    MSQRT_LAUNCH_CHECK();
+    MSQRT_HIP(hipMemcpyAsync(sub.data(), dsub, n - 1, hipMemcpyDeviceToHost, st));
+    MSQRT_HIP(hipStreamSynchronize(st));
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    if (sub[i] == 2 || (sub[i] && i + 2 < n && sub[i + 1])) {
+      if (tm) tm->end();
+      set_last_error("real Schur QR left a non-finite or overlapping 2x2 block");
+      return MSQRT_ERR_NOT_CONVERGED;
+    }
+  }
+  f->qpart_h = quasi_partition(n, sub.data());
+  f->qnt = (int)f->qpart_h.size() - 1;
+  int* dp = f->qpart.ensure<int>((int64_t)f->qpart_h.size());
+  MSQRT_HIP(hipMemcpyAsync(dp, f->qpart_h.data(), sizeof(int) * f->qpart_h.size(),
+                           hipMemcpyHostToDevice, st));
+  trsylv_reset(st, f->tw);
+  trsqrt_quasi<T>(st, n, H, U, dp, f->qnt, f->tw);
+  if (tm) tm->end();
+  int timed_out = 0, nonprincipal = 0;
+  trsylv_errors(st, f->tw, &timed_out, &nonprincipal);
+  if (tm) tm->collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "quasi-triangular square root: dataflow wait timed out"};
+  if (nonprincipal) {
+    set_last_error("an eigenvalue lies on or next to the closed negative real axis");
+    return MSQRT_ERR_NO_PRINCIPAL;
+  }
+  return MSQRT_OK;
+}
+
+template <typename T>
+msqrt_status refine_real(Factor* f, const double* A, int64_t lda, double* X, int64_t ldx, int init,
+                         int maxit, double tol, hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  const T* Q = f->Q.as<T>();
+  const T* U = f->S.as<T>();
+  // X (float64) with an all-zero second plane, so that the wide in/out
+  // kernels of the complex route read and write it unchanged
+  double* Xw = f->gx.ensure<double>(2 * nn);
+  T* M = f->ws1.ensure<T>(nn);
+  T* Wm = f->ws2.ensure<T>(nn);
+  T* Rt = f->gt.ensure<T>(nn);
+  const int ntiles = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  double* part = f->part.ensure<double>((int64_t)ntiles + 2 * kRedBlocks + 64);
+  double* rn = f->rnorm.ensure<double>(1);
+  trsylv_reset(st, f->tw);
+  if (init) {
+    tm.begin(MSQRT_T_X0);
+    MSQRT_HIP(hipMemsetAsync(Xw + nn, 0, sizeof(double) * nn, st));
+    // V = Q U, X_0 = fl64(V Q^T)
+    gstore1<T>(st, false, false, n, Q, U, M);
+    gemm_set_f64<T>(st, false, true, n, n, M, n, 0, Q, n, 0, Xw, n, 0, 1, false);
+  } else {
+    tm.begin(MSQRT_T_VALIDATE);
+    hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, (const double*)X,
+                       ldx, 0, 0, f->rscale_dev(), Xw);
+    MSQRT_LAUNCH_CHECK();
+  }
+  std::vector<double> hist;
+  double best_r = INFINITY;
+  double* best = nullptr;
+  Verdict verdict = Verdict::Continue;
+  int steps = 0;
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    // R = A/4^k - X X
+    const int nt = gemm_residual_ex(st, false, false, n, n, n, Xw, n, 0, Xw, n, 0, A, lda, 0,
+                                    f->ascale_dev(),
+                                    std::is_same<T, float>::value ? (float*)M : nullptr,
+                                    std::is_same<T, float>::value ? nullptr : (double*)M, n, 0,
+                                    part, 1);
+    launch_reduce_sqrt(st, part, nt, 1, rn);
+    double hrn = 0.0;
+    MSQRT_HIP(hipMemcpyAsync(&hrn, rn, sizeof(double), hipMemcpyDeviceToHost, st));
+    tm.end();
+    MSQRT_HIP(hipStreamSynchronize(st));
+    tm.collect();
+    hist.push_back(hrn / f->anorm_scaled[0]);
+    Verdict v = judge_step(hist, tol, it, maxit);
+    if (v != Verdict::Continue) {
+      verdict = v;
+      break;
+    }
+    if (hist.back() < best_r) {
+      best_r = hist.back();
+      if (!best) best = f->best.ensure<double>(nn);
+      MSQRT_HIP(hipMemcpyAsync(best, Xw, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    }
+    correction_real<T>(st, f, M, Wm, Rt, Xw, false, tm);
+    ++steps;
+  }
+  msqrt_status status = MSQRT_OK;
+  double final_r = hist.back();
+  if (verdict != Verdict::Converged) {
+    if (best && !(final_r <= best_r)) {  // also when final_r is NaN
+      MSQRT_HIP(hipMemcpyAsync(Xw, best, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+      final_r = best_r;
+    }
+    status = verdict == Verdict::Diverged ? MSQRT_ERR_DIVERGED : MSQRT_ERR_NOT_CONVERGED;
+    set_last_error(verdict == Verdict::Diverged ? "refinement diverged"
+                                                 : "refinement did not converge");
+  }
+  tm.begin(MSQRT_T_VALIDATE);
+  hipLaunchKernelGGL(x_out_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, (const double*)Xw, 0, 0,
+                     f->uscale_dev(), X, ldx, part);
+  MSQRT_LAUNCH_CHECK();
+  tm.end();
+  int timed_out = 0;
+  trsylv_errors(st, f->tw, &timed_out, nullptr);
+  tm.collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "quasi-triangular Sylvester solve: dataflow wait timed out"};
+  if (info) {
+    info->steps = steps;
+    info->relres = std::isfinite(final_r) ? final_r : INFINITY;
+    info->nhist = (int)std::min<size_t>(64, hist.size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
+  }
+  return status;
+}
+
+// Backward on the real route: X^T G + G X^T = Gbar, i.e. X G~ + G~ X = Gbar^T
+// with G~ = G^T, solved with the factor of A/4^k (root X_s = 2^-k X) and
+// refined with float64 residuals; G = 2^-k G~^T.
+template <typename T>
+msqrt_status backward_real(Factor* f, const double* X, int64_t ldx, const double* Gbar,
+                           int64_t ldgb, double* G, int64_t ldg, int maxit, double tol,
+                           hipStream_t st, msqrt_info* info, PhaseTimer& tm) {
+  const int n = (int)f->n;
+  const int64_t nn = (int64_t)n * n;
+  double* Xw = f->gx.ensure<double>(2 * nn);   // X_s (second plane zero)
+  double* Cw = f->best.ensure<double>(5 * nn);  // Gbar^T (two planes), T1, G~ (two planes)
+  double* T1 = Cw + 2 * nn;
+  double* Gw = Cw + 3 * nn;
+  T* M = f->ws1.ensure<T>(nn);
+  T* Wm = f->ws2.ensure<T>(nn);
+  T* Rt = f->gt.ensure<T>(nn);
+  const int ntiles = (int)(ceil_div(n, 128) * ceil_div(n, 128));
+  double* part = f->part.ensure<double>((int64_t)ntiles + 2 * kRedBlocks + 64);
+  double* rn = f->rnorm.ensure<double>(1);
+  double* one = f->gsc.ensure<double>(1);
+  {
+    const double h = 1.0;
+    MSQRT_HIP(hipMemcpyAsync(one, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  }
+  trsylv_reset(st, f->tw);
+  tm.begin(MSQRT_T_VALIDATE);
+  int* flags = f->active.ensure<int>(1);
+  MSQRT_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
+  hipLaunchKernelGGL(cvalidate_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, Gbar, ldgb, 0,
+                     flags, part);
+  MSQRT_LAUNCH_CHECK();
+  std::vector<double> hp(kRedBlocks);
+  int hf = 0;
+  MSQRT_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * kRedBlocks, hipMemcpyDeviceToHost, st));
+  MSQRT_HIP(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, X, ldx, 0, 0,
+                     f->rscale_dev(), Xw);
+  MSQRT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(x_in_kernel, dim3(blocks_for(nn)), dim3(256), 0, st, n, Gbar, ldgb, 0, 1,
+                     (const double*)nullptr, Cw);
+  MSQRT_LAUNCH_CHECK();
+  MSQRT_HIP(hipMemsetAsync(Gw + nn, 0, sizeof(double) * nn, st));
+  tm.end();
+  MSQRT_HIP(hipStreamSynchronize(st));
+  tm.collect();
+  if (hf & 1) {
+    set_last_error("Gbar contains Inf or NaN");
+    return MSQRT_ERR_NONFINITE;
+  }
+  const double gnorm = std::sqrt(sum_host(hp, 0, kRedBlocks));
+  std::vector<double> hist;
+  Verdict verdict = Verdict::Continue;
+  int steps = 0;
+  for (int it = 0;; ++it) {
+    tm.begin(MSQRT_T_RESIDUAL);
+    if (it == 0) {
+      hist.push_back(gnorm > 0.0 ? 1.0 : 0.0);
+      if (gnorm == 0.0) {
+        verdict = Verdict::Converged;
+        MSQRT_HIP(hipMemsetAsync(Gw, 0, sizeof(double) * nn, st));
+        break;
+      }
+      if (std::is_same<T, float>::value)
+        launch_cast_scale_f64_f32(st, n, Cw, n, 0, nullptr, (float*)M, n, 0, 1);
+      else
+        launch_cast_scale_f64_f64(st, n, Cw, n, 0, nullptr, (double*)M, n, 0, 1);
+    } else {
+      // R = Gbar^T - X_s G~ - G~ X_s
+      MSQRT_HIP(hipMemcpyAsync(T1, Cw, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+      gemm_store_f64(st, false, false, n, n, n, Xw, n, 0, Gw, n, 0, T1, n, 0, -1.0, 1.0, 1, false);
+      const int nt = gemm_residual_ex(st, false, false, n, n, n, Gw, n, 0, Xw, n, 0, T1, n, 0, one,
+                                      std::is_same<T, float>::value ? (float*)M : nullptr,
+                                      std::is_same<T, float>::value ? nullptr : (double*)M, n, 0,
+                                      part, 1);
+      launch_reduce_sqrt(st, part, nt, 1, rn);
+      double hrn = 0.0;
+      MSQRT_HIP(hipMemcpyAsync(&hrn, rn, sizeof(double), hipMemcpyDeviceToHost, st));
+      tm.end();
+      MSQRT_HIP(hipStreamSynchronize(st));
+      tm.collect();
+      hist.push_back(hrn / gnorm);
+      Verdict v = judge_step(hist, tol, it, maxit);
+      if (v != Verdict::Continue) {
+        verdict = v;
+        break;
+      }
+    }
+    correction_real<T>(st, f, M, Wm, Rt, Gw, it == 0, tm);
+    ++steps;
+  }
+  tm.begin(MSQRT_T_VALIDATE);
+  hipLaunchKernelGGL(x_out_kernel, dim3(kRedBlocks), dim3(256), 0, st, n, (const double*)Gw, 0, 1,
+                     f->rscale_dev(), G, ldg, part);
+  MSQRT_LAUNCH_CHECK();
+  tm.end();
+  int timed_out = 0;
+  trsylv_errors(st, f->tw, &timed_out, nullptr);
+  tm.collect();
+  if (timed_out) throw Error{MSQRT_ERR_DEVICE, "quasi-triangular Sylvester solve: dataflow wait timed out"};
+  msqrt_status status = MSQRT_OK;
+  if (verdict == Verdict::Diverged) status = MSQRT_ERR_DIVERGED;
+  else if (verdict != Verdict::Converged) status = MSQRT_ERR_NOT_CONVERGED;
+  if (info) {
+    info->steps = steps;
+    info->relres = hist.back();
+    info->nhist = (int)std::min<size_t>(64, hist.size());
+    for (int k = 0; k < info->nhist; ++k) info->relres_hist[k] = hist[k];
+    info->prec_used = f->prec;
+    info->struct_used = f->structure;
+    info->scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
+  }
+  return status;
+}
+
+#define MSQRT_REAL_INST(T)                                                                      \
+  template msqrt_status factor_real<T>(Factor*, const double*, int64_t, hipStream_t, PhaseTimer*); \
+  template msqrt_status refine_real<T>(Factor*, const double*, int64_t, double*, int64_t, int, int, \
+                                       double, hipStream_t, msqrt_info*, PhaseTimer&);          \
+  template msqrt_status backward_real<T>(Factor*, const double*, int64_t, const double*, int64_t, \
+                                         double*, int64_t, int, double, hipStream_t, msqrt_info*, \
+                                         PhaseTimer&);
+MSQRT_REAL_INST(float)
+MSQRT_REAL_INST(double)
+#undef MSQRT_REAL_INST
 
 template msqrt_status factor_general<float>(Factor*, const double*, int64_t, int, hipStream_t,
                                             PhaseTimer*);

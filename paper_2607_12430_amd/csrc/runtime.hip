@@ -226,6 +226,11 @@ msqrt_status refine(Factor* f, const double* A, int64_t lda, int64_t sA, double*
   }
   if (ws) throw Error{MSQRT_ERR_UNSUPPORTED, "caller workspace: HPD factors only"};
   // general path: one matrix; X is read and written at the caller's scale
+  if (f->real_schur) {
+    if (f->prec == MSQRT_PREC_FP64)
+      return refine_real<double>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
+    return refine_real<float>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
+  }
   if (f->prec == MSQRT_PREC_FP64)
     return refine_general<double>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
   return refine_general<float>(f, A, lda, X, ldx, init, maxit, tol, st, info, tm);
@@ -381,6 +386,11 @@ msqrt_status backward(Factor* f, const double* X, int64_t ldx, const double* Gba
       return backward_hpd<double>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
     return backward_hpd<float>(f, X, ldx, Gbar, ldgb, G, ldg, stride, maxit, tol, st, info, tm);
   }
+  if (f->real_schur) {
+    if (f->prec == MSQRT_PREC_FP64)
+      return backward_real<double>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
+    return backward_real<float>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
+  }
   if (f->prec == MSQRT_PREC_FP64)
     return backward_general<double>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
   return backward_general<float>(f, X, ldx, Gbar, ldgb, G, ldg, maxit, tol, st, info, tm);
@@ -475,6 +485,7 @@ void msqrt_default_options(msqrt_options* o) {
   o->blks = 32;
   o->fallback = 1;
   o->batch = 1;
+  o->real_schur = 1;
 }
 
 const char* msqrt_status_string(msqrt_status s) {
@@ -563,7 +574,8 @@ msqrt_status msqrt_factor_export(msqrt_factor_t fh, void* Qh, void* Sh, int* sca
   const int64_t n = f->n;
   MSQRT_HIP(hipDeviceSynchronize());
   if (Qh) MSQRT_HIP(hipMemcpy(Qh, f->Q.p, es * n * n * f->batch, hipMemcpyDeviceToHost));
-  if (Sh) MSQRT_HIP(hipMemcpy(Sh, f->S.p, es * n * f->batch, hipMemcpyDeviceToHost));
+  const int64_t scount = f->real_schur ? n * n : n * f->batch;
+  if (Sh) MSQRT_HIP(hipMemcpy(Sh, f->S.p, es * scount, hipMemcpyDeviceToHost));
   if (scale_exp) *scale_exp = f->kexp.empty() ? 0 : f->kexp[0];
   return MSQRT_OK;
   MSQRT_API_END

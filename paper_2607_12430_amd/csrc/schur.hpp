@@ -30,6 +30,34 @@ struct HseqrWork {
 template <typename T>
 bool hseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm);
 
+// Real Schur form by the Francis double-shift QR algorithm (real input on
+// the general path): H (real upper Hessenberg, n x n, ld n) becomes
+// quasi-upper-triangular with standardised 2x2 blocks, Z (n x n, ld n)
+// <- Z U.  hnorm = ||H||_F.  Returns false if the iteration did not converge.
+template <typename T>
+bool rhseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm);
+
+// Tile boundaries (nt + 1 entries, first 0, last n) of a quasi-upper-
+// triangular matrix of order n for the real tile solvers: every 32 rows, one
+// row earlier where a boundary would separate the two rows of a 2x2 block.
+// sub[i] != 0 marks a nonzero entry (i + 1, i).
+std::vector<int> quasi_partition(int n, const unsigned char* sub);
+
+// U = T^{1/2} (principal) for quasi-upper-triangular T (n x n, ld n), on the
+// tiles of the device partition part (nt tiles); U may not alias T.  A
+// diagonal block with an eigenvalue on or next to R<=0 sets the tile
+// solvers' nonprincipal flag.
+template <typename T>
+void trsqrt_quasi(hipStream_t st, int n, const T* Tm, T* U, const int* part, int nt,
+                  TrsylvWork& w);
+
+// Solve S Y + Y S2 = C for quasi-upper-triangular S (m x m) and S2 (p x p)
+// with their device tile partitions; C (m x p) is overwritten by Y.
+template <typename T>
+void trsyl_quasi(hipStream_t st, int m, int p, const T* S, int64_t lds, const int* rpart, int mt,
+                 const T* S2, int64_t lds2, const int* cpart, int pt, T* C, int64_t ldc,
+                 TrsylvWork& w);
+
 // Error state of the tile solvers (sticky until trsylv_reset):
 // timed_out = a dataflow wait timed out, nonprincipal = a diagonal entry of T
 // on or next to R<=0.
