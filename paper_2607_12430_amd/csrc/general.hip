@@ -300,15 +300,6 @@ void correction(hipStream_t st, const GView<T>& g, T* M, T* Wst, T* Rt, double* 
 
 // ---- real route helpers
 
-// H (n x n, ld n) = real plane of the stacked Hs (ld 2n).
-template <typename T>
-__global__ void real_plane_kernel(int n, const T* Hs, T* H) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= (int64_t)n * n) return;
-  const int64_t i = x % n, j = x / n;
-  H[i + j * n] = Hs[i + j * 2 * n];
-}
-
 // sub[i] = 1 where t(i+1, i) != 0 (2x2 diagonal blocks of a quasi-
 // triangular T); 2 where that entry is not finite.
 template <typename T>
@@ -870,10 +861,9 @@ msqrt_status backward_general(Factor* f, const double* X, int64_t ldx, const dou
 
 // ---------------------------------------------------------------------------
 // Real route: real input on the general path with the real Schur form
-// A/4^k ~ Q T Q^T (remark on real input in Sec. 2.2.1).  The Hessenberg
-// reduction runs in the complex kernels on the real data (its reflectors
-// and both factors stay real), then the real double-shift QR, the tile
-// partition that keeps 2x2 blocks whole, and U = T^{1/2} on it.
+// A/4^k ~ Q T Q^T (remark on real input in Sec. 2.2.1): real Hessenberg
+// reduction, the real double-shift QR, the tile partition that keeps 2x2
+// blocks whole, and U = T^{1/2} on it.
 
 template <typename T>
 msqrt_status factor_real(Factor* f, const double* A, int64_t lda, hipStream_t st, PhaseTimer* tm) {
@@ -881,24 +871,17 @@ msqrt_status factor_real(Factor* f, const double* A, int64_t lda, hipStream_t st
   const int64_t nn = (int64_t)n * n;
   T* Q = f->Q.ensure<T>(nn);
   T* U = f->S.ensure<T>(nn);
-  T* Hs = f->fw1.ensure<T>(2 * nn);
-  T* Qs = f->fw2.ensure<T>(2 * nn);
   T* H = f->fw3.ensure<T>(nn);
   unsigned char* dsub = f->fw4.ensure<unsigned char>(n + 64);
   f->gq_ready = false;
   f->real_schur = true;
   if (tm) tm->begin(MSQRT_T_REDUCE);
-  hipLaunchKernelGGL(to_stacked_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n, A, lda, 0,
-                     f->ascale_dev(), Hs);
-  MSQRT_LAUNCH_CHECK();
+  if (std::is_same<T, float>::value)
+    launch_cast_scale_f64_f32(st, n, A, lda, 0, f->ascale_dev(), (float*)H, n, 0, 1);
+  else
+    launch_cast_scale_f64_f64(st, n, A, lda, 0, f->ascale_dev(), (double*)H, n, 0, 1);
   GehrdWork gw;
-  gehrd<T>(st, n, Hs, Qs, gw);
-  hipLaunchKernelGGL(real_plane_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n,
-                     (const T*)Hs, H);
-  MSQRT_LAUNCH_CHECK();
-  hipLaunchKernelGGL(real_plane_kernel<T>, dim3(blocks_for(nn)), dim3(256), 0, st, n,
-                     (const T*)Qs, Q);
-  MSQRT_LAUNCH_CHECK();
+  gehrd_real<T>(st, n, H, Q, gw);
   if (tm) tm->begin(MSQRT_T_EIG);
   HseqrWork hw;
   const bool ok = rhseqr<T>(st, n, H, Q, hw, (T)f->anorm_scaled[0]);

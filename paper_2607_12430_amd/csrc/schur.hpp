@@ -19,6 +19,11 @@ struct GehrdWork {
 template <typename T>
 void gehrd(hipStream_t st, int n, T* H, T* Z, GehrdWork& w);
 
+// Real version for the real Schur route: H (n x n, ld n) <- Q1^T H Q1,
+// Q1 formed in Z (n x n, ld n).
+template <typename T>
+void gehrd_real(hipStream_t st, int n, T* H, T* Z, GehrdWork& w);
+
 struct HseqrWork {
   DevBuf U, shifts, flag, scratch;
 };

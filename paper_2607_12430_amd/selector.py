@@ -331,6 +331,9 @@ def main(argv=None):
     ap.add_argument("--eval-kinds", default="spd,nonsym")
     ap.add_argument("--eval-n-nonsym", type=int, default=None,
                     help="order of the nonsymmetric evaluation matrices (default: --eval-n)")
+    ap.add_argument("--only-kinds", default=None,
+                    help="label only the indices of these kinds of the selector law "
+                         "(comma-separated: spd, shifted, kappa)")
     ap.add_argument("--boundary", action="store_true",
                     help="label matrices of the boundary law (boundary_params) instead of the "
                          "selector law")
@@ -367,10 +370,17 @@ def main(argv=None):
     feats = []
     t0 = time.time()
     if args.from_records:
+        # a later file replaces the records of the same index (relabelling)
+        byidx = {}
         for fname in args.from_records.split(","):
             with (gzip.open(fname, "rt") if fname.endswith(".gz") else open(fname)) as fh:
-                records.extend(json.load(fh))
+                for r in json.load(fh):
+                    byidx[(r.get("law", "selector"), r["index"])] = r
+        records = list(byidx.values())
+    only = set(args.only_kinds.split(",")) if args.only_kinds else None
     for k in range(0 if args.from_records else args.count):
+        if only is not None and W.selector_params(args.first + k, args.n_max_nonsym)[0] not in only:
+            continue
         if args.boundary:
             import workloads.device as WD
             kind, n, kappa, seed = boundary_params(args.first + k)
@@ -384,8 +394,9 @@ def main(argv=None):
             ad = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         f = features(ad).cpu().numpy()
         labs = label(ad)
-        records.append({"index": args.first + k, "kind": kind, "n": n, "kappa": kappa,
-                        "features": f.tolist(), "labels": labs})
+        records.append({"index": args.first + k, "law": "boundary" if args.boundary else "selector",
+                        "kind": kind, "n": n, "kappa": kappa, "features": f.tolist(),
+                        "labels": labs})
         feats.append(f)
         if k % 50 == 0:
             print(f"[selector] labelled {k + 1}/{args.count} ({time.time() - t0:.0f} s)", flush=True)
