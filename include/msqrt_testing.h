@@ -69,6 +69,12 @@ msqrt_status msqrt_test_trsyl(msqrt_prec prec, int64_t m, int64_t p, const doubl
 msqrt_status msqrt_test_gemm_f32(int split, int ta, int tb, int64_t M, int64_t N, int64_t K,
                                  const float* A, const float* B, float* C);
 
+/* The symmetric-output GEMM of the refinement (lower-triangle tiles, each
+ * element mirrored by the epilogue): C = A A^T for A n x k column-major in
+ * float (prec FP32) or double (prec FP64); C is n x n.  Large triangles take
+ * the 192 x 192-tile kernels. */
+msqrt_status msqrt_test_syrk(msqrt_prec prec, int64_t n, int64_t k, const void* A, void* C);
+
 #ifdef __cplusplus
 }
 #endif

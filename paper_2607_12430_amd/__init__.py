@@ -362,6 +362,18 @@ def test_gemm_f32(a, b, split=False, ta=False, tb=False):
     return c
 
 
+def test_syrk(a, prec="fp32"):
+    """Test hook: C = A A^T through the symmetric-output (mirroring) GEMM."""
+    import numpy as np
+    dt = np.float32 if prec == "fp32" else np.float64
+    a = np.asfortranarray(a, dtype=dt)
+    n, k = a.shape
+    c = np.zeros((n, n), dt, order="F")
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    check(lib().msqrt_test_syrk(_lib.PREC_NAMES[prec], n, k, vp(a), vp(c)), "msqrt_test_syrk")
+    return c
+
+
 class _SqrtmFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, a, prec, tol, maxit):

@@ -36,7 +36,7 @@ EXPORTED = [
     "msqrt_test_stedc",
     "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt", "msqrt_test_trsyl",
     "msqrt_test_trcbrt", "msqrt_rootm",
-    "msqrt_test_gemm_f32", "msqrt_features", "msqrt_mlp_forward", "msqrt_mlp_grad",
+    "msqrt_test_gemm_f32", "msqrt_test_syrk", "msqrt_features", "msqrt_mlp_forward", "msqrt_mlp_grad",
     "msqrt_mlp_adam", "msqrt_selector_set", "msqrt_selector_load", "msqrt_selector_clear",
     "msqrt_selector_installed",
     "msqrt_profile_enable", "msqrt_profile_query", "msqrt_profile_list",
@@ -139,6 +139,7 @@ def lib():
                               ctypes.POINTER(Info)]
     L.msqrt_test_trsyl.argtypes = [ci, i64, i64, dp, dp, dp, dp]
     L.msqrt_test_gemm_f32.argtypes = [ci, ci, ci, i64, i64, i64, vp, vp, vp]
+    L.msqrt_test_syrk.argtypes = [ci, i64, i64, vp, vp]
     L.msqrt_features.argtypes = [ci, i64, vp, i64, vp, vp]
     L.msqrt_mlp_forward.argtypes = [i64, vp, vp, vp, vp]
     L.msqrt_mlp_grad.argtypes = [i64, vp, vp, vp, vp, vp, vp]
@@ -155,7 +156,7 @@ def lib():
                  "msqrt_factor_wrap", "msqrt_factor_export", "msqrt_test_sytrd",
                  "msqrt_test_stedc", "msqrt_test_gehrd", "msqrt_test_schur", "msqrt_test_trsqrt",
                  "msqrt_test_trcbrt", "msqrt_rootm",
-                 "msqrt_test_trsyl", "msqrt_test_gemm_f32", "msqrt_features",
+                 "msqrt_test_trsyl", "msqrt_test_gemm_f32", "msqrt_test_syrk", "msqrt_features",
                  "msqrt_mlp_forward", "msqrt_mlp_grad", "msqrt_mlp_adam", "msqrt_selector_set",
                  "msqrt_selector_load"):
         getattr(L, name).restype = ci

@@ -45,12 +45,10 @@ int gemm_residual(hipStream_t st, int n, const double* X, int64_t ldx, int64_t s
   GemmShape s = make_shape(n, n, n, ldx, ldx, sX, sX, sym);
   if (Rl) {
     EpiResidual e{A, lda, sA, ascale, Rl, ldr, sR};
-    launch_gemm<double>(st, false, sym, s, X, X, e, partials, batch);
-  } else {
-    EpiResidual64 e{A, lda, sA, ascale, R64, ldr, sR};
-    launch_gemm<double>(st, false, sym, s, X, X, e, partials, batch);
+    return launch_gemm<double>(st, false, sym, s, X, X, e, partials, batch);
   }
-  return s.ntiles;
+  EpiResidual64 e{A, lda, sA, ascale, R64, ldr, sR};
+  return launch_gemm<double>(st, false, sym, s, X, X, e, partials, batch);
 }
 
 int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda_, int64_t sXa,
@@ -60,12 +58,10 @@ int gemm_residual_general(hipStream_t st, int n, const double* Xa, int64_t lda_,
   GemmShape s = make_shape(n, n, n, lda_, ldb_, sXa, sXb, false);
   if (Rl) {
     EpiResidual e{C, ldc, sC, nullptr, Rl, ldr, sR};
-    launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
-  } else {
-    EpiResidual64 e{C, ldc, sC, nullptr, R64, ldr, sR};
-    launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
+    return launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
   }
-  return s.ntiles;
+  EpiResidual64 e{C, ldc, sC, nullptr, R64, ldr, sR};
+  return launch_gemm<double>(st, false, false, s, Xa, Xb, e, partials, batch);
 }
 
 int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
@@ -75,12 +71,10 @@ int gemm_residual_ex(hipStream_t st, bool ta, bool tb, int M, int N, int K, cons
   GemmShape s = make_shape(M, N, K, lda, ldb, sA, sB, false);
   if (Rl) {
     EpiResidual e{C, ldc, sC, cscale, Rl, ldr, sR};
-    launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
-  } else {
-    EpiResidual64 e{C, ldc, sC, cscale, R64, ldr, sR};
-    launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
+    return launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
   }
-  return s.ntiles;
+  EpiResidual64 e{C, ldc, sC, cscale, R64, ldr, sR};
+  return launch_gemm<double>(st, ta, tb, s, A, B, e, partials, batch);
 }
 
 template <typename T>

@@ -72,6 +72,10 @@ struct GemmShape {
 };
 
 constexpr int GBM = 128, GBN = 128, GTHREADS = 256;
+// tile of the wide kernels for large symmetric-output products, and the
+// smallest order of a triangle that takes them
+constexpr int WBM = 192;
+constexpr int kWideMin = 1536;
 
 // Maps the hardware workgroup id to a tile id so that each of the 8 XCDs
 // (workgroups are dispatched round-robin over XCDs) works on a contiguous
@@ -398,6 +402,145 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_f64_kernel(GemmShape s, cons
   }
 }
 
+// Double kernel with 192 x 192 tiles for large symmetric-output products
+// (the float64 residual A - X X^T of the SPD route): a triangle of 128-tiles
+// at n = 4096 has 528 tiles, two workgroups per CU hold 512 and the last 16
+// run in a second, nearly empty round; 192-tiles give 253, one per CU.
+// Eight waves in a 2 x 4 arrangement, 96 x 48 each (6 x 3 blocks of
+// v_mfma_f64_16x16x4f64), K-slabs of 16.
+constexpr int kW64Threads = 512;
+constexpr size_t kGemmF64wLds = (size_t)2 * 2 * WBM * DLD * sizeof(double);
+
+template <bool RC>
+__device__ inline void f64w_slab_index(int t, int e, int& r, int& k) {
+  const int lane = t % kWave, wave = t / kWave;
+  if (RC) {
+    const int id = wave * 6 + e;  // 48 blocks of 8 rows x 8 k
+    r = (id % 24) * 8 + lane % 8;
+    k = (id / 24) * 8 + lane / 8;
+  } else {
+    const int idx = t + kW64Threads * e;
+    k = idx % DBK;
+    r = idx / DBK;
+  }
+}
+
+template <bool RC>
+__device__ inline void f64w_slab_load(const double* __restrict__ X, int64_t ld, int r0, int R, int k0,
+                                      int K, int t, double (&v)[6]) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    int r, k;
+    f64w_slab_index<RC>(t, e, r, k);
+    const int gr = r0 + r, gk = k0 + k;
+    v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.0;
+  }
+}
+
+template <bool RC>
+__device__ inline void f64w_slab_store(double* Xs, int t, const double (&v)[6]) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    int r, k;
+    f64w_slab_index<RC>(t, e, r, k);
+    Xs[r * DLD + k] = v[e];
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(kW64Threads, 1) void gemm_f64w_kernel(GemmShape s, const double* __restrict__ A,
+                                                                   const double* __restrict__ B, Epi epi,
+                                                                   double* __restrict__ partials) {
+  using M = Mfma<double>;
+  constexpr int MBW = 6, NBW = 3;  // 16 x 16 blocks per wave: 6 down, 3 across
+  extern __shared__ __attribute__((aligned(16))) double gemm_lds64w[];
+  __shared__ double red[kW64Threads / kWave];
+  auto slab = [&](int buf, int op) { return gemm_lds64w + (size_t)(buf * 2 + op) * WBM * DLD; };
+
+  int tm, tn;
+  if (!gemm_tile_coords(s, tm, tn)) return;
+  const int batch = blockIdx.y;
+  const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
+  A += (int64_t)batch * s.sA;
+  B += (int64_t)batch * s.sB;
+  const int m0 = tm * WBM, n0 = tn * WBM;
+  const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const int wm = wave % 2, wn = wave / 2;  // rows wm * 96, columns wn * 48
+  constexpr bool ARC = !TA, BRC = TB;
+
+  typename M::acc_t acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.0;
+
+  double ra[6], rb[6];
+  if (K > 0) {
+    f64w_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f64w_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f64w_slab_store<ARC>(slab(0, 0), t, ra);
+    f64w_slab_store<BRC>(slab(0, 1), t, rb);
+  }
+  __syncthreads();
+  const int h = lane / 16, fr = lane % 16;
+  for (int k0 = 0, buf = 0; k0 < K; k0 += DBK, buf ^= 1) {
+    const bool more = k0 + DBK < K;
+    if (more) {
+      f64w_slab_load<ARC>(A, s.lda, m0, s.M, k0 + DBK, K, t, ra);
+      f64w_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + DBK, K, t, rb);
+    }
+    const double* As = slab(buf, 0);
+    const double* Bs = slab(buf, 1);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int kc = h * 4 + half * 2;
+      double2 a2[MBW], b2[NBW];
+#pragma unroll
+      for (int i = 0; i < MBW; ++i)
+        a2[i] = *reinterpret_cast<const double2*>(As + (wm * 96 + i * 16 + fr) * DLD + kc);
+#pragma unroll
+      for (int j = 0; j < NBW; ++j)
+        b2[j] = *reinterpret_cast<const double2*>(Bs + (wn * 48 + j * 16 + fr) * DLD + kc);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < MBW; ++i)
+#pragma unroll
+          for (int j = 0; j < NBW; ++j)
+            acc[i][j] = M::mma(c == 0 ? b2[j].x : b2[j].y, c == 0 ? a2[i].x : a2[i].y, acc[i][j]);
+    }
+    if (more) {
+      f64w_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
+      f64w_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+    }
+    __syncthreads();
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j)
+#pragma unroll
+      for (int r = 0; r < M::NACC; ++r) {
+        const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
+        const int gj = n0 + wn * 48 + j * M::TN + M::c_row(lane, r);
+        if (gi < s.M && gj < s.N) {
+          if (s.tri && gi < gj) continue;
+          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        }
+      }
+  if (Epi::kReduces) {
+    part = block_sum(part, red);
+    if (t == 0) {
+      const int id = (blockIdx.x % 8) * s.per_xcd + blockIdx.x / 8;
+      partials[(int64_t)batch * s.ntiles + id] = part;
+    }
+  }
+}
+
 // Float kernel for launches slightly larger than two workgroups per CU
 // (a triangle of 528 tiles at n = 4096 leaves 16 tiles for a second round):
 // K-slabs of 16 double-buffered (40 KiB of LDS, at most 170 registers), so
@@ -533,9 +676,6 @@ __global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, c
 // (2.06 per CU, so some CUs run a third tile while the rest idle); measured
 // 0.78 ms against 1.01 ms for the n^3 flops of one such product.
 
-constexpr int WBM = 192;
-// smallest order of a triangle that takes the 192-tile kernel
-constexpr int kWideMin = 1536;
 constexpr size_t kGemmF32wLds = (size_t)2 * 2 * WBM * FLD * sizeof(float);
 
 template <bool RC>
@@ -907,7 +1047,10 @@ struct EpiDiagSylv {
 };
 
 // Working-precision update X += fl64(acc) fused into the last product of
-// Q Y Q^T (Alg. 2/3, last line of the loop).
+// Q Y Q^T (Alg. 2/3, last line of the loop).  A mirrored (symmetric) X is
+// exactly symmetric before the update, so the mirror element receives the
+// updated value itself: a store, without the load of the transposed element
+// (which lies in another row for every lane).
 template <typename T>
 struct EpiUpdate {
   static constexpr const char* kName = "update";
@@ -918,9 +1061,9 @@ struct EpiUpdate {
   __device__ double operator()(int b, int i, int j, T v, bool mir) const {
     if (active && !active[b]) return 0.0;
     double* xb = X + (int64_t)b * sX;
-    const double d = (double)v;
-    xb[i + (int64_t)j * ldx] += d;
-    if (mir) xb[j + (int64_t)i * ldx] += d;
+    const double x = xb[i + (int64_t)j * ldx] + (double)v;
+    xb[i + (int64_t)j * ldx] = x;
+    if (mir) xb[j + (int64_t)i * ldx] = x;
     return 0.0;
   }
 };
@@ -955,10 +1098,13 @@ inline GemmShape make_shape(int M, int N, int K, int64_t lda, int64_t ldb, int64
 }
 
 // split = true selects the BF16-split kernel (float operands only).
+// Returns the number of tiles per batch entry of the launch (the count of
+// per-tile partial sums a reducing epilogue wrote), which depends on the
+// kernel chosen.
 template <typename T, class Epi>
-void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A, const T* B,
-                 const Epi& epi, double* partials, int batch, bool split = false) {
-  if (s.M <= 0 || s.N <= 0 || batch <= 0) return;
+int launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A, const T* B,
+                const Epi& epi, double* partials, int batch, bool split = false) {
+  if (s.M <= 0 || s.N <= 0 || batch <= 0) return 0;
   dim3 grid(8 * s.per_xcd, batch), block(GTHREADS);
   const int tok = prof_begin(st);
   if (split) {
@@ -974,7 +1120,7 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
         const std::string cls = std::string("gemm_bf16x3:") + Epi::kName;
         prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
       }
-      return;
+      return s.ntiles;
     }
   }
   if constexpr (std::is_same<T, float>::value) {
@@ -1002,7 +1148,7 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
         const std::string cls = std::string("gemm_f32:") + Epi::kName;
         prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
       }
-      return;
+      return w.ntiles;
     }
     // more tiles than two workgroups per CU hold but no more than three:
     // the 16-deep variant runs them in one round
@@ -1024,6 +1170,28 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
       else go(gemm_f32_kernel<true, true, Epi>, kGemmF32Lds);
     }
   } else {
+    const int64_t ncu = gemm_cu_count();
+    if (s.tri && s.M >= kWideMin && s.K >= 256 && (int64_t)s.ntiles * batch > 2 * ncu) {
+      GemmShape w = make_shape(s.M, s.N, s.K, s.lda, s.ldb, s.sA, s.sB, true, WBM);
+      w.K_last = s.K_last;
+      dim3 gw(8 * w.per_xcd, batch);
+      auto gow = [&](auto kern) {
+        gemm_lds_attr(kern, kGemmF64wLds);
+        hipLaunchKernelGGL(kern, gw, dim3(kW64Threads), kGemmF64wLds, st, w, A, B, epi, partials);
+      };
+      if (!ta && !tb) gow(gemm_f64w_kernel<false, false, Epi>);
+      else if (ta && !tb) gow(gemm_f64w_kernel<true, false, Epi>);
+      else if (!ta && tb) gow(gemm_f64w_kernel<false, true, Epi>);
+      else gow(gemm_f64w_kernel<true, true, Epi>);
+      MSQRT_LAUNCH_CHECK();
+      if (tok >= 0) {
+        const double outs = 0.5 * (double)w.N * (w.N + 1);
+        const double kk = (double)w.K * (batch - 1) + w.K_last;
+        const std::string cls = std::string("gemm_f64:") + Epi::kName;
+        prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
+      }
+      return w.ntiles;
+    }
     auto go = [&](auto kern) {
       gemm_lds_attr(kern, kGemmF64Lds);
       hipLaunchKernelGGL(kern, grid, block, kGemmF64Lds, st, s, A, B, epi, partials);
@@ -1043,6 +1211,7 @@ void launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* 
     const std::string cls = std::string(sizeof(T) == 4 ? "gemm_f32:" : "gemm_f64:") + Epi::kName;
     prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
   }
+  return s.ntiles;
 }
 
 }  // namespace msqrt

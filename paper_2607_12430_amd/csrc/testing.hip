@@ -207,3 +207,29 @@ extern "C" msqrt_status msqrt_test_gemm_f32(int split, int ta, int tb, int64_t M
     return MSQRT_OK;
   });
 }
+
+extern "C" msqrt_status msqrt_test_syrk(msqrt_prec prec, int64_t n, int64_t k, const void* A,
+                                        void* C) {
+  if (n < 1 || k < 0 || !A || !C || n > 65536 || k > 65536 ||
+      (prec != MSQRT_PREC_FP32 && prec != MSQRT_PREC_FP64))
+    return MSQRT_ERR_INVALID_ARG;
+  return guarded([&] {
+    const size_t es = prec == MSQRT_PREC_FP64 ? 8 : 4;
+    const size_t na = (size_t)n * k, nc = (size_t)n * n;
+    DevBuf ab, cb;
+    void* dA = ab.ensure<unsigned char>((int64_t)(es * na + 8));
+    void* dC = cb.ensure<unsigned char>((int64_t)(es * nc));
+    MSQRT_HIP(hipMemcpy(dA, A, es * na, hipMemcpyHostToDevice));
+    const int64_t ld = std::max<int64_t>(n, 1);
+    // lower-triangle tiles only, the epilogue mirrors each element
+    if (prec == MSQRT_PREC_FP64)
+      gemm_store_f64(nullptr, false, true, (int)n, (int)n, (int)k, (const double*)dA, ld, 0,
+                     (const double*)dA, ld, 0, (double*)dC, n, 0, 1.0, 0.0, 1, true);
+    else
+      gemm_store_f32(nullptr, false, true, (int)n, (int)n, (int)k, (const float*)dA, ld, 0,
+                     (const float*)dA, ld, 0, (float*)dC, n, 0, 1.f, 0.f, 1, true, false);
+    MSQRT_HIP(hipDeviceSynchronize());
+    MSQRT_HIP(hipMemcpy(C, dC, es * nc, hipMemcpyDeviceToHost));
+    return MSQRT_OK;
+  });
+}
