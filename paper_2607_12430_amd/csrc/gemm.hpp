@@ -77,6 +77,15 @@ constexpr int GBM = 128, GBN = 128, GTHREADS = 256;
 constexpr int WBM = 192;
 constexpr int kWideMin = 1536;
 
+// Epilogues that define kPrefetch = true also provide pre(b, i, j), a load
+// issued for every element of a block before post(b, i, j, v, mir, pre)
+// stores any of them.
+template <class Epi, class = void>
+struct EpiPrefetches : std::false_type {};
+template <class Epi>
+struct EpiPrefetches<Epi, std::void_t<decltype(Epi::kPrefetch)>>
+    : std::integral_constant<bool, Epi::kPrefetch> {};
+
 // Maps the hardware workgroup id to a tile id so that each of the 8 XCDs
 // (workgroups are dispatched round-robin over XCDs) works on a contiguous
 // range of tiles, then the tile id to (tile_m, tile_n).
@@ -793,16 +802,36 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
 #pragma unroll
   for (int i = 0; i < NBW; ++i)
 #pragma unroll
-    for (int j = 0; j < NBW; ++j)
+    for (int j = 0; j < NBW; ++j) {
+      if constexpr (EpiPrefetches<Epi>::value) {
+        // every load of the block first, then the stores
+        double x0[M::NACC];
 #pragma unroll
-      for (int r = 0; r < M::NACC; ++r) {
-        const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
-        const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
-        if (gi < s.M && gj < s.N) {
-          if (s.tri && gi < gj) continue;
-          part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+        for (int r = 0; r < M::NACC; ++r) {
+          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          const bool ok = gi < s.M && gj < s.N && !(s.tri && gi < gj);
+          x0[r] = ok ? epi.pre(batch, gi, gj) : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < M::NACC; ++r) {
+          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          if (gi < s.M && gj < s.N && !(s.tri && gi < gj))
+            epi.post(batch, gi, gj, acc[i][j][r], s.tri && gi != gj, x0[r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < M::NACC; ++r) {
+          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          if (gi < s.M && gj < s.N) {
+            if (s.tri && gi < gj) continue;
+            part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
+          }
         }
       }
+    }
   if (Epi::kReduces) {
     part = block_sum(part, red);
     if (t == 0) {
@@ -1066,7 +1095,22 @@ struct EpiUpdate {
     if (mir) xb[j + (int64_t)i * ldx] = x;
     return 0.0;
   }
+  // Split form for kernels that load a block's X values before any store
+  // (the loads of one block are then in flight together).
+  static constexpr bool kPrefetch = true;
+  __device__ double pre(int b, int i, int j) const {
+    if (active && !active[b]) return 0.0;
+    return X[(int64_t)b * sX + i + (int64_t)j * ldx];
+  }
+  __device__ void post(int b, int i, int j, T v, bool mir, double x0) const {
+    if (active && !active[b]) return;
+    double* xb = X + (int64_t)b * sX;
+    const double x = x0 + (double)v;
+    xb[i + (int64_t)j * ldx] = x;
+    if (mir) xb[j + (int64_t)i * ldx] = x;
+  }
 };
+
 
 // X = fl64(acc) (initial iterate X_0 = Q S Q^T).
 template <typename T>

@@ -315,16 +315,27 @@ __device__ inline void rwin_store(const T* h, const T* u, T* H, int n, int r0, i
 // shift pairs of its eigenvalues (mode 1, H untouched): sp[2 q] = sum and
 // sp[2 q + 1] = product of pair q, complex conjugate pairs first, then the
 // real eigenvalues paired in order.
-template <typename T>
-__global__ __launch_bounds__(kRQrThreads) void rsmall_kernel(int n, T* H, int b0, int m, int mode,
-                                                             T* Uo, T* sp, int* status, T hnorm) {
+// NT threads: 256 for the blocks finished in LDS, one wave for the shift
+// computation on the trailing ns x ns block (whose barriers then cost
+// almost nothing).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void rsmall_kernel(int n, T* H, int b0, int m, int mode,
+                                                    T* Uo, T* sp, int* status, T hnorm) {
   constexpr int W = RWin<T>::W;
   extern __shared__ unsigned char smem_raw[];
   T* h = reinterpret_cast<T*>(smem_raw);
   T* u = h + (W + 1) * W;
   const int ldh = W + 1;
-  rwin_load<T, W, kRQrThreads>(h, H, n, b0, m, 1);
-  if (mode == 0) rwin_identity<T, W, kRQrThreads>(u, m);
+  if constexpr (NT >= kRQrThreads) {
+    rwin_load<T, W, NT>(h, H, n, b0, m, 1);
+  } else {
+    // small blocks (the shift computation): a plain loop over the m x m block
+    for (int x = threadIdx.x; x < m * m; x += NT) {
+      const int i = x % m, j = x / m;
+      h[i + j * (W + 1)] = i <= j + 1 ? H[(b0 + i) + (int64_t)(b0 + j) * n] : T(0);
+    }
+  }
+  if (mode == 0) rwin_identity<T, W, NT>(u, m);
   __syncthreads();
   const bool ok = lds_francis<T>(h, ldh, mode == 0 ? u : nullptr, m, hnorm);
   __syncthreads();
@@ -365,7 +376,7 @@ __global__ __launch_bounds__(kRQrThreads) void rsmall_kernel(int n, T* H, int b0
     }
     return;
   }
-  rwin_store<T, W, kRQrThreads>(h, u, H, n, b0, m, 1, Uo);
+  rwin_store<T, W, NT>(h, u, H, n, b0, m, 1, Uo);
 }
 
 // ---- the double-shift bulge chain schedule (host)
@@ -735,7 +746,9 @@ bool rhseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm) {
   static_assert(NS / 2 <= kMaxBulges && NS <= W, "shift count");
   static bool attr_set = false;
   if (!attr_set) {
-    MSQRT_HIP(hipFuncSetAttribute((const void*)rsmall_kernel<T>,
+    MSQRT_HIP(hipFuncSetAttribute((const void*)rsmall_kernel<T, kRQrThreads>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)rwin_lds<T>()));
+    MSQRT_HIP(hipFuncSetAttribute((const void*)rsmall_kernel<T, kWave>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)rwin_lds<T>()));
     MSQRT_HIP(hipFuncSetAttribute((const void*)rchase_kernel<T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)rchase_lds<T>()));
@@ -764,8 +777,8 @@ bool rhseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm) {
     const int m = hi - lo + 1;
     if (m <= W) {
       if (m > 1) {
-        hipLaunchKernelGGL(rsmall_kernel<T>, dim3(1), dim3(kRQrThreads), rwin_lds<T>(), st, n, H,
-                           lo, m, 0, U, sp, flag, hnorm);
+        hipLaunchKernelGGL((rsmall_kernel<T, kRQrThreads>), dim3(1), dim3(kRQrThreads), rwin_lds<T>(),
+                           st, n, H, lo, m, 0, U, sp, flag, hnorm);
         MSQRT_LAUNCH_CHECK();
         launch_rapply<T>(st, n, H, Z, lo, m, U);
       }
@@ -778,7 +791,7 @@ bool rhseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm) {
     if (stuck > 300) return false;
     last_hi = hi;
     last_lo = lo;
-    hipLaunchKernelGGL(rsmall_kernel<T>, dim3(1), dim3(kRQrThreads), rwin_lds<T>(), st, n, H,
+    hipLaunchKernelGGL((rsmall_kernel<T, kWave>), dim3(1), dim3(kWave), rwin_lds<T>(), st, n, H,
                        hi - NS + 1, NS, 1, U, sp, flag, hnorm);
     MSQRT_LAUNCH_CHECK();
     if (stuck > 0 && stuck % 6 == 0) {
