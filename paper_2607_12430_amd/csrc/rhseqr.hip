@@ -167,12 +167,14 @@ __device__ void standardize_2x2(T* h, int ldh, T* u, int m, int p) {
 }
 
 // Double-shift QR on the LDS block h (order m) until every diagonal block
-// has order 1 or 2 (2x2 blocks standardised).  Returns false when the
+// has order 1 or 2 (2x2 blocks standardised).  A subdiagonal entry counts as
+// negligible below dtol (|h_kk| + |h_k+1,k+1|): the unit roundoff for a Schur
+// form, a looser value when only shifts are wanted.  Returns false when the
 // iteration limit was hit.
 template <typename T>
-__device__ bool lds_francis(T* h, int ldh, T* u, int m, T hnorm) {
+__device__ bool lds_francis(T* h, int ldh, T* u, int m, T hnorm, T dtol) {
   __shared__ int sh_l;
-  const T ulp = reps<T>(), small = fmax(rtiny<T>() * T(1e4), ulp * hnorm);
+  const T ulp = dtol, small = fmax(rtiny<T>() * T(1e4), reps<T>() * hnorm);
   int hi = m - 1, its = 0, total = 0;
   const int itmax = 30 * max(10, m);
   const bool w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave) == 0;
@@ -337,7 +339,10 @@ __global__ __launch_bounds__(NT) void rsmall_kernel(int n, T* H, int b0, int m, 
   }
   if (mode == 0) rwin_identity<T, W, NT>(u, m);
   __syncthreads();
-  const bool ok = lds_francis<T>(h, ldh, mode == 0 ? u : nullptr, m, hnorm);
+  // shifts need a few correct digits only: blocks of the trailing matrix are
+  // split once their coupling is below 2^-10 of the adjacent diagonal
+  const T dtol = mode == 0 ? reps<T>() : T(9.765625e-4);
+  const bool ok = lds_francis<T>(h, ldh, mode == 0 ? u : nullptr, m, hnorm, dtol);
   __syncthreads();
   if (!ok && threadIdx.x == 0) atomicOr(status, 1);
   if (mode == 1) {
@@ -474,8 +479,10 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
                                                                 int mv0, int nmv, const T* sp,
                                                                 T* Uo) {
   constexpr int W = RWin<T>::W;
-  constexpr int G = 128;                   // lanes per move in the update phases
-  constexpr int NG = kRChaseThreads / G;   // moves handled side by side
+  constexpr int G = kRChaseThreads / kMaxBulges;  // lanes per move: every move at once
+  constexpr int RI = (W + G - 1) / G;             // row-operation columns per lane
+  constexpr int CI = (2 * W + G - 1) / G;         // column-operation rows per lane
+  static_assert(G >= kWave, "a move's lanes form whole waves");
   extern __shared__ unsigned char smem_raw[];
   T* h = reinterpret_cast<T*>(smem_raw);
   T* u = h + (W + 1) * W;
@@ -533,37 +540,66 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
       rz[t] = z;
     }
     __syncthreads();
-    // row operations (rows r..r+nr-1 of every move; disjoint)
-    for (int q = grp; q < nm; q += NG) {
-      const int r = rr[q], nr = rnr[q], z = rz[q];
+    // row operations (rows r..r+nr-1 of every move; disjoint).  Group q (G
+    // lanes) owns move q; a lane's RI column items are all loaded before any
+    // is written, so their LDS latencies overlap.
+    if (grp < nm) {
+      const int q = grp;
+      const int r = rr[q], nr = rnr[q], z = rz[q], c0 = rc0[q];
       const T tau = rtau[q], w1 = rw1[q], w2 = rw2[q];
-      for (int jj = rc0[q] + lane; jj < wl; jj += G) {
+      T y[RI][3];
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int jj = c0 + lane + G * e;
+        const bool live = jj < wl && jj != z;
+        y[e][0] = live ? h[r + jj * ldh] : T(0);
+        y[e][1] = live ? h[r + 1 + jj * ldh] : T(0);
+        y[e][2] = (live && nr == 3) ? h[r + 2 + jj * ldh] : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int jj = c0 + lane + G * e;
+        if (jj >= wl) continue;
         if (jj == z) {
           h[r + jj * ldh] = rbeta[q];
           h[r + 1 + jj * ldh] = T(0);
           if (nr == 3) h[r + 2 + jj * ldh] = T(0);
           continue;
         }
-        T y0 = h[r + jj * ldh], y1 = h[r + 1 + jj * ldh], y2 = nr == 3 ? h[r + 2 + jj * ldh] : T(0);
-        refl3(tau, w1, w2, y0, y1, y2);
-        h[r + jj * ldh] = y0;
-        h[r + 1 + jj * ldh] = y1;
-        if (nr == 3) h[r + 2 + jj * ldh] = y2;
+        refl3(tau, w1, w2, y[e][0], y[e][1], y[e][2]);
+        h[r + jj * ldh] = y[e][0];
+        h[r + 1 + jj * ldh] = y[e][1];
+        if (nr == 3) h[r + 2 + jj * ldh] = y[e][2];
       }
     }
     __syncthreads();
     // column operations of H (rows 0..r1) and U (all rows); disjoint columns
-    for (int q = grp; q < nm; q += NG) {
+    if (grp < nm) {
+      const int q = grp;
       const int r = rr[q], nr = rnr[q], r1 = rr1[q];
+      const int tot = (r1 + 1) + wl;
       const T tau = rtau[q], w1 = rw1[q], w2 = rw2[q];
-      for (int x = lane; x < (r1 + 1) + wl; x += G) {
+      T y[CI][3];
+#pragma unroll
+      for (int e = 0; e < CI; ++e) {
+        const int x = lane + G * e;
+        const bool live = x < tot;
         T* M = x <= r1 ? h : u;
         const int i = x <= r1 ? x : x - (r1 + 1);
-        T y0 = M[i + r * ldh], y1 = M[i + (r + 1) * ldh], y2 = nr == 3 ? M[i + (r + 2) * ldh] : T(0);
-        refl3(tau, w1, w2, y0, y1, y2);
-        M[i + r * ldh] = y0;
-        M[i + (r + 1) * ldh] = y1;
-        if (nr == 3) M[i + (r + 2) * ldh] = y2;
+        y[e][0] = live ? M[i + r * ldh] : T(0);
+        y[e][1] = live ? M[i + (r + 1) * ldh] : T(0);
+        y[e][2] = (live && nr == 3) ? M[i + (r + 2) * ldh] : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < CI; ++e) {
+        const int x = lane + G * e;
+        if (x >= tot) continue;
+        T* M = x <= r1 ? h : u;
+        const int i = x <= r1 ? x : x - (r1 + 1);
+        refl3(tau, w1, w2, y[e][0], y[e][1], y[e][2]);
+        M[i + r * ldh] = y[e][0];
+        M[i + (r + 1) * ldh] = y[e][1];
+        if (nr == 3) M[i + (r + 2) * ldh] = y[e][2];
       }
     }
     __syncthreads();
@@ -777,8 +813,12 @@ bool rhseqr(hipStream_t st, int n, T* H, T* Z, HseqrWork& w, T hnorm) {
     const int m = hi - lo + 1;
     if (m <= W) {
       if (m > 1) {
-        hipLaunchKernelGGL((rsmall_kernel<T, kRQrThreads>), dim3(1), dim3(kRQrThreads), rwin_lds<T>(),
-                           st, n, H, lo, m, 0, U, sp, flag, hnorm);
+        if (m <= kWave)
+          hipLaunchKernelGGL((rsmall_kernel<T, kWave>), dim3(1), dim3(kWave), rwin_lds<T>(), st, n,
+                             H, lo, m, 0, U, sp, flag, hnorm);
+        else
+          hipLaunchKernelGGL((rsmall_kernel<T, kRQrThreads>), dim3(1), dim3(kRQrThreads),
+                             rwin_lds<T>(), st, n, H, lo, m, 0, U, sp, flag, hnorm);
         MSQRT_LAUNCH_CHECK();
         launch_rapply<T>(st, n, H, Z, lo, m, U);
       }
