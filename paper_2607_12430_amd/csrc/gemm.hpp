@@ -905,20 +905,69 @@ __global__ __launch_bounds__(GTHREADS, 2) void gemm_split_kernel(GemmShape s,
   float ra[16], rb[16];
   const int am = TA ? t / 2 : t % GBM, ak = TA ? 16 * (t % 2) : 16 * (t / GBM);
   const int bn = TB ? t % GBN : t / 2, bk = TB ? 16 * (t / GBN) : 16 * (t % 2);
+  // An operand whose k index is the unit-stride one is read 16 bytes at a
+  // time (two lanes cover a 128-byte line of one row) when its leading
+  // dimension and base keep those loads aligned.
+  const bool vecA = TA && s.lda % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool vecB = !TB && s.ldb % 4 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
   auto load = [&](int k0) {
+    if (TA && vecA) {
+      const int gm = m0 + am;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int gm = m0 + am, gk = k0 + ak + i;
-      float v = 0.f;
-      if (gm < s.M && gk < K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
-      ra[i] = v;
+      for (int i4 = 0; i4 < 4; ++i4) {
+        const int gk = k0 + ak + 4 * i4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gm < s.M) {
+          if (gk + 3 < K) {
+            v = *reinterpret_cast<const float4*>(&A[gk + (int64_t)gm * s.lda]);
+          } else {
+            if (gk < K) v.x = A[gk + (int64_t)gm * s.lda];
+            if (gk + 1 < K) v.y = A[gk + 1 + (int64_t)gm * s.lda];
+            if (gk + 2 < K) v.z = A[gk + 2 + (int64_t)gm * s.lda];
+          }
+        }
+        ra[4 * i4] = v.x;
+        ra[4 * i4 + 1] = v.y;
+        ra[4 * i4 + 2] = v.z;
+        ra[4 * i4 + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int gm = m0 + am, gk = k0 + ak + i;
+        float v = 0.f;
+        if (gm < s.M && gk < K) v = TA ? A[gk + (int64_t)gm * s.lda] : A[gm + (int64_t)gk * s.lda];
+        ra[i] = v;
+      }
     }
+    if (!TB && vecB) {
+      const int gn = n0 + bn;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int gn = n0 + bn, gk = k0 + bk + i;
-      float v = 0.f;
-      if (gn < s.N && gk < K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
-      rb[i] = v;
+      for (int i4 = 0; i4 < 4; ++i4) {
+        const int gk = k0 + bk + 4 * i4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gn < s.N) {
+          if (gk + 3 < K) {
+            v = *reinterpret_cast<const float4*>(&B[gk + (int64_t)gn * s.ldb]);
+          } else {
+            if (gk < K) v.x = B[gk + (int64_t)gn * s.ldb];
+            if (gk + 1 < K) v.y = B[gk + 1 + (int64_t)gn * s.ldb];
+            if (gk + 2 < K) v.z = B[gk + 2 + (int64_t)gn * s.ldb];
+          }
+        }
+        rb[4 * i4] = v.x;
+        rb[4 * i4 + 1] = v.y;
+        rb[4 * i4 + 2] = v.z;
+        rb[4 * i4 + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int gn = n0 + bn, gk = k0 + bk + i;
+        float v = 0.f;
+        if (gn < s.N && gk < K) v = TB ? B[gn + (int64_t)gk * s.ldb] : B[gk + (int64_t)gn * s.ldb];
+        rb[i] = v;
+      }
     }
   };
   auto split_store = [&](const float* r, __bf16 (*hi)[SLD], __bf16 (*lo)[SLD], int row, int k) {
