@@ -342,6 +342,13 @@ def main():
                 "relres": gpu_relres(torch, x64, a), "steps": infos64[-1]["steps"],
                 "phases_ms": {k: round(v, 3) for k, v in infos64[-1]["t_ms"].items()}}
 
+    # ---- the BF16-split transforms (same float factor; the Schur-basis
+    # products as three bf16 products with float accumulation)
+    dts, xs, infs = time_solves(msq, torch, a, "bf16split", args.steps, args.warmup)
+    bf16split = {"solves_per_s": args.steps / dts, "ms_per_solve": 1e3 * dts / args.steps,
+                 "relres": gpu_relres(torch, xs, a), "steps": infs[-1]["steps"],
+                 "phases_ms": {k: round(v, 3) for k, v in infs[-1]["t_ms"].items()}}
+
     # ---- learned precision selector (AUTO, fallback on)
     dta, xa, infa = time_solves_opts(msq, torch, a, "auto", args.steps, args.warmup)
     auto = {"solves_per_s": args.steps / dta, "ms_per_solve": 1e3 * dta / args.steps,
@@ -421,6 +428,7 @@ def main():
         "gemm_tflops": gemm_tflops,
         "fp64_schur": fp64,
         "speedup_vs_fp64": (round(value / fp64["solves_per_s"], 4) if fp64 else None),
+        "bf16split": bf16split,
         "auto": auto,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -379,8 +379,9 @@ __global__ __launch_bounds__(kChaseThreads) void chase_kernel(int n, T* H, int s
                                                            const int* __restrict__ mv, int mv0,
                                                            int nmv, const cx<T>* shifts, T* Uo) {
   constexpr int W = Win<T>::W;
-  constexpr int G = W <= 64 ? 64 : 128;  // lanes per move in the rotation phases
-  constexpr int NG = kChaseThreads / G;  // moves handled side by side
+  constexpr int G = kChaseThreads / kMaxNs;  // lanes per move: every move at once
+  constexpr int RI = (W + G - 1) / G;        // columns (rows) per lane
+  static_assert(G * kMaxNs == kChaseThreads, "one lane group per move");
   extern __shared__ unsigned char smem_raw[];
   cx<T>* h = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* u = h + (W + 1) * W;
@@ -426,23 +427,60 @@ __global__ __launch_bounds__(kChaseThreads) void chase_kernel(int n, T* H, int s
       rot_z[t] = kind == 2 ? -1 : kl;  // column whose bulge entry becomes 0
     }
     __syncthreads();
-    // all row rotations (rows r, r+1 of every move; disjoint)
-    for (int m = grp; m < nm; m += NG) {
-      const int j = lane_j;
-      if (j < wl && j >= rot_c0[m]) {
-        const int r = rot_r[m];
-        rot_rows(rot_c[m], rot_s[m], h[r + j * ldh], h[r + 1 + j * ldh]);
-        if (j == rot_z[m]) h[r + 1 + j * ldh] = {T(0), T(0)};
+    // all row rotations (rows r, r+1 of every move; disjoint): lane group
+    // grp owns move grp, and a lane's RI columns are loaded before any is
+    // written, so their LDS latencies overlap
+    if (grp < nm) {
+      const int r = rot_r[grp], c0 = rot_c0[grp], z = rot_z[grp];
+      const T c = rot_c[grp];
+      const cx<T> sr = rot_s[grp];
+      cx<T> a[RI], b[RI];
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int j = lane_j + G * e;
+        const bool live = j < wl && j >= c0;
+        a[e] = live ? h[r + j * ldh] : cx<T>{T(0), T(0)};
+        b[e] = live ? h[r + 1 + j * ldh] : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int j = lane_j + G * e;
+        if (j < wl && j >= c0) {
+          rot_rows(c, sr, a[e], b[e]);
+          h[r + j * ldh] = a[e];
+          h[r + 1 + j * ldh] = j == z ? cx<T>{T(0), T(0)} : b[e];
+        }
       }
     }
     __syncthreads();
-    // all column rotations of H and U (columns r, r+1; disjoint)
-    for (int m = grp; m < nm; m += NG) {
-      const int i = lane_j;
-      if (i < wl) {
-        const int r = rot_r[m];
-        if (i <= rot_r1[m]) rot_cols(rot_c[m], rot_s[m], h[i + r * ldh], h[i + (r + 1) * ldh]);
-        rot_cols(rot_c[m], rot_s[m], u[i + r * ldh], u[i + (r + 1) * ldh]);
+    // all column rotations of H (rows <= r1) and U (columns r, r+1; disjoint)
+    if (grp < nm) {
+      const int r = rot_r[grp], r1 = rot_r1[grp];
+      const T c = rot_c[grp];
+      const cx<T> sr = rot_s[grp];
+      cx<T> ha[RI], hb[RI], ua[RI], ub[RI];
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int i = lane_j + G * e;
+        const bool lh = i < wl && i <= r1, lu = i < wl;
+        ha[e] = lh ? h[i + r * ldh] : cx<T>{T(0), T(0)};
+        hb[e] = lh ? h[i + (r + 1) * ldh] : cx<T>{T(0), T(0)};
+        ua[e] = lu ? u[i + r * ldh] : cx<T>{T(0), T(0)};
+        ub[e] = lu ? u[i + (r + 1) * ldh] : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int e = 0; e < RI; ++e) {
+        const int i = lane_j + G * e;
+        if (i < wl && i <= r1) {
+          rot_cols(c, sr, ha[e], hb[e]);
+          h[i + r * ldh] = ha[e];
+          h[i + (r + 1) * ldh] = hb[e];
+        }
+        if (i < wl) {
+          rot_cols(c, sr, ua[e], ub[e]);
+          u[i + r * ldh] = ua[e];
+          u[i + (r + 1) * ldh] = ub[e];
+        }
       }
     }
     __syncthreads();

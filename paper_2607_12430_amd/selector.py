@@ -163,7 +163,9 @@ def label(a: torch.Tensor, maxit=30, tol=1e-13):
 def fit_cost(records):
     """Least-squares fit of ms = c3 n^3 + c2 n^2 + c0 for every structure and
     quantity (factorisation per precision, one correction per precision, one
-    residual) from the phase timers of the labelling runs."""
+    residual) from the phase timers of the labelling runs.  BF16SPLIT keeps
+    the float factorisation, so its factorisation cost is fitted together
+    with FP32's (one set of coefficients for both)."""
     cost = np.zeros(NCOST)
     for s, sname in enumerate(("hpd", "general")):
         for q in range(7):
@@ -176,7 +178,7 @@ def fit_cost(records):
                         continue
                     t = lab["t_ms"]
                     steps = lab["steps"]
-                    if q < 3 and p_i == q:
+                    if (q < 2 and p_i < 2) or (q == 2 and p_i == 2):
                         val = sum(t.get(k, 0.0) for k in PHASES_FAC)
                     elif 3 <= q < 6 and p_i == q - 3 and steps > 0:
                         val = sum(t.get(k, 0.0) for k in PHASES_SWEEP) / steps
