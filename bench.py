@@ -386,6 +386,18 @@ def main():
                        "us_per_launch": round(1e3 * v["ms"] / v["launches"], 1)}
                    for k, v in sorted(stats.items()) if k.split(":")[0] in PEAK}
 
+    # ---- the refinement GEMMs together: per correction W = R Q and V = Q Y
+    # (2 n^3 each) and the two symmetric-output products Q^T W and V Q^T
+    # (n^2 (n + 1) each), over the transform and update phases of the last
+    # timed solve (launch gaps included)
+    rg_flops = float(steps_mixed) * (4.0 * n ** 3 + 2.0 * n * n * (n + 1.0))
+    rg_ms = phases.get("transform", 0.0) + phases.get("update", 0.0)
+    refinement_gemms = None
+    if rg_flops > 0 and rg_ms > 0:
+        rg_tf = rg_flops / (rg_ms * 1e-3) / 1e12
+        refinement_gemms = {"tflops": round(rg_tf, 2), "frac_peak": round(rg_tf / PEAK["gemm_f32"][0], 4),
+                            "ms": round(rg_ms, 3), "flops": rg_flops, "corrections": steps_mixed}
+
     # ---- whole solve against the FP32 / FP64 matrix peaks
     fl = spd_flops(n, steps_mixed)
     t = dt_mixed / args.steps
@@ -426,6 +438,7 @@ def main():
         "kernel_ms_per_solve": kernel_ms,
         "instrumented_ms_per_step": round(1e3 * dt_instr / args.steps, 3),
         "gemm_tflops": gemm_tflops,
+        "refinement_gemms": refinement_gemms,
         "fp64_schur": fp64,
         "speedup_vs_fp64": (round(value / fp64["solves_per_s"], 4) if fp64 else None),
         "bf16split": bf16split,

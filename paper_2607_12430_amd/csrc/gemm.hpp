@@ -86,6 +86,69 @@ template <class Epi>
 struct EpiPrefetches<Epi, std::void_t<decltype(Epi::kPrefetch)>>
     : std::integral_constant<bool, Epi::kPrefetch> {};
 
+// Epilogues that define kStaged = true are written by the float kernels with
+// 32 x 32 accumulator blocks through epi_block_staged.  They provide
+//   out_t                          the type stored,
+//   bool live(b)                   false: batch entry b is left untouched,
+//   out_t* dst(b), int64_t ld()    the output of entry b,
+//   double load(b, i, j)           what value() needs from memory at (i, j),
+//   out_t value(b, i, j, v, x)     the element stored at (i, j), and at (j, i)
+//                                  for a symmetric output (x = load(b, i, j)).
+template <class Epi, class = void>
+struct EpiStages : std::false_type {};
+template <class Epi>
+struct EpiStages<Epi, std::void_t<decltype(Epi::kStaged)>> : std::integral_constant<bool, Epi::kStaged> {};
+
+// One 32 x 32 output block of a float MFMA kernel whose accumulator holds
+// element (gi0 + l % 32, gj0 + c_row(l, r)) in lane l, register r.  Every
+// load of the block is issued before any store.  The direct store is
+// coalesced (32 consecutive rows per half-wave).  For a symmetric output the
+// mirror (j, i) is written from the wave's own LDS block st (32 x 33 out_t),
+// read in transposed order, so those stores are coalesced too instead of
+// touching 32 rows per store instruction.
+constexpr int kStageLd = 33;
+
+template <class Epi, class Acc>
+__device__ inline void epi_block_staged(const GemmShape& s, const Epi& epi, int b, int gi0, int gj0,
+                                        const Acc& acc, typename Epi::out_t* st, int lane) {
+  using O = typename Epi::out_t;
+  using M = Mfma<float>;
+  static_assert(M::TM == 32 && M::TN == 32 && M::NACC == 16, "32 x 32 accumulator blocks");
+  if (s.tri && gi0 + 31 < gj0) return;  // block above the diagonal (wave-uniform)
+  O* dst = epi.dst(b);
+  const int64_t ld = epi.ld();
+  const int gi = gi0 + lane % 32;
+  double x0[M::NACC];
+#pragma unroll
+  for (int r = 0; r < M::NACC; ++r) {
+    const int gj = gj0 + M::c_row(lane, r);
+    const bool ok = gi < s.M && gj < s.N && !(s.tri && gi < gj);
+    x0[r] = ok ? epi.load(b, gi, gj) : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < M::NACC; ++r) {
+    const int gj = gj0 + M::c_row(lane, r);
+    const bool ok = gi < s.M && gj < s.N && !(s.tri && gi < gj);
+    const O x = ok ? epi.value(b, gi, gj, acc[r], x0[r]) : O(0);
+    if (ok) dst[gi + (int64_t)gj * ld] = x;
+    if (s.tri) st[(lane % 32) * kStageLd + M::c_row(lane, r)] = x;
+  }
+  if (!s.tri) return;
+  // other lanes of the same wave read what was just written
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int li = 2 * q + lane / 32, lj = lane % 32;
+    const int mi = gi0 + li, mj = gj0 + lj;
+    if (mi < s.M && mj < s.N && mi > mj) dst[mj + (int64_t)mi * ld] = st[li * kStageLd + lj];
+  }
+  // the next block's writes to st follow these reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Maps the hardware workgroup id to a tile id so that each of the 8 XCDs
 // (workgroups are dispatched round-robin over XCDs) works on a contiguous
 // range of tiles, then the tile id to (tile_m, tile_n).
@@ -798,6 +861,20 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
     __syncthreads();
   }
 
+  if constexpr (EpiStages<Epi>::value) {
+    static_assert(!Epi::kReduces, "staged epilogues return no sums");
+    static_assert((size_t)(GTHREADS / kWave) * 32 * kStageLd * sizeof(typename Epi::out_t) <= kGemmF32wLds,
+                  "staging blocks fit the slab buffers");
+    // the slab buffers are free: the last slab ended with a barrier
+    if (!epi.live(batch)) return;
+    typename Epi::out_t* st = reinterpret_cast<typename Epi::out_t*>(gemm_ldsw) + wave * 32 * kStageLd;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int j = 0; j < NBW; ++j)
+        epi_block_staged(s, epi, batch, m0 + wm * 96 + i * M::TM, n0 + wn * 96 + j * M::TN, acc[i][j], st, lane);
+    return;
+  }
   double part = 0.0;
 #pragma unroll
   for (int i = 0; i < NBW; ++i)
@@ -1064,6 +1141,19 @@ struct EpiStore {
     if (mir) c[j + (int64_t)i * ldc] = r;
     return 0.0;
   }
+  static constexpr bool kStaged = true;
+  typedef T out_t;
+  __device__ bool live(int) const { return true; }
+  __device__ T* dst(int b) const { return C + (int64_t)b * sC; }
+  __device__ int64_t ld() const { return ldc; }
+  __device__ double load(int b, int i, int j) const {
+    return beta != T(0) ? (double)C[(int64_t)b * sC + i + (int64_t)j * ldc] : 0.0;
+  }
+  __device__ T value(int, int, int, T v, double c) const {
+    T r = alpha * v;
+    if (beta != T(0)) r += beta * (T)c;
+    return r;
+  }
 };
 
 // R = ascale * A - acc in float64; writes R_l = fl32(R) and returns R^2
@@ -1122,6 +1212,17 @@ struct EpiDiagSylv {
     if (mir) yb[j + (int64_t)i * ldy] = y;
     return 0.0;
   }
+  static constexpr bool kStaged = true;
+  typedef T out_t;
+  __device__ bool live(int) const { return true; }
+  __device__ T* dst(int b) const { return Y + (int64_t)b * sY; }
+  __device__ int64_t ld() const { return ldy; }
+  // s_i + s_j, summed in T (exact in double)
+  __device__ double load(int b, int i, int j) const {
+    const T* sb = s + (int64_t)b * sS;
+    return (double)(sb[i] + sb[j]);
+  }
+  __device__ T value(int, int, int, T v, double d) const { return v / (T)d; }
 };
 
 // Working-precision update X += fl64(acc) fused into the last product of
@@ -1158,6 +1259,13 @@ struct EpiUpdate {
     xb[i + (int64_t)j * ldx] = x;
     if (mir) xb[j + (int64_t)i * ldx] = x;
   }
+  static constexpr bool kStaged = true;
+  typedef double out_t;
+  __device__ bool live(int b) const { return !active || active[b]; }
+  __device__ double* dst(int b) const { return X + (int64_t)b * sX; }
+  __device__ int64_t ld() const { return ldx; }
+  __device__ double load(int b, int i, int j) const { return X[(int64_t)b * sX + i + (int64_t)j * ldx]; }
+  __device__ double value(int, int, int, T v, double x) const { return x + (double)v; }
 };
 
 
@@ -1175,6 +1283,13 @@ struct EpiSetF64 {
     if (mir) xb[j + (int64_t)i * ldx] = d;
     return 0.0;
   }
+  static constexpr bool kStaged = true;
+  typedef double out_t;
+  __device__ bool live(int) const { return true; }
+  __device__ double* dst(int b) const { return X + (int64_t)b * sX; }
+  __device__ int64_t ld() const { return ldx; }
+  __device__ double load(int, int, int) const { return 0.0; }
+  __device__ double value(int, int, int, T v, double) const { return (double)v; }
 };
 
 // Host-side shape setup shared by the launchers.
