@@ -190,7 +190,7 @@ struct PanelArgs {
   double* vp;    // [2][TR][2 kNbMax]
   unsigned* bar;
   BarrierBase bar_base;  // barrier counters when the launch starts
-  // batch entry b = workgroup id / G: every pointer above advances by b times
+  // batch entry b = blockIdx.y: every pointer above advances by b times
   // its stride
   int64_t sA, sVW, sD, sYP, sSP, sVP, sBar;
 };
@@ -203,7 +203,7 @@ struct PanelArgs {
 // the tile in flight at once.  Row partials stay in zi (NP passes of RPL rows
 // per lane); column partials are reduced over the wave and added to zK.
 template <typename T, int RPL, int NP>
-__device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0,
+__device__ inline void tile_product(const T* __restrict__ A, unsigned ld, int I0, int nI, int K0,
                                     int nK, int jmin, bool offdiag, const T* uI, const T* uK,
                                     T (&zi)[NP][RPL], T* zK, int tid) {
   constexpr int CW = sizeof(T) == 4 ? 12 : 6;            // columns per chunk
@@ -235,7 +235,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
       for (int c = 0; c < CW; ++c) {
         const int k = cb + c;
         const bool colok = k < nK && k >= cfirst;
-        const T* colp = A + (int64_t)(K0 + (colok ? k : cb)) * ld;
+        const T* colp = A + (unsigned)(K0 + (colok ? k : cb)) * ld;
 #pragma unroll
         for (int q = 0; q < RPL; ++q) v[c][q] = (colok && rowok[q]) ? colp[rowoff[q]] : T(0);
       }
@@ -265,7 +265,7 @@ __device__ inline void tile_product(const T* __restrict__ A, int64_t ld, int I0,
 // the current column excludes are cancelled by the zero entries of u there,
 // so the same registers serve every column of the panel.
 template <typename T, int CW, int RPL>
-__device__ inline void tile_load(const T* __restrict__ A, int64_t ld, int I0, int nI, int K0, int nK,
+__device__ inline void tile_load(const T* __restrict__ A, unsigned ld, int I0, int nI, int K0, int nK,
                                  bool diag, T (&v)[CW][RPL], int tid) {
   const int wave = tid / kWave, lane = tid % kWave;
   const int cb = wave * CW;
@@ -273,13 +273,13 @@ __device__ inline void tile_load(const T* __restrict__ A, int64_t ld, int I0, in
   for (int c = 0; c < CW; ++c) {
     const int k = cb + c;
     const bool colok = k < nK;
-    const T* colp = A + (int64_t)(K0 + (colok ? k : 0)) * ld + I0;
+    const T* colp = A + (unsigned)(K0 + (colok ? k : 0)) * ld + I0;
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + q * kWave;
       // the upper part of a diagonal tile is read from its mirror in the
       // lower triangle (only the lower triangle is kept up to date)
-      v[c][q] = (colok && r < nI) ? ((diag && r < k) ? A[K0 + k + (int64_t)(I0 + r) * ld] : colp[r]) : T(0);
+      v[c][q] = (colok && r < nI) ? ((diag && r < k) ? A[K0 + k + (unsigned)(I0 + r) * ld] : colp[r]) : T(0);
     }
   }
 }
@@ -335,9 +335,11 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   constexpr int RPL = 3;
   const int n = a.n, nb = a.nb, TR = a.TR, G = TR * (TR + 1) / 2;
-  // workgroup id = batch entry * G + tile
+  // workgroup (x, y) = (tile, batch entry).  Both ids are scalar registers,
+  // and so is everything derived from them below: the base pointers and the
+  // tile origin never take vector registers.
   {
-    const int64_t bz = blockIdx.x / G;
+    const int64_t bz = blockIdx.y;
     a.A += bz * a.sA;
     a.VW += bz * a.sVW;
     a.WV += bz * a.sVW;
@@ -349,10 +351,10 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     a.vp += bz * a.sVP;
     a.bar += bz * a.sBar;
   }
-  const int blk = blockIdx.x % G;
-  int bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  const int blk = blockIdx.x;
+  // tile (bi, bj) of the lower triangle, row-major: bi (bi + 1) / 2 <= blk
+  int bi = 0;
   while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
-  while (bi * (bi + 1) / 2 > blk) --bi;
   const int bj = blk - bi * (bi + 1) / 2;
   const bool diag = bi == bj, offdiag = !diag;
   // this workgroup's group counter base (selected without dynamic indexing)
@@ -364,7 +366,10 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   const int K0 = a.r0 + bj * a.ts, K1 = max(K0, min(n, K0 + a.ts));
   const int nI = I1 - I0, nK = K1 - K0;
   const int tid = threadIdx.x;
-  const int64_t ld = n;
+  // Offsets inside one batch entry fit 32 bits (n <= 4225, so n^2 < 2^31):
+  // unsigned 32-bit offsets from the uniform base pointers let every global
+  // access use one offset register instead of a 64-bit address.
+  const unsigned ld = (unsigned)n;
   const int p = a.p;
   T* A = a.A;
 
@@ -424,8 +429,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < kSt; ++e) {
         const int x = tid + e * kThreads, t = x / kMaxTs, r = x % kMaxTs;
-        va[e] = (t < w2 && r < nI) ? a.VW[I0 + r + (int64_t)t * ld] : T(0);
-        wa[e] = (t < w2 && r < nK) ? a.WV[K0 + r + (int64_t)t * ld] : T(0);
+        va[e] = (t < w2 && r < nI) ? a.VW[I0 + r + (unsigned)t * ld] : T(0);
+        wa[e] = (t < w2 && r < nK) ? a.WV[K0 + r + (unsigned)t * ld] : T(0);
       }
 #pragma unroll
       for (int e = 0; e < kSt; ++e) {
@@ -437,8 +442,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
     if (tid < w2) {
-      vwp[tid] = a.VW[p + (int64_t)tid * ld];
-      wvp[tid] = a.WV[p + (int64_t)tid * ld];
+      vwp[tid] = a.VW[p + (unsigned)tid * ld];
+      wvp[tid] = a.WV[p + (unsigned)tid * ld];
     }
     __syncthreads();
     if constexpr (kResident) {
@@ -477,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
 #pragma unroll
           for (int q = 0; q < RPL; ++q) {
             const int r = lane + q * kWave;
-            if (r < nI) cstore(&A[I0 + r + (int64_t)(K0 + k) * ld], vt[c][q]);
+            if (r < nI) cstore(&A[I0 + r + (unsigned)(K0 + k) * ld], vt[c][q]);
           }
         }
       }
@@ -489,13 +494,13 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       if (tid < nI) {
         T cr = T(0);
         for (int t = 0; t < w2; ++t) cr += VWs[t * kMaxTs + tid] * wvp[t];
-        uI[tid] = (I0 + tid >= j + 1) ? A[I0 + tid + (int64_t)j * ld] - cr : T(0);
+        uI[tid] = (I0 + tid >= j + 1) ? A[I0 + tid + (unsigned)j * ld] - cr : T(0);
       }
       if (tid >= kKT && tid - kKT < nK) {
         const int r = tid - kKT;
         T cr = T(0);
         for (int t = 0; t < w2; ++t) cr += WVs[((t + nbp) % w2) * kMaxTs + r] * wvp[t];
-        uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] - cr : T(0);
+        uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (unsigned)j * ld] - cr : T(0);
       }
       if (tid >= kPivT && tid < kPivT + kNbMax) {
         const int q = tid - kPivT, r = p + 1 + q;
@@ -503,16 +508,16 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         if (q < nb && r < n) {
           T vr[2 * kNbMax];  // the row's coefficients, all loads issued together
 #pragma unroll
-          for (int t = 0; t < 2 * kNbMax; ++t) vr[t] = (t < w2) ? a.VW[r + (int64_t)t * ld] : T(0);
+          for (int t = 0; t < 2 * kNbMax; ++t) vr[t] = (t < w2) ? a.VW[r + (unsigned)t * ld] : T(0);
           T cr = T(0);
 #pragma unroll
           for (int t = 0; t < 2 * kNbMax; ++t) cr += vr[t] * ((t < w2) ? wvp[t] : T(0));
-          u = A[r + (int64_t)j * ld] - cr;
+          u = A[r + (unsigned)j * ld] - cr;
         }
         if (q < nb) PU[q] = u;
       }
       if (tid == 0) {
-        double s = (double)A[p + (int64_t)p * ld];
+        double s = (double)A[p + (unsigned)p * ld];
         T corr = T(0);
         for (int t = 0; t < w2; ++t) corr += vwp[t] * wvp[t];
         app = s - (double)corr;
@@ -521,10 +526,10 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     grid_barrier(a.bar, a.bar_base, sub_base, blk, G, 1);
   } else {
     const int j = p;
-    for (int r = tid; r < nI; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (int64_t)j * ld] : T(0);
-    for (int r = tid; r < nK; r += kThreads) uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (int64_t)j * ld] : T(0);
-    for (int q = tid; q < nb; q += kThreads) PU[q] = (p + 1 + q < n) ? A[p + 1 + q + (int64_t)j * ld] : T(0);
-    if (tid == 0) app = (double)A[p + (int64_t)p * ld];
+    for (int r = tid; r < nI; r += kThreads) uI[r] = (I0 + r >= j + 1) ? A[I0 + r + (unsigned)j * ld] : T(0);
+    for (int r = tid; r < nK; r += kThreads) uK[r] = (K0 + r >= j + 1) ? A[K0 + r + (unsigned)j * ld] : T(0);
+    for (int q = tid; q < nb; q += kThreads) PU[q] = (p + 1 + q < n) ? A[p + 1 + q + (unsigned)j * ld] : T(0);
+    if (tid == 0) app = (double)A[p + (unsigned)p * ld];
   }
   __syncthreads();
   const int kb0 = nbp > 0 ? 1 : 0;  // barriers before the first column's
@@ -535,12 +540,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // ---- column j+1 of A (a1 for the product, base of the next u), issued
     // together with the tile loads
     T acv_i = T(0), acv_k = T(0), acv_p = T(0);
-    auto rd = [&](int64_t idx) -> T { return nbp > 0 ? cload(&A[idx]) : A[idx]; };
-    if (tid < nI) acv_i = rd(I0 + tid + (int64_t)(j + 1) * ld);
-    if (tid < nK) acv_k = rd(K0 + tid + (int64_t)(j + 1) * ld);
-    if (tid < nb && p + 1 + tid < n) acv_p = rd(p + 1 + tid + (int64_t)(j + 1) * ld);
+    auto rd = [&](unsigned idx) -> T { return nbp > 0 ? cload(&A[idx]) : A[idx]; };
+    if (tid < nI) acv_i = rd(I0 + tid + (unsigned)(j + 1) * ld);
+    if (tid < nK) acv_k = rd(K0 + tid + (unsigned)(j + 1) * ld);
+    if (tid < nb && p + 1 + tid < n) acv_p = rd(p + 1 + tid + (unsigned)(j + 1) * ld);
     // A(j, j) for d_j (never written inside the panel after the prologue)
-    const double ajj = (tid == 0) ? (jj == 0 ? app : (double)rd(j + (int64_t)j * ld)) : 0.0;
+    const double ajj = (tid == 0) ? (jj == 0 ? app : (double)rd(j + (unsigned)j * ld)) : 0.0;
     // ---- tile product; the 16 waves' row partials are folded onto 8 slots;
     // every column sum of zKs is written once, by the wave owning the column
     {
@@ -578,11 +583,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       T z = T(0);
 #pragma unroll
       for (int w = 0; w < 8; ++w) z += zred[w * kMaxTs + r];
-      cstore(&a.ypart[((int64_t)buf * TR + bj) * n + I0 + r], z);
+      cstore(&a.ypart[((unsigned)buf * TR + bj) * n + I0 + r], z);
       s_uAu += (double)uI[r] * (double)z;
     }
     if (offdiag && tid >= kKT && tid - kKT < nK)
-      cstore(&a.ypart[((int64_t)buf * TR + bi) * n + K0 + (tid - kKT)], zKs[tid - kKT]);
+      cstore(&a.ypart[((unsigned)buf * TR + bi) * n + K0 + (tid - kKT)], zKs[tid - kKT]);
     // ---- row-owner partials (diagonal tiles): ||u(2:)||^2, u^T a1, V^T u, W^T u
     double s_sig = 0.0, s_ua1 = 0.0;
     if (diag) {
@@ -606,7 +611,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         }
       }
       s = rsum16(s);
-      if (l16 == 0 && c < 2 * jj) cstore(&a.vp[((int64_t)buf * TR + bi) * (2 * kNbMax) + c], s);
+      if (l16 == 0 && c < 2 * jj) cstore(&a.vp[((unsigned)buf * TR + bi) * (2 * kNbMax) + c], s);
     }
     // one reduction of the three scalars (wave sums, then one thread), and
     // the pivot-row correction of d_j summed by the first wave
@@ -630,7 +635,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
         const double t1 = rsum16(red3[tid][1]), t2 = rsum16(red3[tid][2]);
         if (offdiag) t0 *= 2.0;
         if (tid == 0) {
-          double* spb = a.sp + ((int64_t)buf * G + blk) * 4;
+          double* spb = a.sp + ((unsigned)buf * G + blk) * 4;
           cstore(&spb[0], t0);
           cstore(&spb[1], t1);
           cstore(&spb[2], t2);
@@ -652,15 +657,15 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, gv0 = 0.0, gv1 = 0.0;
     const int nvp = TR * 2 * jj;
     if (tid < G) {
-      const double* spb = a.sp + ((int64_t)buf * G + tid) * 4;
+      const double* spb = a.sp + ((unsigned)buf * G + tid) * 4;
       g0 = cload(&spb[0]);
       g1 = cload(&spb[1]);
       g2 = cload(&spb[2]);
     }
-    if (tid < nvp) gv0 = cload(&a.vp[((int64_t)buf * TR + tid / (2 * jj)) * (2 * kNbMax) + tid % (2 * jj)]);
+    if (tid < nvp) gv0 = cload(&a.vp[((unsigned)buf * TR + tid / (2 * jj)) * (2 * kNbMax) + tid % (2 * jj)]);
     if (tid + kThreads < nvp) {
       const int x = tid + kThreads;
-      gv1 = cload(&a.vp[((int64_t)buf * TR + x / (2 * jj)) * (2 * kNbMax) + x % (2 * jj)]);
+      gv1 = cload(&a.vp[((unsigned)buf * TR + x / (2 * jj)) * (2 * kNbMax) + x % (2 * jj)]);
     }
     // (A22 u)_i = sum of the TR partial products of row i, for the rows of I,
     // K and the pivot rows: all loads of a row issued together.
@@ -668,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       auto rowsum = [&](int i) -> T {
         T yv[kTRMax];
 #pragma unroll
-        for (int b = 0; b < kTRMax; ++b) yv[b] = (b < TR) ? cload(&a.ypart[((int64_t)buf * TR + b) * n + i]) : T(0);
+        for (int b = 0; b < kTRMax; ++b) yv[b] = (b < TR) ? cload(&a.ypart[((unsigned)buf * TR + b) * n + i]) : T(0);
         T z = T(0);
 #pragma unroll
         for (int b = 0; b < kTRMax; ++b) z += yv[b];
@@ -808,11 +813,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       PVI[jj * kMaxTs + r] = vr;
       PWI[jj * kMaxTs + r] = wr;
       if (diag) {
-        a.VW[i + (int64_t)jj * ld] = vr;
-        a.VW[i + (int64_t)(nb + jj) * ld] = wr;
-        a.WV[i + (int64_t)jj * ld] = wr;
-        a.WV[i + (int64_t)(nb + jj) * ld] = vr;
-        A[i + (int64_t)j * ld] = vr;
+        a.VW[i + (unsigned)jj * ld] = vr;
+        a.VW[i + (unsigned)(nb + jj) * ld] = wr;
+        a.WV[i + (unsigned)jj * ld] = wr;
+        a.WV[i + (unsigned)(nb + jj) * ld] = vr;
+        A[i + (unsigned)j * ld] = vr;
       }
     }
     if (offdiag && tid >= kKT && tid - kKT < nK) {
@@ -860,6 +865,8 @@ __global__ void copy_last_diag(const T* A, int n, T* d, int64_t sA, int64_t sD, 
 }  // namespace
 
 int sytrd_max_n() { return kTRMax * kMaxTs + 1; }
+static_assert((int64_t)(kTRMax * kMaxTs + 1) * (kTRMax * kMaxTs + 1) < (int64_t(1) << 31),
+              "the panel kernel's 32-bit offsets cover an n x n matrix");
 
 template <typename T>
 void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* e, T* tau,
@@ -920,7 +927,7 @@ void sytrd_batched(hipStream_t st, int n, int batch, T* A, int64_t sA, T* d, T* 
                       tau + b0 * sD, ypart + b0 * sYP, sp + b0 * sSP, vp + b0 * sVP,
                       bar + b0 * sBar, bar_base, sA, sVW, sD, sYP, sSP, sVP, sBar};
       void* args[] = {&pa};
-      MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G * nbt),
+      MSQRT_HIP(hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T>, dim3(G, nbt),
                                            dim3(kThreads), args, dyn_lds, st));
     }
     const unsigned nbar = (unsigned)nbe + ((kFused && nbp > 0) ? 1u : 0u);  // barriers of the launch
