@@ -126,50 +126,67 @@ struct BarrierBase {
   unsigned sub[8];  // group counters
 };
 
-// Two-level grid barrier.  The G workgroups of a batch entry form 8 groups
-// (workgroup index mod 8, which is the XCD a workgroup is dispatched to when
-// the entry starts on a multiple of 8); a workgroup adds 1 to its group's
-// counter, the group's last arrival (known from the value its add returns)
-// adds 1 to the top counter, and the last arrival there writes the barrier's
-// generation number to the release word, which the other workgroups poll.
-// Spreading the arrivals over 8 counters halves the cost of a barrier of 253
-// workgroups against one shared counter.  Every thread waits for its own
-// coherent stores to complete before the workgroup arrives.  A spin limit
-// keeps a broken launch from hanging: it raises the sticky failure flag.
-__device__ inline void grid_barrier(unsigned* bar, const BarrierBase& base, unsigned sub_base, int blk,
-                                    int G, int k) {
+// Two-level grid barrier, split into arrival and wait so that a workgroup
+// can do work that needs no other workgroup's results while the barrier
+// completes.  The G workgroups of a batch entry form 8 groups (workgroup
+// index mod 8, which is the XCD a workgroup is dispatched to when the entry
+// starts on a multiple of 8); a workgroup adds 1 to its group's counter, the
+// group's last arrival (known from the value its add returns) adds 1 to the
+// top counter, and the last arrival there writes the barrier's generation
+// number to the release word, which the other workgroups poll.  Spreading the
+// arrivals over 8 counters halves the cost of a barrier of 253 workgroups
+// against one shared counter.  Every thread waits for its own coherent
+// stores to complete before the workgroup arrives.  The counters are handled
+// by the first lane of the last wave (kBarT), which has no row work, so the
+// atomics' round trips hold up no thread that has.  A spin limit keeps a
+// broken launch from hanging: it raises the sticky failure flag.
+constexpr int kBarT = kThreads - kWave;
+
+// Arrival; returns true in thread kBarT if this workgroup released barrier k.
+__device__ inline bool grid_arrive(unsigned* bar, const BarrierBase& base, unsigned sub_base, int blk,
+                                   int G, int k) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  bool released = false;
+  if (threadIdx.x == kBarT) {
     const unsigned g = (unsigned)blk & 7u;
     const unsigned gsz = (unsigned)G / 8u + (g < ((unsigned)G & 7u) ? 1u : 0u);
     const unsigned ng = G < 8 ? (unsigned)G : 8u;
-    const unsigned gen = base.gen + (unsigned)k;
     const unsigned old =
         __hip_atomic_fetch_add(&bar[kBarSub + kBarSubStride * g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool released = false;
     if (old + 1u == sub_base + gsz * (unsigned)k) {
       const unsigned o2 = __hip_atomic_fetch_add(&bar[kBarTop], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (o2 + 1u == base.top + ng * (unsigned)k) {
-        cstore(&bar[kBarRel], gen);
+        cstore(&bar[kBarRel], base.gen + (unsigned)k);
         released = true;
       }
     }
-    if (!released) {
-      unsigned spins = 0;
-      while (cload(&bar[kBarRel]) < gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 255u) == 0u) {
-          if (cload(&bar[kBarFail]) != 0u) break;
-          if (spins > (1u << 24)) {
-            cstore(&bar[kBarFail], 1u);
-            break;
-          }
+  }
+  return released;
+}
+
+// Wait for barrier k (released: what grid_arrive returned).
+__device__ inline void grid_wait(unsigned* bar, const BarrierBase& base, int k, bool released) {
+  if (threadIdx.x == kBarT && !released) {
+    const unsigned gen = base.gen + (unsigned)k;
+    unsigned spins = 0;
+    while (cload(&bar[kBarRel]) < gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0u) {
+        if (cload(&bar[kBarFail]) != 0u) break;
+        if (spins > (1u << 24)) {
+          cstore(&bar[kBarFail], 1u);
+          break;
         }
       }
     }
   }
   __syncthreads();
+}
+
+__device__ inline void grid_barrier(unsigned* bar, const BarrierBase& base, unsigned sub_base, int blk,
+                                    int G, int k) {
+  grid_wait(bar, base, k, grid_arrive(bar, base, sub_base, blk, G, k));
 }
 
 template <typename T>
@@ -392,7 +409,9 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
   // column: every workgroup keeps its own copy, so no value written by another
   // workgroup in the current phase is ever read.
   __shared__ T PV[kNbMax][kNbMax + 1], PW[kNbMax][kNbMax + 1], PU[kNbMax];
-  __shared__ T VTv[kNbMax], WTv[kNbMax];
+  // V^T v and W^T v, rounded to T and held as double (they enter only
+  // double sums)
+  __shared__ double VTv[kNbMax], WTv[kNbMax];
   __shared__ double vts[2 * kNbMax];  // V^T u, W^T u summed over the row tiles
   __shared__ double red3[kThreads / kWave][3];
   __shared__ double sc[8];
@@ -647,7 +666,30 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       }
     }
 
-    grid_barrier(a.bar, a.bar_base, sub_base, blk, G, kb0 + jj + 1);
+    const bool released = grid_arrive(a.bar, a.bar_base, sub_base, blk, G, kb0 + jj + 1);
+    // While the barrier completes: this thread's row share of the next
+    // column's correction, up_i = sum_{t < jj} V(i,t) W(jn,t) + W(i,t) V(jn,t)
+    // for jn = j+1 (row jn's coefficients are pivot row jj).  It reads only
+    // panel coefficients of earlier columns; the t = jj term is added once
+    // this column's pivot row is finished.
+    const int qp = jj + tid - kPivT;  // pivot row of this thread
+    const bool pivt = tid >= kPivT && tid < kPivT + kNbMax && qp < nb;
+    T upr = T(0);
+    {
+      auto upsum = [&](auto Vt, auto Wt) {
+        T us = T(0);
+        for (int t = 0; t < jj; ++t) us += Vt(t) * PW[jj][t] + Wt(t) * PV[jj][t];
+        return us;
+      };
+      if (pivt && p + 1 + qp < n) upr = upsum([&](int t) { return PV[qp][t]; }, [&](int t) { return PW[qp][t]; });
+      if (tid < nI && I0 + tid >= j + 1)
+        upr = upsum([&](int t) { return PVI[t * kMaxTs + tid]; }, [&](int t) { return PWI[t * kMaxTs + tid]; });
+      if (offdiag && tid >= kKT && tid - kKT < nK && K0 + tid - kKT >= j + 1) {
+        const int r = tid - kKT;
+        upr = upsum([&](int t) { return PVK[t * kMaxTs + r]; }, [&](int t) { return PWK[t * kMaxTs + r]; });
+      }
+    }
+    grid_wait(a.bar, a.bar_base, kb0 + jj + 1, released);
 
     // ---- gather the partial sums of all workgroups into LDS in parallel
     // (one load per thread), then reduce them there.
@@ -747,8 +789,8 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       if (tid < jj) {
         const T vt = (T)(c * (vts[tid] - beta * (double)PV[jj][tid]));
         const T wt = (T)(c * (vts[jj + tid] - beta * (double)PW[jj][tid]));
-        VTv[tid] = vt;
-        WTv[tid] = wt;
+        VTv[tid] = (double)vt;
+        WTv[tid] = (double)wt;
         vw = (double)vt * (double)wt;
       }
       vw = wsum(vw);
@@ -765,20 +807,12 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
 
     // y_i, v_i, w_i of the current column for a row i >= j+1, given u_i,
     // (A22 u)_i, a1_i = A(i, j+1) and the row's panel coefficients.
-    //
-    // The same pass over the row's panel coefficients also sums
-    // up_i = sum_{t < jj} V(i,t) W(jn,t) + W(i,t) V(jn,t) for the next column
-    // jn = j+1 (row jn's coefficients are pivot row jj, known for t < jj); the
-    // t = jj term is added once this column's pivot row is finished.
-    auto finish = [&](int i, T ui, T yzi, T a1i, auto Vt, auto Wt, T& vi, T& wi, T& up) {
+    auto finish = [&](int i, T ui, T yzi, T a1i, auto Vt, auto Wt, T& vi, T& wi) {
       double ys = 0.0;
-      T us = T(0);
       for (int t = 0; t < jj; ++t) {
         const T vt = Vt(t), wt = Wt(t);
-        ys += (double)vt * (double)WTv[t] + (double)wt * (double)VTv[t];
-        us += vt * PW[jj][t] + wt * PV[jj][t];
+        ys += (double)vt * WTv[t] + (double)wt * VTv[t];
       }
-      up = us;
       if (zero_refl) {
         vi = (i == j + 1) ? T(1) : T(0);
         wi = T(0);
@@ -794,14 +828,11 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
     // rows p+1+q >= j+1, i.e. q >= jj), a row of I or a row of K.  The
     // diagonal tile's workgroup owns its rows and publishes V, W and the
     // explicit reflector column A(:, j).
-    T vr = T(0), wr = T(0), upr = T(0);
-    const int qp = jj + tid - kPivT;  // pivot row of this thread
-    const bool pivt = tid >= kPivT && tid < kPivT + kNbMax && qp < nb;
+    T vr = T(0), wr = T(0);
     if (pivt) {
       const int r = p + 1 + qp;
       if (r < n)
-        finish(r, PU[qp], yzP[qp], acP[qp], [&](int t) { return PV[qp][t]; }, [&](int t) { return PW[qp][t]; }, vr, wr,
-               upr);
+        finish(r, PU[qp], yzP[qp], acP[qp], [&](int t) { return PV[qp][t]; }, [&](int t) { return PW[qp][t]; }, vr, wr);
       PV[qp][jj] = vr;
       PW[qp][jj] = wr;
     }
@@ -809,7 +840,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       const int r = tid, i = I0 + r;
       if (i >= j + 1)
         finish(i, uI[r], yzI[r], acI[r], [&](int t) { return PVI[t * kMaxTs + r]; }, [&](int t) { return PWI[t * kMaxTs + r]; },
-               vr, wr, upr);
+               vr, wr);
       PVI[jj * kMaxTs + r] = vr;
       PWI[jj * kMaxTs + r] = wr;
       if (diag) {
@@ -824,7 +855,7 @@ __global__ __launch_bounds__(kThreads) void sytrd_panel_kernel(PanelArgs<T> a) {
       const int r = tid - kKT, i = K0 + r;
       if (i >= j + 1)
         finish(i, uK[r], yzK[r], acK[r], [&](int t) { return PVK[t * kMaxTs + r]; }, [&](int t) { return PWK[t * kMaxTs + r]; },
-               vr, wr, upr);
+               vr, wr);
       PVK[jj * kMaxTs + r] = vr;
       PWK[jj * kMaxTs + r] = wr;
     }
