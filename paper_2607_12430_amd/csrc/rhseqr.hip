@@ -487,9 +487,6 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
   T* h = reinterpret_cast<T*>(smem_raw);
   T* u = h + (W + 1) * W;
   int* sched = reinterpret_cast<int*>(u + (W + 1) * W);
-  __shared__ T rtau[kMaxBulges], rw1[kMaxBulges], rw2[kMaxBulges], rbeta[kMaxBulges];
-  __shared__ int rr[kMaxBulges], rnr[kMaxBulges], rc0[kMaxBulges], rr1[kMaxBulges],
-      rz[kMaxBulges];
   const int ldh = W + 1;
   const int t = threadIdx.x;
   for (int x = t; x < 2 * nrounds; x += blockDim.x) sched[x] = rnd[x];
@@ -499,13 +496,20 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
   __syncthreads();
   const int* smv = sched + 2 * nrounds;
   const int lane = t % G, grp = t / G;
+  static_assert(G == kWave, "one wave per move: its lanes read the reflector's vector before any writes it");
   for (int ri = 0; ri < nrounds; ++ri) {
     const int moff = sched[2 * ri] - mv0, nm = sched[2 * ri + 1];
-    if (t < nm) {
-      const int code = smv[moff + t];
+    // Wave q owns move q of the round.  Every lane forms the move's
+    // reflector itself (the same values in every lane) from the state the
+    // previous round left: no other move of this round writes the entries it
+    // reads (a bulge's rows and columns are disjoint from its neighbours'),
+    // so no barrier separates the reflectors from the row operations.
+    T tau = T(0), w1 = T(0), w2 = T(0), beta = T(0);
+    int r = 0, nr = 0, c0 = 0, z = -1, r1 = 0;
+    if (grp < nm) {
+      const int code = smv[moff + grp];
       const int kind = code >> 24, j = (code >> 16) & 0xff, kl = code & 0xffff;
       T x0, x1, x2;
-      int r, nr, c0, z;
       if (kind == 2) {
         // introduction at lo (local kl) from shift pair j
         const T tr = sp[2 * j], det = sp[2 * j + 1];
@@ -527,26 +531,12 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
         c0 = kl;
         z = kl;
       }
-      T tau, w1, w2, beta;
       house3(x0, x1, x2, tau, w1, w2, beta);
-      rtau[t] = tau;
-      rw1[t] = w1;
-      rw2[t] = nr == 3 ? w2 : T(0);
-      rbeta[t] = beta;
-      rr[t] = r;
-      rnr[t] = nr;
-      rc0[t] = c0;
-      rr1[t] = min(r + nr, wl - 1);  // last row of the column operation
-      rz[t] = z;
-    }
-    __syncthreads();
-    // row operations (rows r..r+nr-1 of every move; disjoint).  Group q (G
-    // lanes) owns move q; a lane's RI column items are all loaded before any
-    // is written, so their LDS latencies overlap.
-    if (grp < nm) {
-      const int q = grp;
-      const int r = rr[q], nr = rnr[q], z = rz[q], c0 = rc0[q];
-      const T tau = rtau[q], w1 = rw1[q], w2 = rw2[q];
+      if (nr != 3) w2 = T(0);
+      r1 = min(r + nr, wl - 1);  // last row of the column operation
+      // row operations (rows r..r+nr-1 of every move; disjoint).  A lane's
+      // RI column items are all loaded before any is written, so their LDS
+      // latencies overlap.
       T y[RI][3];
 #pragma unroll
       for (int e = 0; e < RI; ++e) {
@@ -561,7 +551,7 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
         const int jj = c0 + lane + G * e;
         if (jj >= wl) continue;
         if (jj == z) {
-          h[r + jj * ldh] = rbeta[q];
+          h[r + jj * ldh] = beta;
           h[r + 1 + jj * ldh] = T(0);
           if (nr == 3) h[r + 2 + jj * ldh] = T(0);
           continue;
@@ -575,10 +565,7 @@ __global__ __launch_bounds__(kRChaseThreads) void rchase_kernel(int n, T* H, int
     __syncthreads();
     // column operations of H (rows 0..r1) and U (all rows); disjoint columns
     if (grp < nm) {
-      const int q = grp;
-      const int r = rr[q], nr = rnr[q], r1 = rr1[q];
       const int tot = (r1 + 1) + wl;
-      const T tau = rtau[q], w1 = rw1[q], w2 = rw2[q];
       T y[CI][3];
 #pragma unroll
       for (int e = 0; e < CI; ++e) {
