@@ -30,10 +30,17 @@ __global__ void clean_reflectors(int n, T* V, int64_t sV) {
 
 // T factor of one block from its Gram matrix G = V^T V (forward, columnwise):
 // T(i,i) = tau_i,  T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i).
+// Column i is a triangular matrix-vector product, so each row r of T has
+// kParts lanes that sum every kParts-th term of its row (adjacent lanes of
+// one wave, combined with lane shuffles): the serial chain of a column is
+// i / kParts products instead of i.
+constexpr int kParts = 8;
+constexpr int kLarftThreads = kBlk * kParts;
 template <typename T>
-__global__ __launch_bounds__(kBlk) void larft_kernel(int nb_total, const T* G, const T* tau,
-                                                     T* Tm, int64_t sG, int64_t sTau,
-                                                     int64_t sTm) {
+__global__ __launch_bounds__(kLarftThreads) void larft_kernel(int nb_total, const T* G, const T* tau,
+                                                              T* Tm, int64_t sG, int64_t sTau,
+                                                              int64_t sTm) {
+  static_assert(kWave % kParts == 0, "a row's lanes lie in one wave");
   const int blk = blockIdx.x;
   G += (int64_t)blockIdx.y * sG;
   tau += (int64_t)blockIdx.y * sTau;
@@ -42,24 +49,27 @@ __global__ __launch_bounds__(kBlk) void larft_kernel(int nb_total, const T* G, c
   const int nbk = min(kBlk, nb_total - B);
   const T* g = G + (int64_t)blk * kBlk * kBlk;
   T* t = Tm + (int64_t)blk * kBlk * kBlk;
-  const int r = threadIdx.x;
+  const int r = threadIdx.x / kParts, part = threadIdx.x % kParts;
   // Row r of T lives in LDS (padded to avoid bank conflicts on columns).
   __shared__ T tl[kBlk][kBlk + 1];
   __shared__ T col[kBlk];
-  for (int c = 0; c < kBlk; ++c) tl[r][c] = T(0);
+  for (int x = threadIdx.x; x < kBlk * (kBlk + 1); x += kLarftThreads) (&tl[0][0])[x] = T(0);
   __syncthreads();
   for (int i = 0; i < nbk; ++i) {
-    if (r < i) col[r] = g[r + (int64_t)i * kBlk];
+    if (threadIdx.x < i) col[threadIdx.x] = g[threadIdx.x + (int64_t)i * kBlk];
     __syncthreads();
-    if (r < i) {
-      T acc = T(0);
-      for (int c = r; c < i; ++c) acc += tl[r][c] * col[c];
-      tl[r][i] = -tau[B + i] * acc;
+    T acc = T(0);
+    if (r < i)
+      for (int c = r + part; c < i; c += kParts) acc += tl[r][c] * col[c];
+#pragma unroll
+    for (int m = kParts / 2; m >= 1; m /= 2) acc += __shfl_xor(acc, m, kParts);
+    if (part == 0) {
+      if (r < i) tl[r][i] = -tau[B + i] * acc;
+      if (r == i) tl[i][i] = tau[B + i];
     }
-    if (r == i) tl[i][i] = tau[B + i];
     __syncthreads();
   }
-  for (int c = 0; c < kBlk; ++c) t[r + (int64_t)c * kBlk] = tl[r][c];
+  for (int x = threadIdx.x; x < kBlk * kBlk; x += kLarftThreads) t[x % kBlk + (int64_t)(x / kBlk) * kBlk] = tl[x % kBlk][x / kBlk];
 }
 
 template <typename T>
@@ -114,7 +124,7 @@ void ormtr_blocks(hipStream_t st, int n, int nref, int off, const T* Vc, const T
     gemm(true, false, nbk, nbk, n - r0, Vb, n, 0, Vb, n, 0, G + (int64_t)full * kBlk * kBlk, kBlk, 0,
          T(1), T(0), 1);
   }
-  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kBlk), 0, st, nref, (const T*)G, tau, Tm,
+  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk), dim3(kLarftThreads), 0, st, nref, (const T*)G, tau, Tm,
                      (int64_t)0, (int64_t)0, (int64_t)0);
   MSQRT_LAUNCH_CHECK();
   // VT_b = V_b T_b (n x nbk)
@@ -193,7 +203,7 @@ void ormtr_batched(hipStream_t st, int n, int batch, const T* Vc, int64_t sV, co
     gemm(true, false, nbk, nbk, n - r0, Vb, n, sV, Vb, n, sV, Gall + (int64_t)b * kBlk * kBlk, kBlk,
          sG, T(1), T(0), batch);
   }
-  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk, batch), dim3(kBlk), 0, st, nref, (const T*)Gall,
+  hipLaunchKernelGGL(larft_kernel<T>, dim3(nblk, batch), dim3(kLarftThreads), 0, st, nref, (const T*)Gall,
                      tau, Gall + offT, sG, sTau, sG);
   MSQRT_LAUNCH_CHECK();
   for (int b = 0; b < nblk; ++b) {
