@@ -747,17 +747,27 @@ __global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, c
 // lower triangle has 253 tiles of 192 (one per CU) against 528 of 128
 // (2.06 per CU, so some CUs run a third tile while the rest idle); measured
 // 0.78 ms against 1.01 ms for the n^3 flops of one such product.
+//
+// The same kernel with 256 x 256 tiles (each wave 128 x 128: 4 x 4 blocks,
+// 256 accumulator registers, which the MFMA instructions take from the
+// accumulation register file; 144 KiB of slabs) serves large full products
+// whose 256-tiles fill one round on the CUs where the 128 kernel needs two:
+// at n = 4096 the 256 tiles of 256 against 1024 of 128 (1.33 against 1.36 ms).
 
-constexpr size_t kGemmF32wLds = (size_t)2 * 2 * WBM * FLD * sizeof(float);
+template <int WB>
+constexpr size_t f32w_lds() { return (size_t)2 * 2 * WB * FLD * sizeof(float); }
+constexpr size_t kGemmF32wLds = f32w_lds<WBM>();
+constexpr int WBX = 256;
 
-template <bool RC>
+template <bool RC, int WB>
 __device__ inline void f32w_slab_index(int t, int e, int& r, int& k) {
+  constexpr int SL = WB * FBK / GTHREADS;  // slab elements per thread
   const int lane = t % kWave, wave = t / kWave;
   if (RC) {
-    // 96 blocks of 8 rows x 8 k, 24 per wave
-    const int id = wave * 24 + e;
-    r = (id % 24) * 8 + lane % 8;
-    k = (id / 24) * 8 + lane / 8;
+    // WB / 2 blocks of 8 rows x 8 k, SL per wave
+    const int id = wave * SL + e;
+    r = (id % (WB / 8)) * 8 + lane % 8;
+    k = (id / (WB / 8)) * 8 + lane / 8;
   } else {
     const int idx = t + GTHREADS * e;
     k = idx % FBK;
@@ -765,37 +775,40 @@ __device__ inline void f32w_slab_index(int t, int e, int& r, int& k) {
   }
 }
 
-template <bool RC>
+template <bool RC, int WB>
 __device__ inline void f32w_slab_load(const float* __restrict__ X, int64_t ld, int r0, int R, int k0,
-                                      int K, int t, float (&v)[24]) {
+                                      int K, int t, float (&v)[WB * FBK / GTHREADS]) {
 #pragma unroll
-  for (int e = 0; e < 24; ++e) {
+  for (int e = 0; e < WB * FBK / GTHREADS; ++e) {
     int r, k;
-    f32w_slab_index<RC>(t, e, r, k);
+    f32w_slab_index<RC, WB>(t, e, r, k);
     const int gr = r0 + r, gk = k0 + k;
     v[e] = (gr < R && gk < K) ? (RC ? X[gr + (int64_t)gk * ld] : X[gk + (int64_t)gr * ld]) : 0.f;
   }
 }
 
-template <bool RC>
-__device__ inline void f32w_slab_store(float* Xs, int t, const float (&v)[24]) {
+template <bool RC, int WB>
+__device__ inline void f32w_slab_store(float* Xs, int t, const float (&v)[WB * FBK / GTHREADS]) {
 #pragma unroll
-  for (int e = 0; e < 24; ++e) {
+  for (int e = 0; e < WB * FBK / GTHREADS; ++e) {
     int r, k;
-    f32w_slab_index<RC>(t, e, r, k);
+    f32w_slab_index<RC, WB>(t, e, r, k);
     Xs[r * FLD + k] = v[e];
   }
 }
 
-template <bool TA, bool TB, class Epi>
+template <bool TA, bool TB, class Epi, int WB = WBM>
 __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, const float* __restrict__ A,
                                                                 const float* __restrict__ B, Epi epi,
                                                                 double* __restrict__ partials) {
   using M = Mfma<float>;
-  constexpr int NBW = 3;  // 32 x 32 blocks per wave side
+  constexpr int NBW = WB / 64;      // 32 x 32 blocks per wave side
+  constexpr int HW = WB / 2;        // wave block side
+  constexpr int SL = WB * FBK / GTHREADS;
+  static_assert(WB % 64 == 0 && SL * GTHREADS == WB * FBK, "tile size");
   extern __shared__ __attribute__((aligned(16))) float gemm_ldsw[];
   __shared__ double red[GTHREADS / kWave];
-  auto slab = [&](int buf, int op) { return gemm_ldsw + (size_t)(buf * 2 + op) * WBM * FLD; };
+  auto slab = [&](int buf, int op) { return gemm_ldsw + (size_t)(buf * 2 + op) * WB * FLD; };
 
   int tm, tn;
   if (!gemm_tile_coords(s, tm, tn)) return;
@@ -803,7 +816,7 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
   const int K = (batch == (int)gridDim.y - 1) ? s.K_last : s.K;
   A += (int64_t)batch * s.sA;
   B += (int64_t)batch * s.sB;
-  const int m0 = tm * WBM, n0 = tn * WBM;
+  const int m0 = tm * WB, n0 = tn * WB;
   const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
   const int wm = wave % 2, wn = wave / 2;
   constexpr bool ARC = !TA, BRC = TB;
@@ -816,20 +829,20 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
 #pragma unroll
       for (int r = 0; r < M::NACC; ++r) acc[i][j][r] = 0.f;
 
-  float ra[24], rb[24];
+  float ra[SL], rb[SL];
   if (K > 0) {
-    f32w_slab_load<ARC>(A, s.lda, m0, s.M, 0, K, t, ra);
-    f32w_slab_load<BRC>(B, s.ldb, n0, s.N, 0, K, t, rb);
-    f32w_slab_store<ARC>(slab(0, 0), t, ra);
-    f32w_slab_store<BRC>(slab(0, 1), t, rb);
+    f32w_slab_load<ARC, WB>(A, s.lda, m0, s.M, 0, K, t, ra);
+    f32w_slab_load<BRC, WB>(B, s.ldb, n0, s.N, 0, K, t, rb);
+    f32w_slab_store<ARC, WB>(slab(0, 0), t, ra);
+    f32w_slab_store<BRC, WB>(slab(0, 1), t, rb);
   }
   __syncthreads();
   const int h = lane / 32, fr = lane % 32;
   for (int k0 = 0, buf = 0; k0 < K; k0 += FBK, buf ^= 1) {
     const bool more = k0 + FBK < K;
     if (more) {
-      f32w_slab_load<ARC>(A, s.lda, m0, s.M, k0 + FBK, K, t, ra);
-      f32w_slab_load<BRC>(B, s.ldb, n0, s.N, k0 + FBK, K, t, rb);
+      f32w_slab_load<ARC, WB>(A, s.lda, m0, s.M, k0 + FBK, K, t, ra);
+      f32w_slab_load<BRC, WB>(B, s.ldb, n0, s.N, k0 + FBK, K, t, rb);
     }
     const float* As = slab(buf, 0);
     const float* Bs = slab(buf, 1);
@@ -839,10 +852,10 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
       float4 a4[NBW], b4[NBW];
 #pragma unroll
       for (int i = 0; i < NBW; ++i)
-        a4[i] = *reinterpret_cast<const float4*>(As + (wm * 96 + i * 32 + fr) * FLD + kc);
+        a4[i] = *reinterpret_cast<const float4*>(As + (wm * HW + i * 32 + fr) * FLD + kc);
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
-        b4[j] = *reinterpret_cast<const float4*>(Bs + (wn * 96 + j * 32 + fr) * FLD + kc);
+        b4[j] = *reinterpret_cast<const float4*>(Bs + (wn * HW + j * 32 + fr) * FLD + kc);
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -855,15 +868,15 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
           }
     }
     if (more) {
-      f32w_slab_store<ARC>(slab(buf ^ 1, 0), t, ra);
-      f32w_slab_store<BRC>(slab(buf ^ 1, 1), t, rb);
+      f32w_slab_store<ARC, WB>(slab(buf ^ 1, 0), t, ra);
+      f32w_slab_store<BRC, WB>(slab(buf ^ 1, 1), t, rb);
     }
     __syncthreads();
   }
 
   if constexpr (EpiStages<Epi>::value) {
     static_assert(!Epi::kReduces, "staged epilogues return no sums");
-    static_assert((size_t)(GTHREADS / kWave) * 32 * kStageLd * sizeof(typename Epi::out_t) <= kGemmF32wLds,
+    static_assert((size_t)(GTHREADS / kWave) * 32 * kStageLd * sizeof(typename Epi::out_t) <= f32w_lds<WB>(),
                   "staging blocks fit the slab buffers");
     // the slab buffers are free: the last slab ended with a barrier
     if (!epi.live(batch)) return;
@@ -872,7 +885,7 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
-        epi_block_staged(s, epi, batch, m0 + wm * 96 + i * M::TM, n0 + wn * 96 + j * M::TN, acc[i][j], st, lane);
+        epi_block_staged(s, epi, batch, m0 + wm * HW + i * M::TM, n0 + wn * HW + j * M::TN, acc[i][j], st, lane);
     return;
   }
   double part = 0.0;
@@ -885,23 +898,23 @@ __global__ __launch_bounds__(GTHREADS, 1) void gemm_f32w_kernel(GemmShape s, con
         double x0[M::NACC];
 #pragma unroll
         for (int r = 0; r < M::NACC; ++r) {
-          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
-          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          const int gi = m0 + wm * HW + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * HW + j * M::TN + M::c_row(lane, r);
           const bool ok = gi < s.M && gj < s.N && !(s.tri && gi < gj);
           x0[r] = ok ? epi.pre(batch, gi, gj) : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < M::NACC; ++r) {
-          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
-          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          const int gi = m0 + wm * HW + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * HW + j * M::TN + M::c_row(lane, r);
           if (gi < s.M && gj < s.N && !(s.tri && gi < gj))
             epi.post(batch, gi, gj, acc[i][j][r], s.tri && gi != gj, x0[r]);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < M::NACC; ++r) {
-          const int gi = m0 + wm * 96 + i * M::TM + M::c_col(lane, r);
-          const int gj = n0 + wn * 96 + j * M::TN + M::c_row(lane, r);
+          const int gi = m0 + wm * HW + i * M::TM + M::c_col(lane, r);
+          const int gj = n0 + wn * HW + j * M::TN + M::c_row(lane, r);
           if (gi < s.M && gj < s.N) {
             if (s.tri && gi < gj) continue;
             part += epi(batch, gi, gj, acc[i][j][r], s.tri && gi != gj);
@@ -1355,6 +1368,33 @@ int launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A
         const double kk = (double)w.K * (batch - 1) + w.K_last;
         const std::string cls = std::string("gemm_f32:") + Epi::kName;
         prof_end(tok, st, cls.c_str(), 2.0 * outs * kk, 0.0);
+      }
+      return w.ntiles;
+    }
+    // full products that 128-tiles would spread over more than two
+    // workgroups per CU while 256-tiles fill one round on at least 90% of
+    // the CUs: 256 x 256 tiles, one workgroup per CU (at n = 4096 measured
+    // about 2% faster than the 128 kernel; with fewer tiles than CUs the
+    // single wave per SIMD leaves it behind, so it is not used there)
+    const int64_t t256 = ceil_div(s.M, WBX) * ceil_div(s.N, WBX) * batch;
+    if (!s.tri && s.K >= 512 && (int64_t)s.ntiles * batch > 2 * ncu && t256 <= ncu &&
+        10 * t256 >= 9 * ncu) {
+      GemmShape w = make_shape(s.M, s.N, s.K, s.lda, s.ldb, s.sA, s.sB, false, WBX);
+      w.K_last = s.K_last;
+      dim3 gw(8 * w.per_xcd, batch);
+      auto gox = [&](auto kern) {
+        gemm_lds_attr(kern, f32w_lds<WBX>());
+        hipLaunchKernelGGL(kern, gw, block, f32w_lds<WBX>(), st, w, A, B, epi, partials);
+      };
+      if (!ta && !tb) gox(gemm_f32w_kernel<false, false, Epi, WBX>);
+      else if (ta && !tb) gox(gemm_f32w_kernel<true, false, Epi, WBX>);
+      else if (!ta && tb) gox(gemm_f32w_kernel<false, true, Epi, WBX>);
+      else gox(gemm_f32w_kernel<true, true, Epi, WBX>);
+      MSQRT_LAUNCH_CHECK();
+      if (tok >= 0) {
+        const double kk = (double)w.K * (batch - 1) + w.K_last;
+        const std::string cls = std::string("gemm_f32:") + Epi::kName;
+        prof_end(tok, st, cls.c_str(), 2.0 * (double)w.M * w.N * kk, 0.0);
       }
       return w.ntiles;
     }
