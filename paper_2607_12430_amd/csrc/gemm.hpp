@@ -752,7 +752,8 @@ __global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, c
 // 256 accumulator registers, which the MFMA instructions take from the
 // accumulation register file; 144 KiB of slabs) serves large full products
 // whose 256-tiles fill one round on the CUs where the 128 kernel needs two:
-// at n = 4096 the 256 tiles of 256 against 1024 of 128 (1.33 against 1.36 ms).
+// at n = 4096 the 256 tiles of 256 against 1024 of 128 (1.27 against 1.36 ms
+// per product).
 
 template <int WB>
 constexpr size_t f32w_lds() { return (size_t)2 * 2 * WB * FLD * sizeof(float); }
@@ -1374,8 +1375,8 @@ int launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A
     // full products that 128-tiles would spread over more than two
     // workgroups per CU while 256-tiles fill one round on at least 90% of
     // the CUs: 256 x 256 tiles, one workgroup per CU (at n = 4096 measured
-    // about 2% faster than the 128 kernel; with fewer tiles than CUs the
-    // single wave per SIMD leaves it behind, so it is not used there)
+    // 7% faster than the 128 kernel; with far fewer tiles than CUs its single
+    // wave per SIMD is not expected to keep up, so it is not used there)
     const int64_t t256 = ceil_div(s.M, WBX) * ceil_div(s.N, WBX) * batch;
     if (!s.tri && s.K >= 512 && (int64_t)s.ntiles * batch > 2 * ncu && t256 <= ncu &&
         10 * t256 >= 9 * ncu) {
