@@ -147,13 +147,23 @@ __device__ inline bool grid_arrive(unsigned* bar, const BarrierBase& base, unsig
                                    int G, int k) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // A launch of one workgroup per batch entry synchronises with itself only:
+  // the wait above and the workgroup barrier make its stores visible to its
+  // own later loads.  (The trailing order only shrinks, so every later launch
+  // of the reduction has G = 1 too and no counter is read again.)
+  if (G == 1) return true;
   bool released = false;
   if (threadIdx.x == kBarT) {
     const unsigned g = (unsigned)blk & 7u;
     const unsigned gsz = (unsigned)G / 8u + (g < ((unsigned)G & 7u) ? 1u : 0u);
     const unsigned ng = G < 8 ? (unsigned)G : 8u;
+    // with G <= 8 every group has one member, which is always its group's
+    // last arrival: its counter is skipped (later launches of the reduction
+    // have G <= 8 too, so the group counters are not read again)
     const unsigned old =
-        __hip_atomic_fetch_add(&bar[kBarSub + kBarSubStride * g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        G <= 8 ? sub_base + gsz * (unsigned)k - 1u
+               : __hip_atomic_fetch_add(&bar[kBarSub + kBarSubStride * g], 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u == sub_base + gsz * (unsigned)k) {
       const unsigned o2 = __hip_atomic_fetch_add(&bar[kBarTop], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (o2 + 1u == base.top + ng * (unsigned)k) {
