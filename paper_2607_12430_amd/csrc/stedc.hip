@@ -750,7 +750,41 @@ void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int
     MSQRT_HIP(hipMemsetAsync(M, 0, sizeof(T) * nn * batch, st));
     hipLaunchKernelGGL(vectors_kernel<T>, dim3(N), dim3(64), 0, st, dmd, pos_merge, mt, M, lamB, n);
     MSQRT_LAUNCH_CHECK();
-    // One GEMM per merge of the level, batched over the entries; a single
+    // C = A M for each merge, A the merge's m x m block of eigenvectors, M its
+    // secular block.  Before the deflation rotations A = diag(Z1, Z2); a
+    // level whose merges rotated no pair of columns keeps that structure, and
+    // the product splits into Z1 M(0:n1, :) and Z2 M(n1:m, :) (half the
+    // flops).  For a single matrix the rotation counts come to the host once
+    // per level; otherwise, or after a rotation, the full product is formed.
+    bool halves = false;
+    if (batch == 1) {
+      std::vector<int> kc(3 * (size_t)nm);
+      MSQRT_HIP(hipMemcpyAsync(kc.data(), mt.kcnt, sizeof(int) * kc.size(), hipMemcpyDeviceToHost, st));
+      MSQRT_HIP(hipStreamSynchronize(st));
+      halves = true;
+      for (int b = 0; b < nm && halves; ++b) halves = kc[3 * b + 2] == 0;
+    }
+    auto gemm = [&](int Mr, int Nc, int Kk, const T* A_, int64_t sA_, const T* B_, int ldb_, int64_t sB_,
+                    T* C_, int64_t sC_, int nb_) {
+      if (std::is_same<T, float>::value)
+        gemm_store_f32(st, false, false, Mr, Nc, Kk, (const float*)A_, n, sA_, (const float*)B_, ldb_, sB_,
+                       (float*)C_, n, sC_, 1.f, 0.f, nb_, false);
+      else
+        gemm_store_f64(st, false, false, Mr, Nc, Kk, (const double*)A_, n, sA_, (const double*)B_, ldb_,
+                       sB_, (double*)C_, n, sC_, 1.0, 0.0, nb_, false);
+    };
+    auto merge_product = [&](const MergeDesc& g, const T* Ablk, int64_t sA_, const T* Mb, int64_t sM_,
+                             T* Cblk, int64_t sC_, int nb_) {
+      if (halves) {
+        const int n1 = g.n1, n2 = g.m - g.n1;
+        if (n1 > 0) gemm(n1, g.m, n1, Ablk, sA_, Mb, g.m, sM_, Cblk, sC_, nb_);
+        if (n2 > 0)
+          gemm(n2, g.m, n2, Ablk + blk_off(n1, n), sA_, Mb + n1, g.m, sM_, Cblk + n1, sC_, nb_);
+      } else {
+        gemm(g.m, g.m, g.m, Ablk, sA_, Mb, g.m, sM_, Cblk, sC_, nb_);
+      }
+    };
+    // One product per merge of the level, batched over the entries; a single
     // entry whose merges are equal and adjacent (n a power of two times the
     // leaf size) takes the whole level as one batch instead.
     bool uniform = batch == 1 && nm1 > 1;
@@ -759,27 +793,11 @@ void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int
     if (uniform) {
       const MergeDesc& g = lv[0];
       const int64_t sBlk = (int64_t)g.m * (n + 1), sM = (int64_t)g.m * n;
-      const T* Ablk = Za + blk_off(g.s, n);
-      T* Cblk = Zb + blk_off(g.s, n);
-      const T* Mb = M + (int64_t)g.s * n;
-      if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, sBlk, (const float*)Mb,
-                       g.m, sM, (float*)Cblk, n, sBlk, 1.f, 0.f, nm1, false);
-      else
-        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, sBlk, (const double*)Mb,
-                       g.m, sM, (double*)Cblk, n, sBlk, 1.0, 0.0, nm1, false);
+      merge_product(g, Za + blk_off(g.s, n), sBlk, M + (int64_t)g.s * n, sM, Zb + blk_off(g.s, n), sBlk, nm1);
     }
     for (int b = 0; b < nm1 && !uniform; ++b) {
       const MergeDesc& g = lv[b];
-      const T* Ablk = Za + blk_off(g.s, n);
-      T* Cblk = Zb + blk_off(g.s, n);
-      const T* Mb = M + (int64_t)g.s * n;
-      if (std::is_same<T, float>::value)
-        gemm_store_f32(st, false, false, g.m, g.m, g.m, (const float*)Ablk, n, nn, (const float*)Mb,
-                       g.m, nn, (float*)Cblk, n, nn, 1.f, 0.f, batch, false);
-      else
-        gemm_store_f64(st, false, false, g.m, g.m, g.m, (const double*)Ablk, n, nn, (const double*)Mb,
-                       g.m, nn, (double*)Cblk, n, nn, 1.0, 0.0, batch, false);
+      merge_product(g, Za + blk_off(g.s, n), nn, M + (int64_t)g.s * n, nn, Zb + blk_off(g.s, n), nn, batch);
     }
     for (auto& pr : carried[L]) {
       hipLaunchKernelGGL(copy_block<T>, dim3((unsigned)pr.second, (unsigned)batch), dim3(64), 0, st, n,
