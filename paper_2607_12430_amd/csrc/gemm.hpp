@@ -751,7 +751,8 @@ __global__ __launch_bounds__(GTHREADS, 3) void gemm_f32k16_kernel(GemmShape s, c
 // The same kernel with 256 x 256 tiles (each wave 128 x 128: 4 x 4 blocks,
 // 256 accumulator registers, which the MFMA instructions take from the
 // accumulation register file; 144 KiB of slabs) serves large full products
-// whose 256-tiles fill one round on the CUs where the 128 kernel needs two:
+// (single products with K >= 2048) whose 256-tiles fill one round on the CUs
+// where the 128 kernel needs two:
 // at n = 4096 the 256 tiles of 256 against 1024 of 128 (1.27 against 1.36 ms
 // per product).
 
@@ -1372,13 +1373,14 @@ int launch_gemm(hipStream_t st, bool ta, bool tb, const GemmShape& s, const T* A
       }
       return w.ntiles;
     }
-    // full products that 128-tiles would spread over more than two
-    // workgroups per CU while 256-tiles fill one round on at least 90% of
-    // the CUs: 256 x 256 tiles, one workgroup per CU (at n = 4096 measured
-    // 7% faster than the 128 kernel; with far fewer tiles than CUs its single
-    // wave per SIMD is not expected to keep up, so it is not used there)
-    const int64_t t256 = ceil_div(s.M, WBX) * ceil_div(s.N, WBX) * batch;
-    if (!s.tri && s.K >= 512 && (int64_t)s.ntiles * batch > 2 * ncu && t256 <= ncu &&
+    // single full products with a long K that 128-tiles would spread over
+    // more than two workgroups per CU while 256-tiles fill one round on at
+    // least 90% of the CUs: 256 x 256 tiles, one workgroup per CU (at
+    // n = 4096 measured 7% faster than the 128 kernel).  Batches of short
+    // products (64 x 512^3) measured 40% slower on it than on the 128 kernel,
+    // so they keep that one.
+    const int64_t t256 = ceil_div(s.M, WBX) * ceil_div(s.N, WBX);
+    if (batch == 1 && !s.tri && s.K >= 2048 && (int64_t)s.ntiles > 2 * ncu && t256 <= ncu &&
         10 * t256 >= 9 * ncu) {
       GemmShape w = make_shape(s.M, s.N, s.K, s.lda, s.ldb, s.sA, s.sB, false, WBX);
       w.K_last = s.K_last;

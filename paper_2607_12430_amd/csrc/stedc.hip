@@ -754,14 +754,17 @@ void stedc_batched(hipStream_t st, int n, int batch, const T* d, const T* e, int
     // secular block.  Before the deflation rotations A = diag(Z1, Z2); a
     // level whose merges rotated no pair of columns keeps that structure, and
     // the product splits into Z1 M(0:n1, :) and Z2 M(n1:m, :) (half the
-    // flops).  The rotation counts of every merge of the level (every batch
-    // entry's) come to the host once per level; after any rotation the
-    // level forms the full products.
-    bool halves = true;
-    {
+    // flops).  For a single matrix the rotation counts come to the host once
+    // per level; after a rotation the level forms the full products.  (A
+    // batch nearly always has a rotation in some entry at every level, so it
+    // skips the read and its host synchronisation: for 64 x n = 512 the
+    // eigensolver measured 2.49 ms without the read and 2.67 ms with it.)
+    bool halves = false;
+    if (batch == 1) {
       std::vector<int> kc(3 * (size_t)nm);
       MSQRT_HIP(hipMemcpyAsync(kc.data(), mt.kcnt, sizeof(int) * kc.size(), hipMemcpyDeviceToHost, st));
       MSQRT_HIP(hipStreamSynchronize(st));
+      halves = true;
       for (int b = 0; b < nm && halves; ++b) halves = kc[3 * b + 2] == 0;
     }
     auto gemm = [&](int Mr, int Nc, int Kk, const T* A_, int64_t sA_, const T* B_, int ldb_, int64_t sB_,

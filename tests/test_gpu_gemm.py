@@ -1,7 +1,8 @@
 """The MFMA GEMMs element by element against a float64 product: the float
 kernels for ragged sizes and every transpose (|C - AB| <= 4 k 2^-24 |A||B|),
-including full products large enough for the 256 x 256-tile kernel (more
-than two 128-tiles per CU, one 256-tile on 90-100% of the CUs),
+including single full products large enough for the 256 x 256-tile kernel
+(K >= 2048, more than two 128-tiles per CU, one 256-tile on 90-100% of the
+CUs),
 and the symmetric-output (mirroring) launches in float and double at orders
 whose triangle of 128-tiles exceeds two workgroups per CU, where the 192 x
 192-tile kernels run (float: 4 k 2^-24 |A||A|^T; double: 4 k 2^-53)."""
@@ -14,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("m,n,k", [(1601, 1543, 301), (1537, 2113, 257), (2048, 2048, 512),
-                                   (3900, 4000, 600), (4096, 4096, 520)])
+                                   (3900, 4000, 2100), (4096, 4096, 2056)])
 def test_wide_tile_float_gemm(ta, tb, m, n, k):
     import paper_2607_12430_amd as msq
     rng = np.random.Generator(np.random.PCG64(m + 3 * n + 7 * k + 11 * ta + 13 * tb))
