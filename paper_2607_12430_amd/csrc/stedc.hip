@@ -96,13 +96,14 @@ __global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const i
   }
   __syncthreads();
   const double eps = 1.1102230246251565e-16;
+  static_assert(kLeaf <= kWave, "one lane per off-diagonal entry of a leaf");
   int hi = L - 1, iters = 0;
   while (hi > 0 && iters < 60 * kLeaf) {
-    int lo = hi;
-    while (lo > 0) {
-      if (fabs(e[lo - 1]) <= eps * (fabs(d[lo - 1]) + fabs(d[lo]))) break;
-      --lo;
-    }
+    // lo = 1 + the last negligible e[l] below hi (0 if none): every lane
+    // tests its own entry and a ballot finds the last one
+    const bool small = lane < hi && fabs(e[lane]) <= eps * (fabs(d[lane]) + fabs(d[lane + 1]));
+    const unsigned long long sm = __ballot(small);
+    const int lo = sm ? 64 - __clzll(sm) : 0;
     if (lo == hi) { --hi; continue; }
     ++iters;
     const double dd = (d[hi - 1] - d[hi]) * 0.5;
@@ -110,11 +111,16 @@ __global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const i
     const double den = dd + copysign(sqrt(dd * dd + b2), dd);
     const double mu = (den == 0.0) ? d[hi] : d[hi] - b2 / den;
     double x = d[lo] - mu, z = e[lo];
+    // d[k] and e[k] were written by the previous step and are carried in
+    // registers; d[k+1] and e[k+1] are not touched before step k
+    double cd = d[lo], ce = e[lo];
     for (int k = lo; k < hi; ++k) {
+      const double dk1 = d[k + 1];
+      const double ek1 = (k + 1 < hi) ? e[k + 1] : 0.0;
       const double r = hypot(x, z);
       const double c = (r == 0.0) ? 1.0 : x / r;
       const double sn = (r == 0.0) ? 0.0 : z / r;
-      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      const double dk = cd, ek = ce;
       const double ekm = (k > lo) ? r : 0.0;
       const double nd0 = c * c * dk + 2.0 * c * sn * ek + sn * sn * dk1;
       const double nd1 = sn * sn * dk - 2.0 * c * sn * ek + c * c * dk1;
@@ -122,9 +128,11 @@ __global__ __launch_bounds__(64) void leaf_kernel(const int* leaf_start, const i
       double nx = 0.0, nz = 0.0, nek1 = 0.0;
       if (k + 1 < hi) {
         nx = ne;
-        nz = sn * e[k + 1];
-        nek1 = c * e[k + 1];
+        nz = sn * ek1;
+        nek1 = c * ek1;
       }
+      cd = nd1;
+      ce = nek1;
       // Every lane computed the same scalars and writes them itself, so each
       // lane's later reads depend only on its own writes (no barrier).
       if (k > lo) e[k - 1] = ekm;
